@@ -1,0 +1,192 @@
+"""Pins of the oracle's solve (O3 FGMRES + O4 preconditioner) against plain definitions.
+
+* dense LAPACK and SuperLU solves of the assembled matrix (exact to round-off);
+* second-order convergence on manufactured solutions (Sec. 4.2.4 states second
+  order in space), 2D and 3D, smooth and high-contrast coefficients;
+* the well-balanced still tank: with gravity taken from the flow density only
+  (Sec. 5) the exact discrete answer is u = 0 and a hydrostatic pressure; the
+  full density (with the solid) must instead drive spurious currents (Sec. 8.4);
+* with theta = 0 the projection preconditioner is the exact inverse when its
+  Poisson solve is exact, so FGMRES stops after one iteration.
+"""
+import math
+
+import numpy as np
+import pytest
+import sympy as S
+
+import workloads as W
+from oracle import assemble as A
+from oracle import direct as D
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def _compare(prob, xu, xp, ref_u, ref_p, tol):
+    for c in range(prob.dim):
+        assert _rel(xu[c], ref_u[c]) <= tol, ("comp", c, _rel(xu[c], ref_u[c]))
+    assert _rel(xp - xp.mean(), ref_p - ref_p.mean()) <= tol
+
+
+@pytest.mark.parametrize("maker", [lambda: W.config1(scale=4), lambda: W.config3(scale=16),
+                                   lambda: W.config4(scale=32), lambda: W.config5(n_cells=8)])
+def test_fgmres_matches_dense_direct(oracle_lib, maker):
+    prob = maker()
+    sys = A.from_problem(prob)
+    (ru, rp) = D.solve_problem(prob, sys, dense=True)
+    xu, xp, info = oracle_lib.solve_problem(prob, tol=1e-13, max_iters=200)
+    assert info["status"] == 0, info
+    _compare(prob, xu, xp, ru, rp, 1e-10)
+    # the Givens estimate agrees with the recomputed residual
+    assert abs(info["rel_res_est"] - info["rel_res_true"]) <= 1e-12 + 0.5 * info["rel_res_true"]
+
+
+@pytest.mark.parametrize("maker", [lambda: W.config1(), lambda: W.config2(scale=4)])
+def test_fgmres_matches_superlu(oracle_lib, maker):
+    prob = maker()
+    sys = A.from_problem(prob)
+    ru, rp = D.solve_problem(prob, sys, dense=False)
+    xu, xp, info = oracle_lib.solve_problem(prob, tol=1e-13, max_iters=300)
+    assert info["status"] == 0, info
+    _compare(prob, xu, xp, ru, rp, 1e-9)
+    # the returned field satisfies the discrete continuity equation
+    b = sys.pack(prob.rhs_u, prob.rhs_p)
+    r = b - sys.K @ sys.pack(xu, xp)
+    assert np.linalg.norm(r[sys.n_vel:]) * info["sigma"] <= 2e-13 * np.linalg.norm(b)
+
+
+# ------------------------------------------------------------------ MMS
+X, Y, Z = S.symbols("x y z")
+
+
+def _mms_fields(dim, contrast):
+    if dim == 2:
+        psi = S.sin(S.pi * X) ** 2 * S.sin(S.pi * Y) ** 2
+        u = [S.diff(psi, Y), -S.diff(psi, X)]
+        p = S.cos(S.pi * X) * S.cos(S.pi * Y)
+        coords = [X, Y]
+    else:
+        psi = S.sin(S.pi * X) ** 2 * S.sin(S.pi * Y) ** 2 * S.sin(S.pi * Z) ** 2
+        a = (1.0, 0.5, -0.7)
+        Ap = [a[0] * psi, a[1] * psi, a[2] * psi]
+        u = [S.diff(Ap[2], Y) - S.diff(Ap[1], Z), S.diff(Ap[0], Z) - S.diff(Ap[2], X),
+             S.diff(Ap[1], X) - S.diff(Ap[0], Y)]
+        p = S.cos(S.pi * X) * S.cos(S.pi * Y) * S.cos(S.pi * Z)
+        coords = [X, Y, Z]
+    if contrast:
+        H = (1 + S.tanh((Y - 0.5) / 0.1)) / 2
+        rho = 1000 + (1 - 1000) * H
+        mu = 1.0 + (0.05 - 1.0) * H
+    else:
+        rho = 1 + S.Rational(1, 2) * S.sin(S.pi * X + S.Rational(3, 10)) * S.cos(S.pi * Y)
+        mu = 1 + S.Rational(1, 2) * S.cos(S.pi * X) * S.sin(S.pi * Y + S.Rational(1, 5))
+    return coords, u, p, rho, mu
+
+
+def _mms_problem(dim, N, dt, theta, contrast):
+    coords, u, p, rho, mu = _mms_fields(dim, contrast)
+    f = []
+    for c in range(dim):
+        visc = 0
+        for d in range(dim):
+            visc += S.diff(mu * (S.diff(u[c], coords[d]) + S.diff(u[d], coords[c])), coords[d])
+        f.append(rho / dt * u[c] - theta * visc + S.diff(p, coords[c]))
+    args = (X, Y, Z)
+    lam = lambda e: S.lambdify(args, e, "numpy")
+    n = (N, N, N if dim == 3 else 1)
+    h = (1.0 / N,) * 3
+    rho_f, f_f, u_f = [None] * 3, [None] * 3, [None] * 3
+    for c in range(dim):
+        Xc, Yc, Zc = W.face_coords(n, h, c)
+        rho_f[c] = np.broadcast_to(lam(rho)(Xc, Yc, Zc), Xc.shape).astype(np.float64).copy()
+        f_f[c] = np.broadcast_to(lam(f[c])(Xc, Yc, Zc), Xc.shape).astype(np.float64).copy()
+        u_f[c] = np.broadcast_to(lam(u[c])(Xc, Yc, Zc), Xc.shape).astype(np.float64).copy()
+        sl = [slice(None)] * 3
+        for end in (0, -1):
+            sl[2 - c] = end
+            f_f[c][tuple(sl)] = 0.0
+    Xc, Yc, Zc = W.cell_coords(n, h)
+    mu_c = np.broadcast_to(lam(mu)(Xc, Yc, Zc), Xc.shape).astype(np.float64).copy()
+    p_c = np.broadcast_to(lam(p)(Xc, Yc, Zc), Xc.shape).astype(np.float64).copy()
+    prob = W.Problem(name="mms", dim=dim, n=n, h=h, dt=dt, rho_faces=rho_f, mu=mu_c, rhs_u=f_f,
+                     rhs_p=np.zeros(Xc.shape), tol=1e-12)
+    return prob, u_f, p_c
+
+
+def _errors(prob, xu, xp, u_ex, p_ex):
+    cell = np.prod(prob.h[:prob.dim])
+    eu = math.sqrt(sum(np.sum((xu[c] - u_ex[c]) ** 2) for c in range(prob.dim)) * cell)
+    pe = p_ex - p_ex.mean()
+    ep = math.sqrt(np.sum((xp - xp.mean() - pe) ** 2) * cell)
+    return eu, ep
+
+
+@pytest.mark.parametrize("contrast,sizes", [(False, (32, 64, 128)), (True, (64, 128, 256))])
+def test_mms_2d_second_order(contrast, sizes):
+    errs = []
+    for N in sizes:
+        prob, u_ex, p_ex = _mms_problem(2, N, 2e-3, 1.0, contrast)
+        sys = A.from_problem(prob)
+        xu, xp = D.solve_problem(prob, sys, dense=False)
+        errs.append(_errors(prob, xu, xp, u_ex, p_ex))
+    errs = np.array(errs)
+    rates = np.log2(errs[:-1] / errs[1:])
+    assert np.all(rates[-1] >= 1.8), (errs, rates)
+
+
+def test_mms_3d_second_order(oracle_lib):
+    errs = []
+    for N in (16, 32, 64):
+        prob, u_ex, p_ex = _mms_problem(3, N, 2e-3, 1.0, False)
+        xu, xp, info = oracle_lib.solve_problem(prob, tol=1e-12, max_iters=300)
+        assert info["status"] == 0, info
+        errs.append(_errors(prob, xu, xp, u_ex, p_ex))
+    errs = np.array(errs)
+    rates = np.log2(errs[:-1] / errs[1:])
+    assert np.all(rates[-1] >= 1.8), (errs, rates)
+
+
+# ------------------------------------------------------------------ well-balanced gravity
+def _still_tank(full_density):
+    prob = W.config1()
+    g = -9.81
+    src = prob.rho_faces if full_density else prob.rho_flow_faces
+    prob.rhs_u = [np.zeros_like(prob.rho_faces[0]), src[1] * g, None]
+    for end in (0, -1):
+        prob.rhs_u[1][:, end, :] = 0.0
+    return prob, g
+
+
+def test_well_balanced_still_tank(oracle_lib):
+    prob, g = _still_tank(False)
+    xu, xp, info = oracle_lib.solve_problem(prob, tol=1e-13, max_iters=200)
+    assert info["status"] == 0
+    umax = max(np.abs(xu[0]).max(), np.abs(xu[1]).max())
+    assert umax / (abs(g) * prob.dt) <= 1e-9
+    # exact discrete hydrostatic pressure: p_j - p_{j-1} = h rho_flow(face j) g
+    h = prob.h[1]
+    p = np.zeros_like(xp)
+    for j in range(1, prob.n[1]):
+        p[:, j, :] = p[:, j - 1, :] + h * prob.rho_flow_faces[1][:, j, :] * g
+    p -= p.mean()
+    assert _rel(xp - xp.mean(), p) <= 1e-11
+    # negative control: the full density (with the solid) is not hydrostatic
+    prob2, _ = _still_tank(True)
+    yu, yp, info2 = oracle_lib.solve_problem(prob2, tol=1e-13, max_iters=200)
+    umax2 = max(np.abs(yu[0]).max(), np.abs(yu[1]).max())
+    assert umax2 / (abs(g) * prob.dt) >= 1e-4
+
+
+def test_inviscid_projection_is_exact(oracle_lib):
+    """theta = 0: A is diagonal, one Gauss-Seidel sweep inverts it, and with a fully
+    converged Poisson solve the projection preconditioner is the exact inverse."""
+    prob = W.config1(scale=2)
+    xu, xp, info = oracle_lib.solve(prob.dim, prob.n, prob.h, prob.dt, 0.0, prob.rho_faces, prob.mu,
+                                    prob.rhs_u[:2], prob.rhs_p, 1e-9, p_cycles=60, max_iters=10)
+    assert info["iters"] == 1 and info["status"] == 0, info
+    # and a wrong sign in the velocity correction would not converge in one step
+    sys = A.assemble(A.OGrid(2, prob.n, prob.h), prob.rho_faces, prob.mu, prob.dt, 0.0)
+    ru, rp = sys.unpack(D.solve(sys, sys.pack(prob.rhs_u, prob.rhs_p))[0])
+    _compare(prob, xu, xp, ru, rp, 1e-7)
