@@ -1,0 +1,160 @@
+/*
+ * stokes.h -- C-ABI of the MI355X (gfx950) variable-coefficient Stokes solver.
+ *
+ * The operation is one implicit solve of the conservative momentum and
+ * continuity equations on a staggered MAC grid (Nangia, Patankar & Bhalla,
+ * arXiv:1901.07892, Sec. 4.2.2, eqs. eq_c_discrete_momentum and
+ * eq_c_discrete_continuity, layout of Sec. 3.1):
+ *
+ *     (rho_face/dt) u - theta * div_h[ mu (grad_h u + grad_h u^T) ] + grad_h p = f
+ *                                                          -div_h u = g
+ *
+ * rho is given on faces (the face density the momentum equation uses), mu at
+ * cell centres; shear viscosities on cell edges (2D: nodes) are the harmonic
+ * mean of the surrounding cells (Sec. 4.2, footnote on harmonic averaging).
+ * theta scales the implicit viscous operator: 1 gives the full operator, 1/2
+ * the Crank-Nicolson half of Sec. 4.2.2.  Every boundary is a no-slip wall:
+ * wall-normal velocity is zero and is not an unknown, tangential ghosts are
+ * minus the interior value, and the pressure is defined up to a constant
+ * (returned with zero mean).
+ *
+ * The solver is restarted flexible GMRES on the coupled (u, p) system
+ * (Sec. 4.2.4), right-preconditioned by a projection step with a
+ * local-viscosity pressure update whose velocity and pressure subsolves are
+ * geometric-multigrid V-cycles with red-black Gauss-Seidel smoothing.
+ *
+ * Conventions for every entry point
+ *   - Arrays are C order with x fastest.  u is (Nz, Ny, Nx+1), v is
+ *     (Nz, Ny+1, Nx), w is (Nz+1, Ny, Nx), p and mu are (Nz, Ny, Nx).  In 2D
+ *     Nz = 1 and every w / rho_z pointer is NULL.
+ *   - Every array pointer (coefficients, right-hand sides, solutions and the
+ *     workspace) is a DEVICE pointer owned by the caller.  The library never
+ *     allocates device memory: everything it keeps lives in the workspace.
+ *   - Wall-normal face entries are ignored on input and written as 0 on output.
+ *   - Work is queued on the caller's HIP stream (passed as void*; NULL is the
+ *     default stream).  A context belongs to one stream and is not thread-safe.
+ *   - Negative status codes mean nothing was written to the outputs.  No C++
+ *     exception crosses this interface.
+ */
+#ifndef PAPER_1901_07892_STOKES_H
+#define PAPER_1901_07892_STOKES_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    STOKES_OK = 0,
+    STOKES_NOT_CONVERGED = 1,   /* max_iters reached or stagnation; best iterate returned */
+    STOKES_BREAKDOWN = 2,       /* Arnoldi breakdown without convergence */
+    STOKES_EINVAL = -1,         /* bad argument: grid, options, rho <= 0, mu < 0, NULL pointer */
+    STOKES_ESHAPE = -2,         /* grid unsupported (e.g. fewer than 2 cells along an axis) */
+    STOKES_ENOMEM = -3,         /* workspace smaller than stokes_workspace_size() */
+    STOKES_EHIP = -4,           /* a HIP runtime call failed */
+    STOKES_ENAN = -5            /* NaN or Inf in the right-hand side or the residual */
+} stokes_status;
+
+typedef struct {
+    int dim;          /* 2 or 3 */
+    int n[3];         /* cells Nx, Ny, Nz (Nz ignored and taken as 1 in 2D) */
+    double h[3];      /* spacings hx, hy, hz */
+} stokes_grid;
+
+typedef struct {
+    int precision;       /* 0: all FP64; 1: multigrid in FP32 inside FP64 FGMRES */
+    double visc_scale;   /* theta; 1.0 full viscous operator, 0.5 Crank-Nicolson half */
+    double cont_scale;   /* weight sigma of the continuity rows in the residual norm,
+                            ||(r_u, r_p)||^2 = ||r_u||^2 + sigma^2 ||r_p||^2;
+                            0 = automatic balance (see stokes_solve), 1 = plain 2-norm */
+    int restart;         /* FGMRES restart length m (>= 1) */
+    int max_iters;       /* total FGMRES iterations allowed */
+    int nu1, nu2;        /* pre- and post-smoothing sweeps per V-cycle level */
+    int vel_cycles;      /* velocity V-cycles per preconditioner application (>= 0) */
+    int p_cycles;        /* pressure V-cycles per preconditioner application (>= 1) */
+    int coarse_sweeps;   /* smoothing sweeps on the coarsest velocity level (and on the
+                            coarsest pressure level when it is too big for a dense solve) */
+    int vel_levels;      /* velocity multigrid levels: 0 = as many as the pressure hierarchy,
+                            1 = smoother only on the fine grid */
+} stokes_options;
+
+typedef struct {
+    int iters;            /* FGMRES iterations (= preconditioner applications) */
+    int restarts;
+    int vcycles;          /* velocity + pressure V-cycles */
+    int levels;           /* multigrid levels built */
+    double rel_res_est;   /* Givens estimate at exit, weighted norm */
+    double rel_res_true;  /* recomputed ||b - K x|| / ||b|| in FP64, weighted norm */
+    double rel_res_plain; /* the same in the plain 2-norm */
+    double rel_res_mom;   /* ||r_u|| / ||b|| (plain) */
+    double rel_res_cont;  /* ||r_p|| / ||b|| (plain) */
+    double sigma;         /* continuity weight used */
+    double g_mean;        /* mean removed from rhs_p before solving */
+    double ms_total;      /* wall time of the call on the host, milliseconds */
+    int fell_back;        /* reserved (0) */
+} stokes_stats;
+
+typedef struct stokes_ctx stokes_ctx;
+
+/* Fill *opts with the defaults (FP64, theta 1, automatic sigma, restart 30,
+ * max_iters 200, V(2,2), one velocity and one pressure cycle, 40 coarse sweeps,
+ * full velocity hierarchy). */
+void stokes_default_options(stokes_options *opts);
+
+/* Bytes of device workspace that stokes_setup needs for this grid and these
+ * options (opts may be NULL for the defaults).  Returns 0 for an invalid grid.
+ * Host-only; makes no HIP call. */
+size_t stokes_workspace_size(const stokes_grid *grid, const stokes_options *opts);
+
+/* Build a solver context for one coefficient set (once per time step).
+ *   rho_face[3]  face densities (rho_face[2] NULL in 2D); interior values must be > 0
+ *   mu_cell      cell viscosities, >= 0
+ *   dt           time step (> 0); the mass term is rho_face/dt
+ *   workspace    device buffer of ws_bytes >= stokes_workspace_size(grid, opts),
+ *                owned by the caller and kept alive until stokes_destroy
+ *   stream       hipStream_t (as void*)
+ * Validates shapes and options on the host, copies the coefficients into the
+ * workspace (the caller may free its arrays afterwards), builds the multigrid
+ * hierarchy and factors the coarsest pressure problem.  Checks rho > 0 and
+ * mu >= 0 on the device (EINVAL).  Blocks until setup has finished.  On success
+ * *out owns a host-side context to release with stokes_destroy. */
+stokes_status stokes_setup(const double *const rho_face[3], const double *mu_cell, double dt,
+                           const stokes_grid *grid, const stokes_options *opts,
+                           void *workspace, size_t ws_bytes, void *stream, stokes_ctx **out);
+
+/* y = K x: y_u = A x_u + G x_p on interior faces, y_p = -D x_u on cells.
+ * Asynchronous on the context's stream; wall-normal outputs are 0.  In-place
+ * (y aliasing x) is not allowed. */
+stokes_status stokes_apply(stokes_ctx *ctx, const double *const x_u[3], const double *x_p,
+                           double *const y_u[3], double *y_p);
+
+/* Solve K x = (rhs_u, rhs_p) to ||b - K x|| <= tol ||b|| in the weighted norm
+ * ||(a, c)||^2 = ||a||^2 + sigma^2 ||c||^2 over interior unknowns, with sigma =
+ * opts.cont_scale, or, when that is 0, sigma = a_ref * l / pi: l is the
+ * longest side of the domain and a_ref = sqrt(min rho * max rho)/dt +
+ * theta * max(mu) * (pi/l)^2.  This balances the momentum rows (scale rho/dt)
+ * against the continuity rows (scale 1/h) at the slowest pressure mode; in the
+ * plain 2-norm the system's condition number is near 1e14 and the pressure is
+ * barely determined.  With rhs_p = 0, convergence in this norm implies
+ * convergence in the plain 2-norm.
+ * The mean of rhs_p (incompatible with walls everywhere) is removed first and
+ * reported in stats->g_mean.  x holds the initial guess on entry (its wall
+ * entries ignored) and the solution on exit (p with zero mean); the residual is
+ * recomputed in FP64 before returning.  Blocks until done.  stats may be NULL.
+ * Returns OK, NOT_CONVERGED (best iterate in x), BREAKDOWN, ENAN, EINVAL or EHIP. */
+stokes_status stokes_solve(stokes_ctx *ctx, const double *const rhs_u[3], const double *rhs_p,
+                           double tol, double *const x_u[3], double *x_p, stokes_stats *stats);
+
+/* Release the host-side context (the workspace stays the caller's). NULL is a no-op. */
+void stokes_destroy(stokes_ctx *ctx);
+
+/* Message describing the last failure on this context ("" if none).  With
+ * ctx == NULL, the message of the last failed stokes_setup in this thread. */
+const char *stokes_last_error(const stokes_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

@@ -1,0 +1,23 @@
+"""MI355X-native variable-coefficient Stokes solver (MAC grid, FGMRES + multigrid).
+
+The compute path is the HIP library ``libstokes.so`` built from ``csrc/``; this
+package only marshals arguments to its C-ABI (``include/stokes.h``).  There is
+no CPU fallback: importing the binding without the built library raises.
+"""
+from ._binding import (  # noqa: F401
+    STATUS_NAMES,
+    StokesError,
+    StokesGrid,
+    StokesOptions,
+    StokesStats,
+    StokesSolver,
+    library_path,
+    load_library,
+    stokes_apply,
+    stokes_default_options,
+    stokes_destroy,
+    stokes_last_error,
+    stokes_setup,
+    stokes_solve,
+    stokes_workspace_size,
+)

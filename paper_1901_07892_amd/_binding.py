@@ -1,0 +1,210 @@
+"""ctypes binding of libstokes.so: the C-ABI of include/stokes.h, same names.
+
+Device arrays are passed as torch tensors (float64, contiguous, on the GPU);
+the binding only extracts their pointers and the current HIP stream.  Every
+step of the solve runs in the library's kernels.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(HERE, "libstokes.so")
+_lib = None
+
+STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", 2: "BREAKDOWN", -1: "EINVAL", -2: "ESHAPE",
+                -3: "ENOMEM", -4: "EHIP", -5: "ENAN"}
+
+
+class StokesError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s (%d): %s" % (STATUS_NAMES.get(status, "?"), status, msg))
+        self.status = status
+
+
+class StokesGrid(C.Structure):
+    _fields_ = [("dim", C.c_int), ("n", C.c_int * 3), ("h", C.c_double * 3)]
+
+
+class StokesOptions(C.Structure):
+    _fields_ = [("precision", C.c_int), ("visc_scale", C.c_double), ("cont_scale", C.c_double),
+                ("restart", C.c_int), ("max_iters", C.c_int), ("nu1", C.c_int), ("nu2", C.c_int),
+                ("vel_cycles", C.c_int), ("p_cycles", C.c_int), ("coarse_sweeps", C.c_int),
+                ("vel_levels", C.c_int)]
+
+
+class StokesStats(C.Structure):
+    _fields_ = [("iters", C.c_int), ("restarts", C.c_int), ("vcycles", C.c_int), ("levels", C.c_int),
+                ("rel_res_est", C.c_double), ("rel_res_true", C.c_double),
+                ("rel_res_plain", C.c_double), ("rel_res_mom", C.c_double),
+                ("rel_res_cont", C.c_double), ("sigma", C.c_double), ("g_mean", C.c_double),
+                ("ms_total", C.c_double), ("fell_back", C.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def load_library():
+    """Load libstokes.so; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError("libstokes.so is not built; run __graft_entry__.build() or "
+                          "python paper_1901_07892_amd/build.py")
+    L = C.CDLL(_LIB_PATH)
+    dp = C.c_void_p
+    L.stokes_default_options.argtypes = [C.POINTER(StokesOptions)]
+    L.stokes_default_options.restype = None
+    L.stokes_workspace_size.argtypes = [C.POINTER(StokesGrid), C.POINTER(StokesOptions)]
+    L.stokes_workspace_size.restype = C.c_size_t
+    L.stokes_setup.argtypes = [C.c_void_p * 3, dp, C.c_double, C.POINTER(StokesGrid),
+                               C.POINTER(StokesOptions), dp, C.c_size_t, dp, C.POINTER(C.c_void_p)]
+    L.stokes_setup.restype = C.c_int
+    L.stokes_apply.argtypes = [C.c_void_p, C.c_void_p * 3, dp, C.c_void_p * 3, dp]
+    L.stokes_apply.restype = C.c_int
+    L.stokes_solve.argtypes = [C.c_void_p, C.c_void_p * 3, dp, C.c_double, C.c_void_p * 3, dp,
+                               C.POINTER(StokesStats)]
+    L.stokes_solve.restype = C.c_int
+    L.stokes_destroy.argtypes = [C.c_void_p]
+    L.stokes_destroy.restype = None
+    L.stokes_last_error.argtypes = [C.c_void_p]
+    L.stokes_last_error.restype = C.c_char_p
+    _lib = L
+    return L
+
+
+# ---------------------------------------------------------------- marshalling helpers
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    if hasattr(t, "data_ptr"):
+        import torch
+        if t.dtype != torch.float64 or not t.is_contiguous() or not t.is_cuda:
+            raise ValueError("arrays must be contiguous float64 CUDA/HIP tensors")
+        return t.data_ptr()
+    return int(t)
+
+
+def _ptr3(ts: Sequence) -> "C.Array":
+    arr = (C.c_void_p * 3)()
+    for a, t in enumerate(list(ts)[:3]):
+        arr[a] = _ptr(t)
+    return arr
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return getattr(stream, "cuda_stream", stream)
+
+
+def make_grid(dim: int, n: Sequence[int], h: Sequence[float]) -> StokesGrid:
+    g = StokesGrid()
+    g.dim = dim
+    for a in range(3):
+        g.n[a] = int(n[a]) if a < len(n) else 1
+        g.h[a] = float(h[a]) if a < len(h) else float(h[0])
+    return g
+
+
+# ---------------------------------------------------------------- the C-ABI, same names
+def stokes_default_options() -> StokesOptions:
+    o = StokesOptions()
+    load_library().stokes_default_options(C.byref(o))
+    return o
+
+
+def stokes_workspace_size(grid: StokesGrid, opts: Optional[StokesOptions] = None) -> int:
+    return int(load_library().stokes_workspace_size(C.byref(grid), C.byref(opts) if opts else None))
+
+
+def stokes_setup(rho_face, mu_cell, dt, grid, opts, workspace, ws_bytes, stream=None):
+    """Returns an opaque context handle (int); raises StokesError on failure."""
+    L = load_library()
+    ctx = C.c_void_p()
+    st = L.stokes_setup(_ptr3(list(rho_face) + [None] * 3), _ptr(mu_cell), float(dt), C.byref(grid),
+                        C.byref(opts) if opts is not None else None, _ptr(workspace), int(ws_bytes),
+                        _stream(stream), C.byref(ctx))
+    if st != 0:
+        raise StokesError(st, L.stokes_last_error(None).decode())
+    return ctx.value
+
+
+def stokes_apply(ctx, x_u, x_p, y_u, y_p) -> int:
+    L = load_library()
+    st = L.stokes_apply(ctx, _ptr3(list(x_u) + [None] * 3), _ptr(x_p), _ptr3(list(y_u) + [None] * 3), _ptr(y_p))
+    if st < 0:
+        raise StokesError(st, L.stokes_last_error(ctx).decode())
+    return st
+
+
+def stokes_solve(ctx, rhs_u, rhs_p, tol, x_u, x_p):
+    """Returns (status, StokesStats); raises StokesError on negative status."""
+    L = load_library()
+    stats = StokesStats()
+    st = L.stokes_solve(ctx, _ptr3(list(rhs_u) + [None] * 3), _ptr(rhs_p), float(tol),
+                        _ptr3(list(x_u) + [None] * 3), _ptr(x_p), C.byref(stats))
+    if st < 0:
+        raise StokesError(st, L.stokes_last_error(ctx).decode())
+    return st, stats
+
+
+def stokes_destroy(ctx) -> None:
+    if ctx:
+        load_library().stokes_destroy(ctx)
+
+
+def stokes_last_error(ctx=None) -> str:
+    return load_library().stokes_last_error(ctx).decode()
+
+
+# ---------------------------------------------------------------- convenience wrapper
+class StokesSolver:
+    """Owns a workspace tensor and a context for one coefficient set.
+
+    ``rho_face`` (list of 2 or 3 tensors) and ``mu_cell`` are device float64
+    tensors in the caller layout of include/stokes.h.
+    """
+
+    def __init__(self, dim, n, h, rho_face, mu_cell, dt, opts: Optional[StokesOptions] = None,
+                 stream=None, **overrides):
+        import torch
+        load_library()
+        self.grid = make_grid(dim, n, h)
+        self.opts = opts if opts is not None else stokes_default_options()
+        for k, v in overrides.items():
+            setattr(self.opts, k, v)
+        self.ws_bytes = stokes_workspace_size(self.grid, self.opts)
+        if self.ws_bytes == 0:
+            raise StokesError(-1, "invalid grid or options")
+        dev = mu_cell.device
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=dev)
+        self.stream = stream
+        self.ctx = stokes_setup(rho_face, mu_cell, dt, self.grid, self.opts, self.workspace.data_ptr(),
+                                self.ws_bytes, stream)
+        self.dim = dim
+
+    def apply(self, x_u, x_p, y_u, y_p):
+        return stokes_apply(self.ctx, x_u, x_p, y_u, y_p)
+
+    def solve(self, rhs_u, rhs_p, tol, x_u, x_p):
+        return stokes_solve(self.ctx, rhs_u, rhs_p, tol, x_u, x_p)
+
+    def close(self):
+        if self.ctx:
+            stokes_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

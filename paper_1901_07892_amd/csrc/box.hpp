@@ -1,0 +1,49 @@
+// Padded-box layout shared by every staggered field of one multigrid level.
+//
+// A level with Nx x Ny x Nz cells stores every field -- cell (p, mu), face
+// (u, v, w, rho, beta) and edge (mu_xy, mu_xz, mu_yz) -- in one index space of
+// (Nx+1) x (Ny+1) x (Nz+1) points (Nz+1 -> 1 in 2D), x fastest.  Point (i,j,k)
+// holds cell (i,j,k), the x-face at x = i*hx, the y-face at y = j*hy, the
+// z-face at z = k*hz and the edges through the lower corner of that cell, so
+// that every stencil uses the same neighbour offsets (1, px, px*py) whatever
+// the field.  Slots that are not an unknown (wall-normal faces, padding) hold
+// zero.  Each field is surrounded by a zero guard of at least one plane, so a
+// +-1 neighbour of any box point is a valid address; stencils whose weight
+// vanishes there (beta = 0 on wall faces) need no branch.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace stk {
+
+struct Box {
+    int dim;                 // 2 or 3
+    int nx, ny, nz;          // cells (nz = 1 in 2D)
+    int px, py, pz;          // padded extents: nx+1, ny+1, nz+1 (1 in 2D)
+    int plane;               // px * py
+    int nb;                  // px * py * pz points
+    int guard;               // zero elements before and after each field
+    int stride;              // nb + 2*guard: field-to-field distance in a vector
+    double hx, hy, hz;
+    double ihx, ihy, ihz;    // 1/h
+};
+
+inline Box make_box(int dim, int nx, int ny, int nz, double hx, double hy, double hz) {
+    Box b;
+    b.dim = dim;
+    b.nx = nx; b.ny = ny; b.nz = dim == 3 ? nz : 1;
+    b.px = nx + 1; b.py = ny + 1; b.pz = dim == 3 ? nz + 1 : 1;
+    b.plane = b.px * b.py;
+    b.nb = b.plane * b.pz;
+    b.guard = ((b.plane + 1 + 63) / 64) * 64;    // keeps each field 512-byte aligned
+    b.stride = b.nb + 2 * b.guard;
+    b.stride = ((b.stride + 63) / 64) * 64;
+    b.hx = hx; b.hy = hy; b.hz = dim == 3 ? hz : hx;
+    b.ihx = 1.0 / b.hx; b.ihy = 1.0 / b.hy; b.ihz = 1.0 / b.hz;
+    return b;
+}
+
+__host__ __device__ inline int box_index(const Box &b, int i, int j, int k) {
+    return i + b.px * (j + b.py * k);
+}
+
+}  // namespace stk

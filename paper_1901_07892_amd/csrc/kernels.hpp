@@ -1,0 +1,708 @@
+// Device kernels of the MAC-grid Stokes solver (gfx950).
+//
+// All kernels are memory-bound stencils or streaming BLAS-1 operations.  One
+// thread handles one point of the padded box (see box.hpp); launches use
+// 256-thread blocks (four wave64 wavefronts).  Templates: DIM (2 or 3) and R,
+// the number type of the multigrid data (double, or float for the FP32
+// multigrid form).  The fine-level Stokes operator, FGMRES vectors and inner
+// products are always double.
+#pragma once
+#include <hip/hip_runtime.h>
+#include "box.hpp"
+
+namespace stk {
+
+constexpr int kBlock = 256;
+
+__device__ inline void decompose(const Box &b, int idx, int &i, int &j, int &k) {
+    i = idx % b.px;
+    int t = idx / b.px;
+    j = t % b.py;
+    k = t / b.py;
+}
+
+// Coefficients of one level's velocity operator A = mass - theta * L_mu.
+template <class R>
+struct VelCoef {
+    const R *mass[3];   // rho_face / dt
+    const R *mu;        // cell viscosity
+    const R *mxy, *mxz, *myz;  // edge viscosity (harmonic)
+    R theta;
+};
+
+// Which velocity arrays hold valid values during a smoothing pass.  Invalid
+// arrays read as zero: the first sweep after a zero initial guess skips the
+// zero fill of the correction.
+enum { VALID_U = 1, VALID_V = 2, VALID_W = 4 };
+
+// ---------------------------------------------------------------- momentum rows
+// Each returns the off-diagonal part of one momentum row (the row evaluated with
+// the centre value set to zero, wall ghosts included) and its diagonal, so that
+// (A u)_row = diag * u_c + off.  Formulas: strain-rate divergence on the MAC
+// grid; normal stresses 2 mu du/dx at cells, shear stresses mu_e (du/dy + dv/dx)
+// at edges; tangential ghosts beyond a wall are minus the interior value.
+
+template <int DIM, class R>
+__device__ inline void row_u(const Box &b, int idx, int j, int k, const R *u, const R *v,
+                             const R *w, int valid, const VelCoef<R> &c, R &off, R &diag) {
+    const int sy = b.px, sz = b.plane;
+    const R ihx = (R)b.ihx, ihy = (R)b.ihy, ihz = (R)b.ihz;
+    const bool vu = valid & VALID_U, vv = valid & VALID_V, vw = valid & VALID_W;
+    R uE = vu ? u[idx + 1] : R(0), uW = vu ? u[idx - 1] : R(0);
+    R uN = (j + 1 < b.ny && vu) ? u[idx + sy] : R(0);
+    R uS = (j > 0 && vu) ? u[idx - sy] : R(0);
+    R gN = j + 1 < b.ny ? R(1) : R(2), gS = j > 0 ? R(1) : R(2);
+    R m1 = c.mu[idx], m0 = c.mu[idx - 1];
+    R mN = c.mxy[idx + sy], mS = c.mxy[idx];
+    R dvN = vv ? (v[idx + sy] - v[idx + sy - 1]) : R(0);
+    R dvS = vv ? (v[idx] - v[idx - 1]) : R(0);
+    // lap with u_c = 0
+    R lap = R(2) * (m1 * uE + m0 * uW) * ihx * ihx
+          + (mN * (uN * ihy + dvN * ihx) - mS * (-uS * ihy + dvS * ihx)) * ihy;
+    R dg = R(2) * (m0 + m1) * ihx * ihx + (mN * gN + mS * gS) * ihy * ihy;
+    if (DIM == 3) {
+        R uT = (k + 1 < b.nz && vu) ? u[idx + sz] : R(0);
+        R uB = (k > 0 && vu) ? u[idx - sz] : R(0);
+        R gT = k + 1 < b.nz ? R(1) : R(2), gB = k > 0 ? R(1) : R(2);
+        R mT = c.mxz[idx + sz], mB = c.mxz[idx];
+        R dwT = vw ? (w[idx + sz] - w[idx + sz - 1]) : R(0);
+        R dwB = vw ? (w[idx] - w[idx - 1]) : R(0);
+        lap += (mT * (uT * ihz + dwT * ihx) - mB * (-uB * ihz + dwB * ihx)) * ihz;
+        dg += (mT * gT + mB * gB) * ihz * ihz;
+    }
+    off = -c.theta * lap;
+    diag = c.mass[0][idx] + c.theta * dg;
+}
+
+template <int DIM, class R>
+__device__ inline void row_v(const Box &b, int idx, int i, int k, const R *u, const R *v,
+                             const R *w, int valid, const VelCoef<R> &c, R &off, R &diag) {
+    const int sy = b.px, sz = b.plane;
+    const R ihx = (R)b.ihx, ihy = (R)b.ihy, ihz = (R)b.ihz;
+    const bool vu = valid & VALID_U, vv = valid & VALID_V, vw = valid & VALID_W;
+    R vN = vv ? v[idx + sy] : R(0), vS = vv ? v[idx - sy] : R(0);
+    R vE = (i + 1 < b.nx && vv) ? v[idx + 1] : R(0);
+    R vW = (i > 0 && vv) ? v[idx - 1] : R(0);
+    R gE = i + 1 < b.nx ? R(1) : R(2), gW = i > 0 ? R(1) : R(2);
+    R m1 = c.mu[idx], m0 = c.mu[idx - sy];
+    R mE = c.mxy[idx + 1], mW = c.mxy[idx];
+    R duE = vu ? (u[idx + 1] - u[idx + 1 - sy]) : R(0);
+    R duW = vu ? (u[idx] - u[idx - sy]) : R(0);
+    R lap = R(2) * (m1 * vN + m0 * vS) * ihy * ihy
+          + (mE * (vE * ihx + duE * ihy) - mW * (-vW * ihx + duW * ihy)) * ihx;
+    R dg = R(2) * (m0 + m1) * ihy * ihy + (mE * gE + mW * gW) * ihx * ihx;
+    if (DIM == 3) {
+        R vT = (k + 1 < b.nz && vv) ? v[idx + sz] : R(0);
+        R vB = (k > 0 && vv) ? v[idx - sz] : R(0);
+        R gT = k + 1 < b.nz ? R(1) : R(2), gB = k > 0 ? R(1) : R(2);
+        R mT = c.myz[idx + sz], mB = c.myz[idx];
+        R dwT = vw ? (w[idx + sz] - w[idx + sz - sy]) : R(0);
+        R dwB = vw ? (w[idx] - w[idx - sy]) : R(0);
+        lap += (mT * (vT * ihz + dwT * ihy) - mB * (-vB * ihz + dwB * ihy)) * ihz;
+        dg += (mT * gT + mB * gB) * ihz * ihz;
+    }
+    off = -c.theta * lap;
+    diag = c.mass[1][idx] + c.theta * dg;
+}
+
+template <class R>
+__device__ inline void row_w(const Box &b, int idx, int i, int j, const R *u, const R *v,
+                             const R *w, int valid, const VelCoef<R> &c, R &off, R &diag) {
+    const int sy = b.px, sz = b.plane;
+    const R ihx = (R)b.ihx, ihy = (R)b.ihy, ihz = (R)b.ihz;
+    const bool vu = valid & VALID_U, vv = valid & VALID_V, vw = valid & VALID_W;
+    R wT = vw ? w[idx + sz] : R(0), wB = vw ? w[idx - sz] : R(0);
+    R wE = (i + 1 < b.nx && vw) ? w[idx + 1] : R(0);
+    R wW = (i > 0 && vw) ? w[idx - 1] : R(0);
+    R wN = (j + 1 < b.ny && vw) ? w[idx + sy] : R(0);
+    R wS = (j > 0 && vw) ? w[idx - sy] : R(0);
+    R gE = i + 1 < b.nx ? R(1) : R(2), gW = i > 0 ? R(1) : R(2);
+    R gN = j + 1 < b.ny ? R(1) : R(2), gS = j > 0 ? R(1) : R(2);
+    R m1 = c.mu[idx], m0 = c.mu[idx - sz];
+    R mE = c.mxz[idx + 1], mW = c.mxz[idx];
+    R mN = c.myz[idx + sy], mS = c.myz[idx];
+    R duE = vu ? (u[idx + 1] - u[idx + 1 - sz]) : R(0);
+    R duW = vu ? (u[idx] - u[idx - sz]) : R(0);
+    R dvN = vv ? (v[idx + sy] - v[idx + sy - sz]) : R(0);
+    R dvS = vv ? (v[idx] - v[idx - sz]) : R(0);
+    R lap = R(2) * (m1 * wT + m0 * wB) * ihz * ihz
+          + (mE * (wE * ihx + duE * ihz) - mW * (-wW * ihx + duW * ihz)) * ihx
+          + (mN * (wN * ihy + dvN * ihz) - mS * (-wS * ihy + dvS * ihz)) * ihy;
+    R dg = R(2) * (m0 + m1) * ihz * ihz + (mE * gE + mW * gW) * ihx * ihx + (mN * gN + mS * gS) * ihy * ihy;
+    off = -c.theta * lap;
+    diag = c.mass[2][idx] + c.theta * dg;
+}
+
+__device__ inline bool is_ux(const Box &b, int i, int j, int k) { return i >= 1 && i < b.nx && j < b.ny && k < b.nz; }
+__device__ inline bool is_vy(const Box &b, int i, int j, int k) { return j >= 1 && j < b.ny && i < b.nx && k < b.nz; }
+__device__ inline bool is_wz(const Box &b, int i, int j, int k) { return k >= 1 && k < b.nz && i < b.nx && j < b.ny; }
+__device__ inline bool is_cell(const Box &b, int i, int j, int k) { return i < b.nx && j < b.ny && k < b.nz; }
+
+// ---------------------------------------------------------------- fine operator (FP64)
+// y = K x  (or y = f - K x when f != nullptr) for the coupled system
+// K = [A G; -D 0]; all four outputs of a box point are written by one thread.
+template <int DIM>
+__global__ void __launch_bounds__(kBlock) k_apply(Box b, VelCoef<double> c,
+        const double *__restrict__ xu, const double *__restrict__ xv,
+        const double *__restrict__ xw, const double *__restrict__ xp,
+        const double *__restrict__ fu, const double *__restrict__ fv,
+        const double *__restrict__ fw, const double *__restrict__ fp,
+        double *__restrict__ yu, double *__restrict__ yv,
+        double *__restrict__ yw, double *__restrict__ yp) {
+    int idx = blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= b.nb) return;
+    int i, j, k;
+    decompose(b, idx, i, j, k);
+    const int sy = b.px, sz = b.plane;
+    const int all = VALID_U | VALID_V | VALID_W;
+    double off, dg, r;
+    r = 0.0;
+    if (is_ux(b, i, j, k)) {
+        row_u<DIM, double>(b, idx, j, k, xu, xv, xw, all, c, off, dg);
+        r = dg * xu[idx] + off + (xp[idx] - xp[idx - 1]) * b.ihx;
+        if (fu) r = fu[idx] - r;
+    }
+    yu[idx] = r;
+    r = 0.0;
+    if (is_vy(b, i, j, k)) {
+        row_v<DIM, double>(b, idx, i, k, xu, xv, xw, all, c, off, dg);
+        r = dg * xv[idx] + off + (xp[idx] - xp[idx - sy]) * b.ihy;
+        if (fv) r = fv[idx] - r;
+    }
+    yv[idx] = r;
+    if (DIM == 3) {
+        r = 0.0;
+        if (is_wz(b, i, j, k)) {
+            row_w<double>(b, idx, i, j, xu, xv, xw, all, c, off, dg);
+            r = dg * xw[idx] + off + (xp[idx] - xp[idx - sz]) * b.ihz;
+            if (fw) r = fw[idx] - r;
+        }
+        yw[idx] = r;
+    }
+    r = 0.0;
+    if (is_cell(b, i, j, k)) {
+        double dv = (xu[idx + 1] - xu[idx]) * b.ihx + (xv[idx + sy] - xv[idx]) * b.ihy;
+        if (DIM == 3) dv += (xw[idx + sz] - xw[idx]) * b.ihz;
+        r = -dv;
+        if (fp) r = fp[idx] - r;
+    }
+    yp[idx] = r;
+}
+
+// ---------------------------------------------------------------- velocity multigrid
+// t = r - A e on interior faces (0 elsewhere), all components.
+template <int DIM, class R>
+__global__ void __launch_bounds__(kBlock) k_vel_residual(Box b, VelCoef<R> c,
+        const R *__restrict__ eu, const R *__restrict__ ev, const R *__restrict__ ew,
+        const R *__restrict__ ru, const R *__restrict__ rv, const R *__restrict__ rw,
+        R *__restrict__ tu, R *__restrict__ tv, R *__restrict__ tw) {
+    int idx = blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= b.nb) return;
+    int i, j, k;
+    decompose(b, idx, i, j, k);
+    const int all = VALID_U | VALID_V | VALID_W;
+    R off, dg;
+    R t = 0;
+    if (is_ux(b, i, j, k)) { row_u<DIM, R>(b, idx, j, k, eu, ev, ew, all, c, off, dg); t = ru[idx] - (dg * eu[idx] + off); }
+    tu[idx] = t;
+    t = 0;
+    if (is_vy(b, i, j, k)) { row_v<DIM, R>(b, idx, i, k, eu, ev, ew, all, c, off, dg); t = rv[idx] - (dg * ev[idx] + off); }
+    tv[idx] = t;
+    if (DIM == 3) {
+        t = 0;
+        if (is_wz(b, i, j, k)) { row_w<R>(b, idx, i, j, eu, ev, ew, all, c, off, dg); t = rw[idx] - (dg * ew[idx] + off); }
+        tw[idx] = t;
+    }
+}
+
+// One colour of a red-black Gauss-Seidel pass on one velocity component:
+// e_c = (r - off) / diag on faces with (i+j+k) % 2 == colour.
+template <int DIM, class R>
+__global__ void __launch_bounds__(kBlock) k_vel_gs(Box b, VelCoef<R> c, int comp, int colour, int valid,
+        R *eu, R *ev, R *ew, const R *__restrict__ ru, const R *__restrict__ rv, const R *__restrict__ rw) {
+    int idx = blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= b.nb) return;
+    int i, j, k;
+    decompose(b, idx, i, j, k);
+    if (((i + j + k) & 1) != colour) return;
+    R off, dg;
+    if (comp == 0) {
+        if (!is_ux(b, i, j, k)) return;
+        row_u<DIM, R>(b, idx, j, k, eu, ev, ew, valid, c, off, dg);
+        eu[idx] = (ru[idx] - off) / dg;
+    } else if (comp == 1) {
+        if (!is_vy(b, i, j, k)) return;
+        row_v<DIM, R>(b, idx, i, k, eu, ev, ew, valid, c, off, dg);
+        ev[idx] = (rv[idx] - off) / dg;
+    } else {
+        if (!is_wz(b, i, j, k)) return;
+        row_w<R>(b, idx, i, j, eu, ev, ew, valid, c, off, dg);
+        ew[idx] = (rw[idx] - off) / dg;
+    }
+}
+
+// Face restriction for component comp: the coarse face averages the fine faces
+// it covers with weight 2 for the coincident ones and 1 for those half a coarse
+// cell to either side (2D: (1/8)[2 2 1 1 1 1]); coarse wall faces get 0.
+template <int DIM, class R>
+__global__ void __launch_bounds__(kBlock) k_face_restrict(Box fb, Box cb, int comp,
+        const R *__restrict__ f, R *__restrict__ c) {
+    int idx = blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= cb.nb) return;
+    int I, J, K;
+    decompose(cb, idx, I, J, K);
+    bool inner = comp == 0 ? is_ux(cb, I, J, K) : comp == 1 ? is_vy(cb, I, J, K) : is_wz(cb, I, J, K);
+    if (!inner) { c[idx] = R(0); return; }
+    const int s[3] = {1, fb.px, fb.plane};
+    int base = box_index(fb, 2 * I, 2 * J, DIM == 3 ? 2 * K : 0);
+    const int sn = s[comp];
+    const int t1 = comp == 0 ? s[1] : s[0];
+    const int t2 = comp == 2 ? s[1] : s[2];
+    R acc = 0;
+    const int n2 = DIM == 3 ? 2 : 1;
+    for (int a2 = 0; a2 < n2; ++a2)
+        for (int a1 = 0; a1 < 2; ++a1) {
+            int q = base + a1 * t1 + a2 * t2;
+            acc += R(2) * f[q] + f[q - sn] + f[q + sn];
+        }
+    c[idx] = acc * (DIM == 3 ? R(1.0 / 16.0) : R(1.0 / 8.0));
+}
+
+// Face prolongation for component comp, added to the fine correction: linear
+// along the face normal, constant across; fine wall faces untouched.
+template <int DIM, class R>
+__global__ void __launch_bounds__(kBlock) k_face_prolong_add(Box fb, Box cb, int comp,
+        const R *__restrict__ c, R *__restrict__ f) {
+    int idx = blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= fb.nb) return;
+    int i, j, k;
+    decompose(fb, idx, i, j, k);
+    bool inner = comp == 0 ? is_ux(fb, i, j, k) : comp == 1 ? is_vy(fb, i, j, k) : is_wz(fb, i, j, k);
+    if (!inner) return;
+    int ci[3] = {i >> 1, j >> 1, DIM == 3 ? (k >> 1) : 0};
+    int fi[3] = {i, j, k};
+    const int cs[3] = {1, cb.px, cb.plane};
+    int q = box_index(cb, ci[0], ci[1], ci[2]);
+    R val;
+    if ((fi[comp] & 1) == 0) {
+        val = c[q];
+    } else {
+        val = R(0.5) * (c[q] + c[q + cs[comp]]);
+    }
+    f[idx] += val;
+}
+
+// ---------------------------------------------------------------- pressure multigrid
+// -L_rho phi = -D beta G phi at a cell; beta is zero on wall faces, so the
+// Neumann walls need no branch.
+template <int DIM, class R>
+__device__ inline void prow(const Box &b, int idx, const R *e, const R *bx, const R *by,
+                            const R *bz, R &off, R &diag) {
+    const int sy = b.px, sz = b.plane;
+    const R ix2 = R(b.ihx * b.ihx), iy2 = R(b.ihy * b.ihy), iz2 = R(b.ihz * b.ihz);
+    R wW = bx[idx] * ix2, wE = bx[idx + 1] * ix2;
+    R wS = by[idx] * iy2, wN = by[idx + sy] * iy2;
+    off = wW * e[idx - 1] + wE * e[idx + 1] + wS * e[idx - sy] + wN * e[idx + sy];
+    diag = wW + wE + wS + wN;
+    if (DIM == 3) {
+        R wB = bz[idx] * iz2, wT = bz[idx + sz] * iz2;
+        off += wB * e[idx - sz] + wT * e[idx + sz];
+        diag += wB + wT;
+    }
+}
+
+template <int DIM, class R>
+__global__ void __launch_bounds__(kBlock) k_p_gs(Box b, int colour, int zero_guess, R *e,
+        const R *__restrict__ r, const R *__restrict__ bx, const R *__restrict__ by,
+        const R *__restrict__ bz) {
+    int idx = blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= b.nb) return;
+    int i, j, k;
+    decompose(b, idx, i, j, k);
+    if (!is_cell(b, i, j, k) || ((i + j + k) & 1) != colour) return;
+    R off, dg;
+    prow<DIM, R>(b, idx, e, bx, by, bz, off, dg);
+    if (zero_guess) off = R(0);
+    e[idx] = dg > R(0) ? (r[idx] + off) / dg : R(0);
+}
+
+// Coarse right-hand side: average over the 2^d children of the fine residual
+// r - (-L_rho) e.
+template <int DIM, class R>
+__global__ void __launch_bounds__(kBlock) k_p_residual_restrict(Box fb, Box cb, const R *__restrict__ e,
+        const R *__restrict__ r, const R *__restrict__ bx, const R *__restrict__ by,
+        const R *__restrict__ bz, R *__restrict__ rc) {
+    int idx = blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= cb.nb) return;
+    int I, J, K;
+    decompose(cb, idx, I, J, K);
+    if (!is_cell(cb, I, J, K)) { rc[idx] = R(0); return; }
+    R acc = 0;
+    const int n2 = DIM == 3 ? 2 : 1;
+    for (int dk = 0; dk < n2; ++dk)
+        for (int dj = 0; dj < 2; ++dj)
+            for (int di = 0; di < 2; ++di) {
+                int q = box_index(fb, 2 * I + di, 2 * J + dj, DIM == 3 ? 2 * K + dk : 0);
+                R off, dg;
+                prow<DIM, R>(fb, q, e, bx, by, bz, off, dg);
+                acc += r[q] - (dg * e[q] - off);
+            }
+    rc[idx] = acc * (DIM == 3 ? R(0.125) : R(0.25));
+}
+
+// Fine correction += coarse value of the parent cell (piecewise constant).
+template <int DIM, class R>
+__global__ void __launch_bounds__(kBlock) k_p_prolong_add(Box fb, Box cb, const R *__restrict__ c, R *__restrict__ f) {
+    int idx = blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= fb.nb) return;
+    int i, j, k;
+    decompose(fb, idx, i, j, k);
+    if (!is_cell(fb, i, j, k)) return;
+    f[idx] += c[box_index(cb, i >> 1, j >> 1, DIM == 3 ? (k >> 1) : 0)];
+}
+
+// Coarsest pressure level: e = M r with M the dense pseudo-inverse of the
+// level's Neumann operator (it also projects out the constant).  One block.
+template <class R>
+__global__ void __launch_bounds__(1024) k_dense_solve(int n, const R *__restrict__ M, const int *__restrict__ map,
+        const R *__restrict__ r, R *__restrict__ e) {
+    extern __shared__ unsigned char smem_raw[];
+    R *rs = reinterpret_cast<R *>(smem_raw);
+    for (int t = threadIdx.x; t < n; t += blockDim.x) rs[t] = r[map[t]];
+    __syncthreads();
+    for (int t = threadIdx.x; t < n; t += blockDim.x) {
+        R acc = 0;
+        const R *row = M + (size_t)t * n;
+        for (int q = 0; q < n; ++q) acc += row[q] * rs[q];
+        e[map[t]] = acc;
+    }
+}
+
+// ---------------------------------------------------------------- coefficients
+// Coarse cell viscosity: harmonic mean of the 2^d children.
+template <int DIM, class R>
+__global__ void __launch_bounds__(kBlock) k_coarsen_mu(Box fb, Box cb, const R *__restrict__ f, R *__restrict__ c) {
+    int idx = blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= cb.nb) return;
+    int I, J, K;
+    decompose(cb, idx, I, J, K);
+    if (!is_cell(cb, I, J, K)) { c[idx] = R(0); return; }
+    double s = 0.0;
+    const int n2 = DIM == 3 ? 2 : 1;
+    for (int dk = 0; dk < n2; ++dk)
+        for (int dj = 0; dj < 2; ++dj)
+            for (int di = 0; di < 2; ++di)
+                s += 1.0 / (double)f[box_index(fb, 2 * I + di, 2 * J + dj, DIM == 3 ? 2 * K + dk : 0)];
+    c[idx] = (R)((DIM == 3 ? 8.0 : 4.0) / s);
+}
+
+// Coarse Poisson coefficient on the faces normal to comp: arithmetic mean of the
+// coincident fine beta (the harmonic mean of rho); wall faces stay zero.
+template <int DIM, class R>
+__global__ void __launch_bounds__(kBlock) k_coarsen_beta(Box fb, Box cb, int comp, const R *__restrict__ f, R *__restrict__ c) {
+    int idx = blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= cb.nb) return;
+    int I, J, K;
+    decompose(cb, idx, I, J, K);
+    bool inner = comp == 0 ? is_ux(cb, I, J, K) : comp == 1 ? is_vy(cb, I, J, K) : is_wz(cb, I, J, K);
+    if (!inner) { c[idx] = R(0); return; }
+    const int s[3] = {1, fb.px, fb.plane};
+    const int t1 = comp == 0 ? s[1] : s[0];
+    const int t2 = comp == 2 ? s[1] : s[2];
+    int base = box_index(fb, 2 * I, 2 * J, DIM == 3 ? 2 * K : 0);
+    double acc = (double)f[base] + (double)f[base + t1];
+    if (DIM == 3) acc += (double)f[base + t2] + (double)f[base + t1 + t2];
+    c[idx] = (R)(acc * (DIM == 3 ? 0.25 : 0.5));
+}
+
+// Edge viscosities of a level: harmonic mean of the 4 cells around each edge,
+// out-of-domain cells mirrored.  mxy at (x-face i, y-face j, cell k), mxz at
+// (x-face i, cell j, z-face k), myz at (cell i, y-face j, z-face k).
+template <int DIM, class R>
+__global__ void __launch_bounds__(kBlock) k_edge_mu(Box b, const R *__restrict__ mu, R *__restrict__ mxy,
+        R *__restrict__ mxz, R *__restrict__ myz) {
+    int idx = blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= b.nb) return;
+    int i, j, k;
+    decompose(b, idx, i, j, k);
+    auto cl = [](int a, int n) { return a < 0 ? 0 : (a > n - 1 ? n - 1 : a); };
+    int i0 = cl(i - 1, b.nx), i1 = cl(i, b.nx), j0 = cl(j - 1, b.ny), j1 = cl(j, b.ny);
+    if (k < b.nz) {
+        double s = 1.0 / (double)mu[box_index(b, i0, j0, k)] + 1.0 / (double)mu[box_index(b, i1, j0, k)]
+                 + 1.0 / (double)mu[box_index(b, i0, j1, k)] + 1.0 / (double)mu[box_index(b, i1, j1, k)];
+        mxy[idx] = (R)(4.0 / s);
+    } else {
+        mxy[idx] = R(0);
+    }
+    if (DIM == 3) {
+        int k0 = cl(k - 1, b.nz), k1 = cl(k, b.nz);
+        if (j < b.ny) {
+            double s = 1.0 / (double)mu[box_index(b, i0, j, k0)] + 1.0 / (double)mu[box_index(b, i1, j, k0)]
+                     + 1.0 / (double)mu[box_index(b, i0, j, k1)] + 1.0 / (double)mu[box_index(b, i1, j, k1)];
+            mxz[idx] = (R)(4.0 / s);
+        } else {
+            mxz[idx] = R(0);
+        }
+        if (i < b.nx) {
+            double s = 1.0 / (double)mu[box_index(b, i, j0, k0)] + 1.0 / (double)mu[box_index(b, i, j1, k0)]
+                     + 1.0 / (double)mu[box_index(b, i, j0, k1)] + 1.0 / (double)mu[box_index(b, i, j1, k1)];
+            myz[idx] = (R)(4.0 / s);
+        } else {
+            myz[idx] = R(0);
+        }
+    }
+}
+
+// ---------------------------------------------------------------- layout conversion
+// Caller layout (C order, x fastest, per-field shape) <-> padded box.
+// comp 0,1,2: face arrays normal to x,y,z; comp 3: cell array.
+// mode 0: copy, 1: reciprocal (beta = 1/rho), 2: multiply by s.
+// Only interior unknowns are copied (faces: interior faces; with keep_walls the
+// wall faces too); everything else in the box is written as 0.
+__device__ inline bool api_index(const Box &b, int comp, int i, int j, int k, int &a) {
+    int ex = b.nx + (comp == 0), ey = b.ny + (comp == 1), ez = b.nz + (comp == 2);
+    if (i >= ex || j >= ey || k >= ez) return false;
+    a = i + ex * (j + ey * k);
+    return true;
+}
+
+__global__ void __launch_bounds__(kBlock) k_pack(Box b, int comp, int mode, int keep_walls, double s,
+        const double *__restrict__ src, double *__restrict__ dst) {
+    int idx = blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= b.nb) return;
+    int i, j, k, a;
+    decompose(b, idx, i, j, k);
+    double val = 0.0;
+    if (api_index(b, comp, i, j, k, a)) {
+        bool wall = (comp == 0 && (i == 0 || i == b.nx)) || (comp == 1 && (j == 0 || j == b.ny)) ||
+                    (comp == 2 && (k == 0 || k == b.nz));
+        if (!wall || keep_walls) {
+            double x = src[a];
+            val = mode == 0 ? x : mode == 1 ? 1.0 / x : s * x;
+        }
+    }
+    dst[idx] = val;
+}
+
+__global__ void __launch_bounds__(kBlock) k_unpack(Box b, int comp, const double *__restrict__ src,
+        double *__restrict__ dst) {
+    int idx = blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= b.nb) return;
+    int i, j, k, a;
+    decompose(b, idx, i, j, k);
+    if (api_index(b, comp, i, j, k, a)) dst[a] = src[idx];
+}
+
+// Flags non-physical coefficients: rho <= 0 or non-finite on interior faces, mu < 0
+// or non-finite on cells.  flag[0] is set to 1 on failure (vector store).
+__global__ void __launch_bounds__(kBlock) k_check_coef(Box b, const double *__restrict__ rx,
+        const double *__restrict__ ry, const double *__restrict__ rz, const double *__restrict__ mu,
+        int *__restrict__ flag) {
+    int idx = blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= b.nb) return;
+    int i, j, k;
+    decompose(b, idx, i, j, k);
+    bool bad = false;
+    if (is_ux(b, i, j, k)) bad |= !(rx[idx] > 0.0) || !isfinite(rx[idx]);
+    if (is_vy(b, i, j, k)) bad |= !(ry[idx] > 0.0) || !isfinite(ry[idx]);
+    if (b.dim == 3 && is_wz(b, i, j, k)) bad |= !(rz[idx] > 0.0) || !isfinite(rz[idx]);
+    if (is_cell(b, i, j, k)) bad |= !(mu[idx] >= 0.0) || !isfinite(mu[idx]);
+    if (bad) flag[0] = 1;
+}
+
+// ---------------------------------------------------------------- preconditioner glue
+// q = r_p + D u~ (FP64), s = -q/dt (right-hand side of -L_rho phi = -s_paper).
+template <int DIM, class R>
+__global__ void __launch_bounds__(kBlock) k_precond_div(Box b, const R *__restrict__ eu, const R *__restrict__ ev,
+        const R *__restrict__ ew, const double *__restrict__ rp, double dt, double *__restrict__ q,
+        R *__restrict__ s) {
+    int idx = blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= b.nb) return;
+    int i, j, k;
+    decompose(b, idx, i, j, k);
+    double qq = 0.0;
+    if (is_cell(b, i, j, k)) {
+        double dv = ((double)eu[idx + 1] - (double)eu[idx]) * b.ihx + ((double)ev[idx + b.px] - (double)ev[idx]) * b.ihy;
+        if (DIM == 3) dv += ((double)ew[idx + b.plane] - (double)ew[idx]) * b.ihz;
+        qq = rp[idx] + dv;
+    }
+    q[idx] = qq;
+    s[idx] = (R)(-qq / dt);
+}
+
+// z_u = u~ - dt beta G phi on interior faces; z_p = phi - 2 theta mu q on cells.
+// eu/ev/ew may alias zu/zv/zw (FP64 multigrid): each point is read, then written,
+// by the same thread.
+template <int DIM, class R>
+__global__ void __launch_bounds__(kBlock) k_precond_update(Box b, const R *eu, const R *ev, const R *ew,
+        const R *__restrict__ phi, const double *__restrict__ bx, const double *__restrict__ by,
+        const double *__restrict__ bz, const double *__restrict__ mu, const double *__restrict__ q,
+        double dt, double theta, double *zu, double *zv, double *zw, double *__restrict__ zp) {
+    int idx = blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= b.nb) return;
+    int i, j, k;
+    decompose(b, idx, i, j, k);
+    const double ph = (double)phi[idx];
+    double z = 0.0;
+    if (is_ux(b, i, j, k)) z = (double)eu[idx] - dt * bx[idx] * (ph - (double)phi[idx - 1]) * b.ihx;
+    zu[idx] = z;
+    z = 0.0;
+    if (is_vy(b, i, j, k)) z = (double)ev[idx] - dt * by[idx] * (ph - (double)phi[idx - b.px]) * b.ihy;
+    zv[idx] = z;
+    if (DIM == 3) {
+        z = 0.0;
+        if (is_wz(b, i, j, k)) z = (double)ew[idx] - dt * bz[idx] * (ph - (double)phi[idx - b.plane]) * b.ihz;
+        zw[idx] = z;
+    }
+    z = 0.0;
+    if (is_cell(b, i, j, k)) z = ph - 2.0 * theta * mu[idx] * q[idx];
+    zp[idx] = z;
+}
+
+// ---------------------------------------------------------------- BLAS-1
+template <class A, class B>
+__global__ void __launch_bounds__(kBlock) k_cast(long long n, const A *__restrict__ x, B *__restrict__ y) {
+    long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+    long long st = (long long)gridDim.x * kBlock;
+    for (; t < n; t += st) y[t] = (B)x[t];
+}
+
+template <class R>
+__global__ void __launch_bounds__(kBlock) k_fill(long long n, R *__restrict__ x, R v) {
+    long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+    long long st = (long long)gridDim.x * kBlock;
+    for (; t < n; t += st) x[t] = v;
+}
+
+// wave64 + LDS block reduction of NV partial sums; the result is in lane 0 of
+// warp 0 for each of the NV values.
+template <int NV>
+__device__ inline void block_reduce(double (&v)[NV], double *lds /* [NV][kBlock/64] */) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int m = 0; m < NV; ++m) {
+        double x = v[m];
+        for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
+        if (lane == 0) lds[m * (kBlock / 64) + wid] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+#pragma unroll
+        for (int m = 0; m < NV; ++m) {
+            double x = threadIdx.x < kBlock / 64 ? lds[m * (kBlock / 64) + threadIdx.x] : 0.0;
+            for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
+            v[m] = x;
+        }
+    }
+}
+
+// partial[m * gridDim.x + block] = sum over this block's elements of
+// wgt * V_m[t] * w[t], for m < nv (nv <= NV); wgt = w2 for t >= pstart.
+template <int NV>
+__global__ void __launch_bounds__(kBlock) k_multidot(long long n, long long pstart, double w2,
+        const double *__restrict__ V, long long ldv, int nv, const double *__restrict__ w,
+        double *__restrict__ partial) {
+    __shared__ double lds[NV * (kBlock / 64)];
+    double acc[NV];
+#pragma unroll
+    for (int m = 0; m < NV; ++m) acc[m] = 0.0;
+    long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+    long long st = (long long)gridDim.x * kBlock;
+    for (; t < n; t += st) {
+        double x = w[t];
+        if (t >= pstart) x *= w2;
+#pragma unroll
+        for (int m = 0; m < NV; ++m)
+            if (m < nv) acc[m] += V[m * ldv + t] * x;
+    }
+    block_reduce<NV>(acc, lds);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int m = 0; m < NV; ++m)
+            if (m < nv) partial[m * gridDim.x + blockIdx.x] = acc[m];
+    }
+}
+
+// out[m] (=, or += if accumulate) sum over blocks of partial[m * nblk + .], in a
+// fixed order: the result is bitwise reproducible.  One block per m.
+__global__ void __launch_bounds__(kBlock) k_reduce_partials(int nblk, const double *__restrict__ partial,
+        double *__restrict__ out, int accumulate) {
+    __shared__ double lds[kBlock / 64];
+    const int m = blockIdx.x;
+    double v[1] = {0.0};
+    for (int t = threadIdx.x; t < nblk; t += kBlock) v[0] += partial[(size_t)m * nblk + t];
+    block_reduce<1>(v, lds);
+    if (threadIdx.x == 0) out[m] = accumulate ? out[m] + v[0] : v[0];
+}
+
+// w[t] += sign * sum_m c[m] * V_m[t]   (c on the device)
+template <int NV>
+__global__ void __launch_bounds__(kBlock) k_maxpy(long long n, double sign, const double *__restrict__ V,
+        long long ldv, int nv, const double *__restrict__ c, double *__restrict__ w) {
+    double cc[NV];
+#pragma unroll
+    for (int m = 0; m < NV; ++m) cc[m] = m < nv ? sign * c[m] : 0.0;
+    long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+    long long st = (long long)gridDim.x * kBlock;
+    for (; t < n; t += st) {
+        double x = w[t];
+#pragma unroll
+        for (int m = 0; m < NV; ++m)
+            if (m < nv) x += cc[m] * V[m * ldv + t];
+        w[t] = x;
+    }
+}
+
+// x[t] *= 1/sqrt(nrm2[0]) (nothing if the norm is zero)
+__global__ void __launch_bounds__(kBlock) k_scale_inv_sqrt(long long n, const double *__restrict__ nrm2,
+        double *__restrict__ x) {
+    double s2 = nrm2[0];
+    if (!(s2 > 0.0)) return;
+    double s = 1.0 / sqrt(s2);
+    long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+    long long st = (long long)gridDim.x * kBlock;
+    for (; t < n; t += st) x[t] *= s;
+}
+
+// x[t] *= s
+__global__ void __launch_bounds__(kBlock) k_scale(long long n, double s, double *__restrict__ x) {
+    long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+    long long st = (long long)gridDim.x * kBlock;
+    for (; t < n; t += st) x[t] *= s;
+}
+
+// subtract mean = sum[0] / ncell on the cells of a cell array
+__global__ void __launch_bounds__(kBlock) k_sub_mean(Box b, const double *__restrict__ sum, double *__restrict__ p) {
+    int idx = blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= b.nb) return;
+    int i, j, k;
+    decompose(b, idx, i, j, k);
+    if (!is_cell(b, i, j, k)) return;
+    p[idx] -= sum[0] / ((double)b.nx * b.ny * b.nz);
+}
+
+// partial sums (plain) of a range; used for means and norms of sub-blocks
+__global__ void __launch_bounds__(kBlock) k_partial_sum(long long n, const double *__restrict__ x, int squared,
+        double *__restrict__ partial) {
+    __shared__ double lds[kBlock / 64];
+    double v[1] = {0.0};
+    long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+    long long st = (long long)gridDim.x * kBlock;
+    for (; t < n; t += st) {
+        double a = x[t];
+        v[0] += squared ? a * a : a;
+    }
+    block_reduce<1>(v, lds);
+    if (threadIdx.x == 0) partial[blockIdx.x] = v[0];
+}
+
+// flags non-finite values in a range
+__global__ void __launch_bounds__(kBlock) k_check_finite(long long n, const double *__restrict__ x, int *__restrict__ flag) {
+    long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+    long long st = (long long)gridDim.x * kBlock;
+    bool bad = false;
+    for (; t < n; t += st) bad |= !isfinite(x[t]);
+    if (bad) flag[0] = 1;
+}
+
+}  // namespace stk

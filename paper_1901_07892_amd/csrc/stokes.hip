@@ -1,0 +1,952 @@
+// Host side of the MI355X Stokes solver: workspace layout, coefficient setup and
+// multigrid hierarchy, V-cycles, the projection preconditioner, FGMRES and the
+// C-ABI declared in include/stokes.h.
+//
+// Everything the solver keeps lives in the caller's workspace; no device memory
+// is allocated here.  All work is queued on the context's stream; the host
+// synchronises once per FGMRES iteration to read the new Hessenberg column.
+#include "../../include/stokes.h"
+#include "kernels.hpp"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace stk;
+
+namespace {
+
+constexpr int kMaxLev = 24;
+constexpr int kDenseMax = 2048;     // largest coarsest pressure level solved densely
+constexpr int kRedBlocks = 2048;    // blocks of the streaming reduction kernels
+constexpr int kGroup = 8;           // vectors per multidot / maxpy launch
+
+thread_local std::string g_setup_error;
+
+struct HipError {
+    hipError_t e;
+    const char *what;
+};
+
+#define HIPCHK(call)                                                  \
+    do {                                                              \
+        hipError_t e_ = (call);                                       \
+        if (e_ != hipSuccess) throw HipError{e_, #call};              \
+    } while (0)
+
+// ---------------------------------------------------------------- workspace carving
+struct Carver {
+    char *base;        // nullptr: only count
+    size_t off = 0;
+    template <class T>
+    T *take(size_t count) {
+        off = (off + 255) & ~size_t(255);
+        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+    // nf consecutive fields of one box; returns the pointer of field 0's origin
+    template <class T>
+    T *fields(const Box &b, int nf) {
+        T *p = take<T>((size_t)b.stride * nf);
+        return p ? p + b.guard : nullptr;
+    }
+};
+
+template <class R>
+struct Level {
+    Box b;
+    R *mass[3] = {nullptr, nullptr, nullptr};
+    R *beta[3] = {nullptr, nullptr, nullptr};
+    R *mu = nullptr, *mxy = nullptr, *mxz = nullptr, *myz = nullptr;
+    R *eu[3] = {nullptr, nullptr, nullptr}, *ru[3] = {nullptr, nullptr, nullptr}, *tu[3] = {nullptr, nullptr, nullptr};
+    R *ep = nullptr, *rp = nullptr;
+};
+
+template <class R>
+struct MG {
+    int nlev = 0;      // pressure levels
+    int nvlev = 0;     // velocity levels
+    Level<R> L[kMaxLev];
+    R *dense = nullptr;
+    int *dmap = nullptr;
+    int ndense = 0;
+    bool use_dense = false;
+};
+
+bool can_coarsen(const Box &b) {
+    bool ok = b.nx % 2 == 0 && b.ny % 2 == 0 && b.nx >= 4 && b.ny >= 4;
+    if (b.dim == 3) ok = ok && b.nz % 2 == 0 && b.nz >= 4;
+    long long cells = (long long)b.nx * b.ny * b.nz;
+    return ok && cells > 64;
+}
+
+Box coarse_of(const Box &f) {
+    return make_box(f.dim, f.nx / 2, f.ny / 2, f.dim == 3 ? f.nz / 2 : 1, 2 * f.hx, 2 * f.hy, 2 * f.hz);
+}
+
+}  // namespace
+
+struct stokes_ctx {
+    stokes_grid grid;
+    stokes_options opt;
+    double dt = 0, theta = 1, sigma = 1;
+    hipStream_t stream = nullptr;
+    char *ws = nullptr;
+    size_t ws_bytes = 0, ws_need = 0;
+    int dim = 3, nf = 4;
+    Box fine;
+    // fine-level FP64 operator
+    double *mass[3] = {nullptr, nullptr, nullptr}, *beta[3] = {nullptr, nullptr, nullptr};
+    double *mu = nullptr, *mxy = nullptr, *mxz = nullptr, *myz = nullptr;
+    MG<double> mgd;
+    MG<float> mgf;
+    // Krylov storage: V (m+1 vectors), Z (m vectors), each nf fields of fine.stride
+    int m = 30;
+    long long vlen = 0;
+    double *V = nullptr, *Z = nullptr, *xk = nullptr, *bk = nullptr, *q = nullptr;
+    double *partial = nullptr, *dsc = nullptr;
+    int *dflag = nullptr;
+    int vcycles = 0;
+    std::string err;
+
+    double *vec(double *base, int j) const { return base + (size_t)j * vlen; }
+    double *fld(double *vbase, int f) const { return vbase + (size_t)f * fine.stride + fine.guard; }
+};
+
+namespace {
+
+// ---------------------------------------------------------------- layout
+template <class R>
+void carve_mg(Carver &cv, stokes_ctx &c, MG<R> &mg, bool alias_level0) {
+    Box b = c.fine;
+    int nl = 0;
+    for (;;) {
+        Level<R> &L = mg.L[nl];
+        L.b = b;
+        const int d = b.dim;
+        if (nl == 0 && alias_level0) {
+            // FP64 multigrid: level 0 uses the fine operator's own arrays
+            for (int a = 0; a < d; ++a) {
+                L.mass[a] = reinterpret_cast<R *>(c.mass[a]);
+                L.beta[a] = reinterpret_cast<R *>(c.beta[a]);
+            }
+            L.mu = reinterpret_cast<R *>(c.mu);
+            L.mxy = reinterpret_cast<R *>(c.mxy);
+            L.mxz = reinterpret_cast<R *>(c.mxz);
+            L.myz = reinterpret_cast<R *>(c.myz);
+        } else {
+            for (int a = 0; a < d; ++a) L.mass[a] = cv.fields<R>(b, 1);
+            for (int a = 0; a < d; ++a) L.beta[a] = cv.fields<R>(b, 1);
+            L.mu = cv.fields<R>(b, 1);
+            L.mxy = cv.fields<R>(b, 1);
+            if (d == 3) {
+                L.mxz = cv.fields<R>(b, 1);
+                L.myz = cv.fields<R>(b, 1);
+            }
+        }
+        R *e = cv.fields<R>(b, d), *r = cv.fields<R>(b, d), *t = cv.fields<R>(b, d);
+        for (int a = 0; a < d; ++a) {
+            L.eu[a] = e ? e + (size_t)a * b.stride : nullptr;
+            L.ru[a] = r ? r + (size_t)a * b.stride : nullptr;
+            L.tu[a] = t ? t + (size_t)a * b.stride : nullptr;
+        }
+        L.ep = cv.fields<R>(b, 1);
+        L.rp = cv.fields<R>(b, 1);
+        ++nl;
+        if (nl >= kMaxLev || !can_coarsen(b)) break;
+        b = coarse_of(b);
+    }
+    mg.nlev = nl;
+    int vl = c.opt.vel_levels;
+    mg.nvlev = (vl <= 0 || vl > nl) ? nl : vl;
+    const Box &cb = mg.L[nl - 1].b;
+    mg.ndense = cb.nx * cb.ny * cb.nz;
+    mg.use_dense = mg.ndense <= kDenseMax;
+    if (mg.use_dense) {
+        mg.dense = cv.take<R>((size_t)mg.ndense * mg.ndense);
+        mg.dmap = cv.take<int>(mg.ndense);
+    }
+}
+
+void carve_all(Carver &cv, stokes_ctx &c) {
+    const Box &b = c.fine;
+    const int d = c.dim;
+    for (int a = 0; a < d; ++a) c.mass[a] = cv.fields<double>(b, 1);
+    for (int a = 0; a < d; ++a) c.beta[a] = cv.fields<double>(b, 1);
+    c.mu = cv.fields<double>(b, 1);
+    c.mxy = cv.fields<double>(b, 1);
+    if (d == 3) {
+        c.mxz = cv.fields<double>(b, 1);
+        c.myz = cv.fields<double>(b, 1);
+    }
+    if (c.opt.precision == 1) carve_mg<float>(cv, c, c.mgf, false);
+    else carve_mg<double>(cv, c, c.mgd, true);
+    c.vlen = (long long)b.stride * c.nf;
+    c.V = cv.take<double>((size_t)c.vlen * (c.m + 1));
+    c.Z = cv.take<double>((size_t)c.vlen * c.m);
+    c.xk = cv.take<double>((size_t)c.vlen);
+    c.bk = cv.take<double>((size_t)c.vlen);
+    c.q = cv.fields<double>(b, 1);
+    c.partial = cv.take<double>((size_t)kRedBlocks * kGroup);
+    c.dsc = cv.take<double>(4 * (size_t)(c.m + 8));
+    c.dflag = cv.take<int>(64);
+    c.ws_need = cv.off + 256;
+}
+
+// ---------------------------------------------------------------- launch helpers
+inline unsigned nblocks_box(const Box &b) { return (unsigned)((b.nb + kBlock - 1) / kBlock); }
+inline unsigned nblocks_stream(long long n) {
+    long long g = (n + kBlock - 1) / kBlock;
+    return (unsigned)std::max<long long>(1, std::min<long long>(g, kRedBlocks));
+}
+
+template <class R>
+VelCoef<R> vcoef(const Level<R> &L, double theta) {
+    VelCoef<R> c;
+    for (int a = 0; a < 3; ++a) c.mass[a] = L.mass[a];
+    c.mu = L.mu;
+    c.mxy = L.mxy;
+    c.mxz = L.mxz;
+    c.myz = L.myz;
+    c.theta = (R)theta;
+    return c;
+}
+
+VelCoef<double> fine_coef(const stokes_ctx &c) {
+    VelCoef<double> v;
+    for (int a = 0; a < 3; ++a) v.mass[a] = c.mass[a];
+    v.mu = c.mu;
+    v.mxy = c.mxy;
+    v.mxz = c.mxz;
+    v.myz = c.myz;
+    v.theta = c.theta;
+    return v;
+}
+
+template <class R>
+void fill(stokes_ctx &c, R *p, long long n, R v) {
+    k_fill<R><<<nblocks_stream(n), kBlock, 0, c.stream>>>(n, p, v);
+}
+
+// ---------------------------------------------------------------- velocity multigrid
+template <int DIM, class R>
+void vel_smooth(stokes_ctx &c, Level<R> &L, R *const e[3], R *const r[3], int sweeps, bool zero_guess) {
+    VelCoef<R> co = vcoef(L, c.theta);
+    for (int s = 0; s < sweeps; ++s) {
+        for (int comp = 0; comp < DIM; ++comp) {
+            for (int colour = 0; colour < 2; ++colour) {
+                int valid = VALID_U | VALID_V | VALID_W;
+                if (zero_guess && s == 0) {
+                    valid = 0;
+                    for (int a = 0; a < comp; ++a) valid |= 1 << a;
+                    if (colour == 1) valid |= 1 << comp;
+                }
+                k_vel_gs<DIM, R><<<nblocks_box(L.b), kBlock, 0, c.stream>>>(
+                    L.b, co, comp, colour, valid, e[0], e[1], e[2], r[0], r[1], r[2]);
+            }
+        }
+    }
+}
+
+template <int DIM, class R>
+void vel_vcycle(stokes_ctx &c, MG<R> &mg, int l, R *const e[3], R *const r[3], bool zero_guess) {
+    Level<R> &L = mg.L[l];
+    const int nu1 = c.opt.nu1, nu2 = c.opt.nu2;
+    if (l == mg.nvlev - 1) {
+        int sw = l == 0 ? std::max(1, nu1 + nu2) : std::max(1, c.opt.coarse_sweeps);
+        vel_smooth<DIM, R>(c, L, e, r, sw, zero_guess);
+        return;
+    }
+    if (zero_guess && nu1 == 0)
+        for (int a = 0; a < DIM; ++a) fill<R>(c, e[a] - L.b.guard, L.b.stride, R(0));
+    vel_smooth<DIM, R>(c, L, e, r, nu1, zero_guess);
+    Level<R> &C = mg.L[l + 1];
+    k_vel_residual<DIM, R><<<nblocks_box(L.b), kBlock, 0, c.stream>>>(
+        L.b, vcoef(L, c.theta), e[0], e[1], e[2], r[0], r[1], r[2], L.tu[0], L.tu[1], L.tu[2]);
+    for (int a = 0; a < DIM; ++a)
+        k_face_restrict<DIM, R><<<nblocks_box(C.b), kBlock, 0, c.stream>>>(L.b, C.b, a, L.tu[a], C.ru[a]);
+    vel_vcycle<DIM, R>(c, mg, l + 1, C.eu, C.ru, true);
+    for (int a = 0; a < DIM; ++a)
+        k_face_prolong_add<DIM, R><<<nblocks_box(L.b), kBlock, 0, c.stream>>>(L.b, C.b, a, C.eu[a], e[a]);
+    vel_smooth<DIM, R>(c, L, e, r, nu2, false);
+}
+
+// ---------------------------------------------------------------- pressure multigrid
+template <int DIM, class R>
+void p_smooth(stokes_ctx &c, Level<R> &L, R *e, const R *r, int sweeps, bool zero_guess) {
+    for (int s = 0; s < sweeps; ++s)
+        for (int colour = 0; colour < 2; ++colour)
+            k_p_gs<DIM, R><<<nblocks_box(L.b), kBlock, 0, c.stream>>>(
+                L.b, colour, (zero_guess && s == 0 && colour == 0) ? 1 : 0, e, r, L.beta[0], L.beta[1],
+                DIM == 3 ? L.beta[2] : L.beta[1]);
+}
+
+template <int DIM, class R>
+void p_vcycle(stokes_ctx &c, MG<R> &mg, int l, R *e, R *r, bool zero_guess) {
+    Level<R> &L = mg.L[l];
+    if (l == mg.nlev - 1) {
+        if (mg.use_dense) {
+            int nt = std::min(1024, ((mg.ndense + 63) / 64) * 64);
+            k_dense_solve<R><<<1, nt, mg.ndense * sizeof(R), c.stream>>>(mg.ndense, mg.dense, mg.dmap, r, e);
+        } else {
+            p_smooth<DIM, R>(c, L, e, r, std::max(1, c.opt.coarse_sweeps), zero_guess);
+        }
+        return;
+    }
+    if (zero_guess && c.opt.nu1 == 0) fill<R>(c, e - L.b.guard, L.b.stride, R(0));
+    p_smooth<DIM, R>(c, L, e, r, c.opt.nu1, zero_guess);
+    Level<R> &C = mg.L[l + 1];
+    const R *bz = DIM == 3 ? L.beta[2] : L.beta[1];
+    k_p_residual_restrict<DIM, R><<<nblocks_box(C.b), kBlock, 0, c.stream>>>(L.b, C.b, e, r, L.beta[0], L.beta[1], bz, C.rp);
+    p_vcycle<DIM, R>(c, mg, l + 1, C.ep, C.rp, true);
+    k_p_prolong_add<DIM, R><<<nblocks_box(L.b), kBlock, 0, c.stream>>>(L.b, C.b, C.ep, e);
+    p_smooth<DIM, R>(c, L, e, r, c.opt.nu2, false);
+}
+
+// ---------------------------------------------------------------- preconditioner
+// z = P^{-1} v:
+//   1. u~ ~= A^{-1} v_u                      (velocity V-cycles)
+//   2. q = v_p + D u~,  s = q / dt
+//   3. phi ~= L_rho^{-1} s, L_rho = D beta G (pressure V-cycles on -L_rho)
+//   4. z_u = u~ - dt beta G phi
+//   5. z_p = phi - 2 theta mu q              (local-viscosity pressure update)
+// Its derivation: with constant coefficients A (dt beta G phi) = G p exactly
+// when p = phi - 2 theta mu dt beta Lap(phi), and beta Lap(phi) ~= s.
+template <int DIM, class R>
+void precond(stokes_ctx &c, MG<R> &mg, double *v, double *z) {
+    Level<R> &L0 = mg.L[0];
+    double *vu[3] = {c.fld(v, 0), c.fld(v, 1), DIM == 3 ? c.fld(v, 2) : nullptr};
+    double *zu[3] = {c.fld(z, 0), c.fld(z, 1), DIM == 3 ? c.fld(z, 2) : nullptr};
+    double *vp = c.fld(v, DIM), *zp = c.fld(z, DIM);
+    R *eu[3], *ru[3];
+    if (sizeof(R) == sizeof(double)) {
+        for (int a = 0; a < 3; ++a) {
+            eu[a] = reinterpret_cast<R *>(zu[a]);
+            ru[a] = reinterpret_cast<R *>(vu[a]);
+        }
+    } else {
+        long long n = (long long)DIM * c.fine.stride;
+        k_cast<double, R><<<nblocks_stream(n), kBlock, 0, c.stream>>>(n, v, L0.ru[0] - L0.b.guard);
+        for (int a = 0; a < 3; ++a) {
+            eu[a] = L0.eu[a];
+            ru[a] = L0.ru[a];
+        }
+    }
+    if (c.opt.vel_cycles <= 0) {
+        for (int a = 0; a < DIM; ++a) fill<R>(c, eu[a] - L0.b.guard, L0.b.stride, R(0));
+    }
+    for (int cyc = 0; cyc < c.opt.vel_cycles; ++cyc) {
+        vel_vcycle<DIM, R>(c, mg, 0, eu, ru, cyc == 0);
+        c.vcycles++;
+    }
+    k_precond_div<DIM, R><<<nblocks_box(c.fine), kBlock, 0, c.stream>>>(c.fine, eu[0], eu[1], eu[2], vp, c.dt, c.q, L0.rp);
+    for (int cyc = 0; cyc < c.opt.p_cycles; ++cyc) {
+        p_vcycle<DIM, R>(c, mg, 0, L0.ep, L0.rp, cyc == 0);
+        c.vcycles++;
+    }
+    k_precond_update<DIM, R><<<nblocks_box(c.fine), kBlock, 0, c.stream>>>(
+        c.fine, eu[0], eu[1], eu[2], L0.ep, c.beta[0], c.beta[1], DIM == 3 ? c.beta[2] : c.beta[1], c.mu, c.q,
+        c.dt, c.theta, zu[0], zu[1], DIM == 3 ? zu[2] : zu[1], zp);
+}
+
+// ---------------------------------------------------------------- BLAS helpers
+// out[0..nv) = <V_m, w>_W for m < nv (W: pressure block weighted by w2)
+void multidot(stokes_ctx &c, const double *V, int nv, const double *w, double w2, double *out) {
+    const long long n = c.vlen, pstart = (long long)c.dim * c.fine.stride;
+    const unsigned g = nblocks_stream(n);
+    for (int m0 = 0; m0 < nv; m0 += kGroup) {
+        int cnt = std::min(kGroup, nv - m0);
+        k_multidot<kGroup><<<g, kBlock, 0, c.stream>>>(n, pstart, w2, V + (size_t)m0 * c.vlen, c.vlen, cnt, w, c.partial);
+        k_reduce_partials<<<cnt, kBlock, 0, c.stream>>>((int)g, c.partial, out + m0, 0);
+    }
+}
+
+// w += sign * sum_m coef[m] V_m   (coef on the device)
+void maxpy(stokes_ctx &c, double sign, const double *V, int nv, const double *coef, double *w) {
+    const long long n = c.vlen;
+    const unsigned g = nblocks_stream(n);
+    for (int m0 = 0; m0 < nv; m0 += kGroup) {
+        int cnt = std::min(kGroup, nv - m0);
+        k_maxpy<kGroup><<<g, kBlock, 0, c.stream>>>(n, sign, V + (size_t)m0 * c.vlen, c.vlen, cnt, coef + m0, w);
+    }
+}
+
+void sync_read(stokes_ctx &c, const double *dsrc, double *hdst, int n) {
+    HIPCHK(hipMemcpyAsync(hdst, dsrc, sizeof(double) * n, hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(hipStreamSynchronize(c.stream));
+}
+
+template <int DIM>
+void apply_fine(stokes_ctx &c, double *x, double *f, double *y) {
+    k_apply<DIM><<<nblocks_box(c.fine), kBlock, 0, c.stream>>>(
+        c.fine, fine_coef(c), c.fld(x, 0), c.fld(x, 1), DIM == 3 ? c.fld(x, 2) : nullptr, c.fld(x, DIM),
+        f ? c.fld(f, 0) : nullptr, f ? c.fld(f, 1) : nullptr, (f && DIM == 3) ? c.fld(f, 2) : nullptr,
+        f ? c.fld(f, DIM) : nullptr, c.fld(y, 0), c.fld(y, 1), DIM == 3 ? c.fld(y, 2) : nullptr, c.fld(y, DIM));
+}
+
+void remove_p_mean(stokes_ctx &c, double *x) {
+    double *p = c.fld(x, c.dim) - c.fine.guard;
+    const long long n = c.fine.stride;
+    const unsigned g = nblocks_stream(n);
+    k_partial_sum<<<g, kBlock, 0, c.stream>>>(n, p, 0, c.partial);
+    k_reduce_partials<<<1, kBlock, 0, c.stream>>>((int)g, c.partial, c.dsc, 0);
+    k_sub_mean<<<nblocks_box(c.fine), kBlock, 0, c.stream>>>(c.fine, c.dsc, c.fld(x, c.dim));
+}
+
+// ---------------------------------------------------------------- FGMRES
+template <int DIM, class R>
+stokes_status fgmres(stokes_ctx &c, MG<R> &mg, double tol, stokes_stats &st) {
+    const int m = c.m;
+    const double w2 = c.sigma * c.sigma;
+    std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1), y(m), hbuf(2 * m + 4);
+    auto HH = [&](int i, int j) -> double & { return H[(size_t)i * m + j]; };
+    double *dh = c.dsc, *dh2 = c.dsc + (m + 2), *dy = c.dsc + 2 * (m + 2);
+
+    multidot(c, c.bk, 1, c.bk, w2, dh);
+    double bn2;
+    sync_read(c, dh, &bn2, 1);
+    if (!std::isfinite(bn2)) { c.err = "non-finite right-hand side"; return STOKES_ENAN; }
+    const double bnorm = std::sqrt(bn2);
+    st.iters = 0;
+    st.restarts = 0;
+    if (bnorm == 0.0) {
+        fill<double>(c, c.xk, c.vlen, 0.0);
+        st.rel_res_est = st.rel_res_true = 0.0;
+        return STOKES_OK;
+    }
+    double prev = INFINITY;
+    stokes_status status = STOKES_NOT_CONVERGED;
+    for (;;) {
+        double *v0 = c.vec(c.V, 0);
+        apply_fine<DIM>(c, c.xk, c.bk, v0);
+        multidot(c, v0, 1, v0, w2, dh);
+        double be2;
+        sync_read(c, dh, &be2, 1);
+        if (!std::isfinite(be2)) { c.err = "non-finite residual"; return STOKES_ENAN; }
+        const double beta = std::sqrt(be2);
+        st.rel_res_true = beta / bnorm;
+        if (beta <= tol * bnorm) { status = STOKES_OK; break; }
+        if (st.iters >= c.opt.max_iters) { status = STOKES_NOT_CONVERGED; break; }
+        if (beta >= 0.999 * prev) { status = STOKES_NOT_CONVERGED; break; }   // stagnation across a restart
+        prev = beta;
+        if (st.iters > 0) st.restarts++;
+        k_scale<<<nblocks_stream(c.vlen), kBlock, 0, c.stream>>>(c.vlen, 1.0 / beta, v0);
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int nj = 0;
+        bool breakdown = false;
+        for (int j = 0; j < m && st.iters < c.opt.max_iters; ++j) {
+            double *vj = c.vec(c.V, j), *zj = c.vec(c.Z, j), *w = c.vec(c.V, j + 1);
+            precond<DIM, R>(c, mg, vj, zj);
+            apply_fine<DIM>(c, zj, nullptr, w);
+            // classical Gram-Schmidt, twice
+            multidot(c, c.V, j + 1, w, w2, dh);
+            maxpy(c, -1.0, c.V, j + 1, dh, w);
+            multidot(c, c.V, j + 1, w, w2, dh2);
+            maxpy(c, -1.0, c.V, j + 1, dh2, w);
+            multidot(c, w, 1, w, w2, dh2 + (j + 1));
+            HIPCHK(hipMemcpyAsync(hbuf.data(), dh, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, c.stream));
+            HIPCHK(hipMemcpyAsync(hbuf.data() + (m + 2), dh2, sizeof(double) * (j + 2), hipMemcpyDeviceToHost, c.stream));
+            HIPCHK(hipStreamSynchronize(c.stream));
+            for (int i = 0; i <= j; ++i) HH(i, j) = hbuf[i] + hbuf[m + 2 + i];
+            double hn2 = hbuf[m + 2 + j + 1];
+            if (!std::isfinite(hn2)) { c.err = "non-finite Arnoldi vector"; return STOKES_ENAN; }
+            double hn = std::sqrt(std::max(hn2, 0.0));
+            HH(j + 1, j) = hn;
+            if (hn > 0.0) k_scale<<<nblocks_stream(c.vlen), kBlock, 0, c.stream>>>(c.vlen, 1.0 / hn, w);
+            for (int i = 0; i < j; ++i) {
+                double t = cs[i] * HH(i, j) + sn[i] * HH(i + 1, j);
+                HH(i + 1, j) = -sn[i] * HH(i, j) + cs[i] * HH(i + 1, j);
+                HH(i, j) = t;
+            }
+            double a = HH(j, j), bb = HH(j + 1, j);
+            double den = std::hypot(a, bb);
+            cs[j] = den > 0.0 ? a / den : 1.0;
+            sn[j] = den > 0.0 ? bb / den : 0.0;
+            HH(j, j) = den;
+            HH(j + 1, j) = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            st.iters++;
+            nj = j + 1;
+            st.rel_res_est = std::fabs(g[j + 1]) / bnorm;
+            if (std::fabs(g[j + 1]) <= tol * bnorm) break;
+            if (hn == 0.0) { breakdown = true; break; }
+        }
+        for (int i = nj - 1; i >= 0; --i) {
+            double s = g[i];
+            for (int k = i + 1; k < nj; ++k) s -= HH(i, k) * y[k];
+            y[i] = HH(i, i) != 0.0 ? s / HH(i, i) : 0.0;
+        }
+        HIPCHK(hipMemcpyAsync(dy, y.data(), sizeof(double) * nj, hipMemcpyHostToDevice, c.stream));
+        maxpy(c, 1.0, c.Z, nj, dy, c.xk);
+        if (breakdown) {
+            apply_fine<DIM>(c, c.xk, c.bk, v0);
+            multidot(c, v0, 1, v0, w2, dh);
+            sync_read(c, dh, &be2, 1);
+            st.rel_res_true = std::sqrt(be2) / bnorm;
+            status = st.rel_res_true <= tol ? STOKES_OK : STOKES_BREAKDOWN;
+            break;
+        }
+    }
+    return status;
+}
+
+// ---------------------------------------------------------------- setup helpers
+// Dense pseudo-inverse of the coarsest Neumann operator -D beta G: with
+// B = L + (s/n) 1 1^T (s = mean diagonal) nonsingular, L^+ = B^{-1} - 1 1^T/(s n).
+template <class R>
+void build_dense(stokes_ctx &c, MG<R> &mg) {
+    Level<R> &L = mg.L[mg.nlev - 1];
+    const Box &b = L.b;
+    const int n = mg.ndense, d = b.dim;
+    std::vector<R> bt[3];
+    for (int a = 0; a < d; ++a) {
+        bt[a].resize(b.nb);
+        HIPCHK(hipMemcpyAsync(bt[a].data(), L.beta[a], sizeof(R) * b.nb, hipMemcpyDeviceToHost, c.stream));
+    }
+    HIPCHK(hipStreamSynchronize(c.stream));
+    std::vector<int> map(n);
+    std::vector<double> A((size_t)n * n, 0.0);
+    auto cid = [&](int i, int j, int k) { return i + b.nx * (j + b.ny * k); };
+    const double ih2[3] = {b.ihx * b.ihx, b.ihy * b.ihy, b.ihz * b.ihz};
+    for (int k = 0; k < b.nz; ++k)
+        for (int j = 0; j < b.ny; ++j)
+            for (int i = 0; i < b.nx; ++i) {
+                int r = cid(i, j, k);
+                map[r] = box_index(b, i, j, k);
+                int pos[3] = {i, j, k}, ext[3] = {b.nx, b.ny, b.nz};
+                for (int a = 0; a < d; ++a) {
+                    for (int side = 0; side < 2; ++side) {
+                        int nb[3] = {i, j, k};
+                        nb[a] += side ? 1 : -1;
+                        if (nb[a] < 0 || nb[a] >= ext[a]) continue;
+                        int f[3] = {i, j, k};
+                        if (side) f[a] += 1;
+                        double w = (double)bt[a][box_index(b, f[0], f[1], f[2])] * ih2[a];
+                        A[(size_t)r * n + r] += w;
+                        A[(size_t)r * n + cid(nb[0], nb[1], nb[2])] -= w;
+                    }
+                }
+                (void)pos;
+            }
+    double sdiag = 0.0;
+    for (int r = 0; r < n; ++r) sdiag += A[(size_t)r * n + r];
+    sdiag /= n;
+    for (auto &x : A) x += sdiag / n;
+    // Gauss-Jordan inverse with partial pivoting
+    std::vector<double> Inv((size_t)n * n, 0.0);
+    for (int r = 0; r < n; ++r) Inv[(size_t)r * n + r] = 1.0;
+    for (int col = 0; col < n; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < n; ++r)
+            if (std::fabs(A[(size_t)r * n + col]) > std::fabs(A[(size_t)piv * n + col])) piv = r;
+        if (piv != col)
+            for (int k = 0; k < n; ++k) {
+                std::swap(A[(size_t)piv * n + k], A[(size_t)col * n + k]);
+                std::swap(Inv[(size_t)piv * n + k], Inv[(size_t)col * n + k]);
+            }
+        double p = A[(size_t)col * n + col];
+        double ip = 1.0 / p;
+        for (int k = 0; k < n; ++k) {
+            A[(size_t)col * n + k] *= ip;
+            Inv[(size_t)col * n + k] *= ip;
+        }
+        for (int r = 0; r < n; ++r) {
+            if (r == col) continue;
+            double f = A[(size_t)r * n + col];
+            if (f == 0.0) continue;
+            for (int k = 0; k < n; ++k) {
+                A[(size_t)r * n + k] -= f * A[(size_t)col * n + k];
+                Inv[(size_t)r * n + k] -= f * Inv[(size_t)col * n + k];
+            }
+        }
+    }
+    std::vector<R> M((size_t)n * n);
+    const double corr = 1.0 / (sdiag * n);
+    for (size_t t = 0; t < M.size(); ++t) M[t] = (R)(Inv[t] - corr);
+    HIPCHK(hipMemcpyAsync(mg.dense, M.data(), sizeof(R) * M.size(), hipMemcpyHostToDevice, c.stream));
+    HIPCHK(hipMemcpyAsync(mg.dmap, map.data(), sizeof(int) * n, hipMemcpyHostToDevice, c.stream));
+    HIPCHK(hipStreamSynchronize(c.stream));
+}
+
+template <int DIM, class R>
+void build_hierarchy(stokes_ctx &c, MG<R> &mg, bool cast_level0) {
+    Level<R> &L0 = mg.L[0];
+    if (cast_level0) {
+        const long long n = c.fine.stride;
+        auto cast = [&](const double *src, R *dst) {
+            k_cast<double, R><<<nblocks_stream(n), kBlock, 0, c.stream>>>(n, src - c.fine.guard, dst - L0.b.guard);
+        };
+        for (int a = 0; a < DIM; ++a) {
+            cast(c.mass[a], L0.mass[a]);
+            cast(c.beta[a], L0.beta[a]);
+        }
+        cast(c.mu, L0.mu);
+        cast(c.mxy, L0.mxy);
+        if (DIM == 3) {
+            cast(c.mxz, L0.mxz);
+            cast(c.myz, L0.myz);
+        }
+    }
+    for (int l = 1; l < mg.nlev; ++l) {
+        Level<R> &F = mg.L[l - 1], &C = mg.L[l];
+        unsigned gb = nblocks_box(C.b);
+        k_coarsen_mu<DIM, R><<<gb, kBlock, 0, c.stream>>>(F.b, C.b, F.mu, C.mu);
+        k_edge_mu<DIM, R><<<gb, kBlock, 0, c.stream>>>(C.b, C.mu, C.mxy, C.mxz, C.myz);
+        for (int a = 0; a < DIM; ++a) {
+            k_face_restrict<DIM, R><<<gb, kBlock, 0, c.stream>>>(F.b, C.b, a, F.mass[a], C.mass[a]);
+            k_coarsen_beta<DIM, R><<<gb, kBlock, 0, c.stream>>>(F.b, C.b, a, F.beta[a], C.beta[a]);
+        }
+    }
+    if (mg.use_dense) build_dense<R>(c, mg);
+}
+
+__global__ void k_minmax(Box b, const double *__restrict__ m0, const double *__restrict__ m1,
+                         const double *__restrict__ m2, const double *__restrict__ mu, double *__restrict__ out) {
+    // out: [min mass, max mass, max mu] per block -> out[3*block + .]
+    __shared__ double s0[kBlock], s1[kBlock], s2[kBlock];
+    double mn = INFINITY, mx = 0.0, mm = 0.0;
+    for (int idx = blockIdx.x * kBlock + threadIdx.x; idx < b.nb; idx += gridDim.x * kBlock) {
+        int i, j, k;
+        decompose(b, idx, i, j, k);
+        if (is_ux(b, i, j, k)) { mn = fmin(mn, m0[idx]); mx = fmax(mx, m0[idx]); }
+        if (is_vy(b, i, j, k)) { mn = fmin(mn, m1[idx]); mx = fmax(mx, m1[idx]); }
+        if (b.dim == 3 && is_wz(b, i, j, k)) { mn = fmin(mn, m2[idx]); mx = fmax(mx, m2[idx]); }
+        if (is_cell(b, i, j, k)) mm = fmax(mm, mu[idx]);
+    }
+    s0[threadIdx.x] = mn; s1[threadIdx.x] = mx; s2[threadIdx.x] = mm;
+    __syncthreads();
+    for (int o = kBlock / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            s0[threadIdx.x] = fmin(s0[threadIdx.x], s0[threadIdx.x + o]);
+            s1[threadIdx.x] = fmax(s1[threadIdx.x], s1[threadIdx.x + o]);
+            s2[threadIdx.x] = fmax(s2[threadIdx.x], s2[threadIdx.x + o]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[3 * blockIdx.x] = s0[0];
+        out[3 * blockIdx.x + 1] = s1[0];
+        out[3 * blockIdx.x + 2] = s2[0];
+    }
+}
+
+stokes_options defaults() {
+    stokes_options o;
+    o.precision = 0;
+    o.visc_scale = 1.0;
+    o.cont_scale = 0.0;
+    o.restart = 30;
+    o.max_iters = 200;
+    o.nu1 = 2;
+    o.nu2 = 2;
+    o.vel_cycles = 1;
+    o.p_cycles = 1;
+    o.coarse_sweeps = 40;
+    o.vel_levels = 0;
+    return o;
+}
+
+const char *check_grid_opts(const stokes_grid *g, const stokes_options &o) {
+    if (!g) return "grid is NULL";
+    if (g->dim != 2 && g->dim != 3) return "grid.dim must be 2 or 3";
+    for (int a = 0; a < g->dim; ++a) {
+        if (g->n[a] < 2) return "every axis needs at least 2 cells";
+        if (!(g->h[a] > 0.0) || !std::isfinite(g->h[a])) return "grid spacings must be positive";
+    }
+    long long pts = (long long)(g->n[0] + 1) * (g->n[1] + 1) * (g->dim == 3 ? g->n[2] + 1 : 1);
+    if (pts * (g->dim + 1) > (1LL << 30)) return "grid too large for 32-bit vector indexing";
+    if (o.precision != 0 && o.precision != 1) return "precision must be 0 (FP64) or 1 (FP32 multigrid)";
+    if (!(o.visc_scale >= 0.0) || !std::isfinite(o.visc_scale)) return "visc_scale must be >= 0";
+    if (!(o.cont_scale >= 0.0) || !std::isfinite(o.cont_scale)) return "cont_scale must be >= 0";
+    if (o.restart < 1 || o.restart > 200) return "restart must be in [1, 200]";
+    if (o.max_iters < 1) return "max_iters must be >= 1";
+    if (o.nu1 < 0 || o.nu2 < 0 || o.nu1 + o.nu2 < 1) return "nu1, nu2 >= 0 with nu1 + nu2 >= 1";
+    if (o.vel_cycles < 0 || o.p_cycles < 1) return "vel_cycles >= 0 and p_cycles >= 1";
+    if (o.coarse_sweeps < 1) return "coarse_sweeps must be >= 1";
+    if (o.vel_levels < 0) return "vel_levels must be >= 0";
+    return nullptr;
+}
+
+void init_ctx_shape(stokes_ctx &c, const stokes_grid *g, const stokes_options &o) {
+    c.grid = *g;
+    c.opt = o;
+    c.dim = g->dim;
+    c.nf = g->dim + 1;
+    c.m = o.restart;
+    c.theta = o.visc_scale;
+    c.fine = make_box(g->dim, g->n[0], g->n[1], g->dim == 3 ? g->n[2] : 1, g->h[0], g->h[1],
+                      g->dim == 3 ? g->h[2] : g->h[0]);
+}
+
+template <int DIM>
+stokes_status setup_impl(stokes_ctx &c, const double *const rho[3], const double *mu) {
+    const Box &b = c.fine;
+    const unsigned gb = nblocks_box(b);
+    HIPCHK(hipMemsetAsync(c.ws, 0, c.ws_need, c.stream));
+    for (int a = 0; a < DIM; ++a) {
+        k_pack<<<gb, kBlock, 0, c.stream>>>(b, a, 2, 0, 1.0 / c.dt, rho[a], c.mass[a]);
+        k_pack<<<gb, kBlock, 0, c.stream>>>(b, a, 1, 0, 1.0, rho[a], c.beta[a]);
+    }
+    k_pack<<<gb, kBlock, 0, c.stream>>>(b, 3, 0, 0, 1.0, mu, c.mu);
+    k_check_coef<<<gb, kBlock, 0, c.stream>>>(b, c.mass[0], c.mass[1], DIM == 3 ? c.mass[2] : c.mass[1], c.mu, c.dflag);
+    int flag = 0;
+    HIPCHK(hipMemcpyAsync(&flag, c.dflag, sizeof(int), hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(hipStreamSynchronize(c.stream));
+    if (flag) {
+        c.err = "rho must be > 0 on interior faces and mu >= 0 on cells (finite)";
+        return STOKES_EINVAL;
+    }
+    k_edge_mu<DIM, double><<<gb, kBlock, 0, c.stream>>>(b, c.mu, c.mxy, c.mxz, c.myz);
+    if (c.opt.precision == 1) build_hierarchy<DIM, float>(c, c.mgf, true);
+    else build_hierarchy<DIM, double>(c, c.mgd, false);
+    // continuity weight
+    if (c.opt.cont_scale > 0.0) {
+        c.sigma = c.opt.cont_scale;
+    } else {
+        const int nbk = 256;
+        k_minmax<<<nbk, kBlock, 0, c.stream>>>(b, c.mass[0], c.mass[1], DIM == 3 ? c.mass[2] : c.mass[1], c.mu, c.partial);
+        std::vector<double> h(3 * nbk);
+        HIPCHK(hipMemcpyAsync(h.data(), c.partial, sizeof(double) * h.size(), hipMemcpyDeviceToHost, c.stream));
+        HIPCHK(hipStreamSynchronize(c.stream));
+        double mn = INFINITY, mx = 0.0, mm = 0.0;
+        for (int t = 0; t < nbk; ++t) {
+            mn = std::min(mn, h[3 * t]);
+            mx = std::max(mx, h[3 * t + 1]);
+            mm = std::max(mm, h[3 * t + 2]);
+        }
+        double l = std::max(b.nx * b.hx, b.ny * b.hy);
+        if (DIM == 3) l = std::max(l, b.nz * b.hz);
+        const double k = M_PI / l;
+        const double aref = std::sqrt(mn * mx) + c.theta * mm * k * k;   // mass already holds rho/dt
+        c.sigma = aref / k;
+    }
+    HIPCHK(hipStreamSynchronize(c.stream));
+    HIPCHK(hipGetLastError());
+    return STOKES_OK;
+}
+
+template <int DIM>
+void pack_vector(stokes_ctx &c, const double *const u[3], const double *p, double *vb) {
+    const Box &b = c.fine;
+    const unsigned gb = nblocks_box(b);
+    for (int a = 0; a < DIM; ++a) k_pack<<<gb, kBlock, 0, c.stream>>>(b, a, 0, 0, 1.0, u[a], c.fld(vb, a));
+    k_pack<<<gb, kBlock, 0, c.stream>>>(b, 3, 0, 0, 1.0, p, c.fld(vb, DIM));
+}
+
+template <int DIM>
+void unpack_vector(stokes_ctx &c, double *vb, double *const u[3], double *p) {
+    const Box &b = c.fine;
+    const unsigned gb = nblocks_box(b);
+    for (int a = 0; a < DIM; ++a) k_unpack<<<gb, kBlock, 0, c.stream>>>(b, a, c.fld(vb, a), u[a]);
+    k_unpack<<<gb, kBlock, 0, c.stream>>>(b, 3, c.fld(vb, DIM), p);
+}
+
+template <int DIM>
+stokes_status solve_impl(stokes_ctx &c, const double *const rhs_u[3], const double *rhs_p, double tol,
+                         double *const x_u[3], double *x_p, stokes_stats &st) {
+    c.vcycles = 0;
+    pack_vector<DIM>(c, rhs_u, rhs_p, c.bk);
+    k_fill<int><<<1, kBlock, 0, c.stream>>>(1, c.dflag, 0);
+    k_check_finite<<<nblocks_stream(c.vlen), kBlock, 0, c.stream>>>(c.vlen, c.bk - c.fine.guard, c.dflag);
+    int flag = 0;
+    // mean of rhs_p
+    {
+        double *p = c.fld(c.bk, DIM) - c.fine.guard;
+        const unsigned g = nblocks_stream(c.fine.stride);
+        k_partial_sum<<<g, kBlock, 0, c.stream>>>(c.fine.stride, p, 0, c.partial);
+        k_reduce_partials<<<1, kBlock, 0, c.stream>>>((int)g, c.partial, c.dsc, 0);
+        double s;
+        HIPCHK(hipMemcpyAsync(&flag, c.dflag, sizeof(int), hipMemcpyDeviceToHost, c.stream));
+        sync_read(c, c.dsc, &s, 1);
+        if (flag) { c.err = "non-finite right-hand side"; return STOKES_ENAN; }
+        st.g_mean = s / ((double)c.fine.nx * c.fine.ny * c.fine.nz);
+        k_sub_mean<<<nblocks_box(c.fine), kBlock, 0, c.stream>>>(c.fine, c.dsc, c.fld(c.bk, DIM));
+    }
+    pack_vector<DIM>(c, x_u, x_p, c.xk);
+    k_fill<int><<<1, kBlock, 0, c.stream>>>(1, c.dflag, 0);
+    k_check_finite<<<nblocks_stream(c.vlen), kBlock, 0, c.stream>>>(c.vlen, c.xk - c.fine.guard, c.dflag);
+    HIPCHK(hipMemcpyAsync(&flag, c.dflag, sizeof(int), hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(hipStreamSynchronize(c.stream));
+    if (flag) { c.err = "non-finite initial guess"; return STOKES_ENAN; }
+    remove_p_mean(c, c.xk);
+    stokes_status s = c.opt.precision == 1 ? fgmres<DIM, float>(c, c.mgf, tol, st)
+                                           : fgmres<DIM, double>(c, c.mgd, tol, st);
+    if (s < 0) return s;
+    remove_p_mean(c, c.xk);
+    // final residual split into its blocks (plain 2-norm)
+    double *v0 = c.vec(c.V, 0);
+    apply_fine<DIM>(c, c.xk, c.bk, v0);
+    {
+        const long long nvel = (long long)DIM * c.fine.stride;
+        const unsigned g1 = nblocks_stream(nvel), g2 = nblocks_stream(c.fine.stride), g3 = nblocks_stream(c.vlen);
+        k_partial_sum<<<g1, kBlock, 0, c.stream>>>(nvel, v0 - c.fine.guard, 1, c.partial);
+        k_reduce_partials<<<1, kBlock, 0, c.stream>>>((int)g1, c.partial, c.dsc, 0);
+        k_partial_sum<<<g2, kBlock, 0, c.stream>>>(c.fine.stride, c.fld(v0, DIM) - c.fine.guard, 1, c.partial);
+        k_reduce_partials<<<1, kBlock, 0, c.stream>>>((int)g2, c.partial, c.dsc + 1, 0);
+        k_partial_sum<<<g3, kBlock, 0, c.stream>>>(c.vlen, c.bk - c.fine.guard, 1, c.partial);
+        k_reduce_partials<<<1, kBlock, 0, c.stream>>>((int)g3, c.partial, c.dsc + 2, 0);
+        double h3[3];
+        sync_read(c, c.dsc, h3, 3);
+        double bn = std::sqrt(h3[2]);
+        if (bn > 0) {
+            st.rel_res_mom = std::sqrt(h3[0]) / bn;
+            st.rel_res_cont = std::sqrt(h3[1]) / bn;
+            st.rel_res_plain = std::sqrt(h3[0] + h3[1]) / bn;
+        }
+    }
+    unpack_vector<DIM>(c, c.xk, x_u, x_p);
+    HIPCHK(hipStreamSynchronize(c.stream));
+    HIPCHK(hipGetLastError());
+    return s;
+}
+
+}  // namespace
+
+// ====================================================================== C-ABI
+extern "C" {
+
+void stokes_default_options(stokes_options *opts) {
+    if (opts) *opts = defaults();
+}
+
+size_t stokes_workspace_size(const stokes_grid *grid, const stokes_options *opts) {
+    stokes_options o = opts ? *opts : defaults();
+    if (check_grid_opts(grid, o)) return 0;
+    stokes_ctx c;
+    init_ctx_shape(c, grid, o);
+    Carver cv{nullptr};
+    carve_all(cv, c);
+    return c.ws_need;
+}
+
+stokes_status stokes_setup(const double *const rho_face[3], const double *mu_cell, double dt,
+                           const stokes_grid *grid, const stokes_options *opts, void *workspace,
+                           size_t ws_bytes, void *stream, stokes_ctx **out) {
+    g_setup_error.clear();
+    if (!out) { g_setup_error = "out is NULL"; return STOKES_EINVAL; }
+    *out = nullptr;
+    stokes_options o = opts ? *opts : defaults();
+    if (const char *msg = check_grid_opts(grid, o)) {
+        g_setup_error = msg;
+        return (grid && (grid->dim == 2 || grid->dim == 3)) && std::strstr(msg, "cells") ? STOKES_ESHAPE : STOKES_EINVAL;
+    }
+    if (!(dt > 0.0) || !std::isfinite(dt)) { g_setup_error = "dt must be > 0"; return STOKES_EINVAL; }
+    if (!rho_face || !rho_face[0] || !rho_face[1] || (grid->dim == 3 && !rho_face[2]) || !mu_cell) {
+        g_setup_error = "coefficient pointer is NULL";
+        return STOKES_EINVAL;
+    }
+    if (!workspace) { g_setup_error = "workspace is NULL"; return STOKES_EINVAL; }
+    stokes_ctx *c = new stokes_ctx();
+    init_ctx_shape(*c, grid, o);
+    c->dt = dt;
+    c->stream = reinterpret_cast<hipStream_t>(stream);
+    {
+        Carver dry{nullptr};
+        carve_all(dry, *c);
+    }
+    if (ws_bytes < c->ws_need) {
+        char buf[160];
+        std::snprintf(buf, sizeof buf, "workspace too small: %zu bytes given, %zu needed", ws_bytes, c->ws_need);
+        g_setup_error = buf;
+        delete c;
+        return STOKES_ENOMEM;
+    }
+    c->ws = reinterpret_cast<char *>(workspace);
+    c->ws_bytes = ws_bytes;
+    Carver cv{c->ws};
+    carve_all(cv, *c);
+    stokes_status s;
+    try {
+        s = c->dim == 3 ? setup_impl<3>(*c, rho_face, mu_cell) : setup_impl<2>(*c, rho_face, mu_cell);
+    } catch (const HipError &e) {
+        g_setup_error = std::string("HIP error in ") + e.what + ": " + hipGetErrorString(e.e);
+        delete c;
+        return STOKES_EHIP;
+    }
+    if (s != STOKES_OK) {
+        g_setup_error = c->err;
+        delete c;
+        return s;
+    }
+    *out = c;
+    return STOKES_OK;
+}
+
+stokes_status stokes_apply(stokes_ctx *ctx, const double *const x_u[3], const double *x_p,
+                           double *const y_u[3], double *y_p) {
+    if (!ctx) return STOKES_EINVAL;
+    ctx->err.clear();
+    const int d = ctx->dim;
+    if (!x_u || !y_u || !x_p || !y_p || !x_u[0] || !x_u[1] || !y_u[0] || !y_u[1] ||
+        (d == 3 && (!x_u[2] || !y_u[2]))) {
+        ctx->err = "NULL array pointer";
+        return STOKES_EINVAL;
+    }
+    try {
+        double *vin = ctx->vec(ctx->V, 0), *vout = ctx->vec(ctx->V, 1 % (ctx->m + 1));
+        if (d == 3) {
+            pack_vector<3>(*ctx, x_u, x_p, vin);
+            apply_fine<3>(*ctx, vin, nullptr, vout);
+            unpack_vector<3>(*ctx, vout, y_u, y_p);
+        } else {
+            pack_vector<2>(*ctx, x_u, x_p, vin);
+            apply_fine<2>(*ctx, vin, nullptr, vout);
+            unpack_vector<2>(*ctx, vout, y_u, y_p);
+        }
+        HIPCHK(hipGetLastError());
+    } catch (const HipError &e) {
+        ctx->err = std::string("HIP error in ") + e.what + ": " + hipGetErrorString(e.e);
+        return STOKES_EHIP;
+    }
+    return STOKES_OK;
+}
+
+stokes_status stokes_solve(stokes_ctx *ctx, const double *const rhs_u[3], const double *rhs_p, double tol,
+                           double *const x_u[3], double *x_p, stokes_stats *stats) {
+    if (!ctx) return STOKES_EINVAL;
+    ctx->err.clear();
+    const int d = ctx->dim;
+    if (!rhs_u || !x_u || !rhs_p || !x_p || !rhs_u[0] || !rhs_u[1] || !x_u[0] || !x_u[1] ||
+        (d == 3 && (!rhs_u[2] || !x_u[2]))) {
+        ctx->err = "NULL array pointer";
+        return STOKES_EINVAL;
+    }
+    if (!(tol > 0.0) || !std::isfinite(tol)) {
+        ctx->err = "tol must be > 0";
+        return STOKES_EINVAL;
+    }
+    stokes_stats st;
+    std::memset(&st, 0, sizeof st);
+    auto t0 = std::chrono::steady_clock::now();
+    stokes_status s;
+    try {
+        s = d == 3 ? solve_impl<3>(*ctx, rhs_u, rhs_p, tol, x_u, x_p, st)
+                   : solve_impl<2>(*ctx, rhs_u, rhs_p, tol, x_u, x_p, st);
+    } catch (const HipError &e) {
+        ctx->err = std::string("HIP error in ") + e.what + ": " + hipGetErrorString(e.e);
+        s = STOKES_EHIP;
+    }
+    auto t1 = std::chrono::steady_clock::now();
+    st.ms_total = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    st.vcycles = ctx->vcycles;
+    st.levels = ctx->opt.precision == 1 ? ctx->mgf.nlev : ctx->mgd.nlev;
+    st.sigma = ctx->sigma;
+    if (stats) *stats = st;
+    return s;
+}
+
+void stokes_destroy(stokes_ctx *ctx) { delete ctx; }
+
+const char *stokes_last_error(const stokes_ctx *ctx) {
+    if (!ctx) return g_setup_error.c_str();
+    return ctx->err.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,70 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it loads, exports every
+function include/stokes.h declares, sizes workspaces and rejects bad arguments
+before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "stokes.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(stokes_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def S():
+    import paper_1901_07892_amd as S
+    S.load_library()
+    return S
+
+
+def test_exports_every_declared_symbol(S):
+    names = _declared()
+    assert "stokes_solve" in names and "stokes_setup" in names and "stokes_apply" in names
+    lib = ctypes.CDLL(S.library_path())
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_workspace_size_host_logic(S):
+    g = S._binding.make_grid(3, (256, 256, 256), (1 / 256,) * 3)
+    o = S.stokes_default_options()
+    assert o.restart == 30 and o.nu1 == 2 and o.nu2 == 2
+    big = S.stokes_workspace_size(g, o)
+    # (m+1) + m + 2 Krylov vectors of 4 padded fields dominate
+    vec = 4 * 257 ** 3 * 8
+    assert (2 * o.restart + 3) * vec < big < (2 * o.restart + 20) * vec
+    o.restart = 10
+    assert S.stokes_workspace_size(g, o) < big
+    g2 = S._binding.make_grid(2, (64, 64, 1), (1 / 64,) * 3)
+    assert 0 < S.stokes_workspace_size(g2, None) < 64 * 2 ** 20
+
+
+@pytest.mark.parametrize("dim,n,h", [(4, (8, 8, 8), (1, 1, 1)), (2, (1, 8, 1), (1, 1, 1)),
+                                     (3, (8, 8, 8), (1, 0, 1))])
+def test_bad_grids_rejected_on_host(S, dim, n, h):
+    g = S._binding.make_grid(dim, n, h)
+    assert S.stokes_workspace_size(g, None) == 0
+    with pytest.raises(S.StokesError) as e:
+        S.stokes_setup([1, 2, 3], 4, 1e-3, g, None, 8, 16, stream=0)
+    assert e.value.status in (-1, -2)
+    assert len(S.stokes_last_error(None)) > 0
+
+
+def test_bad_options_rejected_on_host(S):
+    g = S._binding.make_grid(2, (8, 8, 1), (1, 1, 1))
+    o = S.stokes_default_options()
+    o.p_cycles = 0
+    assert S.stokes_workspace_size(g, o) == 0
+    o = S.stokes_default_options()
+    with pytest.raises(S.StokesError) as e:
+        S.stokes_setup([1, 2, None], 4, -1.0, g, o, 8, 1 << 30, stream=0)
+    assert e.value.status == -1
+    with pytest.raises(S.StokesError) as e:
+        S.stokes_setup([1, 2, None], 4, 1e-3, g, o, 8, 16, stream=0)
+    assert e.value.status == -3          # workspace too small, detected on the host

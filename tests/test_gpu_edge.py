@@ -1,0 +1,122 @@
+"""GPU edge cases and error paths of the C-ABI (forced from the host)."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import assemble as A
+from oracle import direct as D
+from tests.gpu_util import gpu_solve, rel, solver_for, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+def test_zero_rhs_gives_zero():
+    prob = W.config1(scale=4)
+    prob.rhs_u = [np.zeros_like(r) for r in prob.rhs_u[:2]] + [None]
+    xu, xp, st, stats = gpu_solve(prob)
+    assert st == 0 and stats.iters == 0
+    assert all(np.all(a == 0) for a in xu) and np.all(xp == 0)
+
+
+def test_exact_initial_guess_needs_no_iteration():
+    prob = W.config1(scale=2)
+    sys = A.from_problem(prob)
+    ru, rp = D.solve_problem(prob, sys)
+    xu, xp, st, stats = gpu_solve(prob, tol=1e-9, x0=(ru[:2], rp))
+    assert st == 0 and stats.iters == 0
+
+
+def test_rhs_p_mean_removed_and_reported():
+    prob = W.config1(scale=2)
+    prob.rhs_p = prob.rhs_p + 0.25
+    xu, xp, st, stats = gpu_solve(prob, tol=1e-12)
+    assert st == 0
+    assert abs(stats.g_mean - 0.25) <= 1e-15
+    prob.rhs_p = prob.rhs_p - 0.25
+    yu, yp, st2, _ = gpu_solve(prob, tol=1e-12)
+    assert rel(xu[0], yu[0]) <= 1e-9
+
+
+def test_nan_rhs_reports_enan():
+    import paper_1901_07892_amd as S
+    prob = W.config1(scale=4)
+    prob.rhs_u[0][0, 3, 3] = np.nan
+    with pytest.raises(S.StokesError) as e:
+        gpu_solve(prob)
+    assert e.value.status == -5
+
+
+def test_max_iters_not_converged_returns_best_iterate():
+    prob = W.config1(scale=2)
+    xu, xp, st, stats = gpu_solve(prob, tol=1e-14, max_iters=1)
+    assert st == 1 and stats.iters == 1
+    assert stats.rel_res_true < 1.0
+
+
+def test_nonpositive_density_rejected():
+    import paper_1901_07892_amd as S
+    prob = W.config1(scale=4)
+    prob.rho_faces[1][0, 5, 5] = 0.0
+    with pytest.raises(S.StokesError) as e:
+        solver_for(prob)
+    assert e.value.status == -1
+
+
+def test_small_workspace_rejected():
+    import torch
+    import paper_1901_07892_amd as S
+    prob = W.config1(scale=4)
+    g = S._binding.make_grid(2, prob.n, prob.h)
+    o = S.stokes_default_options()
+    need = S.stokes_workspace_size(g, o)
+    ws = torch.empty(need // 2, dtype=torch.uint8, device="cuda")
+    with pytest.raises(S.StokesError) as e:
+        S.stokes_setup([to_dev(prob.rho_faces[0]), to_dev(prob.rho_faces[1])], to_dev(prob.mu), prob.dt, g, o,
+                       ws.data_ptr(), need // 2)
+    assert e.value.status == -3
+
+
+def test_minimal_grids_solve():
+    for n, dim in (((2, 2, 1), 2), ((2, 2, 2), 3), ((3, 2, 5), 3)):
+        h = (0.5, 0.5, 0.5)
+        prob = W.make_problem("tiny", dim, n, h, 1e-3, 1e-12, lambda X, Y, Z: Y - 0.5, [], 9)
+        sys = A.from_problem(prob)
+        ru, rp = D.solve_problem(prob, sys)
+        xu, xp, st, stats = gpu_solve(prob, tol=1e-13)
+        assert st == 0, (n, stats.as_dict())
+        for c in range(dim):
+            assert rel(xu[c], ru[c]) <= 1e-9
+        assert rel(xp, rp) <= 1e-9
+
+
+def test_solve_is_bitwise_deterministic():
+    prob = W.config3(scale=8)
+    a = gpu_solve(prob)
+    b = gpu_solve(prob)
+    for c in range(3):
+        assert np.array_equal(a[0][c], b[0][c])
+    assert np.array_equal(a[1], b[1])
+    assert a[3].iters == b[3].iters
+
+
+@pytest.mark.parametrize("theta", [0.5, 0.0])
+def test_theta_variants_match_direct(theta):
+    prob = W.config1()
+    sys = A.from_problem(prob, theta=theta)
+    ru, rp = D.solve_problem(prob, sys)
+    xu, xp, st, stats = gpu_solve(prob, tol=1e-13, theta=theta)
+    assert st == 0
+    for c in range(2):
+        assert rel(xu[c], ru[c]) <= 1e-9
+    assert rel(xp - xp.mean(), rp - rp.mean()) <= 1e-9
+
+
+def test_well_balanced_still_tank():
+    prob = W.config1()
+    g = -9.81
+    prob.rhs_u = [np.zeros_like(prob.rho_faces[0]), prob.rho_flow_faces[1] * g, None]
+    for end in (0, -1):
+        prob.rhs_u[1][:, end, :] = 0.0
+    xu, xp, st, stats = gpu_solve(prob, tol=1e-13)
+    assert st == 0
+    assert max(np.abs(xu[0]).max(), np.abs(xu[1]).max()) / (abs(g) * prob.dt) <= 1e-9
