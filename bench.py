@@ -28,6 +28,8 @@ def parse():
     ap.add_argument("--precision", type=int, default=0, help="0 FP64 multigrid, 1 FP32 multigrid")
     ap.add_argument("--n", type=int, default=256, help="cells per axis of the headline workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--opt", action="append", default=[],
+                    help="solver option override key=value (fields of stokes_options)")
     ap.add_argument("--verbose", action="store_true")
     return ap.parse_args()
 
@@ -60,7 +62,11 @@ def main():
     torch.cuda.synchronize()
 
     ts = time.time()
-    solver = S.StokesSolver(3, prob.n, prob.h, rho, mu, prob.dt, precision=args.precision)
+    overrides = {"precision": args.precision}
+    for kv in args.opt:
+        k, v = kv.split("=")
+        overrides[k] = float(v) if k in ("visc_scale", "cont_scale") else int(v)
+    solver = S.StokesSolver(3, prob.n, prob.h, rho, mu, prob.dt, **overrides)
     torch.cuda.synchronize()
     setup_ms = (time.time() - ts) * 1e3
     log("setup %.1f ms, workspace %.2f GB" % (setup_ms, solver.ws_bytes / 1e9))
@@ -106,7 +112,8 @@ def main():
         "dtype": "f64" if args.precision == 0 else "f64 (f32 multigrid)",
         "data": "synthetic",
         "config": {"workload": prob.name + " air/water/solids density ratio 1000, seed 900000",
-                   "tol": prob.tol, "dt": prob.dt, "precision": args.precision},
+                   "tol": prob.tol, "dt": prob.dt, "precision": args.precision,
+                   "options": {k: getattr(solver.opts, k) for k, _ in solver.opts._fields_}},
         "solves_per_s": 1e3 / ms,
         "median_ms": float(np.median(times)),
         "fgmres_iters": int(np.median(iters)),

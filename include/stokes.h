@@ -75,8 +75,19 @@ typedef struct {
     int p_cycles;        /* pressure V-cycles per preconditioner application (>= 1) */
     int coarse_sweeps;   /* smoothing sweeps on the coarsest velocity level (and on the
                             coarsest pressure level when it is too big for a dense solve) */
-    int vel_levels;      /* velocity multigrid levels: 0 = as many as the pressure hierarchy,
-                            1 = smoother only on the fine grid */
+    int vel_levels;      /* velocity multigrid levels.  0 = automatic: a single level (the
+                            smoother alone) when the viscous part of every momentum diagonal
+                            is below 1% of its mass term rho/dt -- the coarse-grid correction
+                            can then improve the subsolve by at most that fraction -- and the
+                            full hierarchy otherwise.  n > 0: min(n, pressure levels). */
+    int vel_sweeps;      /* red-black sweeps of the velocity smoother when the velocity
+                            hierarchy is a single level (>= 1) */
+    int p_prolong;       /* pressure prolongation: 0 piecewise constant, 1 bi/trilinear */
+    int vel_smoother;    /* 0: red-black Gauss-Seidel.  1: when the velocity hierarchy is a
+                            single level with one sweep and one cycle, that sweep is a point
+                            Jacobi (diagonal) step folded into the projection kernels;
+                            otherwise red-black Gauss-Seidel is used */
+    int orth;            /* Arnoldi orthogonalisation: 1 classical Gram-Schmidt, 2 twice */
 } stokes_options;
 
 typedef struct {
@@ -98,8 +109,9 @@ typedef struct {
 typedef struct stokes_ctx stokes_ctx;
 
 /* Fill *opts with the defaults (FP64, theta 1, automatic sigma, restart 30,
- * max_iters 200, V(2,2), one velocity and one pressure cycle, 40 coarse sweeps,
- * full velocity hierarchy). */
+ * max_iters 200, V(2,2), one velocity and three pressure cycles, 40 coarse sweeps,
+ * automatic velocity levels, 1 single-level velocity sweep, trilinear pressure
+ * prolongation). */
 void stokes_default_options(stokes_options *opts);
 
 /* Bytes of device workspace that stokes_setup needs for this grid and these
@@ -145,6 +157,26 @@ stokes_status stokes_apply(stokes_ctx *ctx, const double *const x_u[3], const do
  * Returns OK, NOT_CONVERGED (best iterate in x), BREAKDOWN, ENAN, EINVAL or EHIP. */
 stokes_status stokes_solve(stokes_ctx *ctx, const double *const rhs_u[3], const double *rhs_p,
                            double tol, double *const x_u[3], double *x_p, stokes_stats *stats);
+
+/* Measurement hook.  Kernel classes that can be timed: */
+enum {
+    STOKES_PROF_MATVEC = 0,    /* fine-level K x and b - K x (k_apply) */
+    STOKES_PROF_P_SWEEP = 1,   /* fused 3D red-black pressure sweep on the finest level */
+    STOKES_PROF_MULTIDOT = 2,  /* Arnoldi inner products, up to 8 vectors per launch */
+    STOKES_PROF_MAXPY = 3      /* Arnoldi vector updates, up to 8 vectors per launch */
+};
+
+/* Time every launch of one kernel class (kernel = -1 stops) with a pair of HIP
+ * events on the context's stream during the following stokes_solve calls, and
+ * add up the algorithmic bytes each launch must move (unique inputs and
+ * outputs of that launch, documented with each class).  The events are created
+ * here on first use (at most 8192; later launches go untimed).  Resets the
+ * accumulators.  Returns EINVAL for an unknown class, EHIP if event creation fails. */
+stokes_status stokes_profile_kernel(stokes_ctx *ctx, int kernel);
+
+/* Read and reset the accumulators: summed event time (ms), launches timed and
+ * their summed algorithmic bytes. */
+stokes_status stokes_profile_read(stokes_ctx *ctx, double *ms_total, long long *launches, double *bytes);
 
 /* Release the host-side context (the workspace stays the caller's). NULL is a no-op. */
 void stokes_destroy(stokes_ctx *ctx);

@@ -17,6 +17,8 @@ from ._binding import (  # noqa: F401
     stokes_default_options,
     stokes_destroy,
     stokes_last_error,
+    stokes_profile_kernel,
+    stokes_profile_read,
     stokes_setup,
     stokes_solve,
     stokes_workspace_size,

@@ -32,7 +32,8 @@ class StokesOptions(C.Structure):
     _fields_ = [("precision", C.c_int), ("visc_scale", C.c_double), ("cont_scale", C.c_double),
                 ("restart", C.c_int), ("max_iters", C.c_int), ("nu1", C.c_int), ("nu2", C.c_int),
                 ("vel_cycles", C.c_int), ("p_cycles", C.c_int), ("coarse_sweeps", C.c_int),
-                ("vel_levels", C.c_int)]
+                ("vel_levels", C.c_int), ("vel_sweeps", C.c_int), ("p_prolong", C.c_int),
+                ("vel_smoother", C.c_int), ("orth", C.c_int)]
 
 
 class StokesStats(C.Structure):
@@ -76,6 +77,11 @@ def load_library():
     L.stokes_destroy.restype = None
     L.stokes_last_error.argtypes = [C.c_void_p]
     L.stokes_last_error.restype = C.c_char_p
+    L.stokes_profile_kernel.argtypes = [C.c_void_p, C.c_int]
+    L.stokes_profile_kernel.restype = C.c_int
+    L.stokes_profile_read.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_longlong),
+                                      C.POINTER(C.c_double)]
+    L.stokes_profile_read.restype = C.c_int
     _lib = L
     return L
 
@@ -164,6 +170,23 @@ def stokes_destroy(ctx) -> None:
 
 def stokes_last_error(ctx=None) -> str:
     return load_library().stokes_last_error(ctx).decode()
+
+
+PROF_MATVEC, PROF_P_SWEEP, PROF_MULTIDOT, PROF_MAXPY = 0, 1, 2, 3
+
+
+def stokes_profile_kernel(ctx, kernel: int) -> None:
+    L = load_library()
+    st = L.stokes_profile_kernel(ctx, int(kernel))
+    if st < 0:
+        raise StokesError(st, L.stokes_last_error(ctx).decode())
+
+
+def stokes_profile_read(ctx):
+    """Returns (ms_total, launches, algorithmic_bytes) and resets them."""
+    ms, n, b = C.c_double(), C.c_longlong(), C.c_double()
+    load_library().stokes_profile_read(ctx, C.byref(ms), C.byref(n), C.byref(b))
+    return ms.value, n.value, b.value
 
 
 # ---------------------------------------------------------------- convenience wrapper

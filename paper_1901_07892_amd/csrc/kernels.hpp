@@ -350,15 +350,42 @@ __global__ void __launch_bounds__(kBlock) k_p_residual_restrict(Box fb, Box cb, 
     rc[idx] = acc * (DIM == 3 ? R(0.125) : R(0.25));
 }
 
-// Fine correction += coarse value of the parent cell (piecewise constant).
+// Prolonged coarse correction at fine cell (i,j,k).  lin == 0: the parent's
+// value (piecewise constant).  lin == 1: bi/trilinear interpolation between the
+// cell centres, weights 3/4 (parent) and 1/4 (the coarse neighbour on the
+// child's side) per axis; beyond a wall the parent is mirrored.
 template <int DIM, class R>
-__global__ void __launch_bounds__(kBlock) k_p_prolong_add(Box fb, Box cb, const R *__restrict__ c, R *__restrict__ f) {
+__device__ inline R prolong_value(const Box &cb, const R *ec, int i, int j, int k, int lin) {
+    const int I = i >> 1, J = j >> 1, K = DIM == 3 ? (k >> 1) : 0;
+    if (!lin) return ec[box_index(cb, I, J, K)];
+    int I2 = (i & 1) ? I + 1 : I - 1;
+    int J2 = (j & 1) ? J + 1 : J - 1;
+    I2 = I2 < 0 ? 0 : (I2 >= cb.nx ? cb.nx - 1 : I2);
+    J2 = J2 < 0 ? 0 : (J2 >= cb.ny ? cb.ny - 1 : J2);
+    const R a = R(0.75), b = R(0.25);
+    if (DIM == 2) {
+        return a * (a * ec[box_index(cb, I, J, 0)] + b * ec[box_index(cb, I2, J, 0)])
+             + b * (a * ec[box_index(cb, I, J2, 0)] + b * ec[box_index(cb, I2, J2, 0)]);
+    }
+    int K2 = (k & 1) ? K + 1 : K - 1;
+    K2 = K2 < 0 ? 0 : (K2 >= cb.nz ? cb.nz - 1 : K2);
+    R p0 = a * (a * ec[box_index(cb, I, J, K)] + b * ec[box_index(cb, I2, J, K)])
+         + b * (a * ec[box_index(cb, I, J2, K)] + b * ec[box_index(cb, I2, J2, K)]);
+    R p1 = a * (a * ec[box_index(cb, I, J, K2)] + b * ec[box_index(cb, I2, J, K2)])
+         + b * (a * ec[box_index(cb, I, J2, K2)] + b * ec[box_index(cb, I2, J2, K2)]);
+    return a * p0 + b * p1;
+}
+
+// Fine correction += prolonged coarse correction (see prolong_value).
+template <int DIM, class R>
+__global__ void __launch_bounds__(kBlock) k_p_prolong_add(Box fb, Box cb, int lin, const R *__restrict__ c,
+        R *__restrict__ f) {
     int idx = blockIdx.x * kBlock + threadIdx.x;
     if (idx >= fb.nb) return;
     int i, j, k;
     decompose(fb, idx, i, j, k);
     if (!is_cell(fb, i, j, k)) return;
-    f[idx] += c[box_index(cb, i >> 1, j >> 1, DIM == 3 ? (k >> 1) : 0)];
+    f[idx] += prolong_value<DIM, R>(cb, c, i, j, k, lin);
 }
 
 // Coarsest pressure level: e = M r with M the dense pseudo-inverse of the
@@ -375,6 +402,102 @@ __global__ void __launch_bounds__(1024) k_dense_solve(int n, const R *__restrict
         const R *row = M + (size_t)t * n;
         for (int q = 0; q < n; ++q) acc += row[q] * rs[q];
         e[map[t]] = acc;
+    }
+}
+
+// One full red-black Gauss-Seidel sweep of -L_rho e = r in 3D, both colours in
+// one launch.  A block owns a TX x TY column of cells and a chunk of KC planes,
+// marching in z with rings of three planes in LDS: the old values (tile plus a
+// 2-cell x-y halo) and the values after the red half-sweep (tile plus 1).  Red
+// points of the 1-cell halo ring and of the planes next to the chunk are
+// recomputed by every block that needs them, so blocks are independent and the
+// result equals the global two-pass sweep.  Input and output are separate
+// arrays (ein is never written), so blocks never race.  With zero_guess the old
+// values are taken as zero (ein is not read).  With ec != nullptr the old value
+// is ein + the prolonged coarse correction ec: the prolongation of a coarse
+// correction (see prolong_value) is folded into the sweep that follows it.
+template <class R, int TX, int TY>
+__global__ void __launch_bounds__(TX *TY) k_p_sweep3(Box b, int kc, int zero_guess, const R *__restrict__ ein,
+        const R *__restrict__ ec, Box cb, int lin, R *__restrict__ eout, const R *__restrict__ r,
+        const R *__restrict__ bx, const R *__restrict__ by, const R *__restrict__ bz) {
+    constexpr int NT = TX * TY;
+    constexpr int EX1 = TX + 2, EY1 = TY + 2, N1 = EX1 * EY1;
+    constexpr int EX2 = TX + 4, EY2 = TY + 4, N2 = EX2 * EY2;
+    __shared__ R oldp[3][N2];
+    __shared__ R newp[3][N1];
+    const int tid = threadIdx.x;
+    const int i0 = blockIdx.x * TX, j0 = blockIdx.y * TY;
+    const int k0 = blockIdx.z * kc, k1 = min(k0 + kc, b.nz);
+    const int sy = b.px, sz = b.plane;
+    const R ix2 = R(b.ihx * b.ihx), iy2 = R(b.ihy * b.ihy), iz2 = R(b.ihz * b.ihz);
+    auto slot = [](int k) { return ((k % 3) + 3) % 3; };
+    auto load_old = [&](int k) {
+        R *dst = oldp[slot(k)];
+        for (int t = tid; t < N2; t += NT) {
+            int i = i0 + (t % EX2) - 2, j = j0 + (t / EX2) - 2;
+            R v = R(0);
+            if (!zero_guess && k >= 0 && k < b.nz && i >= 0 && i < b.nx && j >= 0 && j < b.ny) {
+                int q = box_index(b, i, j, k);
+                v = ein[q];
+                if (ec) v += prolong_value<3, R>(cb, ec, i, j, k, lin);
+            }
+            dst[t] = v;
+        }
+    };
+    load_old(k0 - 2);
+    load_old(k0 - 1);
+    for (int k = k0 - 1; k <= k1; ++k) {
+        load_old(k + 1);
+        __syncthreads();
+        // red half-sweep on plane k over the tile plus a 1-cell ring
+        {
+            const R *om = oldp[slot(k - 1)], *oc = oldp[slot(k)], *op = oldp[slot(k + 1)];
+            R *dst = newp[slot(k)];
+            for (int t = tid; t < N1; t += NT) {
+                int ex = t % EX1, ey = t / EX1;
+                int i = i0 + ex - 1, j = j0 + ey - 1;
+                R v = R(0);
+                if (k >= 0 && k < b.nz && i >= 0 && i < b.nx && j >= 0 && j < b.ny) {
+                    int o2 = (ey + 1) * EX2 + (ex + 1);
+                    if (((i + j + k) & 1) == 0) {
+                        int q = box_index(b, i, j, k);
+                        R wW = bx[q] * ix2, wE = bx[q + 1] * ix2, wS = by[q] * iy2, wN = by[q + sy] * iy2;
+                        R wB = bz[q] * iz2, wT = bz[q + sz] * iz2;
+                        R dg = wW + wE + wS + wN + wB + wT;
+                        R off = wW * oc[o2 - 1] + wE * oc[o2 + 1] + wS * oc[o2 - EX2] + wN * oc[o2 + EX2]
+                              + wB * om[o2] + wT * op[o2];
+                        v = dg > R(0) ? (r[q] + off) / dg : R(0);
+                    } else {
+                        v = oc[o2];
+                    }
+                }
+                dst[t] = v;
+            }
+        }
+        __syncthreads();
+        // black half-sweep on plane k-1 over the tile, written out with the red values
+        const int kk = k - 1;
+        if (kk >= k0 && kk < k1) {
+            const R *nm = newp[slot(kk - 1)], *nc = newp[slot(kk)], *np = newp[slot(kk + 1)];
+            int tx = tid % TX, ty = tid / TX;
+            int i = i0 + tx, j = j0 + ty;
+            if (i < b.nx && j < b.ny) {
+                int o1 = (ty + 1) * EX1 + (tx + 1);
+                int q = box_index(b, i, j, kk);
+                R v;
+                if (((i + j + kk) & 1) == 1) {
+                    R wW = bx[q] * ix2, wE = bx[q + 1] * ix2, wS = by[q] * iy2, wN = by[q + sy] * iy2;
+                    R wB = bz[q] * iz2, wT = bz[q + sz] * iz2;
+                    R dg = wW + wE + wS + wN + wB + wT;
+                    R off = wW * nc[o1 - 1] + wE * nc[o1 + 1] + wS * nc[o1 - EX1] + wN * nc[o1 + EX1]
+                          + wB * nm[o1] + wT * np[o1];
+                    v = dg > R(0) ? (r[q] + off) / dg : R(0);
+                } else {
+                    v = nc[o1];
+                }
+                eout[q] = v;
+            }
+        }
     }
 }
 
@@ -559,6 +682,78 @@ __global__ void __launch_bounds__(kBlock) k_precond_update(Box b, const R *eu, c
     zp[idx] = z;
 }
 
+// Diagonal (point-Jacobi) form of step 1 folded into the glue kernels: when the
+// velocity operator is mass dominated, u~ = D_A^{-1} v_u with dinv the inverse
+// diagonal of A.  Same formulas as k_precond_div / k_precond_update otherwise.
+template <int DIM, class R>
+__global__ void __launch_bounds__(kBlock) k_precond_div_jac(Box b, const double *__restrict__ vu,
+        const double *__restrict__ vv, const double *__restrict__ vw, const double *__restrict__ du,
+        const double *__restrict__ dv, const double *__restrict__ dw, const double *__restrict__ rp, double dt,
+        double *__restrict__ q, R *__restrict__ s) {
+    int idx = blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= b.nb) return;
+    int i, j, k;
+    decompose(b, idx, i, j, k);
+    double qq = 0.0;
+    if (is_cell(b, i, j, k)) {
+        double d = (vu[idx + 1] * du[idx + 1] - vu[idx] * du[idx]) * b.ihx
+                 + (vv[idx + b.px] * dv[idx + b.px] - vv[idx] * dv[idx]) * b.ihy;
+        if (DIM == 3) d += (vw[idx + b.plane] * dw[idx + b.plane] - vw[idx] * dw[idx]) * b.ihz;
+        qq = rp[idx] + d;
+    }
+    q[idx] = qq;
+    s[idx] = (R)(-qq / dt);
+}
+
+template <int DIM, class R>
+__global__ void __launch_bounds__(kBlock) k_precond_update_jac(Box b, const double *__restrict__ vu,
+        const double *__restrict__ vv, const double *__restrict__ vw, const double *__restrict__ du,
+        const double *__restrict__ dv, const double *__restrict__ dw, const R *__restrict__ phi,
+        const double *__restrict__ bx, const double *__restrict__ by, const double *__restrict__ bz,
+        const double *__restrict__ mu, const double *__restrict__ q, double dt, double theta,
+        double *__restrict__ zu, double *__restrict__ zv, double *__restrict__ zw, double *__restrict__ zp) {
+    int idx = blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= b.nb) return;
+    int i, j, k;
+    decompose(b, idx, i, j, k);
+    const double ph = (double)phi[idx];
+    double z = 0.0;
+    if (is_ux(b, i, j, k)) z = vu[idx] * du[idx] - dt * bx[idx] * (ph - (double)phi[idx - 1]) * b.ihx;
+    zu[idx] = z;
+    z = 0.0;
+    if (is_vy(b, i, j, k)) z = vv[idx] * dv[idx] - dt * by[idx] * (ph - (double)phi[idx - b.px]) * b.ihy;
+    zv[idx] = z;
+    if (DIM == 3) {
+        z = 0.0;
+        if (is_wz(b, i, j, k)) z = vw[idx] * dw[idx] - dt * bz[idx] * (ph - (double)phi[idx - b.plane]) * b.ihz;
+        zw[idx] = z;
+    }
+    z = 0.0;
+    if (is_cell(b, i, j, k)) z = ph - 2.0 * theta * mu[idx] * q[idx];
+    zp[idx] = z;
+}
+
+// Inverse diagonal of the fine velocity operator (0 off the interior faces).
+template <int DIM>
+__global__ void __launch_bounds__(kBlock) k_vel_inv_diag(Box b, VelCoef<double> c, double *__restrict__ du,
+        double *__restrict__ dv, double *__restrict__ dw) {
+    int idx = blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= b.nb) return;
+    int i, j, k;
+    decompose(b, idx, i, j, k);
+    double off, dg, v = 0.0;
+    if (is_ux(b, i, j, k)) { row_u<DIM, double>(b, idx, j, k, nullptr, nullptr, nullptr, 0, c, off, dg); v = 1.0 / dg; }
+    du[idx] = v;
+    v = 0.0;
+    if (is_vy(b, i, j, k)) { row_v<DIM, double>(b, idx, i, k, nullptr, nullptr, nullptr, 0, c, off, dg); v = 1.0 / dg; }
+    dv[idx] = v;
+    if (DIM == 3) {
+        v = 0.0;
+        if (is_wz(b, i, j, k)) { row_w<double>(b, idx, i, j, nullptr, nullptr, nullptr, 0, c, off, dg); v = 1.0 / dg; }
+        dw[idx] = v;
+    }
+}
+
 // ---------------------------------------------------------------- BLAS-1
 template <class A, class B>
 __global__ void __launch_bounds__(kBlock) k_cast(long long n, const A *__restrict__ x, B *__restrict__ y) {
@@ -635,13 +830,18 @@ __global__ void __launch_bounds__(kBlock) k_reduce_partials(int nblk, const doub
     if (threadIdx.x == 0) out[m] = accumulate ? out[m] + v[0] : v[0];
 }
 
-// w[t] += sign * sum_m c[m] * V_m[t]   (c on the device)
+// w[t] += sign * sum_m c[m] * V_m[t]   (c on the device).  With partial !=
+// nullptr also the weighted squared norm of the updated w (weight w2 from
+// pstart on), one partial sum per block.
 template <int NV>
 __global__ void __launch_bounds__(kBlock) k_maxpy(long long n, double sign, const double *__restrict__ V,
-        long long ldv, int nv, const double *__restrict__ c, double *__restrict__ w) {
+        long long ldv, int nv, const double *__restrict__ c, double *__restrict__ w,
+        long long pstart, double w2, double *__restrict__ partial) {
+    __shared__ double lds[kBlock / 64];
     double cc[NV];
 #pragma unroll
     for (int m = 0; m < NV; ++m) cc[m] = m < nv ? sign * c[m] : 0.0;
+    double nrm[1] = {0.0};
     long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
     long long st = (long long)gridDim.x * kBlock;
     for (; t < n; t += st) {
@@ -650,6 +850,11 @@ __global__ void __launch_bounds__(kBlock) k_maxpy(long long n, double sign, cons
         for (int m = 0; m < NV; ++m)
             if (m < nv) x += cc[m] * V[m * ldv + t];
         w[t] = x;
+        nrm[0] += (t >= pstart ? w2 : 1.0) * x * x;
+    }
+    if (partial) {
+        block_reduce<1>(nrm, lds);
+        if (threadIdx.x == 0) partial[blockIdx.x] = nrm[0];
     }
 }
 

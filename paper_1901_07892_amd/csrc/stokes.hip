@@ -64,7 +64,7 @@ struct Level {
     R *beta[3] = {nullptr, nullptr, nullptr};
     R *mu = nullptr, *mxy = nullptr, *mxz = nullptr, *myz = nullptr;
     R *eu[3] = {nullptr, nullptr, nullptr}, *ru[3] = {nullptr, nullptr, nullptr}, *tu[3] = {nullptr, nullptr, nullptr};
-    R *ep = nullptr, *rp = nullptr;
+    R *ep = nullptr, *ep2 = nullptr, *rp = nullptr;   // ep2: second buffer of the fused 3D sweep
 };
 
 template <class R>
@@ -103,15 +103,28 @@ struct stokes_ctx {
     // fine-level FP64 operator
     double *mass[3] = {nullptr, nullptr, nullptr}, *beta[3] = {nullptr, nullptr, nullptr};
     double *mu = nullptr, *mxy = nullptr, *mxz = nullptr, *myz = nullptr;
+    double *dinv[3] = {nullptr, nullptr, nullptr};   // inverse velocity diagonal (diagonal step)
     MG<double> mgd;
     MG<float> mgf;
     // Krylov storage: V (m+1 vectors), Z (m vectors), each nf fields of fine.stride
     int m = 30;
     long long vlen = 0;
+    double unknowns = 0;        // interior unknowns (velocity faces + cells)
     double *V = nullptr, *Z = nullptr, *xk = nullptr, *bk = nullptr, *q = nullptr;
     double *partial = nullptr, *dsc = nullptr;
     int *dflag = nullptr;
     int vcycles = 0;
+    double visc_ratio = -1.0;   // max viscous/mass diagonal ratio (automatic velocity levels)
+    bool diag_vel = false;      // velocity subsolve is one diagonal step (see stokes_options.vel_smoother)
+    // measurement: HIP events around every finest-level launch of one kernel class
+    int prof_kind = -1;
+    std::vector<hipEvent_t> ev;
+    size_t ev_used = 0;
+    double prof_ms = 0.0, prof_bytes = 0.0;
+    long long prof_launches = 0;
+    ~stokes_ctx() {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    }
     std::string err;
 
     double *vec(double *base, int j) const { return base + (size_t)j * vlen; }
@@ -156,6 +169,7 @@ void carve_mg(Carver &cv, stokes_ctx &c, MG<R> &mg, bool alias_level0) {
             L.tu[a] = t ? t + (size_t)a * b.stride : nullptr;
         }
         L.ep = cv.fields<R>(b, 1);
+        L.ep2 = cv.fields<R>(b, 1);
         L.rp = cv.fields<R>(b, 1);
         ++nl;
         if (nl >= kMaxLev || !can_coarsen(b)) break;
@@ -163,7 +177,7 @@ void carve_mg(Carver &cv, stokes_ctx &c, MG<R> &mg, bool alias_level0) {
     }
     mg.nlev = nl;
     int vl = c.opt.vel_levels;
-    mg.nvlev = (vl <= 0 || vl > nl) ? nl : vl;
+    mg.nvlev = (vl <= 0 || vl > nl) ? nl : vl;   // auto (vl == 0) is settled in setup
     const Box &cb = mg.L[nl - 1].b;
     mg.ndense = cb.nx * cb.ny * cb.nz;
     mg.use_dense = mg.ndense <= kDenseMax;
@@ -184,6 +198,7 @@ void carve_all(Carver &cv, stokes_ctx &c) {
         c.mxz = cv.fields<double>(b, 1);
         c.myz = cv.fields<double>(b, 1);
     }
+    for (int a = 0; a < d; ++a) c.dinv[a] = cv.fields<double>(b, 1);
     if (c.opt.precision == 1) carve_mg<float>(cv, c, c.mgf, false);
     else carve_mg<double>(cv, c, c.mgd, true);
     c.vlen = (long long)b.stride * c.nf;
@@ -203,6 +218,37 @@ inline unsigned nblocks_box(const Box &b) { return (unsigned)((b.nb + kBlock - 1
 inline unsigned nblocks_stream(long long n) {
     long long g = (n + kBlock - 1) / kBlock;
     return (unsigned)std::max<long long>(1, std::min<long long>(g, kRedBlocks));
+}
+
+// Records a pair of HIP events around one launch when that kernel class is
+// being measured (finest level only); the bytes are the launch's algorithmic
+// traffic.
+struct ProfScope {
+    stokes_ctx &c;
+    bool on;
+    ProfScope(stokes_ctx &cc, int kind, double bytes, bool finest = true) : c(cc) {
+        on = finest && c.prof_kind == kind && c.ev_used + 2 <= c.ev.size();
+        if (on) {
+            HIPCHK(hipEventRecord(c.ev[c.ev_used], c.stream));
+            c.prof_bytes += bytes;
+            c.prof_launches++;
+        }
+    }
+    ~ProfScope() {
+        if (on) {
+            (void)hipEventRecord(c.ev[c.ev_used + 1], c.stream);
+            c.ev_used += 2;
+        }
+    }
+};
+
+void prof_collect(stokes_ctx &c) {
+    for (size_t t = 0; t + 1 < c.ev_used; t += 2) {
+        float ms = 0.0f;
+        HIPCHK(hipEventElapsedTime(&ms, c.ev[t], c.ev[t + 1]));
+        c.prof_ms += ms;
+    }
+    c.ev_used = 0;
 }
 
 template <class R>
@@ -258,7 +304,7 @@ void vel_vcycle(stokes_ctx &c, MG<R> &mg, int l, R *const e[3], R *const r[3], b
     Level<R> &L = mg.L[l];
     const int nu1 = c.opt.nu1, nu2 = c.opt.nu2;
     if (l == mg.nvlev - 1) {
-        int sw = l == 0 ? std::max(1, nu1 + nu2) : std::max(1, c.opt.coarse_sweeps);
+        int sw = l == 0 ? c.opt.vel_sweeps : std::max(1, c.opt.coarse_sweeps);
         vel_smooth<DIM, R>(c, L, e, r, sw, zero_guess);
         return;
     }
@@ -286,26 +332,73 @@ void p_smooth(stokes_ctx &c, Level<R> &L, R *e, const R *r, int sweeps, bool zer
                 DIM == 3 ? L.beta[2] : L.beta[1]);
 }
 
+constexpr int kSweepTX = 32, kSweepTY = 8;
+
+// One fused 3D sweep from `in` into `out` (optionally adding the prolonged coarse
+// correction `ec` to the old values first).
+template <class R>
+void p_sweep3(stokes_ctx &c, Level<R> &L, const R *in, R *out, const R *r, bool zero_guess,
+              const R *ec, const Box *cb) {
+    const int lin = c.opt.p_prolong;
+    const Box &b = L.b;
+    int gx = (b.nx + kSweepTX - 1) / kSweepTX, gy = (b.ny + kSweepTY - 1) / kSweepTY;
+    // z chunks: enough blocks to fill the chip, at least 8 planes per chunk
+    int kc = b.nz;
+    while (kc > 8 && (long long)gx * gy * ((b.nz + kc - 1) / kc) < 2048) kc = (kc + 1) / 2;
+    int gz = (b.nz + kc - 1) / kc;
+    const double cells = (double)b.nx * b.ny * b.nz;
+    // old and new iterate, right-hand side, three face coefficients (+ coarse correction)
+    ProfScope ps(c, STOKES_PROF_P_SWEEP, cells * sizeof(R) * (6.0 + (ec ? 0.125 : 0.0)), b.nx == c.fine.nx);
+    k_p_sweep3<R, kSweepTX, kSweepTY><<<dim3(gx, gy, gz), kSweepTX * kSweepTY, 0, c.stream>>>(
+        b, kc, zero_guess ? 1 : 0, in, ec, cb ? *cb : b, lin, out, r, L.beta[0], L.beta[1], L.beta[2]);
+}
+
+// V-cycle on -L_rho e = r at level l.  Returns the array that holds the new
+// iterate: e itself, or (3D, after an odd number of fused sweeps) the level's
+// other buffer.
 template <int DIM, class R>
-void p_vcycle(stokes_ctx &c, MG<R> &mg, int l, R *e, R *r, bool zero_guess) {
+R *p_vcycle(stokes_ctx &c, MG<R> &mg, int l, R *e, R *r, bool zero_guess) {
     Level<R> &L = mg.L[l];
+    R *cur = e;
+    R *spare = (e == L.ep) ? L.ep2 : L.ep;
+    auto sweep = [&](bool zg, const R *ec, const Box *cb) {
+        p_sweep3<R>(c, L, cur, spare, r, zg, ec, cb);
+        std::swap(cur, spare);
+    };
     if (l == mg.nlev - 1) {
         if (mg.use_dense) {
             int nt = std::min(1024, ((mg.ndense + 63) / 64) * 64);
             k_dense_solve<R><<<1, nt, mg.ndense * sizeof(R), c.stream>>>(mg.ndense, mg.dense, mg.dmap, r, e);
+        } else if (DIM == 3) {
+            for (int s = 0; s < std::max(1, c.opt.coarse_sweeps); ++s) sweep(zero_guess && s == 0, nullptr, nullptr);
         } else {
             p_smooth<DIM, R>(c, L, e, r, std::max(1, c.opt.coarse_sweeps), zero_guess);
         }
-        return;
+        return cur;
     }
-    if (zero_guess && c.opt.nu1 == 0) fill<R>(c, e - L.b.guard, L.b.stride, R(0));
-    p_smooth<DIM, R>(c, L, e, r, c.opt.nu1, zero_guess);
+    const int nu1 = c.opt.nu1, nu2 = c.opt.nu2;
+    if (zero_guess && nu1 == 0) fill<R>(c, cur - L.b.guard, L.b.stride, R(0));
+    if (DIM == 3) {
+        for (int s = 0; s < nu1; ++s) sweep(zero_guess && s == 0, nullptr, nullptr);
+    } else {
+        p_smooth<DIM, R>(c, L, cur, r, nu1, zero_guess);
+    }
     Level<R> &C = mg.L[l + 1];
     const R *bz = DIM == 3 ? L.beta[2] : L.beta[1];
-    k_p_residual_restrict<DIM, R><<<nblocks_box(C.b), kBlock, 0, c.stream>>>(L.b, C.b, e, r, L.beta[0], L.beta[1], bz, C.rp);
-    p_vcycle<DIM, R>(c, mg, l + 1, C.ep, C.rp, true);
-    k_p_prolong_add<DIM, R><<<nblocks_box(L.b), kBlock, 0, c.stream>>>(L.b, C.b, C.ep, e);
-    p_smooth<DIM, R>(c, L, e, r, c.opt.nu2, false);
+    k_p_residual_restrict<DIM, R><<<nblocks_box(C.b), kBlock, 0, c.stream>>>(L.b, C.b, cur, r, L.beta[0], L.beta[1], bz, C.rp);
+    R *ce = p_vcycle<DIM, R>(c, mg, l + 1, C.ep, C.rp, true);
+    if (DIM == 3 && nu2 > 0) {
+        sweep(false, ce, &C.b);                    // prolongation folded into the first post-sweep
+        for (int s = 1; s < nu2; ++s) sweep(false, nullptr, nullptr);
+    } else {
+        k_p_prolong_add<DIM, R><<<nblocks_box(L.b), kBlock, 0, c.stream>>>(L.b, C.b, c.opt.p_prolong, ce, cur);
+        if (DIM == 3) {
+            for (int s = 0; s < nu2; ++s) sweep(false, nullptr, nullptr);
+        } else {
+            p_smooth<DIM, R>(c, L, cur, r, nu2, false);
+        }
+    }
+    return cur;
 }
 
 // ---------------------------------------------------------------- preconditioner
@@ -323,6 +416,21 @@ void precond(stokes_ctx &c, MG<R> &mg, double *v, double *z) {
     double *vu[3] = {c.fld(v, 0), c.fld(v, 1), DIM == 3 ? c.fld(v, 2) : nullptr};
     double *zu[3] = {c.fld(z, 0), c.fld(z, 1), DIM == 3 ? c.fld(z, 2) : nullptr};
     double *vp = c.fld(v, DIM), *zp = c.fld(z, DIM);
+    if (c.diag_vel) {
+        // step 1 as one diagonal step, folded into the divergence and update kernels
+        double *d2 = DIM == 3 ? c.dinv[2] : c.dinv[1];
+        k_precond_div_jac<DIM, R><<<nblocks_box(c.fine), kBlock, 0, c.stream>>>(
+            c.fine, vu[0], vu[1], DIM == 3 ? vu[2] : vu[1], c.dinv[0], c.dinv[1], d2, vp, c.dt, c.q, L0.rp);
+        R *phi = L0.ep;
+        for (int cyc = 0; cyc < c.opt.p_cycles; ++cyc) {
+            phi = p_vcycle<DIM, R>(c, mg, 0, phi, L0.rp, cyc == 0);
+            c.vcycles++;
+        }
+        k_precond_update_jac<DIM, R><<<nblocks_box(c.fine), kBlock, 0, c.stream>>>(
+            c.fine, vu[0], vu[1], DIM == 3 ? vu[2] : vu[1], c.dinv[0], c.dinv[1], d2, phi, c.beta[0], c.beta[1],
+            DIM == 3 ? c.beta[2] : c.beta[1], c.mu, c.q, c.dt, c.theta, zu[0], zu[1], DIM == 3 ? zu[2] : zu[1], zp);
+        return;
+    }
     R *eu[3], *ru[3];
     if (sizeof(R) == sizeof(double)) {
         for (int a = 0; a < 3; ++a) {
@@ -345,12 +453,13 @@ void precond(stokes_ctx &c, MG<R> &mg, double *v, double *z) {
         c.vcycles++;
     }
     k_precond_div<DIM, R><<<nblocks_box(c.fine), kBlock, 0, c.stream>>>(c.fine, eu[0], eu[1], eu[2], vp, c.dt, c.q, L0.rp);
+    R *phi = L0.ep;
     for (int cyc = 0; cyc < c.opt.p_cycles; ++cyc) {
-        p_vcycle<DIM, R>(c, mg, 0, L0.ep, L0.rp, cyc == 0);
+        phi = p_vcycle<DIM, R>(c, mg, 0, phi, L0.rp, cyc == 0);
         c.vcycles++;
     }
     k_precond_update<DIM, R><<<nblocks_box(c.fine), kBlock, 0, c.stream>>>(
-        c.fine, eu[0], eu[1], eu[2], L0.ep, c.beta[0], c.beta[1], DIM == 3 ? c.beta[2] : c.beta[1], c.mu, c.q,
+        c.fine, eu[0], eu[1], eu[2], phi, c.beta[0], c.beta[1], DIM == 3 ? c.beta[2] : c.beta[1], c.mu, c.q,
         c.dt, c.theta, zu[0], zu[1], DIM == 3 ? zu[2] : zu[1], zp);
 }
 
@@ -361,19 +470,26 @@ void multidot(stokes_ctx &c, const double *V, int nv, const double *w, double w2
     const unsigned g = nblocks_stream(n);
     for (int m0 = 0; m0 < nv; m0 += kGroup) {
         int cnt = std::min(kGroup, nv - m0);
+        ProfScope ps(c, STOKES_PROF_MULTIDOT, (double)(cnt + 1) * c.unknowns * 8.0);
         k_multidot<kGroup><<<g, kBlock, 0, c.stream>>>(n, pstart, w2, V + (size_t)m0 * c.vlen, c.vlen, cnt, w, c.partial);
         k_reduce_partials<<<cnt, kBlock, 0, c.stream>>>((int)g, c.partial, out + m0, 0);
     }
 }
 
-// w += sign * sum_m coef[m] V_m   (coef on the device)
-void maxpy(stokes_ctx &c, double sign, const double *V, int nv, const double *coef, double *w) {
-    const long long n = c.vlen;
+// w += sign * sum_m coef[m] V_m   (coef on the device).  With nrm2 != nullptr
+// the weighted squared norm of the result is reduced into nrm2[0].
+void maxpy(stokes_ctx &c, double sign, const double *V, int nv, const double *coef, double *w,
+           double w2 = 1.0, double *nrm2 = nullptr) {
+    const long long n = c.vlen, pstart = (long long)c.dim * c.fine.stride;
     const unsigned g = nblocks_stream(n);
     for (int m0 = 0; m0 < nv; m0 += kGroup) {
         int cnt = std::min(kGroup, nv - m0);
-        k_maxpy<kGroup><<<g, kBlock, 0, c.stream>>>(n, sign, V + (size_t)m0 * c.vlen, c.vlen, cnt, coef + m0, w);
+        bool last = m0 + kGroup >= nv;
+        ProfScope ps(c, STOKES_PROF_MAXPY, (double)(cnt + 2) * c.unknowns * 8.0);
+        k_maxpy<kGroup><<<g, kBlock, 0, c.stream>>>(n, sign, V + (size_t)m0 * c.vlen, c.vlen, cnt, coef + m0, w,
+                                                    pstart, w2, (last && nrm2) ? c.partial : nullptr);
     }
+    if (nrm2) k_reduce_partials<<<1, kBlock, 0, c.stream>>>((int)g, c.partial, nrm2, 0);
 }
 
 void sync_read(stokes_ctx &c, const double *dsrc, double *hdst, int n) {
@@ -383,6 +499,10 @@ void sync_read(stokes_ctx &c, const double *dsrc, double *hdst, int n) {
 
 template <int DIM>
 void apply_fine(stokes_ctx &c, double *x, double *f, double *y) {
+    const double cells = (double)c.fine.nx * c.fine.ny * c.fine.nz;
+    // x: 4 unknown fields, coefficients: DIM mass + mu + edges; y: 4 fields; f: 4 more
+    const int nedge = DIM == 3 ? 3 : 1;
+    ProfScope ps(c, STOKES_PROF_MATVEC, cells * 8.0 * ((DIM + 1) * (f ? 3 : 2) + DIM + 1 + nedge));
     k_apply<DIM><<<nblocks_box(c.fine), kBlock, 0, c.stream>>>(
         c.fine, fine_coef(c), c.fld(x, 0), c.fld(x, 1), DIM == 3 ? c.fld(x, 2) : nullptr, c.fld(x, DIM),
         f ? c.fld(f, 0) : nullptr, f ? c.fld(f, 1) : nullptr, (f && DIM == 3) ? c.fld(f, 2) : nullptr,
@@ -444,16 +564,20 @@ stokes_status fgmres(stokes_ctx &c, MG<R> &mg, double tol, stokes_stats &st) {
             double *vj = c.vec(c.V, j), *zj = c.vec(c.Z, j), *w = c.vec(c.V, j + 1);
             precond<DIM, R>(c, mg, vj, zj);
             apply_fine<DIM>(c, zj, nullptr, w);
-            // classical Gram-Schmidt, twice
+            // classical Gram-Schmidt: one pass (orth 1) or two (orth 2); the last
+            // update pass also reduces the norm of the new vector
             multidot(c, c.V, j + 1, w, w2, dh);
-            maxpy(c, -1.0, c.V, j + 1, dh, w);
-            multidot(c, c.V, j + 1, w, w2, dh2);
-            maxpy(c, -1.0, c.V, j + 1, dh2, w);
-            multidot(c, w, 1, w, w2, dh2 + (j + 1));
+            if (c.opt.orth >= 2) {
+                maxpy(c, -1.0, c.V, j + 1, dh, w);
+                multidot(c, c.V, j + 1, w, w2, dh2);
+                maxpy(c, -1.0, c.V, j + 1, dh2, w, w2, dh2 + (j + 1));
+            } else {
+                maxpy(c, -1.0, c.V, j + 1, dh, w, w2, dh2 + (j + 1));
+            }
             HIPCHK(hipMemcpyAsync(hbuf.data(), dh, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, c.stream));
             HIPCHK(hipMemcpyAsync(hbuf.data() + (m + 2), dh2, sizeof(double) * (j + 2), hipMemcpyDeviceToHost, c.stream));
             HIPCHK(hipStreamSynchronize(c.stream));
-            for (int i = 0; i <= j; ++i) HH(i, j) = hbuf[i] + hbuf[m + 2 + i];
+            for (int i = 0; i <= j; ++i) HH(i, j) = hbuf[i] + (c.opt.orth >= 2 ? hbuf[m + 2 + i] : 0.0);
             double hn2 = hbuf[m + 2 + j + 1];
             if (!std::isfinite(hn2)) { c.err = "non-finite Arnoldi vector"; return STOKES_ENAN; }
             double hn = std::sqrt(std::max(hn2, 0.0));
@@ -637,6 +761,29 @@ __global__ void k_minmax(Box b, const double *__restrict__ m0, const double *__r
     }
 }
 
+// Largest ratio (viscous part of a momentum diagonal) / (its mass term rho/dt)
+// over the interior faces; per-block maxima in out[block].
+template <int DIM>
+__global__ void k_visc_ratio(Box b, VelCoef<double> c, double *__restrict__ out) {
+    __shared__ double sm[kBlock];
+    double mx = 0.0;
+    for (int idx = blockIdx.x * kBlock + threadIdx.x; idx < b.nb; idx += gridDim.x * kBlock) {
+        int i, j, k;
+        decompose(b, idx, i, j, k);
+        double off, dg;
+        if (is_ux(b, i, j, k)) { row_u<DIM, double>(b, idx, j, k, nullptr, nullptr, nullptr, 0, c, off, dg); mx = fmax(mx, dg / c.mass[0][idx] - 1.0); }
+        if (is_vy(b, i, j, k)) { row_v<DIM, double>(b, idx, i, k, nullptr, nullptr, nullptr, 0, c, off, dg); mx = fmax(mx, dg / c.mass[1][idx] - 1.0); }
+        if (DIM == 3 && is_wz(b, i, j, k)) { row_w<double>(b, idx, i, j, nullptr, nullptr, nullptr, 0, c, off, dg); mx = fmax(mx, dg / c.mass[2][idx] - 1.0); }
+    }
+    sm[threadIdx.x] = mx;
+    __syncthreads();
+    for (int o = kBlock / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + o]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = sm[0];
+}
+
 stokes_options defaults() {
     stokes_options o;
     o.precision = 0;
@@ -647,9 +794,13 @@ stokes_options defaults() {
     o.nu1 = 2;
     o.nu2 = 2;
     o.vel_cycles = 1;
-    o.p_cycles = 1;
+    o.p_cycles = 3;
     o.coarse_sweeps = 40;
     o.vel_levels = 0;
+    o.vel_sweeps = 1;
+    o.p_prolong = 1;
+    o.vel_smoother = 1;
+    o.orth = 2;
     return o;
 }
 
@@ -671,6 +822,10 @@ const char *check_grid_opts(const stokes_grid *g, const stokes_options &o) {
     if (o.vel_cycles < 0 || o.p_cycles < 1) return "vel_cycles >= 0 and p_cycles >= 1";
     if (o.coarse_sweeps < 1) return "coarse_sweeps must be >= 1";
     if (o.vel_levels < 0) return "vel_levels must be >= 0";
+    if (o.vel_sweeps < 1) return "vel_sweeps must be >= 1";
+    if (o.p_prolong != 0 && o.p_prolong != 1) return "p_prolong must be 0 or 1";
+    if (o.vel_smoother != 0 && o.vel_smoother != 1) return "vel_smoother must be 0 or 1";
+    if (o.orth != 1 && o.orth != 2) return "orth must be 1 or 2";
     return nullptr;
 }
 
@@ -683,6 +838,12 @@ void init_ctx_shape(stokes_ctx &c, const stokes_grid *g, const stokes_options &o
     c.theta = o.visc_scale;
     c.fine = make_box(g->dim, g->n[0], g->n[1], g->dim == 3 ? g->n[2] : 1, g->h[0], g->h[1],
                       g->dim == 3 ? g->h[2] : g->h[0]);
+    {
+        const Box &b = c.fine;
+        double nc = (double)b.nx * b.ny * b.nz;
+        c.unknowns = nc + (double)(b.nx - 1) * b.ny * b.nz + (double)b.nx * (b.ny - 1) * b.nz +
+                     (g->dim == 3 ? (double)b.nx * b.ny * (b.nz - 1) : 0.0);
+    }
 }
 
 template <int DIM>
@@ -704,8 +865,26 @@ stokes_status setup_impl(stokes_ctx &c, const double *const rho[3], const double
         return STOKES_EINVAL;
     }
     k_edge_mu<DIM, double><<<gb, kBlock, 0, c.stream>>>(b, c.mu, c.mxy, c.mxz, c.myz);
+    if (c.opt.vel_levels == 0) {
+        // automatic velocity hierarchy: smoother only when the operator is mass dominated
+        const int nbk = 256;
+        k_visc_ratio<DIM><<<nbk, kBlock, 0, c.stream>>>(b, fine_coef(c), c.partial);
+        std::vector<double> h(nbk);
+        HIPCHK(hipMemcpyAsync(h.data(), c.partial, sizeof(double) * nbk, hipMemcpyDeviceToHost, c.stream));
+        HIPCHK(hipStreamSynchronize(c.stream));
+        c.visc_ratio = *std::max_element(h.begin(), h.end());
+        int nl = c.opt.precision == 1 ? c.mgf.nlev : c.mgd.nlev;
+        int nv = c.visc_ratio < 1e-2 ? 1 : nl;
+        c.mgf.nvlev = c.opt.precision == 1 ? nv : 0;
+        c.mgd.nvlev = c.opt.precision == 1 ? 0 : nv;
+    }
     if (c.opt.precision == 1) build_hierarchy<DIM, float>(c, c.mgf, true);
     else build_hierarchy<DIM, double>(c, c.mgd, false);
+    k_vel_inv_diag<DIM><<<gb, kBlock, 0, c.stream>>>(b, fine_coef(c), c.dinv[0], c.dinv[1], DIM == 3 ? c.dinv[2] : c.dinv[1]);
+    {
+        int nv = c.opt.precision == 1 ? c.mgf.nvlev : c.mgd.nvlev;
+        c.diag_vel = c.opt.vel_smoother == 1 && nv == 1 && c.opt.vel_sweeps == 1 && c.opt.vel_cycles == 1;
+    }
     // continuity weight
     if (c.opt.cont_scale > 0.0) {
         c.sigma = c.opt.cont_scale;
@@ -754,7 +933,7 @@ stokes_status solve_impl(stokes_ctx &c, const double *const rhs_u[3], const doub
     c.vcycles = 0;
     pack_vector<DIM>(c, rhs_u, rhs_p, c.bk);
     k_fill<int><<<1, kBlock, 0, c.stream>>>(1, c.dflag, 0);
-    k_check_finite<<<nblocks_stream(c.vlen), kBlock, 0, c.stream>>>(c.vlen, c.bk - c.fine.guard, c.dflag);
+    k_check_finite<<<nblocks_stream(c.vlen), kBlock, 0, c.stream>>>(c.vlen, c.bk, c.dflag);
     int flag = 0;
     // mean of rhs_p
     {
@@ -771,7 +950,7 @@ stokes_status solve_impl(stokes_ctx &c, const double *const rhs_u[3], const doub
     }
     pack_vector<DIM>(c, x_u, x_p, c.xk);
     k_fill<int><<<1, kBlock, 0, c.stream>>>(1, c.dflag, 0);
-    k_check_finite<<<nblocks_stream(c.vlen), kBlock, 0, c.stream>>>(c.vlen, c.xk - c.fine.guard, c.dflag);
+    k_check_finite<<<nblocks_stream(c.vlen), kBlock, 0, c.stream>>>(c.vlen, c.xk, c.dflag);
     HIPCHK(hipMemcpyAsync(&flag, c.dflag, sizeof(int), hipMemcpyDeviceToHost, c.stream));
     HIPCHK(hipStreamSynchronize(c.stream));
     if (flag) { c.err = "non-finite initial guess"; return STOKES_ENAN; }
@@ -786,11 +965,11 @@ stokes_status solve_impl(stokes_ctx &c, const double *const rhs_u[3], const doub
     {
         const long long nvel = (long long)DIM * c.fine.stride;
         const unsigned g1 = nblocks_stream(nvel), g2 = nblocks_stream(c.fine.stride), g3 = nblocks_stream(c.vlen);
-        k_partial_sum<<<g1, kBlock, 0, c.stream>>>(nvel, v0 - c.fine.guard, 1, c.partial);
+        k_partial_sum<<<g1, kBlock, 0, c.stream>>>(nvel, v0, 1, c.partial);
         k_reduce_partials<<<1, kBlock, 0, c.stream>>>((int)g1, c.partial, c.dsc, 0);
         k_partial_sum<<<g2, kBlock, 0, c.stream>>>(c.fine.stride, c.fld(v0, DIM) - c.fine.guard, 1, c.partial);
         k_reduce_partials<<<1, kBlock, 0, c.stream>>>((int)g2, c.partial, c.dsc + 1, 0);
-        k_partial_sum<<<g3, kBlock, 0, c.stream>>>(c.vlen, c.bk - c.fine.guard, 1, c.partial);
+        k_partial_sum<<<g3, kBlock, 0, c.stream>>>(c.vlen, c.bk, 1, c.partial);
         k_reduce_partials<<<1, kBlock, 0, c.stream>>>((int)g3, c.partial, c.dsc + 2, 0);
         double h3[3];
         sync_read(c, c.dsc, h3, 3);
@@ -804,6 +983,7 @@ stokes_status solve_impl(stokes_ctx &c, const double *const rhs_u[3], const doub
     unpack_vector<DIM>(c, c.xk, x_u, x_p);
     HIPCHK(hipStreamSynchronize(c.stream));
     HIPCHK(hipGetLastError());
+    prof_collect(c);
     return s;
 }
 
@@ -940,6 +1120,38 @@ stokes_status stokes_solve(stokes_ctx *ctx, const double *const rhs_u[3], const 
     st.sigma = ctx->sigma;
     if (stats) *stats = st;
     return s;
+}
+
+stokes_status stokes_profile_kernel(stokes_ctx *ctx, int kernel) {
+    if (!ctx) return STOKES_EINVAL;
+    if (kernel < -1 || kernel > STOKES_PROF_MAXPY) {
+        ctx->err = "unknown kernel class";
+        return STOKES_EINVAL;
+    }
+    try {
+        if (kernel >= 0 && ctx->ev.empty()) {
+            ctx->ev.resize(8192);
+            for (auto &e : ctx->ev) HIPCHK(hipEventCreate(&e));
+        }
+    } catch (const HipError &e) {
+        ctx->err = std::string("HIP error in ") + e.what + ": " + hipGetErrorString(e.e);
+        return STOKES_EHIP;
+    }
+    ctx->prof_kind = kernel;
+    ctx->ev_used = 0;
+    ctx->prof_ms = ctx->prof_bytes = 0.0;
+    ctx->prof_launches = 0;
+    return STOKES_OK;
+}
+
+stokes_status stokes_profile_read(stokes_ctx *ctx, double *ms_total, long long *launches, double *bytes) {
+    if (!ctx) return STOKES_EINVAL;
+    if (ms_total) *ms_total = ctx->prof_ms;
+    if (launches) *launches = ctx->prof_launches;
+    if (bytes) *bytes = ctx->prof_bytes;
+    ctx->prof_ms = ctx->prof_bytes = 0.0;
+    ctx->prof_launches = 0;
+    return STOKES_OK;
 }
 
 void stokes_destroy(stokes_ctx *ctx) { delete ctx; }

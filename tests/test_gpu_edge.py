@@ -120,3 +120,59 @@ def test_well_balanced_still_tank():
     xu, xp, st, stats = gpu_solve(prob, tol=1e-13)
     assert st == 0
     assert max(np.abs(xu[0]).max(), np.abs(xu[1]).max()) / (abs(g) * prob.dt) <= 1e-9
+
+
+@pytest.mark.parametrize("opts", [dict(vel_levels=99, vel_smoother=0),
+                                  dict(vel_levels=1, vel_sweeps=2, vel_smoother=0),
+                                  dict(orth=1, p_cycles=2, p_prolong=0),
+                                  dict(nu1=0, nu2=2, vel_levels=99, vel_smoother=0),
+                                  dict(nu1=3, nu2=0, vel_levels=99, vel_smoother=0)])
+@pytest.mark.parametrize("maker", [lambda: W.config1(), lambda: W.config3(scale=4)])
+def test_solver_variants_match_direct_or_oracle(oracle_lib, opts, maker):
+    """Every multigrid/Krylov variant reaches the same solution: full velocity
+    hierarchy, multi-sweep single level, one-pass Gram-Schmidt, constant
+    prolongation, pre- or post-smoothing only."""
+    prob = maker()
+    if prob.dim == 2:
+        sys = A.from_problem(prob)
+        ru, rp = D.solve_problem(prob, sys)
+    else:
+        ru, rp, info = oracle_lib.solve_problem(prob, tol=1e-13, max_iters=300)
+    xu, xp, st, stats = gpu_solve(prob, tol=1e-12, max_iters=400, **opts)
+    assert st == 0 or (st == 1 and stats.rel_res_true <= 1e-11), stats.as_dict()
+    for c in range(prob.dim):
+        assert rel(xu[c], ru[c]) <= 1e-8
+    assert rel(xp - xp.mean(), rp - rp.mean()) <= 1e-8
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_viscous_dominated_uses_velocity_multigrid(precision):
+    """dt = 100: the viscous part dominates the mass term, the automatic rule
+    keeps the full velocity hierarchy, and the solve still matches the direct one."""
+    prob = W.config1()
+    prob.dt = 100.0
+    sys = A.from_problem(prob)
+    ru, rp = D.solve_problem(prob, sys)
+    xu, xp, st, stats = gpu_solve(prob, tol=1e-12, max_iters=400, precision=precision)
+    assert st == 0 or (st == 1 and stats.rel_res_true <= 1e-11), stats.as_dict()
+    tol = 1e-8 if precision == 0 else 1e-7
+    for c in range(2):
+        assert rel(xu[c], ru[c]) <= tol
+    assert rel(xp - xp.mean(), rp - rp.mean()) <= tol
+
+
+@pytest.mark.parametrize("maker", [lambda: W.config2(scale=2), lambda: W.config3(scale=2),
+                                   lambda: W.config4(scale=4)])
+def test_fp32_multigrid_reaches_fp64_residual(oracle_lib, maker):
+    """Multigrid in FP32 inside FP64 FGMRES: the recomputed FP64 residual meets tol
+    (1e-8); the error against the FP64 oracle is printed for the record."""
+    prob = maker()
+    xu, xp, st, stats = gpu_solve(prob, precision=1)
+    assert st == 0 and stats.rel_res_true <= prob.tol, stats.as_dict()
+    if prob.dim == 2:
+        ru, rp = D.solve_problem(prob, A.from_problem(prob))
+    else:
+        ru, rp, _ = oracle_lib.solve_problem(prob, tol=1e-12, max_iters=300)
+    errs = [rel(xu[c], ru[c]) for c in range(prob.dim)] + [rel(xp - xp.mean(), rp - rp.mean())]
+    print("fp32-mg", prob.name, "iters", stats.iters, "rel errors vs oracle", ["%.1e" % e for e in errs])
+    assert max(errs) <= 1e-5
