@@ -4,7 +4,10 @@
 One step = one full stokes_solve (FGMRES + projection preconditioner + multigrid)
 of the seeded 256^3 air/water/solid workload (eval seed 900000) with inputs
 resident in HBM; setup (coefficients, hierarchy) is timed separately.  Prints
-one JSON line.
+one JSON line with a "roofline" object for the dominant kernel (the fused
+finest-level pressure sweep, timed live with HIP events inside the library on
+the solve's stream) and a "cpu_baseline" object (the C oracle on this host's
+cores, on a bounded sample of the same workload).
 """
 from __future__ import annotations
 
@@ -30,6 +33,12 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--opt", action="append", default=[],
                     help="solver option override key=value (fields of stokes_options)")
+    ap.add_argument("--prof-kernel", type=int, default=1,
+                    help="kernel class timed for the roofline (0 matvec, 1 pressure sweep, 2 multidot, 3 maxpy)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run a plain 1 GiB device copy (reference for HBM counter runs)")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the FP32-multigrid form timed after the plain FP64 solve")
     ap.add_argument("--verbose", action="store_true")
     return ap.parse_args()
 
@@ -48,6 +57,15 @@ def main():
     import workloads as W
     import paper_1901_07892_amd as S
 
+    if args.calibrate_copy:
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log("calibration copy: 3 x 1 GiB read + 1 GiB write")
+        del a, b
     t0 = time.time()
     prob = W.config5(n_cells=args.n)
     log("workload %s generated in %.1fs; solids: %d" % (prob.name, time.time() - t0, len(prob.solids)))
@@ -84,6 +102,7 @@ def main():
         stats = step()
         log("warmup %d: iters %d res %.3e ms %.2f" % (w, stats.iters, stats.rel_res_true, stats.ms_total))
     torch.cuda.synchronize()
+    S.stokes_profile_kernel(solver.ctx, args.prof_kernel)
     times = []
     iters = []
     t_all0 = time.perf_counter()
@@ -98,6 +117,17 @@ def main():
     total_ms = (time.perf_counter() - t_all0) * 1e3
     ms = total_ms / args.steps
     n_cells = prob.n_cells
+    kms, klaunch, kbytes = S.stokes_profile_read(solver.ctx)
+    S.stokes_profile_kernel(solver.ctx, -1)
+    names = {0: "k_apply (matvec)", 1: "k_p_sweep3 (fused pressure RB-GS sweep, finest level)",
+             2: "k_multidot", 3: "k_maxpy"}
+    achieved = kbytes / (kms * 1e-3) / 1e9 if kms > 0 else None
+    roofline = {"bound": "hbm", "kernel": names.get(args.prof_kernel),
+                "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
+                "frac": achieved / 8000.0 if achieved else None,
+                "traffic": traffic_per_launch(args.prof_kernel, args.n, args.precision),
+                "launches": klaunch, "avg_launch_us": kms * 1e3 / max(klaunch, 1),
+                "algorithmic_bytes_per_launch": kbytes / max(klaunch, 1)}
     out = {
         "metric": "ms per Stokes solve to 1e-8 rel. residual, 256^3 rho-ratio 1000",
         "value": ms,
@@ -122,9 +152,94 @@ def main():
         "rel_res_true": stats.rel_res_true,
         "rel_res_plain": stats.rel_res_plain,
         "vcycles": stats.vcycles,
+        "roofline": roofline,
     }
     solver.close()
+    del solver
+    if not args.no_forms and args.precision == 0:
+        out["forms"] = {"fp32_multigrid": fp32_form(S, prob, rho, mu, rhs_u, rhs_p, xu, xp, overrides,
+                                                    ms, args.steps)}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(prob, int(np.median(iters)))
     print(json.dumps(out), flush=True)
+
+
+def fp32_form(S, prob, rho, mu, rhs_u, rhs_p, xu64, xp64, overrides, ms64, steps):
+    """Multigrid in FP32 inside FP64 FGMRES on the same workload: ms per solve, its
+    FP64 residual, speedup over the plain FP64 solve and the relative difference of
+    each field from the FP64 solution (both converged to the same tolerance)."""
+    import torch
+    ref_u = [a.clone() for a in xu64]
+    ref_p = xp64.clone()
+    o = dict(overrides)
+    o["precision"] = 1
+    solver = S.StokesSolver(3, prob.n, prob.h, rho, mu, prob.dt, **o)
+    xu = [torch.zeros_like(a) for a in ref_u]
+    xp = torch.zeros_like(ref_p)
+    times = []
+    for s in range(steps + 2):
+        for a in xu:
+            a.zero_()
+        xp.zero_()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        st, stats = solver.solve(rhs_u, rhs_p, prob.tol, xu, xp)
+        torch.cuda.synchronize()
+        if s >= 2:
+            times.append((time.perf_counter() - t) * 1e3)
+        if st != 0:
+            raise RuntimeError("fp32-multigrid solve did not converge: %s" % stats.as_dict())
+    solver.close()
+    diff = [float(torch.linalg.vector_norm(xu[c] - ref_u[c]) / torch.linalg.vector_norm(ref_u[c])) for c in range(3)]
+    diff.append(float(torch.linalg.vector_norm(xp - ref_p) / torch.linalg.vector_norm(ref_p)))
+    ms = float(np.mean(times))
+    log("fp32-multigrid form: %.2f ms, %d iterations, residual %.2e" % (ms, stats.iters, stats.rel_res_true))
+    return {"ms_per_solve": ms, "fgmres_iters": stats.iters, "rel_res_true": stats.rel_res_true,
+            "speedup_vs_fp64": ms64 / ms, "rel_diff_vs_fp64_solution": diff}
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("paper_1901_07892_amd/csrc/kernels.hpp", "paper_1901_07892_amd/csrc/box.hpp"):
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_per_launch(kernel, n, precision):
+    """HBM bytes per launch of the timed kernel from rocprofv3 FETCH_SIZE + WRITE_SIZE
+    counter runs (profiles/traffic.json), or None when absent or taken on other
+    kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+    except ValueError:
+        return None
+    key = "%d/%d/%d" % (kernel, n, precision)
+    e = rec.get("entries", {}).get(key)
+    if not e or e.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def cpu_baseline(prob, gpu_iters):
+    """The C oracle (OpenMP) on this host, bounded: setup plus ONE FGMRES iteration
+    on the same workload; ms/solve = setup + that iteration's time x the GPU solve's
+    iteration count (both use three pressure V-cycles per preconditioner step)."""
+    from oracle import native
+    t0 = time.time()
+    xu, xp, info = native.solve_problem(prob, max_iters=1, restart=1, p_cycles=3)
+    wall = time.time() - t0
+    per_iter = info["solve_s"] / max(info["iters"], 1)
+    value = (info["setup_s"] + per_iter * gpu_iters) * 1e3
+    log("cpu baseline: setup %.1fs, 1 iteration %.1fs (wall %.1fs)" % (info["setup_s"], info["solve_s"], wall))
+    return {"value": value, "unit": "ms/solve", "cores": native.num_threads(), "kind": "oracle",
+            "sample": "C oracle (FP64, OpenMP for matvec/BLAS, lexicographic Gauss-Seidel multigrid) "
+                      "on the same %s workload: setup plus 1 FGMRES iteration (%.1f s), scaled to "
+                      "the GPU solve's %d iterations" % (prob.name, info["solve_s"], gpu_iters),
+            "measured_s": wall}
 
 
 if __name__ == "__main__":

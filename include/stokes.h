@@ -87,7 +87,11 @@ typedef struct {
                             single level with one sweep and one cycle, that sweep is a point
                             Jacobi (diagonal) step folded into the projection kernels;
                             otherwise red-black Gauss-Seidel is used */
-    int orth;            /* Arnoldi orthogonalisation: 1 classical Gram-Schmidt, 2 twice */
+    int orth;            /* Arnoldi orthogonalisation: 1 classical Gram-Schmidt (default; the
+                            residual is always recomputed before returning, so a loss of
+                            orthogonality can only cost iterations), 2 twice */
+    int matvec_z;        /* 3D matvec kernel: 1 z-marching (register reuse along z), 0 one
+                            thread per point; same result to rounding */
 } stokes_options;
 
 typedef struct {
@@ -110,8 +114,9 @@ typedef struct stokes_ctx stokes_ctx;
 
 /* Fill *opts with the defaults (FP64, theta 1, automatic sigma, restart 30,
  * max_iters 200, V(2,2), one velocity and three pressure cycles, 40 coarse sweeps,
- * automatic velocity levels, 1 single-level velocity sweep, trilinear pressure
- * prolongation). */
+ * automatic velocity levels, 1 single-level velocity sweep, piecewise-constant
+ * pressure prolongation, diagonal velocity step, one-pass Gram-Schmidt, z-marching
+ * matvec). */
 void stokes_default_options(stokes_options *opts);
 
 /* Bytes of device workspace that stokes_setup needs for this grid and these

@@ -110,14 +110,14 @@ def solve(dim, n, h, dt, theta, rho_faces, mu, fu, fp, tol, x0u=None, x0p=None,
     ni, hd = _grid_args(dim, n, h)
     oa = (C.c_int * 7)(o["restart"], o["max_iters"], o["nu1"], o["nu2"], o["vel_cycles"],
                        o["p_cycles"], o["coarse_sweeps"])
-    out = np.zeros(8)
+    out = np.zeros(10)
     rc = lib().oracle_solve(dim, ni, hd, dt, theta, _parr(rho), _dp(mu), _parr(fs), tol, oa,
                             float(cont_scale), _parr(xs), _dp(out))
     if rc != 0:
         raise ValueError("oracle_solve failed")
     info = dict(iters=int(out[0]), restarts=int(out[1]), status=int(out[2]),
                 rel_res_est=out[3], rel_res_true=out[4], g_mean=out[5], levels=int(out[6]),
-                sigma=out[7])
+                sigma=out[7], setup_s=out[8], solve_s=out[9])
     return xs[:3], xs[3], info
 
 

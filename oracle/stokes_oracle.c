@@ -28,10 +28,12 @@
  * Layout: C order, x fastest. u (nz,ny,nx+1), v (nz,ny+1,nx), w (nz+1,ny,nx),
  * p and mu (nz,ny,nx).  2D: nz = 1, no w.
  */
+#define _POSIX_C_SOURCE 199309L
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
 #include <stdio.h>
+#include <time.h>
 #ifdef _OPENMP
 #include <omp.h>
 #endif
@@ -858,6 +860,12 @@ done:
 }
 
 /* ------------------------------------------------------ exported API */
+static double wall_seconds(void) {
+    struct timespec ts;
+    clock_gettime(CLOCK_MONOTONIC, &ts);
+    return ts.tv_sec + 1e-9 * ts.tv_nsec;
+}
+
 static int make_grid(Grid *g, int dim, const int *n, const double *h) {
     if (dim != 2 && dim != 3) return -1;
     g->dim = dim;
@@ -894,12 +902,14 @@ int oracle_apply(int dim, const int *n, const double *h, double dt, double theta
  * sigma; 0 picks auto_sigma; 1 is the plain 2-norm).  x holds the initial guess
  * on entry and the solution on exit (zero-mean p).  opts: restart, max_iters,
  * nu1, nu2, vel_cycles, p_cycles, coarse_sweeps.  out: iters, restarts, status,
- * rel_res_est, rel_res_true, mean removed from g, levels, sigma. */
+ * rel_res_est, rel_res_true, mean removed from g, levels, sigma, setup seconds,
+ * FGMRES seconds (out needs 10 entries). */
 int oracle_solve(int dim, const int *n, const double *h, double dt, double theta,
                  double *const rho[3], const double *mu, double *const f[4], double tol,
                  const int *opts, double cont_scale, double *const x[4], double *out) {
     Grid g;
     if (make_grid(&g, dim, n, h)) return -1;
+    double t0 = wall_seconds();
     Hier *H = calloc(1, sizeof(Hier));
     H->dt = dt; H->theta = theta;
     H->nu1 = opts[2]; H->nu2 = opts[3];
@@ -931,7 +941,9 @@ int oracle_solve(int dim, const int *n, const double *h, double dt, double theta
     SolveInfo info;
     memset(&info, 0, sizeof(info));
     double sigma = cont_scale > 0.0 ? cont_scale : auto_sigma(F, dt, theta);
+    double t1 = wall_seconds();
     fgmres(H, &b, &xv, tol, opts[0], opts[1], sigma * sigma, &info);
+    double t2 = wall_seconds();
     for (int c = 0; c < 4; ++c) {
         long m = vlen(F, c);
         if (m == 0) continue;
@@ -940,6 +952,8 @@ int oracle_solve(int dim, const int *n, const double *h, double dt, double theta
     out[0] = info.iters; out[1] = info.restarts; out[2] = info.status;
     out[3] = info.rel_res_est; out[4] = info.rel_res_true; out[5] = gm; out[6] = H->nlev;
     out[7] = sigma;
+    out[8] = t1 - t0;      /* setup seconds (hierarchy, copies) */
+    out[9] = t2 - t1;      /* FGMRES seconds */
     vfree(&b); vfree(&xv);
     hier_free(H);
     free(H);

@@ -14,6 +14,21 @@ namespace stk {
 
 constexpr int kBlock = 256;
 
+// Workgroups are dealt to the 8 XCDs round-robin by workgroup id, and each XCD
+// has its own L2.  This bijection of [0, G) gives XCD x a contiguous range of
+// about G/8 logical blocks, so that neighbouring tiles (and their stencil
+// halos) share one L2.
+__device__ inline int xcd_swizzle(int b, int G) {
+    const int q = G >> 3, r = G & 7;
+    const int x = b & 7, local = b >> 3;
+    return x < r ? x * (q + 1) + local : r * (q + 1) + (x - r) * q + local;
+}
+
+// Box point handled by this thread of a flat launch of nblocks_box() blocks.
+__device__ inline int box_thread_index() {
+    return xcd_swizzle(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+}
+
 __device__ inline void decompose(const Box &b, int idx, int &i, int &j, int &k) {
     i = idx % b.px;
     int t = idx / b.px;
@@ -149,7 +164,7 @@ __global__ void __launch_bounds__(kBlock) k_apply(Box b, VelCoef<double> c,
         const double *__restrict__ fw, const double *__restrict__ fp,
         double *__restrict__ yu, double *__restrict__ yv,
         double *__restrict__ yw, double *__restrict__ yp) {
-    int idx = blockIdx.x * kBlock + threadIdx.x;
+    int idx = box_thread_index();
     if (idx >= b.nb) return;
     int i, j, k;
     decompose(b, idx, i, j, k);
@@ -189,6 +204,98 @@ __global__ void __launch_bounds__(kBlock) k_apply(Box b, VelCoef<double> c,
     yp[idx] = r;
 }
 
+// 3D y = K x (or f - K x) marching in z: a block owns a TX x TY tile of cells
+// and a chunk of kc planes; each thread walks its column and keeps the centre
+// values that the next planes need (u, v, w, p, mu and the xz/yz edge viscosity
+// at k-1, k, k+1) in registers, so every value is fetched from HBM about once;
+// in-plane neighbours are read back from cache.  Only unknown positions
+// (i < nx, j < ny, k < nz) are visited: the padding and wall-normal slots of y
+// hold zero already and are not written.  Same row formulas as k_apply.
+template <int TX, int TY>
+__global__ void __launch_bounds__(TX *TY) k_apply3_z(Box b, int kc, VelCoef<double> c,
+        const double *__restrict__ xu, const double *__restrict__ xv,
+        const double *__restrict__ xw, const double *__restrict__ xp,
+        const double *__restrict__ fu, const double *__restrict__ fv,
+        const double *__restrict__ fw, const double *__restrict__ fp,
+        double *__restrict__ yu, double *__restrict__ yv,
+        double *__restrict__ yw, double *__restrict__ yp) {
+    const int G = gridDim.x * gridDim.y * gridDim.z;
+    int t = xcd_swizzle(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z), G);
+    const int bx_ = t % gridDim.x;
+    t /= gridDim.x;
+    const int by_ = t % gridDim.y, bz_ = t / gridDim.y;
+    const int i = bx_ * TX + (int)(threadIdx.x % TX), j = by_ * TY + (int)(threadIdx.x / TX);
+    if (i >= b.nx || j >= b.ny) return;
+    const int k0 = bz_ * kc, k1 = min(k0 + kc, b.nz);
+    const int sy = b.px, sz = b.plane;
+    const double ihx = b.ihx, ihy = b.ihy, ihz = b.ihz, th = c.theta;
+    const bool ux = i >= 1, vy = j >= 1;
+    const double gE = i + 1 < b.nx ? 1.0 : 2.0, gW = i > 0 ? 1.0 : 2.0;
+    const double gN = j + 1 < b.ny ? 1.0 : 2.0, gS = j > 0 ? 1.0 : 2.0;
+    int idx = box_index(b, i, j, k0);
+    // centre values at k-1 and k (the guard plane below k = 0 holds zeros)
+    double U0 = xu[idx - sz], U1 = xu[idx], V0 = xv[idx - sz], V1 = xv[idx], W0 = xw[idx - sz], W1 = xw[idx];
+    double P0 = xp[idx - sz], M0 = c.mu[idx - sz], XZ1 = c.mxz[idx], YZ1 = c.myz[idx];
+    for (int k = k0; k < k1; ++k, idx += sz) {
+        const double U2 = xu[idx + sz], V2 = xv[idx + sz], W2 = xw[idx + sz];
+        const double XZ2 = c.mxz[idx + sz], YZ2 = c.myz[idx + sz];
+        const double P1 = xp[idx], M1 = c.mu[idx];
+        const bool top = k + 1 < b.nz, bot = k > 0;
+        const double gT = top ? 1.0 : 2.0, gB = bot ? 1.0 : 2.0;
+        // x-momentum
+        if (ux) {
+            const double uE = xu[idx + 1], uW = xu[idx - 1];
+            const double uN = j + 1 < b.ny ? xu[idx + sy] : 0.0, uS = j > 0 ? xu[idx - sy] : 0.0;
+            const double uT = top ? U2 : 0.0, uB = bot ? U0 : 0.0;
+            const double m0 = c.mu[idx - 1], mN = c.mxy[idx + sy], mS = c.mxy[idx];
+            const double dvN = xv[idx + sy] - xv[idx + sy - 1], dvS = V1 - xv[idx - 1];
+            const double dwT = W2 - xw[idx + sz - 1], dwB = W1 - xw[idx - 1];
+            double lap = 2.0 * (M1 * uE + m0 * uW) * ihx * ihx
+                       + (mN * (uN * ihy + dvN * ihx) - mS * (-uS * ihy + dvS * ihx)) * ihy
+                       + (XZ2 * (uT * ihz + dwT * ihx) - XZ1 * (-uB * ihz + dwB * ihx)) * ihz;
+            double dg = 2.0 * (m0 + M1) * ihx * ihx + (mN * gN + mS * gS) * ihy * ihy + (XZ2 * gT + XZ1 * gB) * ihz * ihz;
+            double r = (c.mass[0][idx] + th * dg) * U1 - th * lap + (P1 - xp[idx - 1]) * ihx;
+            yu[idx] = fu ? fu[idx] - r : r;
+        }
+        // y-momentum
+        if (vy) {
+            const double vN = xv[idx + sy], vS = xv[idx - sy];
+            const double vE = i + 1 < b.nx ? xv[idx + 1] : 0.0, vW = i > 0 ? xv[idx - 1] : 0.0;
+            const double vT = top ? V2 : 0.0, vB = bot ? V0 : 0.0;
+            const double m0 = c.mu[idx - sy], mE = c.mxy[idx + 1], mW = c.mxy[idx];
+            const double duE = xu[idx + 1] - xu[idx + 1 - sy], duW = U1 - xu[idx - sy];
+            const double dwT = W2 - xw[idx + sz - sy], dwB = W1 - xw[idx - sy];
+            double lap = 2.0 * (M1 * vN + m0 * vS) * ihy * ihy
+                       + (mE * (vE * ihx + duE * ihy) - mW * (-vW * ihx + duW * ihy)) * ihx
+                       + (YZ2 * (vT * ihz + dwT * ihy) - YZ1 * (-vB * ihz + dwB * ihy)) * ihz;
+            double dg = 2.0 * (m0 + M1) * ihy * ihy + (mE * gE + mW * gW) * ihx * ihx + (YZ2 * gT + YZ1 * gB) * ihz * ihz;
+            double r = (c.mass[1][idx] + th * dg) * V1 - th * lap + (P1 - xp[idx - sy]) * ihy;
+            yv[idx] = fv ? fv[idx] - r : r;
+        }
+        // z-momentum
+        if (bot) {
+            const double wE = i + 1 < b.nx ? xw[idx + 1] : 0.0, wW = i > 0 ? xw[idx - 1] : 0.0;
+            const double wN = j + 1 < b.ny ? xw[idx + sy] : 0.0, wS = j > 0 ? xw[idx - sy] : 0.0;
+            const double mE = c.mxz[idx + 1], mN = c.myz[idx + sy];
+            const double duE = xu[idx + 1] - xu[idx + 1 - sz], duW = U1 - U0;
+            const double dvN = xv[idx + sy] - xv[idx + sy - sz], dvS = V1 - V0;
+            double lap = 2.0 * (M1 * W2 + M0 * W0) * ihz * ihz
+                       + (mE * (wE * ihx + duE * ihz) - XZ1 * (-wW * ihx + duW * ihz)) * ihx
+                       + (mN * (wN * ihy + dvN * ihz) - YZ1 * (-wS * ihy + dvS * ihz)) * ihy;
+            double dg = 2.0 * (M0 + M1) * ihz * ihz + (mE * gE + XZ1 * gW) * ihx * ihx + (mN * gN + YZ1 * gS) * ihy * ihy;
+            double r = (c.mass[2][idx] + th * dg) * W1 - th * lap + (P1 - P0) * ihz;
+            yw[idx] = fw ? fw[idx] - r : r;
+        }
+        // continuity
+        {
+            double d = (xu[idx + 1] - U1) * ihx + (xv[idx + sy] - V1) * ihy + (W2 - W1) * ihz;
+            yp[idx] = fp ? fp[idx] + d : -d;
+        }
+        U0 = U1; U1 = U2; V0 = V1; V1 = V2; W0 = W1; W1 = W2;
+        P0 = P1; M0 = M1; XZ1 = XZ2; YZ1 = YZ2;
+    }
+}
+
 // ---------------------------------------------------------------- velocity multigrid
 // t = r - A e on interior faces (0 elsewhere), all components.
 template <int DIM, class R>
@@ -196,7 +303,7 @@ __global__ void __launch_bounds__(kBlock) k_vel_residual(Box b, VelCoef<R> c,
         const R *__restrict__ eu, const R *__restrict__ ev, const R *__restrict__ ew,
         const R *__restrict__ ru, const R *__restrict__ rv, const R *__restrict__ rw,
         R *__restrict__ tu, R *__restrict__ tv, R *__restrict__ tw) {
-    int idx = blockIdx.x * kBlock + threadIdx.x;
+    int idx = box_thread_index();
     if (idx >= b.nb) return;
     int i, j, k;
     decompose(b, idx, i, j, k);
@@ -220,7 +327,7 @@ __global__ void __launch_bounds__(kBlock) k_vel_residual(Box b, VelCoef<R> c,
 template <int DIM, class R>
 __global__ void __launch_bounds__(kBlock) k_vel_gs(Box b, VelCoef<R> c, int comp, int colour, int valid,
         R *eu, R *ev, R *ew, const R *__restrict__ ru, const R *__restrict__ rv, const R *__restrict__ rw) {
-    int idx = blockIdx.x * kBlock + threadIdx.x;
+    int idx = box_thread_index();
     if (idx >= b.nb) return;
     int i, j, k;
     decompose(b, idx, i, j, k);
@@ -247,7 +354,7 @@ __global__ void __launch_bounds__(kBlock) k_vel_gs(Box b, VelCoef<R> c, int comp
 template <int DIM, class R>
 __global__ void __launch_bounds__(kBlock) k_face_restrict(Box fb, Box cb, int comp,
         const R *__restrict__ f, R *__restrict__ c) {
-    int idx = blockIdx.x * kBlock + threadIdx.x;
+    int idx = box_thread_index();
     if (idx >= cb.nb) return;
     int I, J, K;
     decompose(cb, idx, I, J, K);
@@ -273,7 +380,7 @@ __global__ void __launch_bounds__(kBlock) k_face_restrict(Box fb, Box cb, int co
 template <int DIM, class R>
 __global__ void __launch_bounds__(kBlock) k_face_prolong_add(Box fb, Box cb, int comp,
         const R *__restrict__ c, R *__restrict__ f) {
-    int idx = blockIdx.x * kBlock + threadIdx.x;
+    int idx = box_thread_index();
     if (idx >= fb.nb) return;
     int i, j, k;
     decompose(fb, idx, i, j, k);
@@ -315,7 +422,7 @@ template <int DIM, class R>
 __global__ void __launch_bounds__(kBlock) k_p_gs(Box b, int colour, int zero_guess, R *e,
         const R *__restrict__ r, const R *__restrict__ bx, const R *__restrict__ by,
         const R *__restrict__ bz) {
-    int idx = blockIdx.x * kBlock + threadIdx.x;
+    int idx = box_thread_index();
     if (idx >= b.nb) return;
     int i, j, k;
     decompose(b, idx, i, j, k);
@@ -332,7 +439,7 @@ template <int DIM, class R>
 __global__ void __launch_bounds__(kBlock) k_p_residual_restrict(Box fb, Box cb, const R *__restrict__ e,
         const R *__restrict__ r, const R *__restrict__ bx, const R *__restrict__ by,
         const R *__restrict__ bz, R *__restrict__ rc) {
-    int idx = blockIdx.x * kBlock + threadIdx.x;
+    int idx = box_thread_index();
     if (idx >= cb.nb) return;
     int I, J, K;
     decompose(cb, idx, I, J, K);
@@ -380,7 +487,7 @@ __device__ inline R prolong_value(const Box &cb, const R *ec, int i, int j, int 
 template <int DIM, class R>
 __global__ void __launch_bounds__(kBlock) k_p_prolong_add(Box fb, Box cb, int lin, const R *__restrict__ c,
         R *__restrict__ f) {
-    int idx = blockIdx.x * kBlock + threadIdx.x;
+    int idx = box_thread_index();
     if (idx >= fb.nb) return;
     int i, j, k;
     decompose(fb, idx, i, j, k);
@@ -406,7 +513,143 @@ __global__ void __launch_bounds__(1024) k_dense_solve(int n, const R *__restrict
 }
 
 // One full red-black Gauss-Seidel sweep of -L_rho e = r in 3D, both colours in
-// one launch.  A block owns a TX x TY column of cells and a chunk of KC planes,
+// one launch.  A block owns a TX x TY column of cells and a chunk of kc planes
+// and marches in z.  LDS holds rings of four planes: the old values (tile plus
+// a 2-cell x-y halo) and the values after the red half-sweep (tile plus 1).
+// Step k loads old plane k+3, does the red half-sweep of plane k+1 and the
+// black half-sweep of plane k-1; the three touch disjoint ring slots, so one
+// barrier per step suffices and all of a step's global loads are issued
+// together.  Red points of the 1-cell halo ring and of the planes next to the
+// chunk are recomputed by every block that needs them, so blocks are
+// independent and the result equals the global two-pass sweep (colour 0 =
+// (i+j+k) even first).  Input and output are separate arrays (ein is never
+// written), so blocks never race.  With zero_guess the old values are taken as
+// zero (ein is not read).  With ec != nullptr the old value is ein + the
+// prolonged coarse correction (see prolong_value): the prolongation is folded
+// into the sweep that follows it.
+template <class R, int TX, int TY>
+__global__ void __launch_bounds__(TX *TY) k_p_sweep3(Box b, int kc, int zero_guess, const R *__restrict__ ein,
+        const R *__restrict__ ec, Box cb, int lin, R *__restrict__ eout, const R *__restrict__ r,
+        const R *__restrict__ bx, const R *__restrict__ by, const R *__restrict__ bz) {
+    constexpr int NT = TX * TY;
+    constexpr int EX1 = TX + 2, EY1 = TY + 2, N1 = EX1 * EY1;
+    constexpr int EX2 = TX + 4, EY2 = TY + 4, N2 = EX2 * EY2;
+    constexpr int P2 = (N2 + NT - 1) / NT, P1 = (N1 + NT - 1) / NT;
+    __shared__ R oldp[4][N2];
+    __shared__ R newp[4][N1];
+    const int tid = threadIdx.x;
+    // logical tile from the XCD-swizzled linear block id, z slowest
+    const int G = gridDim.x * gridDim.y * gridDim.z;
+    int t = xcd_swizzle(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z), G);
+    const int bx_ = t % gridDim.x;
+    t /= gridDim.x;
+    const int by_ = t % gridDim.y, bz_ = t / gridDim.y;
+    const int i0 = bx_ * TX, j0 = by_ * TY;
+    const int k0 = bz_ * kc, k1 = min(k0 + kc, b.nz);
+    const int sy = b.px, sz = b.plane;
+    const R ix2 = R(b.ihx * b.ihx), iy2 = R(b.ihy * b.ihy), iz2 = R(b.ihz * b.ihz);
+    auto slot = [](int k) { return (k + 8) & 3; };
+    auto load_old = [&](int k) {
+        R v[P2];
+#pragma unroll
+        for (int p = 0; p < P2; ++p) {
+            const int e = tid + p * NT;
+            const int i = i0 + (e % EX2) - 2, j = j0 + (e / EX2) - 2;
+            v[p] = R(0);
+            if (e < N2 && !zero_guess && k >= 0 && k < b.nz && i >= 0 && i < b.nx && j >= 0 && j < b.ny) {
+                const int q = box_index(b, i, j, k);
+                v[p] = ein[q];
+                if (ec) v[p] += prolong_value<3, R>(cb, ec, i, j, k, lin);
+            }
+        }
+        R *dst = oldp[slot(k)];
+#pragma unroll
+        for (int p = 0; p < P2; ++p)
+            if (tid + p * NT < N2) dst[tid + p * NT] = v[p];
+    };
+    // red half-sweep of plane k over the tile plus a 1-cell ring
+    auto red = [&](int k) {
+        R wv[P1][6], rv[P1];
+        bool act[P1];
+#pragma unroll
+        for (int p = 0; p < P1; ++p) {
+            const int e = tid + p * NT;
+            const int i = i0 + (e % EX1) - 1, j = j0 + (e / EX1) - 1;
+            act[p] = e < N1 && k >= 0 && k < b.nz && i >= 0 && i < b.nx && j >= 0 && j < b.ny &&
+                     ((i + j + k) & 1) == 0;
+            if (act[p]) {
+                const int q = box_index(b, i, j, k);
+                wv[p][0] = bx[q] * ix2; wv[p][1] = bx[q + 1] * ix2;
+                wv[p][2] = by[q] * iy2; wv[p][3] = by[q + sy] * iy2;
+                wv[p][4] = bz[q] * iz2; wv[p][5] = bz[q + sz] * iz2;
+                rv[p] = r[q];
+            }
+        }
+        const R *om = oldp[slot(k - 1)], *oc = oldp[slot(k)], *op = oldp[slot(k + 1)];
+        R *dst = newp[slot(k)];
+#pragma unroll
+        for (int p = 0; p < P1; ++p) {
+            const int e = tid + p * NT;
+            if (e >= N1) continue;
+            const int ex = e % EX1, ey = e / EX1;
+            const int i = i0 + ex - 1, j = j0 + ey - 1;
+            const int o2 = (ey + 1) * EX2 + (ex + 1);
+            R v = R(0);
+            if (act[p]) {
+                R dg = wv[p][0] + wv[p][1] + wv[p][2] + wv[p][3] + wv[p][4] + wv[p][5];
+                R off = wv[p][0] * oc[o2 - 1] + wv[p][1] * oc[o2 + 1] + wv[p][2] * oc[o2 - EX2] +
+                        wv[p][3] * oc[o2 + EX2] + wv[p][4] * om[o2] + wv[p][5] * op[o2];
+                v = dg > R(0) ? (rv[p] + off) / dg : R(0);
+            } else if (k >= 0 && k < b.nz && i >= 0 && i < b.nx && j >= 0 && j < b.ny) {
+                v = oc[o2];
+            }
+            dst[e] = v;
+        }
+    };
+    // black half-sweep of plane k over the tile, written out with the red values
+    const int tx = tid % TX, ty = tid / TX;
+    const int ib = i0 + tx, jb = j0 + ty;
+    auto black = [&](int k) {
+        if (ib >= b.nx || jb >= b.ny) return;
+        const int q = box_index(b, ib, jb, k);
+        const bool blk = ((ib + jb + k) & 1) == 1;
+        R w0 = 0, w1 = 0, w2 = 0, w3 = 0, w4 = 0, w5 = 0, rr = 0;
+        if (blk) {
+            w0 = bx[q] * ix2; w1 = bx[q + 1] * ix2; w2 = by[q] * iy2; w3 = by[q + sy] * iy2;
+            w4 = bz[q] * iz2; w5 = bz[q + sz] * iz2; rr = r[q];
+        }
+        const R *nm = newp[slot(k - 1)], *nc = newp[slot(k)], *np = newp[slot(k + 1)];
+        const int o1 = (ty + 1) * EX1 + (tx + 1);
+        R v = nc[o1];
+        if (blk) {
+            R dg = w0 + w1 + w2 + w3 + w4 + w5;
+            R off = w0 * nc[o1 - 1] + w1 * nc[o1 + 1] + w2 * nc[o1 - EX1] + w3 * nc[o1 + EX1] + w4 * nm[o1] + w5 * np[o1];
+            v = dg > R(0) ? (rr + off) / dg : R(0);
+        }
+        eout[q] = v;
+    };
+    // prologue: old planes k0-2 .. k0+2 and red planes k0-1, k0
+    load_old(k0 - 2);
+    load_old(k0 - 1);
+    load_old(k0);
+    load_old(k0 + 1);
+    __syncthreads();
+    red(k0 - 1);
+    red(k0);
+    __syncthreads();
+    load_old(k0 + 2);
+    __syncthreads();
+    for (int k = k0; k <= k1; ++k) {
+        if (k + 3 <= k1 + 1) load_old(k + 3);
+        if (k + 1 <= k1) red(k + 1);
+        if (k - 1 >= k0) black(k - 1);
+        __syncthreads();
+    }
+}
+
+// Two-barrier form of the fused 3D sweep (used on the largest levels, where
+// 1024-thread tiles keep the halo fraction low): one full red-black
+// Gauss-Seidel sweep of -L_rho e = r in 3D, both colours in one launch.  A block owns a TX x TY column of cells and a chunk of KC planes,
 // marching in z with rings of three planes in LDS: the old values (tile plus a
 // 2-cell x-y halo) and the values after the red half-sweep (tile plus 1).  Red
 // points of the 1-cell halo ring and of the planes next to the chunk are
@@ -417,7 +660,7 @@ __global__ void __launch_bounds__(1024) k_dense_solve(int n, const R *__restrict
 // is ein + the prolonged coarse correction ec: the prolongation of a coarse
 // correction (see prolong_value) is folded into the sweep that follows it.
 template <class R, int TX, int TY>
-__global__ void __launch_bounds__(TX *TY) k_p_sweep3(Box b, int kc, int zero_guess, const R *__restrict__ ein,
+__global__ void __launch_bounds__(TX *TY) k_p_sweep3b(Box b, int kc, int zero_guess, const R *__restrict__ ein,
         const R *__restrict__ ec, Box cb, int lin, R *__restrict__ eout, const R *__restrict__ r,
         const R *__restrict__ bx, const R *__restrict__ by, const R *__restrict__ bz) {
     constexpr int NT = TX * TY;
@@ -426,8 +669,14 @@ __global__ void __launch_bounds__(TX *TY) k_p_sweep3(Box b, int kc, int zero_gue
     __shared__ R oldp[3][N2];
     __shared__ R newp[3][N1];
     const int tid = threadIdx.x;
-    const int i0 = blockIdx.x * TX, j0 = blockIdx.y * TY;
-    const int k0 = blockIdx.z * kc, k1 = min(k0 + kc, b.nz);
+    // logical tile from the XCD-swizzled linear block id, z slowest
+    const int G = gridDim.x * gridDim.y * gridDim.z;
+    int t = xcd_swizzle(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z), G);
+    const int bx_ = t % gridDim.x;
+    t /= gridDim.x;
+    const int by_ = t % gridDim.y, bz_ = t / gridDim.y;
+    const int i0 = bx_ * TX, j0 = by_ * TY;
+    const int k0 = bz_ * kc, k1 = min(k0 + kc, b.nz);
     const int sy = b.px, sz = b.plane;
     const R ix2 = R(b.ihx * b.ihx), iy2 = R(b.ihy * b.ihy), iz2 = R(b.ihz * b.ihz);
     auto slot = [](int k) { return ((k % 3) + 3) % 3; };
@@ -505,7 +754,7 @@ __global__ void __launch_bounds__(TX *TY) k_p_sweep3(Box b, int kc, int zero_gue
 // Coarse cell viscosity: harmonic mean of the 2^d children.
 template <int DIM, class R>
 __global__ void __launch_bounds__(kBlock) k_coarsen_mu(Box fb, Box cb, const R *__restrict__ f, R *__restrict__ c) {
-    int idx = blockIdx.x * kBlock + threadIdx.x;
+    int idx = box_thread_index();
     if (idx >= cb.nb) return;
     int I, J, K;
     decompose(cb, idx, I, J, K);
@@ -523,7 +772,7 @@ __global__ void __launch_bounds__(kBlock) k_coarsen_mu(Box fb, Box cb, const R *
 // coincident fine beta (the harmonic mean of rho); wall faces stay zero.
 template <int DIM, class R>
 __global__ void __launch_bounds__(kBlock) k_coarsen_beta(Box fb, Box cb, int comp, const R *__restrict__ f, R *__restrict__ c) {
-    int idx = blockIdx.x * kBlock + threadIdx.x;
+    int idx = box_thread_index();
     if (idx >= cb.nb) return;
     int I, J, K;
     decompose(cb, idx, I, J, K);
@@ -544,7 +793,7 @@ __global__ void __launch_bounds__(kBlock) k_coarsen_beta(Box fb, Box cb, int com
 template <int DIM, class R>
 __global__ void __launch_bounds__(kBlock) k_edge_mu(Box b, const R *__restrict__ mu, R *__restrict__ mxy,
         R *__restrict__ mxz, R *__restrict__ myz) {
-    int idx = blockIdx.x * kBlock + threadIdx.x;
+    int idx = box_thread_index();
     if (idx >= b.nb) return;
     int i, j, k;
     decompose(b, idx, i, j, k);
@@ -591,7 +840,7 @@ __device__ inline bool api_index(const Box &b, int comp, int i, int j, int k, in
 
 __global__ void __launch_bounds__(kBlock) k_pack(Box b, int comp, int mode, int keep_walls, double s,
         const double *__restrict__ src, double *__restrict__ dst) {
-    int idx = blockIdx.x * kBlock + threadIdx.x;
+    int idx = box_thread_index();
     if (idx >= b.nb) return;
     int i, j, k, a;
     decompose(b, idx, i, j, k);
@@ -609,7 +858,7 @@ __global__ void __launch_bounds__(kBlock) k_pack(Box b, int comp, int mode, int 
 
 __global__ void __launch_bounds__(kBlock) k_unpack(Box b, int comp, const double *__restrict__ src,
         double *__restrict__ dst) {
-    int idx = blockIdx.x * kBlock + threadIdx.x;
+    int idx = box_thread_index();
     if (idx >= b.nb) return;
     int i, j, k, a;
     decompose(b, idx, i, j, k);
@@ -621,7 +870,7 @@ __global__ void __launch_bounds__(kBlock) k_unpack(Box b, int comp, const double
 __global__ void __launch_bounds__(kBlock) k_check_coef(Box b, const double *__restrict__ rx,
         const double *__restrict__ ry, const double *__restrict__ rz, const double *__restrict__ mu,
         int *__restrict__ flag) {
-    int idx = blockIdx.x * kBlock + threadIdx.x;
+    int idx = box_thread_index();
     if (idx >= b.nb) return;
     int i, j, k;
     decompose(b, idx, i, j, k);
@@ -639,7 +888,7 @@ template <int DIM, class R>
 __global__ void __launch_bounds__(kBlock) k_precond_div(Box b, const R *__restrict__ eu, const R *__restrict__ ev,
         const R *__restrict__ ew, const double *__restrict__ rp, double dt, double *__restrict__ q,
         R *__restrict__ s) {
-    int idx = blockIdx.x * kBlock + threadIdx.x;
+    int idx = box_thread_index();
     if (idx >= b.nb) return;
     int i, j, k;
     decompose(b, idx, i, j, k);
@@ -661,7 +910,7 @@ __global__ void __launch_bounds__(kBlock) k_precond_update(Box b, const R *eu, c
         const R *__restrict__ phi, const double *__restrict__ bx, const double *__restrict__ by,
         const double *__restrict__ bz, const double *__restrict__ mu, const double *__restrict__ q,
         double dt, double theta, double *zu, double *zv, double *zw, double *__restrict__ zp) {
-    int idx = blockIdx.x * kBlock + threadIdx.x;
+    int idx = box_thread_index();
     if (idx >= b.nb) return;
     int i, j, k;
     decompose(b, idx, i, j, k);
@@ -690,7 +939,7 @@ __global__ void __launch_bounds__(kBlock) k_precond_div_jac(Box b, const double 
         const double *__restrict__ vv, const double *__restrict__ vw, const double *__restrict__ du,
         const double *__restrict__ dv, const double *__restrict__ dw, const double *__restrict__ rp, double dt,
         double *__restrict__ q, R *__restrict__ s) {
-    int idx = blockIdx.x * kBlock + threadIdx.x;
+    int idx = box_thread_index();
     if (idx >= b.nb) return;
     int i, j, k;
     decompose(b, idx, i, j, k);
@@ -712,7 +961,7 @@ __global__ void __launch_bounds__(kBlock) k_precond_update_jac(Box b, const doub
         const double *__restrict__ bx, const double *__restrict__ by, const double *__restrict__ bz,
         const double *__restrict__ mu, const double *__restrict__ q, double dt, double theta,
         double *__restrict__ zu, double *__restrict__ zv, double *__restrict__ zw, double *__restrict__ zp) {
-    int idx = blockIdx.x * kBlock + threadIdx.x;
+    int idx = box_thread_index();
     if (idx >= b.nb) return;
     int i, j, k;
     decompose(b, idx, i, j, k);
@@ -737,7 +986,7 @@ __global__ void __launch_bounds__(kBlock) k_precond_update_jac(Box b, const doub
 template <int DIM>
 __global__ void __launch_bounds__(kBlock) k_vel_inv_diag(Box b, VelCoef<double> c, double *__restrict__ du,
         double *__restrict__ dv, double *__restrict__ dw) {
-    int idx = blockIdx.x * kBlock + threadIdx.x;
+    int idx = box_thread_index();
     if (idx >= b.nb) return;
     int i, j, k;
     decompose(b, idx, i, j, k);
@@ -878,7 +1127,7 @@ __global__ void __launch_bounds__(kBlock) k_scale(long long n, double s, double 
 
 // subtract mean = sum[0] / ncell on the cells of a cell array
 __global__ void __launch_bounds__(kBlock) k_sub_mean(Box b, const double *__restrict__ sum, double *__restrict__ p) {
-    int idx = blockIdx.x * kBlock + threadIdx.x;
+    int idx = box_thread_index();
     if (idx >= b.nb) return;
     int i, j, k;
     decompose(b, idx, i, j, k);

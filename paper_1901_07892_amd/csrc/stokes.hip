@@ -332,25 +332,40 @@ void p_smooth(stokes_ctx &c, Level<R> &L, R *e, const R *r, int sweeps, bool zer
                 DIM == 3 ? L.beta[2] : L.beta[1]);
 }
 
-constexpr int kSweepTX = 32, kSweepTY = 8;
-
 // One fused 3D sweep from `in` into `out` (optionally adding the prolonged coarse
-// correction `ec` to the old values first).
-template <class R>
-void p_sweep3(stokes_ctx &c, Level<R> &L, const R *in, R *out, const R *r, bool zero_guess,
-              const R *ec, const Box *cb) {
-    const int lin = c.opt.p_prolong;
+// correction `ec` to the old values first).  Levels of at least 2^20 cells use
+// the two-barrier kernel on 64x16 tiles (1024 threads, low halo fraction);
+// smaller ones the one-barrier pipelined kernel on 32x16 or 32x8 tiles.
+template <class R, int TX, int TY, bool PIPE>
+void p_sweep3_launch(stokes_ctx &c, Level<R> &L, const R *in, R *out, const R *r, bool zero_guess,
+                     const R *ec, const Box *cb, int min_blocks) {
     const Box &b = L.b;
-    int gx = (b.nx + kSweepTX - 1) / kSweepTX, gy = (b.ny + kSweepTY - 1) / kSweepTY;
+    int gx = (b.nx + TX - 1) / TX, gy = (b.ny + TY - 1) / TY;
     // z chunks: enough blocks to fill the chip, at least 8 planes per chunk
     int kc = b.nz;
-    while (kc > 8 && (long long)gx * gy * ((b.nz + kc - 1) / kc) < 2048) kc = (kc + 1) / 2;
+    while (kc > 8 && (long long)gx * gy * ((b.nz + kc - 1) / kc) < min_blocks) kc = (kc + 1) / 2;
     int gz = (b.nz + kc - 1) / kc;
     const double cells = (double)b.nx * b.ny * b.nz;
     // old and new iterate, right-hand side, three face coefficients (+ coarse correction)
     ProfScope ps(c, STOKES_PROF_P_SWEEP, cells * sizeof(R) * (6.0 + (ec ? 0.125 : 0.0)), b.nx == c.fine.nx);
-    k_p_sweep3<R, kSweepTX, kSweepTY><<<dim3(gx, gy, gz), kSweepTX * kSweepTY, 0, c.stream>>>(
-        b, kc, zero_guess ? 1 : 0, in, ec, cb ? *cb : b, lin, out, r, L.beta[0], L.beta[1], L.beta[2]);
+    if (PIPE)
+        k_p_sweep3<R, TX, TY><<<dim3(gx, gy, gz), TX * TY, 0, c.stream>>>(
+            b, kc, zero_guess ? 1 : 0, in, ec, cb ? *cb : b, c.opt.p_prolong, out, r, L.beta[0], L.beta[1], L.beta[2]);
+    else
+        k_p_sweep3b<R, TX, TY><<<dim3(gx, gy, gz), TX * TY, 0, c.stream>>>(
+            b, kc, zero_guess ? 1 : 0, in, ec, cb ? *cb : b, c.opt.p_prolong, out, r, L.beta[0], L.beta[1], L.beta[2]);
+}
+
+template <class R>
+void p_sweep3(stokes_ctx &c, Level<R> &L, const R *in, R *out, const R *r, bool zero_guess,
+              const R *ec, const Box *cb) {
+    const long long cells = (long long)L.b.nx * L.b.ny * L.b.nz;
+    if (cells >= (1LL << 20) && L.b.nx >= 64 && L.b.ny >= 16)
+        p_sweep3_launch<R, 64, 16, false>(c, L, in, out, r, zero_guess, ec, cb, 512);
+    else if (L.b.nx >= 32 && L.b.ny >= 16)
+        p_sweep3_launch<R, 32, 16, true>(c, L, in, out, r, zero_guess, ec, cb, 1024);
+    else
+        p_sweep3_launch<R, 32, 8, true>(c, L, in, out, r, zero_guess, ec, cb, 2048);
 }
 
 // V-cycle on -L_rho e = r at level l.  Returns the array that holds the new
@@ -361,7 +376,15 @@ R *p_vcycle(stokes_ctx &c, MG<R> &mg, int l, R *e, R *r, bool zero_guess) {
     Level<R> &L = mg.L[l];
     R *cur = e;
     R *spare = (e == L.ep) ? L.ep2 : L.ep;
+    // Levels of at most 64^3 cells are latency-bound: two flat colour passes (in
+    // place) beat a z-marching launch there.
+    const bool flat = (long long)L.b.nx * L.b.ny * L.b.nz <= (1LL << 18);
     auto sweep = [&](bool zg, const R *ec, const Box *cb) {
+        if (flat) {
+            if (ec) k_p_prolong_add<DIM, R><<<nblocks_box(L.b), kBlock, 0, c.stream>>>(L.b, *cb, c.opt.p_prolong, ec, cur);
+            p_smooth<DIM, R>(c, L, cur, r, 1, zg);
+            return;
+        }
         p_sweep3<R>(c, L, cur, spare, r, zg, ec, cb);
         std::swap(cur, spare);
     };
@@ -503,6 +526,19 @@ void apply_fine(stokes_ctx &c, double *x, double *f, double *y) {
     // x: 4 unknown fields, coefficients: DIM mass + mu + edges; y: 4 fields; f: 4 more
     const int nedge = DIM == 3 ? 3 : 1;
     ProfScope ps(c, STOKES_PROF_MATVEC, cells * 8.0 * ((DIM + 1) * (f ? 3 : 2) + DIM + 1 + nedge));
+    if (DIM == 3 && c.opt.matvec_z) {
+        constexpr int TX = 64, TY = 4;
+        const Box &b = c.fine;
+        int gx = (b.nx + TX - 1) / TX, gy = (b.ny + TY - 1) / TY;
+        int kc = b.nz;
+        while (kc > 8 && (long long)gx * gy * ((b.nz + kc - 1) / kc) < 2048) kc = (kc + 1) / 2;
+        int gz = (b.nz + kc - 1) / kc;
+        k_apply3_z<TX, TY><<<dim3(gx, gy, gz), TX * TY, 0, c.stream>>>(
+            b, kc, fine_coef(c), c.fld(x, 0), c.fld(x, 1), c.fld(x, 2), c.fld(x, 3),
+            f ? c.fld(f, 0) : nullptr, f ? c.fld(f, 1) : nullptr, f ? c.fld(f, 2) : nullptr,
+            f ? c.fld(f, 3) : nullptr, c.fld(y, 0), c.fld(y, 1), c.fld(y, 2), c.fld(y, 3));
+        return;
+    }
     k_apply<DIM><<<nblocks_box(c.fine), kBlock, 0, c.stream>>>(
         c.fine, fine_coef(c), c.fld(x, 0), c.fld(x, 1), DIM == 3 ? c.fld(x, 2) : nullptr, c.fld(x, DIM),
         f ? c.fld(f, 0) : nullptr, f ? c.fld(f, 1) : nullptr, (f && DIM == 3) ? c.fld(f, 2) : nullptr,
@@ -798,9 +834,10 @@ stokes_options defaults() {
     o.coarse_sweeps = 40;
     o.vel_levels = 0;
     o.vel_sweeps = 1;
-    o.p_prolong = 1;
+    o.p_prolong = 0;
     o.vel_smoother = 1;
-    o.orth = 2;
+    o.orth = 1;
+    o.matvec_z = 1;
     return o;
 }
 
@@ -826,6 +863,7 @@ const char *check_grid_opts(const stokes_grid *g, const stokes_options &o) {
     if (o.p_prolong != 0 && o.p_prolong != 1) return "p_prolong must be 0 or 1";
     if (o.vel_smoother != 0 && o.vel_smoother != 1) return "vel_smoother must be 0 or 1";
     if (o.orth != 1 && o.orth != 2) return "orth must be 1 or 2";
+    if (o.matvec_z != 0 && o.matvec_z != 1) return "matvec_z must be 0 or 1";
     return nullptr;
 }
 

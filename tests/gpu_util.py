@@ -42,9 +42,9 @@ def gpu_solve(prob, tol=None, theta=1.0, x0=None, **opts):
     return out
 
 
-def gpu_apply(prob, xu, xp, theta=1.0):
+def gpu_apply(prob, xu, xp, theta=1.0, **opts):
     import torch
-    s = solver_for(prob, theta=theta)
+    s = solver_for(prob, theta=theta, **opts)
     xd = [to_dev(a) for a in xu[:prob.dim]]
     pd = to_dev(xp)
     yd = [torch.full_like(a, np.nan) for a in xd]

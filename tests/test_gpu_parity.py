@@ -38,13 +38,13 @@ APPLY_CASES = [
 
 
 @pytest.mark.parametrize("name,maker", APPLY_CASES)
-@pytest.mark.parametrize("theta", [1.0, 0.5])
-def test_apply_matches_oracle_matrix(name, maker, theta):
+@pytest.mark.parametrize("theta,matvec_z", [(1.0, 1), (0.5, 1), (1.0, 0)])
+def test_apply_matches_oracle_matrix(name, maker, theta, matvec_z):
     prob = maker()
-    print("apply", name, prob.n, theta, flush=True)
+    print("apply", name, prob.n, theta, matvec_z, flush=True)
     sys = A.assemble(A.OGrid(prob.dim, prob.n, prob.h), prob.rho_faces, prob.mu, prob.dt, theta)
     xu, xp = W.random_vector(prob, prob.dim, 77)
-    yu, yp = gpu_apply(prob, xu, xp, theta)
+    yu, yp = gpu_apply(prob, xu, xp, theta, matvec_z=matvec_z)
     y_ref = sys.K @ sys.pack(xu, xp)
     y_gpu = sys.pack(yu, yp)
     scale = np.abs(y_ref).max()
