@@ -92,6 +92,7 @@ typedef struct {
                             orthogonality can only cost iterations), 2 twice */
     int matvec_z;        /* 3D matvec kernel: 1 z-marching (register reuse along z), 0 one
                             thread per point; same result to rounding */
+    int p_gamma;         /* pressure cycle: 1 V-cycle, 2 W-cycle (two coarse cycles per level) */
 } stokes_options;
 
 typedef struct {
@@ -113,7 +114,7 @@ typedef struct {
 typedef struct stokes_ctx stokes_ctx;
 
 /* Fill *opts with the defaults (FP64, theta 1, automatic sigma, restart 30,
- * max_iters 200, V(2,2), one velocity and three pressure cycles, 40 coarse sweeps,
+ * max_iters 200, (2,2) smoothing, one velocity cycle and two pressure W-cycles, 40 coarse sweeps,
  * automatic velocity levels, 1 single-level velocity sweep, piecewise-constant
  * pressure prolongation, diagonal velocity step, one-pass Gram-Schmidt, z-marching
  * matvec). */

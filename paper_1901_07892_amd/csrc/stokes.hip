@@ -410,6 +410,9 @@ R *p_vcycle(stokes_ctx &c, MG<R> &mg, int l, R *e, R *r, bool zero_guess) {
     const R *bz = DIM == 3 ? L.beta[2] : L.beta[1];
     k_p_residual_restrict<DIM, R><<<nblocks_box(C.b), kBlock, 0, c.stream>>>(L.b, C.b, cur, r, L.beta[0], L.beta[1], bz, C.rp);
     R *ce = p_vcycle<DIM, R>(c, mg, l + 1, C.ep, C.rp, true);
+    // W-cycle (p_gamma = 2): a second coarse cycle on the same coarse equation
+    // (pointless above the exactly solved coarsest level)
+    for (int g = 1; g < c.opt.p_gamma && l + 1 < mg.nlev - 1; ++g) ce = p_vcycle<DIM, R>(c, mg, l + 1, ce, C.rp, false);
     if (DIM == 3 && nu2 > 0) {
         sweep(false, ce, &C.b);                    // prolongation folded into the first post-sweep
         for (int s = 1; s < nu2; ++s) sweep(false, nullptr, nullptr);
@@ -830,7 +833,7 @@ stokes_options defaults() {
     o.nu1 = 2;
     o.nu2 = 2;
     o.vel_cycles = 1;
-    o.p_cycles = 3;
+    o.p_cycles = 2;
     o.coarse_sweeps = 40;
     o.vel_levels = 0;
     o.vel_sweeps = 1;
@@ -838,6 +841,7 @@ stokes_options defaults() {
     o.vel_smoother = 1;
     o.orth = 1;
     o.matvec_z = 1;
+    o.p_gamma = 2;
     return o;
 }
 
@@ -864,6 +868,7 @@ const char *check_grid_opts(const stokes_grid *g, const stokes_options &o) {
     if (o.vel_smoother != 0 && o.vel_smoother != 1) return "vel_smoother must be 0 or 1";
     if (o.orth != 1 && o.orth != 2) return "orth must be 1 or 2";
     if (o.matvec_z != 0 && o.matvec_z != 1) return "matvec_z must be 0 or 1";
+    if (o.p_gamma != 1 && o.p_gamma != 2) return "p_gamma must be 1 (V-cycle) or 2 (W-cycle)";
     return nullptr;
 }
 
