@@ -159,6 +159,9 @@ def main():
     if not args.no_forms and args.precision == 0:
         out["forms"] = {"fp32_multigrid": fp32_form(S, prob, rho, mu, rhs_u, rhs_p, xu, xp, overrides,
                                                     ms, args.steps)}
+        lf = learned_form(S, prob, rho, mu, rhs_u, rhs_p, xu, xp, overrides, ms, args.steps)
+        if lf is not None:
+            out["forms"]["learned"] = lf
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, int(np.median(iters)))
     print(json.dumps(out), flush=True)
@@ -196,6 +199,47 @@ def fp32_form(S, prob, rho, mu, rhs_u, rhs_p, xu64, xp64, overrides, ms64, steps
     log("fp32-multigrid form: %.2f ms, %d iterations, residual %.2e" % (ms, stats.iters, stats.rel_res_true))
     return {"ms_per_solve": ms, "fgmres_iters": stats.iters, "rel_res_true": stats.rel_res_true,
             "speedup_vs_fp64": ms64 / ms, "rel_diff_vs_fp64_solution": diff}
+
+
+def learned_form(S, prob, rho, mu, rhs_u, rhs_p, xu64, xp64, overrides, ms64, steps):
+    """Learned form: the trained U-Net (BF16 on the matrix cores) seeds the pressure
+    cycles from the 32^3 level; plain multigrid takes over on stagnation.  Same
+    FP64 outer solve and residual check.  None if no trained weights are present."""
+    import torch
+    from paper_1901_07892_amd import learned
+    p, meta = learned.load_params()
+    if p is None:
+        return None
+    net = S.UNet(meta["grid"])
+    net.set_params(p)
+    solver = S.StokesSolver(3, prob.n, prob.h, rho, mu, prob.dt, **overrides)
+    S.stokes_attach_learned(solver.ctx, net, 0.9)
+    xu = [torch.zeros_like(a) for a in xu64]
+    xp = torch.zeros_like(xp64)
+    times = []
+    for s in range(steps + 2):
+        for a in xu:
+            a.zero_()
+        xp.zero_()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        st, stats = solver.solve(rhs_u, rhs_p, prob.tol, xu, xp)
+        torch.cuda.synchronize()
+        if s >= 2:
+            times.append((time.perf_counter() - t) * 1e3)
+        if st != 0:
+            raise RuntimeError("learned-form solve did not converge: %s" % stats.as_dict())
+    solver.close()
+    net.close()
+    diff = [float(torch.linalg.vector_norm(xu[c] - xu64[c]) / torch.linalg.vector_norm(xu64[c])) for c in range(3)]
+    diff.append(float(torch.linalg.vector_norm(xp - xp64) / torch.linalg.vector_norm(xp64)))
+    ms = float(np.mean(times))
+    log("learned form: %.2f ms, %d iterations, fell back %d" % (ms, stats.iters, stats.fell_back))
+    return {"ms_per_solve": ms, "fgmres_iters": stats.iters, "fell_back": stats.fell_back,
+            "rel_res_true": stats.rel_res_true, "speedup_vs_fp64": ms64 / ms,
+            "rel_diff_vs_fp64_solution": diff,
+            "training": {k: meta.get(k) for k in ("instances", "epochs", "fine_grid", "level_grid")},
+            "final_val_loss": meta["history"][-1]["val_loss"] if meta.get("history") else None}
 
 
 def kernel_source_hash() -> str:

@@ -108,7 +108,7 @@ typedef struct {
     double sigma;         /* continuity weight used */
     double g_mean;        /* mean removed from rhs_p before solving */
     double ms_total;      /* wall time of the call on the host, milliseconds */
-    int fell_back;        /* reserved (0) */
+    int fell_back;        /* 1 if the learned stage was switched off for stagnation */
 } stokes_stats;
 
 typedef struct stokes_ctx stokes_ctx;
@@ -183,6 +183,75 @@ stokes_status stokes_profile_kernel(stokes_ctx *ctx, int kernel);
 /* Read and reset the accumulators: summed event time (ms), launches timed and
  * their summed algorithmic bytes. */
 stokes_status stokes_profile_read(stokes_ctx *ctx, double *ms_total, long long *launches, double *bytes);
+
+/* ---------------------------------------------------------------------------
+ * Learned form: a 4-level 3D U-Net (channels 16/32/48/64, 3x3x3 convolutions,
+ * ReLU, 2x2x2 average pooling, nearest upsampling, additive skips) in BF16 with
+ * FP32 accumulation on the matrix cores (v_mfma_f32_16x16x16_bf16), with its
+ * backward pass and an Adam optimiser.  It maps three planar FP32 features
+ * (normalised log rho, log mu, and the pressure right-hand side scaled to unit
+ * RMS) on an n^3 grid to a predicted pressure shape.  Its weights are the
+ * caller's (stokes_unet_set_params); all memory is the caller's workspace.
+ * --------------------------------------------------------------------------- */
+typedef struct stokes_unet stokes_unet;
+
+/* Number of FP32 parameters (all weights as [c_out][27][c_in] layer by layer, then all biases). */
+long long stokes_unet_param_count(void);
+
+/* Workspace bytes for an n^3 network (n >= 8, n % 8 == 0), 0 otherwise.  Host-only. */
+size_t stokes_unet_workspace_size(int n);
+
+/* Create a network on the caller's device workspace and HIP stream (void*). */
+stokes_status stokes_unet_create(int n, void *workspace, size_t ws_bytes, void *stream, stokes_unet **out);
+
+/* He-uniform weights from a counter-based generator, zero biases and Adam state. */
+stokes_status stokes_unet_init(stokes_unet *net, unsigned long long seed);
+
+/* Copy the FP32 parameters from / to host memory (count = stokes_unet_param_count()). */
+stokes_status stokes_unet_get_params(stokes_unet *net, float *host, long long count);
+stokes_status stokes_unet_set_params(stokes_unet *net, const float *host, long long count);
+
+/* Forward pass: out = prediction for the planar device features f0, f1, f2 (n^3 FP32 each). */
+stokes_status stokes_unet_forward(stokes_unet *net, const float *f0, const float *f1, const float *f2, float *out);
+
+/* One Adam step (lr, beta 0.9/0.999) on the mean-square error between the
+ * prediction and `target` (device, n^3 FP32); *loss (host) receives the loss
+ * before the step.  Blocks until done. */
+stokes_status stokes_unet_train_step(stokes_unet *net, const float *f0, const float *f1, const float *f2,
+                                     const float *target, float lr, float *loss);
+
+/* Gradient of the last training step's loss (host, count = stokes_unet_param_count()). */
+stokes_status stokes_unet_get_grads(stokes_unet *net, float *host, long long count);
+
+/* Grid size n of a network; 0 for NULL. */
+int stokes_unet_size(const stokes_unet *net);
+
+/* Release the host-side network object (the workspace stays the caller's). */
+void stokes_unet_destroy(stokes_unet *net);
+
+/* Use `net` as the learned stage of this context's preconditioner (NULL
+ * detaches).  The network runs on the multigrid level with net's n^3 cells
+ * (3D, n <= 64; EINVAL if there is none) and must share the context's stream.
+ * Before the pressure cycles of each preconditioner application the pressure
+ * right-hand side is restricted to that level, scaled to unit RMS and fed to
+ * the network with the level's static features; the prediction's amplitude is
+ * fitted by least squares against that level's Poisson operator and the
+ * result, prolonged trilinearly to the finest level, is the initial guess of
+ * the pressure cycles.  Fallback on stagnation: as soon as an FGMRES iteration
+ * reduces the residual estimate by less than the factor stall_ratio (0.9 in
+ * production), the rest of the solve runs plain multigrid and
+ * stokes_stats.fell_back is set.  The FP64 residual check is unchanged. */
+stokes_status stokes_attach_learned(stokes_ctx *ctx, stokes_unet *net, double stall_ratio);
+
+/* Training tuple on the level with n^3 cells (device FP32 planar outputs,
+ * x fastest): static features f0 = log10(rho)/3 - 1/2 (rho from the level's
+ * face coefficients) and f1 = log10(mu)/2 + 2, the pressure right-hand side of
+ * the first preconditioner application for the right-hand side (rhs_u, rhs_p)
+ * restricted to that level and scaled to unit RMS (s_c), and the pressure
+ * solution of that right-hand side after `cycles` pressure cycles, restricted
+ * and scaled to zero mean and unit RMS (phi_c).  Blocks until done. */
+stokes_status stokes_learned_tuple(stokes_ctx *ctx, const double *const rhs_u[3], const double *rhs_p, int n,
+                                   int cycles, float *f0, float *f1, float *s_c, float *phi_c);
 
 /* Release the host-side context (the workspace stays the caller's). NULL is a no-op. */
 void stokes_destroy(stokes_ctx *ctx);

@@ -11,6 +11,9 @@ from ._binding import (  # noqa: F401
     StokesOptions,
     StokesStats,
     StokesSolver,
+    UNet,
+    stokes_attach_learned,
+    stokes_learned_tuple,
     library_path,
     load_library,
     stokes_apply,
@@ -22,4 +25,6 @@ from ._binding import (  # noqa: F401
     stokes_setup,
     stokes_solve,
     stokes_workspace_size,
+    stokes_unet_param_count,
+    stokes_unet_workspace_size,
 )

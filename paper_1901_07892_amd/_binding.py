@@ -83,6 +83,33 @@ def load_library():
     L.stokes_profile_read.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_longlong),
                                       C.POINTER(C.c_double)]
     L.stokes_profile_read.restype = C.c_int
+    L.stokes_unet_param_count.argtypes = []
+    L.stokes_unet_param_count.restype = C.c_longlong
+    L.stokes_unet_workspace_size.argtypes = [C.c_int]
+    L.stokes_unet_workspace_size.restype = C.c_size_t
+    L.stokes_unet_create.argtypes = [C.c_int, dp, C.c_size_t, dp, C.POINTER(C.c_void_p)]
+    L.stokes_unet_create.restype = C.c_int
+    L.stokes_unet_init.argtypes = [C.c_void_p, C.c_ulonglong]
+    L.stokes_unet_init.restype = C.c_int
+    fp = C.POINTER(C.c_float)
+    L.stokes_unet_get_params.argtypes = [C.c_void_p, fp, C.c_longlong]
+    L.stokes_unet_get_params.restype = C.c_int
+    L.stokes_unet_set_params.argtypes = [C.c_void_p, fp, C.c_longlong]
+    L.stokes_unet_set_params.restype = C.c_int
+    L.stokes_unet_get_grads.argtypes = [C.c_void_p, fp, C.c_longlong]
+    L.stokes_unet_get_grads.restype = C.c_int
+    L.stokes_unet_forward.argtypes = [C.c_void_p, dp, dp, dp, dp]
+    L.stokes_unet_forward.restype = C.c_int
+    L.stokes_unet_train_step.argtypes = [C.c_void_p, dp, dp, dp, dp, C.c_float, fp]
+    L.stokes_unet_train_step.restype = C.c_int
+    L.stokes_unet_size.argtypes = [C.c_void_p]
+    L.stokes_unet_size.restype = C.c_int
+    L.stokes_unet_destroy.argtypes = [C.c_void_p]
+    L.stokes_unet_destroy.restype = None
+    L.stokes_attach_learned.argtypes = [C.c_void_p, C.c_void_p, C.c_double]
+    L.stokes_attach_learned.restype = C.c_int
+    L.stokes_learned_tuple.argtypes = [C.c_void_p, C.c_void_p * 3, dp, C.c_int, C.c_int, dp, dp, dp, dp]
+    L.stokes_learned_tuple.restype = C.c_int
     _lib = L
     return L
 
@@ -232,3 +259,101 @@ class StokesSolver:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------- learned form (U-Net)
+def _fptr(t):
+    if hasattr(t, "data_ptr"):
+        import torch
+        if t.dtype != torch.float32 or not t.is_contiguous() or not t.is_cuda:
+            raise ValueError("U-Net arrays must be contiguous float32 device tensors")
+        return t.data_ptr()
+    return int(t)
+
+
+def stokes_unet_param_count() -> int:
+    return int(load_library().stokes_unet_param_count())
+
+
+def stokes_unet_workspace_size(n: int) -> int:
+    return int(load_library().stokes_unet_workspace_size(int(n)))
+
+
+def _chk(st, what):
+    if st != 0:
+        raise StokesError(st, what)
+
+
+class UNet:
+    """Owns a workspace tensor and a stokes_unet on the current device/stream."""
+
+    def __init__(self, n: int, seed: int = 0, stream=None):
+        import torch
+        L = load_library()
+        self.n = n
+        self.ws_bytes = stokes_unet_workspace_size(n)
+        if self.ws_bytes == 0:
+            raise StokesError(-1, "U-Net grid must be a multiple of 8, >= 8")
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device="cuda")
+        h = C.c_void_p()
+        _chk(L.stokes_unet_create(n, self.workspace.data_ptr(), self.ws_bytes, _stream(stream), C.byref(h)),
+             "stokes_unet_create")
+        self.handle = h.value
+        _chk(L.stokes_unet_init(self.handle, int(seed)), "stokes_unet_init")
+        self.count = stokes_unet_param_count()
+
+    def get_params(self):
+        import numpy as np
+        a = np.zeros(self.count, dtype=np.float32)
+        _chk(load_library().stokes_unet_get_params(self.handle, a.ctypes.data_as(C.POINTER(C.c_float)), self.count),
+             "get_params")
+        return a
+
+    def set_params(self, a):
+        import numpy as np
+        a = np.ascontiguousarray(a, dtype=np.float32)
+        _chk(load_library().stokes_unet_set_params(self.handle, a.ctypes.data_as(C.POINTER(C.c_float)), self.count),
+             "set_params")
+
+    def get_grads(self):
+        import numpy as np
+        a = np.zeros(self.count, dtype=np.float32)
+        _chk(load_library().stokes_unet_get_grads(self.handle, a.ctypes.data_as(C.POINTER(C.c_float)), self.count),
+             "get_grads")
+        return a
+
+    def forward(self, f0, f1, f2, out):
+        _chk(load_library().stokes_unet_forward(self.handle, _fptr(f0), _fptr(f1), _fptr(f2), _fptr(out)),
+             "stokes_unet_forward")
+
+    def train_step(self, f0, f1, f2, target, lr):
+        loss = C.c_float()
+        _chk(load_library().stokes_unet_train_step(self.handle, _fptr(f0), _fptr(f1), _fptr(f2), _fptr(target),
+                                                   float(lr), C.byref(loss)), "stokes_unet_train_step")
+        return loss.value
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load_library().stokes_unet_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def stokes_attach_learned(ctx, net, stall_ratio: float = 0.9) -> None:
+    L = load_library()
+    st = L.stokes_attach_learned(ctx, net.handle if net is not None else None, float(stall_ratio))
+    if st != 0:
+        raise StokesError(st, L.stokes_last_error(ctx).decode())
+
+
+def stokes_learned_tuple(ctx, rhs_u, rhs_p, n, cycles, f0, f1, s_c, phi_c) -> None:
+    L = load_library()
+    st = L.stokes_learned_tuple(ctx, _ptr3(list(rhs_u) + [None] * 3), _ptr(rhs_p), int(n), int(cycles),
+                                _fptr(f0), _fptr(f1), _fptr(s_c), _fptr(phi_c))
+    if st != 0:
+        raise StokesError(st, L.stokes_last_error(ctx).decode())

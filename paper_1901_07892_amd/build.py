@@ -7,7 +7,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = os.path.join(HERE, "csrc", "stokes.hip")
+SRC = [os.path.join(HERE, "csrc", "stokes.hip"), os.path.join(HERE, "csrc", "unet.hip")]
 LIB = os.path.join(HERE, "libstokes.so")
 
 HIPCC_FLAGS = [
@@ -19,10 +19,10 @@ HIPCC_FLAGS = [
 
 
 def build(verbose: bool = False) -> str:
-    """Compile csrc/stokes.hip into libstokes.so (always recompiles)."""
+    """Compile csrc/stokes.hip and csrc/unet.hip into libstokes.so (always recompiles)."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     tmp = LIB + ".tmp"
-    cmd = [hipcc] + HIPCC_FLAGS + ["-I", os.path.join(ROOT, "include"), "-o", tmp, SRC]
+    cmd = [hipcc] + HIPCC_FLAGS + ["-I", os.path.join(ROOT, "include"), "-o", tmp] + SRC
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

@@ -1003,6 +1003,149 @@ __global__ void __launch_bounds__(kBlock) k_vel_inv_diag(Box b, VelCoef<double> 
     }
 }
 
+// ---------------------------------------------------------------- learned stage glue
+// Coarse cell = mean of its 8 children (3D).
+template <class R>
+__global__ void __launch_bounds__(kBlock) k_restrict_avg3(Box fb, Box cb, const R *__restrict__ f, R *__restrict__ c) {
+    int idx = box_thread_index();
+    if (idx >= cb.nb) return;
+    int I, J, K;
+    decompose(cb, idx, I, J, K);
+    if (!is_cell(cb, I, J, K)) { c[idx] = R(0); return; }
+    R acc = 0;
+    for (int d = 0; d < 8; ++d)
+        acc += f[box_index(fb, 2 * I + (d & 1), 2 * J + ((d >> 1) & 1), 2 * K + (d >> 2))];
+    c[idx] = acc * R(0.125);
+}
+
+// y = -L_rho e on the cells of one level (0 elsewhere)
+template <class R>
+__global__ void __launch_bounds__(kBlock) k_p_apply3(Box b, const R *__restrict__ e, const R *__restrict__ bx,
+        const R *__restrict__ by, const R *__restrict__ bz, R *__restrict__ y) {
+    int idx = box_thread_index();
+    if (idx >= b.nb) return;
+    int i, j, k;
+    decompose(b, idx, i, j, k);
+    R v = 0;
+    if (is_cell(b, i, j, k)) {
+        R off, dg;
+        prow<3, R>(b, idx, e, bx, by, bz, off, dg);
+        v = dg * e[idx] - off;
+    }
+    y[idx] = v;
+}
+
+// Static features on a level of n^3 cells (planar, x fastest): f0 = log10(rho)/3 - 1/2
+// with rho the harmonic mean of the interior face densities (from beta), and
+// f1 = log10(mu)/2 + 2.
+template <class R>
+__global__ void __launch_bounds__(kBlock) k_learned_static(Box b, const R *__restrict__ bx, const R *__restrict__ by,
+        const R *__restrict__ bz, const R *__restrict__ mu, float *__restrict__ f0, float *__restrict__ f1) {
+    int t = blockIdx.x * kBlock + threadIdx.x;
+    const int nc = b.nx * b.ny * b.nz;
+    if (t >= nc) return;
+    const int i = t % b.nx, j = (t / b.nx) % b.ny, k = t / (b.nx * b.ny);
+    const int q = box_index(b, i, j, k);
+    double sb = 0.0;
+    int cnt = 0;
+    const double f[6] = {(double)bx[q], (double)bx[q + 1], (double)by[q], (double)by[q + b.px],
+                         (double)bz[q], (double)bz[q + b.plane]};
+    for (int a = 0; a < 6; ++a)
+        if (f[a] > 0.0) { sb += f[a]; ++cnt; }
+    const double rho = cnt > 0 ? cnt / sb : 1.0;
+    f0[t] = (float)(log10(rho) / 3.0 - 0.5);
+    f1[t] = (float)(log10(fmax((double)mu[q], 1e-30)) / 2.0 + 2.0);
+}
+
+// One block: rms of the level's cell values, then dst = src / rms (planar FP32,
+// zero mean removed first when `center`).  rms (and the mean) go to stat[0..1].
+template <class R>
+__global__ void __launch_bounds__(1024) k_normalise_planar(Box b, const R *__restrict__ src, int center,
+        float *__restrict__ dst, double *__restrict__ stat) {
+    __shared__ double sh[1024];
+    const int nc = b.nx * b.ny * b.nz;
+    double s1 = 0.0;
+    for (int t = threadIdx.x; t < nc; t += 1024) {
+        const int i = t % b.nx, j = (t / b.nx) % b.ny, k = t / (b.nx * b.ny);
+        s1 += (double)src[box_index(b, i, j, k)];
+    }
+    sh[threadIdx.x] = s1;
+    __syncthreads();
+    for (int o = 512; o > 0; o >>= 1) {
+        if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    const double mean = center ? sh[0] / nc : 0.0;
+    __syncthreads();
+    double s2 = 0.0;
+    for (int t = threadIdx.x; t < nc; t += 1024) {
+        const int i = t % b.nx, j = (t / b.nx) % b.ny, k = t / (b.nx * b.ny);
+        const double v = (double)src[box_index(b, i, j, k)] - mean;
+        s2 += v * v;
+    }
+    sh[threadIdx.x] = s2;
+    __syncthreads();
+    for (int o = 512; o > 0; o >>= 1) {
+        if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    const double rms = sqrt(sh[0] / nc);
+    const double inv = rms > 0.0 ? 1.0 / rms : 0.0;
+    for (int t = threadIdx.x; t < nc; t += 1024) {
+        const int i = t % b.nx, j = (t / b.nx) % b.ny, k = t / (b.nx * b.ny);
+        dst[t] = (float)(((double)src[box_index(b, i, j, k)] - mean) * inv);
+    }
+    if (threadIdx.x == 0) {
+        stat[0] = rms;
+        stat[1] = mean;
+    }
+}
+
+// planar FP32 -> the cells of a level's box array (other slots untouched)
+template <class R>
+__global__ void __launch_bounds__(kBlock) k_planar_to_box(Box b, const float *__restrict__ src, R *__restrict__ dst) {
+    int t = blockIdx.x * kBlock + threadIdx.x;
+    const int nc = b.nx * b.ny * b.nz;
+    if (t >= nc) return;
+    const int i = t % b.nx, j = (t / b.nx) % b.ny, k = t / (b.nx * b.ny);
+    dst[box_index(b, i, j, k)] = (R)src[t];
+}
+
+// One block: alpha = <y, s> / <y, y> over the level's cells (the least-squares
+// amplitude of the prediction e for -L e = s), then e *= alpha (alpha = 0 if
+// not finite).
+template <class R>
+__global__ void __launch_bounds__(1024) k_fit_amplitude(Box b, const R *__restrict__ y, const R *__restrict__ s,
+        R *__restrict__ e, double *__restrict__ stat) {
+    __shared__ double a[1024], c[1024];
+    const int nc = b.nx * b.ny * b.nz;
+    double ys = 0.0, yy = 0.0;
+    for (int t = threadIdx.x; t < nc; t += 1024) {
+        const int i = t % b.nx, j = (t / b.nx) % b.ny, k = t / (b.nx * b.ny);
+        const int q = box_index(b, i, j, k);
+        ys += (double)y[q] * (double)s[q];
+        yy += (double)y[q] * (double)y[q];
+    }
+    a[threadIdx.x] = ys;
+    c[threadIdx.x] = yy;
+    __syncthreads();
+    for (int o = 512; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            a[threadIdx.x] += a[threadIdx.x + o];
+            c[threadIdx.x] += c[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    double alpha = c[0] > 0.0 ? a[0] / c[0] : 0.0;
+    if (!isfinite(alpha)) alpha = 0.0;
+    for (int t = threadIdx.x; t < nc; t += 1024) {
+        const int i = t % b.nx, j = (t / b.nx) % b.ny, k = t / (b.nx * b.ny);
+        const int q = box_index(b, i, j, k);
+        e[q] = (R)(alpha * (double)e[q]);
+    }
+    if (threadIdx.x == 0) stat[2] = alpha;
+}
+
 // ---------------------------------------------------------------- BLAS-1
 template <class A, class B>
 __global__ void __launch_bounds__(kBlock) k_cast(long long n, const A *__restrict__ x, B *__restrict__ y) {

@@ -18,12 +18,15 @@
 
 using namespace stk;
 
+extern "C" void *stokes_unet_stream_internal(const stokes_unet *u);
+
 namespace {
 
 constexpr int kMaxLev = 24;
 constexpr int kDenseMax = 2048;     // largest coarsest pressure level solved densely
 constexpr int kRedBlocks = 2048;    // blocks of the streaming reduction kernels
 constexpr int kGroup = 8;           // vectors per multidot / maxpy launch
+constexpr int kLearnedMaxCells = 1 << 18;   // largest level (64^3) the learned stage may run on
 
 thread_local std::string g_setup_error;
 
@@ -116,6 +119,13 @@ struct stokes_ctx {
     int vcycles = 0;
     double visc_ratio = -1.0;   // max viscous/mass diagonal ratio (automatic velocity levels)
     bool diag_vel = false;      // velocity subsolve is one diagonal step (see stokes_options.vel_smoother)
+    // learned stage: network, the level it runs on, feature/prediction buffers
+    stokes_unet *net = nullptr;
+    int lc = -1;
+    bool learned_active = false;
+    double stall_ratio = 0.9;
+    float *lf[4] = {nullptr, nullptr, nullptr, nullptr};   // f0, f1, f2, prediction (planar, <= 64^3)
+    double *lstat = nullptr;
     // measurement: HIP events around every finest-level launch of one kernel class
     int prof_kind = -1;
     std::vector<hipEvent_t> ev;
@@ -209,6 +219,9 @@ void carve_all(Carver &cv, stokes_ctx &c) {
     c.q = cv.fields<double>(b, 1);
     c.partial = cv.take<double>((size_t)kRedBlocks * kGroup);
     c.dsc = cv.take<double>(4 * (size_t)(c.m + 8));
+    if (d == 3)
+        for (int a = 0; a < 4; ++a) c.lf[a] = cv.take<float>((size_t)kLearnedMaxCells);
+    c.lstat = cv.take<double>(8);
     c.dflag = cv.take<int>(64);
     c.ws_need = cv.off + 256;
 }
@@ -427,6 +440,56 @@ R *p_vcycle(stokes_ctx &c, MG<R> &mg, int l, R *e, R *r, bool zero_guess) {
     return cur;
 }
 
+// ---------------------------------------------------------------- learned stage
+// Initial guess for the pressure cycles from the network: the pressure
+// right-hand side is restricted to the learned level, scaled to unit RMS and
+// fed with the static features; the prediction's amplitude is fitted by least
+// squares against that level's operator, and the result is prolonged
+// (trilinearly, level by level) to the finest level.
+template <class R>
+void learned_guess(stokes_ctx &c, MG<R> &mg, R *phi0) {
+    const int lc = c.lc;
+    const R *src = mg.L[0].rp;
+    for (int l = 0; l < lc; ++l) {
+        k_restrict_avg3<R><<<nblocks_box(mg.L[l + 1].b), kBlock, 0, c.stream>>>(mg.L[l].b, mg.L[l + 1].b, src, mg.L[l + 1].rp);
+        src = mg.L[l + 1].rp;
+    }
+    Level<R> &C = mg.L[lc];
+    const int nc = C.b.nx * C.b.ny * C.b.nz;
+    k_normalise_planar<R><<<1, 1024, 0, c.stream>>>(C.b, C.rp, 0, c.lf[2], c.lstat);
+    stokes_status st = stokes_unet_forward(c.net, c.lf[0], c.lf[1], c.lf[2], c.lf[3]);
+    if (st != STOKES_OK) throw HipError{hipErrorUnknown, "stokes_unet_forward"};
+    k_planar_to_box<R><<<(nc + kBlock - 1) / kBlock, kBlock, 0, c.stream>>>(C.b, c.lf[3], C.ep2);
+    k_p_apply3<R><<<nblocks_box(C.b), kBlock, 0, c.stream>>>(C.b, C.ep2, C.beta[0], C.beta[1], C.beta[2], C.ep);
+    k_fit_amplitude<R><<<1, 1024, 0, c.stream>>>(C.b, C.ep, C.rp, C.ep2, c.lstat);
+    R *cur = C.ep2;
+    for (int l = lc - 1; l >= 0; --l) {
+        R *dst = l == 0 ? phi0 : mg.L[l].ep2;
+        fill<R>(c, dst - mg.L[l].b.guard, mg.L[l].b.stride, R(0));
+        k_p_prolong_add<3, R><<<nblocks_box(mg.L[l].b), kBlock, 0, c.stream>>>(mg.L[l].b, mg.L[l + 1].b, 1, cur, dst);
+        cur = dst;
+    }
+}
+
+// Pressure subsolve of the preconditioner: p_cycles cycles on -L_rho phi = r
+// (level 0 right-hand side already in L0.rp), from zero or from the learned
+// guess.  Returns the array holding phi.
+template <int DIM, class R>
+R *pressure_cycles(stokes_ctx &c, MG<R> &mg) {
+    Level<R> &L0 = mg.L[0];
+    R *phi = L0.ep;
+    bool zero = true;
+    if (DIM == 3 && c.net && c.learned_active) {
+        learned_guess<R>(c, mg, phi);
+        zero = false;
+    }
+    for (int cyc = 0; cyc < c.opt.p_cycles; ++cyc) {
+        phi = p_vcycle<DIM, R>(c, mg, 0, phi, L0.rp, zero && cyc == 0);
+        c.vcycles++;
+    }
+    return phi;
+}
+
 // ---------------------------------------------------------------- preconditioner
 // z = P^{-1} v:
 //   1. u~ ~= A^{-1} v_u                      (velocity V-cycles)
@@ -447,11 +510,7 @@ void precond(stokes_ctx &c, MG<R> &mg, double *v, double *z) {
         double *d2 = DIM == 3 ? c.dinv[2] : c.dinv[1];
         k_precond_div_jac<DIM, R><<<nblocks_box(c.fine), kBlock, 0, c.stream>>>(
             c.fine, vu[0], vu[1], DIM == 3 ? vu[2] : vu[1], c.dinv[0], c.dinv[1], d2, vp, c.dt, c.q, L0.rp);
-        R *phi = L0.ep;
-        for (int cyc = 0; cyc < c.opt.p_cycles; ++cyc) {
-            phi = p_vcycle<DIM, R>(c, mg, 0, phi, L0.rp, cyc == 0);
-            c.vcycles++;
-        }
+        R *phi = pressure_cycles<DIM, R>(c, mg);
         k_precond_update_jac<DIM, R><<<nblocks_box(c.fine), kBlock, 0, c.stream>>>(
             c.fine, vu[0], vu[1], DIM == 3 ? vu[2] : vu[1], c.dinv[0], c.dinv[1], d2, phi, c.beta[0], c.beta[1],
             DIM == 3 ? c.beta[2] : c.beta[1], c.mu, c.q, c.dt, c.theta, zu[0], zu[1], DIM == 3 ? zu[2] : zu[1], zp);
@@ -479,11 +538,7 @@ void precond(stokes_ctx &c, MG<R> &mg, double *v, double *z) {
         c.vcycles++;
     }
     k_precond_div<DIM, R><<<nblocks_box(c.fine), kBlock, 0, c.stream>>>(c.fine, eu[0], eu[1], eu[2], vp, c.dt, c.q, L0.rp);
-    R *phi = L0.ep;
-    for (int cyc = 0; cyc < c.opt.p_cycles; ++cyc) {
-        phi = p_vcycle<DIM, R>(c, mg, 0, phi, L0.rp, cyc == 0);
-        c.vcycles++;
-    }
+    R *phi = pressure_cycles<DIM, R>(c, mg);
     k_precond_update<DIM, R><<<nblocks_box(c.fine), kBlock, 0, c.stream>>>(
         c.fine, eu[0], eu[1], eu[2], phi, c.beta[0], c.beta[1], DIM == 3 ? c.beta[2] : c.beta[1], c.mu, c.q,
         c.dt, c.theta, zu[0], zu[1], DIM == 3 ? zu[2] : zu[1], zp);
@@ -637,7 +692,13 @@ stokes_status fgmres(stokes_ctx &c, MG<R> &mg, double tol, stokes_stats &st) {
             g[j] = cs[j] * g[j];
             st.iters++;
             nj = j + 1;
+            const double prev_est = j == 0 ? 1.0 : st.rel_res_est;
             st.rel_res_est = std::fabs(g[j + 1]) / bnorm;
+            if (c.net && c.learned_active && st.rel_res_est > c.stall_ratio * prev_est) {
+                // the learned guess stopped helping: plain multigrid from here on
+                c.learned_active = false;
+                st.fell_back = 1;
+            }
             if (std::fabs(g[j + 1]) <= tol * bnorm) break;
             if (hn == 0.0) { breakdown = true; break; }
         }
@@ -974,6 +1035,7 @@ template <int DIM>
 stokes_status solve_impl(stokes_ctx &c, const double *const rhs_u[3], const double *rhs_p, double tol,
                          double *const x_u[3], double *x_p, stokes_stats &st) {
     c.vcycles = 0;
+    c.learned_active = c.net != nullptr;
     pack_vector<DIM>(c, rhs_u, rhs_p, c.bk);
     k_fill<int><<<1, kBlock, 0, c.stream>>>(1, c.dflag, 0);
     k_check_finite<<<nblocks_stream(c.vlen), kBlock, 0, c.stream>>>(c.vlen, c.bk, c.dflag);
@@ -1028,6 +1090,74 @@ stokes_status solve_impl(stokes_ctx &c, const double *const rhs_u[3], const doub
     HIPCHK(hipGetLastError());
     prof_collect(c);
     return s;
+}
+
+}  // namespace
+
+namespace {
+
+template <class R>
+int learned_level(const MG<R> &mg, int n) {
+    for (int l = 0; l < mg.nlev; ++l) {
+        const Box &b = mg.L[l].b;
+        if (b.dim == 3 && b.nx == n && b.ny == n && b.nz == n && (long long)n * n * n <= kLearnedMaxCells) return l;
+    }
+    return -1;
+}
+
+template <class R>
+void learned_static(stokes_ctx &c, MG<R> &mg, int lc, float *f0, float *f1) {
+    Level<R> &C = mg.L[lc];
+    const int nc = C.b.nx * C.b.ny * C.b.nz;
+    k_learned_static<R><<<(nc + kBlock - 1) / kBlock, kBlock, 0, c.stream>>>(C.b, C.beta[0], C.beta[1], C.beta[2], C.mu, f0, f1);
+}
+
+// Training tuple on the level with n^3 cells: static features, the restricted
+// pressure right-hand side of the first preconditioner application (unit RMS)
+// and the restricted converged pressure solution (zero mean, unit RMS).
+template <class R>
+void learned_tuple(stokes_ctx &c, MG<R> &mg, int lc, int cycles, float *f0, float *f1, float *s_c, float *phi_c) {
+    const Box &fb = c.fine;
+    Level<R> &L0 = mg.L[0];
+    double *v = c.bk;
+    // steps 1-2 of the preconditioner on v = b: u~ and the Poisson right-hand side
+    if (c.diag_vel) {
+        k_precond_div_jac<3, R><<<nblocks_box(fb), kBlock, 0, c.stream>>>(
+            fb, c.fld(v, 0), c.fld(v, 1), c.fld(v, 2), c.dinv[0], c.dinv[1], c.dinv[2], c.fld(v, 3), c.dt, c.q, L0.rp);
+    } else {
+        double *z = c.vec(c.Z, 0);
+        R *eu[3], *ru[3];
+        if (sizeof(R) == sizeof(double)) {
+            for (int a = 0; a < 3; ++a) {
+                eu[a] = reinterpret_cast<R *>(c.fld(z, a));
+                ru[a] = reinterpret_cast<R *>(c.fld(v, a));
+            }
+        } else {
+            long long n = 3LL * fb.stride;
+            k_cast<double, R><<<nblocks_stream(n), kBlock, 0, c.stream>>>(n, v, L0.ru[0] - L0.b.guard);
+            for (int a = 0; a < 3; ++a) {
+                eu[a] = L0.eu[a];
+                ru[a] = L0.ru[a];
+            }
+        }
+        for (int cyc = 0; cyc < std::max(1, c.opt.vel_cycles); ++cyc) vel_vcycle<3, R>(c, mg, 0, eu, ru, cyc == 0);
+        k_precond_div<3, R><<<nblocks_box(fb), kBlock, 0, c.stream>>>(fb, eu[0], eu[1], eu[2], c.fld(v, 3), c.dt, c.q, L0.rp);
+    }
+    R *phi = L0.ep;
+    for (int cyc = 0; cyc < cycles; ++cyc) phi = p_vcycle<3, R>(c, mg, 0, phi, L0.rp, cyc == 0);
+    const R *ss = L0.rp;
+    const R *pp = phi;
+    for (int l = 0; l < lc; ++l) {
+        Level<R> &F = mg.L[l], &C = mg.L[l + 1];
+        k_restrict_avg3<R><<<nblocks_box(C.b), kBlock, 0, c.stream>>>(F.b, C.b, ss, C.rp);
+        k_restrict_avg3<R><<<nblocks_box(C.b), kBlock, 0, c.stream>>>(F.b, C.b, pp, C.ep);
+        ss = C.rp;
+        pp = C.ep;
+    }
+    Level<R> &C = mg.L[lc];
+    k_normalise_planar<R><<<1, 1024, 0, c.stream>>>(C.b, ss, 0, s_c, c.lstat);
+    k_normalise_planar<R><<<1, 1024, 0, c.stream>>>(C.b, pp, 1, phi_c, c.lstat + 3);
+    learned_static<R>(c, mg, lc, f0, f1);
 }
 
 }  // namespace
@@ -1194,6 +1324,61 @@ stokes_status stokes_profile_read(stokes_ctx *ctx, double *ms_total, long long *
     if (bytes) *bytes = ctx->prof_bytes;
     ctx->prof_ms = ctx->prof_bytes = 0.0;
     ctx->prof_launches = 0;
+    return STOKES_OK;
+}
+
+stokes_status stokes_attach_learned(stokes_ctx *ctx, stokes_unet *net, double stall_ratio) {
+    if (!ctx) return STOKES_EINVAL;
+    ctx->err.clear();
+    if (!net) {
+        ctx->net = nullptr;
+        ctx->lc = -1;
+        return STOKES_OK;
+    }
+    if (ctx->dim != 3) { ctx->err = "the learned stage needs a 3D grid"; return STOKES_EINVAL; }
+    if (stokes_unet_stream_internal(net) != reinterpret_cast<void *>(ctx->stream)) {
+        ctx->err = "network and solver must use the same stream";
+        return STOKES_EINVAL;
+    }
+    const int n = stokes_unet_size(net);
+    int lc = ctx->opt.precision == 1 ? learned_level(ctx->mgf, n) : learned_level(ctx->mgd, n);
+    if (lc < 0) { ctx->err = "no multigrid level has n^3 cells for this network (n <= 64)"; return STOKES_EINVAL; }
+    if (!(stall_ratio >= 0.0)) { ctx->err = "stall_ratio must be >= 0"; return STOKES_EINVAL; }
+    try {
+        if (ctx->opt.precision == 1) learned_static<float>(*ctx, ctx->mgf, lc, ctx->lf[0], ctx->lf[1]);
+        else learned_static<double>(*ctx, ctx->mgd, lc, ctx->lf[0], ctx->lf[1]);
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+    } catch (const HipError &e) {
+        ctx->err = std::string("HIP error in ") + e.what + ": " + hipGetErrorString(e.e);
+        return STOKES_EHIP;
+    }
+    ctx->net = net;
+    ctx->lc = lc;
+    ctx->stall_ratio = stall_ratio;
+    return STOKES_OK;
+}
+
+stokes_status stokes_learned_tuple(stokes_ctx *ctx, const double *const rhs_u[3], const double *rhs_p, int n,
+                                   int cycles, float *f0, float *f1, float *s_c, float *phi_c) {
+    if (!ctx) return STOKES_EINVAL;
+    ctx->err.clear();
+    if (ctx->dim != 3 || !rhs_u || !rhs_u[0] || !rhs_u[1] || !rhs_u[2] || !rhs_p || !f0 || !f1 || !s_c || !phi_c ||
+        cycles < 1) {
+        ctx->err = "bad argument";
+        return STOKES_EINVAL;
+    }
+    int lc = ctx->opt.precision == 1 ? learned_level(ctx->mgf, n) : learned_level(ctx->mgd, n);
+    if (lc < 0) { ctx->err = "no multigrid level has n^3 cells (n <= 64)"; return STOKES_EINVAL; }
+    try {
+        pack_vector<3>(*ctx, rhs_u, rhs_p, ctx->bk);
+        if (ctx->opt.precision == 1) learned_tuple<float>(*ctx, ctx->mgf, lc, cycles, f0, f1, s_c, phi_c);
+        else learned_tuple<double>(*ctx, ctx->mgd, lc, cycles, f0, f1, s_c, phi_c);
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        HIPCHK(hipGetLastError());
+    } catch (const HipError &e) {
+        ctx->err = std::string("HIP error in ") + e.what + ": " + hipGetErrorString(e.e);
+        return STOKES_EHIP;
+    }
     return STOKES_OK;
 }
 
