@@ -93,6 +93,10 @@ typedef struct {
     int matvec_z;        /* 3D matvec kernel: 1 z-marching (register reuse along z), 0 one
                             thread per point; same result to rounding */
     int p_gamma;         /* pressure cycle: 1 V-cycle, 2 W-cycle (two coarse cycles per level) */
+    int p_small;         /* 3D: 1 runs the pressure cycle from the finest level (below the
+                            finest, at most 64^3 cells) whose cycle fits in the LDS of one
+                            workgroup down to the coarsest as one single-workgroup launch per
+                            visit (same passes and arithmetic as 0); 0 one launch per pass */
 } stokes_options;
 
 typedef struct {
@@ -109,6 +113,7 @@ typedef struct {
     double g_mean;        /* mean removed from rhs_p before solving */
     double ms_total;      /* wall time of the call on the host, milliseconds */
     int fell_back;        /* 1 if the learned stage was switched off for stagnation */
+    int small_level;      /* first pressure level cycled in one workgroup (p_small), -1 none */
 } stokes_stats;
 
 typedef struct stokes_ctx stokes_ctx;

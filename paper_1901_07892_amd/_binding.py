@@ -34,7 +34,7 @@ class StokesOptions(C.Structure):
                 ("vel_cycles", C.c_int), ("p_cycles", C.c_int), ("coarse_sweeps", C.c_int),
                 ("vel_levels", C.c_int), ("vel_sweeps", C.c_int), ("p_prolong", C.c_int),
                 ("vel_smoother", C.c_int), ("orth", C.c_int), ("matvec_z", C.c_int),
-                ("p_gamma", C.c_int)]
+                ("p_gamma", C.c_int), ("p_small", C.c_int)]
 
 
 class StokesStats(C.Structure):
@@ -42,7 +42,8 @@ class StokesStats(C.Structure):
                 ("rel_res_est", C.c_double), ("rel_res_true", C.c_double),
                 ("rel_res_plain", C.c_double), ("rel_res_mom", C.c_double),
                 ("rel_res_cont", C.c_double), ("sigma", C.c_double), ("g_mean", C.c_double),
-                ("ms_total", C.c_double), ("fell_back", C.c_int)]
+                ("ms_total", C.c_double), ("fell_back", C.c_int),
+                ("small_level", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

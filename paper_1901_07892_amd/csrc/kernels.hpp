@@ -512,6 +512,158 @@ __global__ void __launch_bounds__(1024) k_dense_solve(int n, const R *__restrict
     }
 }
 
+// ---------------------------------------------------------------- small levels in one workgroup
+// Below a few thousand cells a pressure level costs one launch per colour pass
+// when it is cycled pass by pass, and under W-cycles the small levels are
+// visited 2^l times per cycle, so their launches dominate.  One workgroup runs
+// the whole cycle from such a level down instead: the iterate and right-hand
+// side of every level, and the face coefficients of every level but the first
+// (read from global memory, where they stay in L2), live in LDS, and every
+// pass ends at a workgroup barrier.  The host lists the passes in the order the
+// pass-by-pass cycle launches them; their arithmetic is that of k_p_gs,
+// k_p_residual_restrict, k_p_prolong_add and k_dense_solve.
+enum { SOP_GS = 0, SOP_RESTRICT = 1, SOP_PROLONG = 2, SOP_DENSE = 3, SOP_ZERO = 4 };
+constexpr int kSmallMaxLev = 8;
+constexpr int kSmallThreads = 1024;
+
+// One pass: x = kind, y = level (0 = the first small level), z = colour of a
+// smoothing pass, w = its zero-guess flag (0 no, 1 yes, 2 the launch's).
+struct SmallOp {
+    int kind, level, colour, zero_guess;
+};
+
+template <class R>
+struct SmallMG {
+    int nl;                          // levels in LDS: the first small level and all coarser
+    Box b[kSmallMaxLev];
+    int off_e[kSmallMaxLev];         // LDS element offset of box point 0 of each level's iterate
+    int off_r[kSmallMaxLev];         // ... of its right-hand side
+    int off_b[kSmallMaxLev];         // ... of its three face coefficients (level >= 1), nb + plane apart
+    int stride_b[kSmallMaxLev];
+    const R *gbeta[kSmallMaxLev][3]; // global face coefficients of each level
+    const R *dense;                  // coarsest level: dense pseudo-inverse (global), n x n
+    int ndense;
+    int off_dense;                   // LDS copy of the dense matrix (-1: read from global)
+    int off_rs;                      // LDS staging of the coarsest right-hand side (ndense)
+    int lin;                         // prolongation (see prolong_value)
+    int lds_elems;                   // LDS size in elements of R
+};
+
+template <class R, class BP>
+__device__ inline void small_gs(const Box &b, R *e, const R *r, BP bx, BP by, BP bz, int colour, bool zg) {
+    const int hx = (b.nx + 1) >> 1;
+    const int total = hx * b.ny * b.nz;
+    for (int t = threadIdx.x; t < total; t += kSmallThreads) {
+        const int ii = t % hx, jk = t / hx;
+        const int j = jk % b.ny, k = jk / b.ny;
+        const int i = 2 * ii + ((j + k + colour) & 1);
+        if (i >= b.nx) continue;
+        const int idx = box_index(b, i, j, k);
+        R off, dg;
+        prow<3, R>(b, idx, e, bx, by, bz, off, dg);
+        if (zg) off = R(0);
+        e[idx] = dg > R(0) ? (r[idx] + off) / dg : R(0);
+    }
+}
+
+template <class R, class BP>
+__device__ inline void small_restrict(const Box &fb, const Box &cb, const R *e, const R *r, BP bx, BP by, BP bz,
+                                      R *rc) {
+    const int total = cb.nx * cb.ny * cb.nz;
+    for (int t = threadIdx.x; t < total; t += kSmallThreads) {
+        const int I = t % cb.nx, JK = t / cb.nx;
+        const int J = JK % cb.ny, K = JK / cb.ny;
+        R acc = 0;
+        for (int dk = 0; dk < 2; ++dk)
+            for (int dj = 0; dj < 2; ++dj)
+                for (int di = 0; di < 2; ++di) {
+                    const int q = box_index(fb, 2 * I + di, 2 * J + dj, 2 * K + dk);
+                    R off, dg;
+                    prow<3, R>(fb, q, e, bx, by, bz, off, dg);
+                    acc += r[q] - (dg * e[q] - off);
+                }
+        rc[box_index(cb, I, J, K)] = acc * R(0.125);
+    }
+}
+
+template <class R, class MP>
+__device__ inline void small_dense(const Box &b, int n, MP M, R *rs, const R *r, R *e) {
+    for (int t = threadIdx.x; t < n; t += kSmallThreads) {
+        const int i = t % b.nx, jk = t / b.nx;
+        rs[t] = r[box_index(b, i, jk % b.ny, jk / b.ny)];
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < n; t += kSmallThreads) {
+        R acc = 0;
+        for (int q = 0; q < n; ++q) acc += M[(size_t)t * n + q] * rs[q];
+        const int i = t % b.nx, jk = t / b.nx;
+        e[box_index(b, i, jk % b.ny, jk / b.ny)] = acc;
+    }
+}
+
+template <class R>
+__global__ void __launch_bounds__(kSmallThreads) k_p_small_cycle(SmallMG<R> m, const SmallOp *__restrict__ ops,
+        int nops, int zero_guess, R *__restrict__ e, const R *__restrict__ r) {
+    extern __shared__ unsigned char smem_raw[];
+    R *S = reinterpret_cast<R *>(smem_raw);
+    for (int t = threadIdx.x; t < m.lds_elems; t += kSmallThreads) S[t] = R(0);
+    __syncthreads();
+    const Box &b0 = m.b[0];
+    for (int t = threadIdx.x; t < b0.nb; t += kSmallThreads) {
+        S[m.off_r[0] + t] = r[t];
+        if (!zero_guess) S[m.off_e[0] + t] = e[t];
+    }
+    for (int l = 1; l < m.nl; ++l)
+        for (int a = 0; a < 3; ++a) {
+            R *dst = S + m.off_b[l] + a * m.stride_b[l];
+            const R *src = m.gbeta[l][a];
+            for (int t = threadIdx.x; t < m.b[l].nb; t += kSmallThreads) dst[t] = src[t];
+        }
+    if (m.off_dense >= 0)
+        for (int t = threadIdx.x; t < m.ndense * m.ndense; t += kSmallThreads) S[m.off_dense + t] = m.dense[t];
+    __syncthreads();
+    for (int o = 0; o < nops; ++o) {
+        const SmallOp op = ops[o];
+        const int l = op.level;
+        const Box &b = m.b[l];
+        R *E = S + m.off_e[l];
+        R *Rr = S + m.off_r[l];
+        if (op.kind == SOP_GS) {
+            const bool zg = op.zero_guess == 2 ? zero_guess != 0 : op.zero_guess != 0;
+            if (l == 0) {
+                small_gs<R, const R *__restrict__>(b, E, Rr, m.gbeta[0][0], m.gbeta[0][1], m.gbeta[0][2], op.colour, zg);
+            } else {
+                const R *B = S + m.off_b[l];
+                small_gs<R, const R *>(b, E, Rr, B, B + m.stride_b[l], B + 2 * m.stride_b[l], op.colour, zg);
+            }
+        } else if (op.kind == SOP_RESTRICT) {
+            R *rc = S + m.off_r[l + 1];
+            if (l == 0) {
+                small_restrict<R, const R *__restrict__>(b, m.b[1], E, Rr, m.gbeta[0][0], m.gbeta[0][1], m.gbeta[0][2], rc);
+            } else {
+                const R *B = S + m.off_b[l];
+                small_restrict<R, const R *>(b, m.b[l + 1], E, Rr, B, B + m.stride_b[l], B + 2 * m.stride_b[l], rc);
+            }
+        } else if (op.kind == SOP_PROLONG) {
+            const Box &cb = m.b[l + 1];
+            const R *ec = S + m.off_e[l + 1];
+            const int total = b.nx * b.ny * b.nz;
+            for (int t = threadIdx.x; t < total; t += kSmallThreads) {
+                const int i = t % b.nx, jk = t / b.nx;
+                const int j = jk % b.ny, k = jk / b.ny;
+                E[box_index(b, i, j, k)] += prolong_value<3, R>(cb, ec, i, j, k, m.lin);
+            }
+        } else if (op.kind == SOP_DENSE) {
+            if (m.off_dense >= 0) small_dense<R, const R *>(b, m.ndense, S + m.off_dense, S + m.off_rs, Rr, E);
+            else small_dense<R, const R *__restrict__>(b, m.ndense, m.dense, S + m.off_rs, Rr, E);
+        } else {   // SOP_ZERO
+            for (int t = threadIdx.x; t < b.nb; t += kSmallThreads) E[t] = R(0);
+        }
+        __syncthreads();
+    }
+    for (int t = threadIdx.x; t < b0.nb; t += kSmallThreads) e[t] = S[m.off_e[0] + t];
+}
+
 // One full red-black Gauss-Seidel sweep of -L_rho e = r in 3D, both colours in
 // one launch.  A block owns a TX x TY column of cells and a chunk of kc planes
 // and marches in z.  LDS holds rings of four planes: the old values (tile plus

@@ -27,6 +27,7 @@ constexpr int kDenseMax = 2048;     // largest coarsest pressure level solved de
 constexpr int kRedBlocks = 2048;    // blocks of the streaming reduction kernels
 constexpr int kGroup = 8;           // vectors per multidot / maxpy launch
 constexpr int kLearnedMaxCells = 1 << 18;   // largest level (64^3) the learned stage may run on
+constexpr int kSmallMaxOps = 4096;          // passes of one small-level cycle
 
 thread_local std::string g_setup_error;
 
@@ -79,6 +80,12 @@ struct MG {
     int *dmap = nullptr;
     int ndense = 0;
     bool use_dense = false;
+    // single-workgroup cycle of the small levels (k_p_small_cycle), from level small_l0 down
+    int small_l0 = -1;
+    SmallMG<R> small{};
+    SmallOp *ops = nullptr;
+    int nops = 0;
+    size_t small_lds = 0;
 };
 
 bool can_coarsen(const Box &b) {
@@ -195,6 +202,7 @@ void carve_mg(Carver &cv, stokes_ctx &c, MG<R> &mg, bool alias_level0) {
         mg.dense = cv.take<R>((size_t)mg.ndense * mg.ndense);
         mg.dmap = cv.take<int>(mg.ndense);
     }
+    if (b.dim == 3 && c.opt.p_small) mg.ops = cv.take<SmallOp>(kSmallMaxOps);
 }
 
 void carve_all(Carver &cv, stokes_ctx &c) {
@@ -386,6 +394,11 @@ void p_sweep3(stokes_ctx &c, Level<R> &L, const R *in, R *out, const R *r, bool 
 // other buffer.
 template <int DIM, class R>
 R *p_vcycle(stokes_ctx &c, MG<R> &mg, int l, R *e, R *r, bool zero_guess) {
+    if (DIM == 3 && l == mg.small_l0) {
+        k_p_small_cycle<R><<<1, kSmallThreads, mg.small_lds, c.stream>>>(mg.small, mg.ops, mg.nops,
+                                                                       zero_guess ? 1 : 0, e, r);
+        return e;
+    }
     Level<R> &L = mg.L[l];
     R *cur = e;
     R *spare = (e == L.ep) ? L.ep2 : L.ep;
@@ -799,6 +812,101 @@ void build_dense(stokes_ctx &c, MG<R> &mg) {
     HIPCHK(hipStreamSynchronize(c.stream));
 }
 
+// Passes of the cycle on level l (relative index l - l0 in the pass list), in
+// the order p_vcycle launches them on flat levels.  zg: zero-guess flag of the
+// level's first smoothing pass (0 no, 1 yes, 2 the launch's).
+template <class R>
+void gen_small_ops(const stokes_ctx &c, const MG<R> &mg, int l0, int l, int zg, std::vector<SmallOp> &ops) {
+    const int rel = l - l0;
+    auto sweeps = [&](int n, int z) {
+        for (int s = 0; s < n; ++s)
+            for (int colour = 0; colour < 2; ++colour)
+                ops.push_back({SOP_GS, rel, colour, (s == 0 && colour == 0) ? z : 0});
+    };
+    if (l == mg.nlev - 1) {
+        if (mg.use_dense) ops.push_back({SOP_DENSE, rel, 0, 0});
+        else sweeps(std::max(1, c.opt.coarse_sweeps), zg);
+        return;
+    }
+    // with a zero guess and no pre-smoothing the iterate must read as zero (at
+    // the first level the launch leaves it zero by not loading it)
+    if (zg == 1 && c.opt.nu1 == 0) ops.push_back({SOP_ZERO, rel, 0, 0});
+    sweeps(c.opt.nu1, zg);
+    ops.push_back({SOP_RESTRICT, rel, 0, 0});
+    gen_small_ops<R>(c, mg, l0, l + 1, 1, ops);
+    for (int g = 1; g < c.opt.p_gamma && l + 1 < mg.nlev - 1; ++g) gen_small_ops<R>(c, mg, l0, l + 1, 0, ops);
+    ops.push_back({SOP_PROLONG, rel, 0, 0});
+    sweeps(c.opt.nu2, 0);
+}
+
+// Picks the finest level (below the finest) from which the whole 3D cycle fits
+// in the LDS of one workgroup, lays out that LDS and uploads the pass list.
+template <class R>
+void plan_small(stokes_ctx &c, MG<R> &mg) {
+    mg.small_l0 = -1;
+    if (c.dim != 3 || !c.opt.p_small || !mg.ops || mg.nlev < 3) return;
+    int dev = 0, lds_max = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    size_t budget = std::min<size_t>((size_t)lds_max, 160 * 1024);
+    for (int l0 = 1; l0 <= mg.nlev - 2; ++l0) {
+        const Box &f = mg.L[l0].b;
+        if ((long long)f.nx * f.ny * f.nz > (1LL << 18) || mg.nlev - l0 > kSmallMaxLev) continue;
+        SmallMG<R> s{};
+        s.nl = mg.nlev - l0;
+        size_t off = 0;
+        for (int k = 0; k < s.nl; ++k) {
+            const Level<R> &L = mg.L[l0 + k];
+            const Box &b = L.b;
+            const size_t nl = (size_t)b.nb + b.plane;     // one zero plane below the box
+            s.b[k] = b;
+            s.off_e[k] = (int)(off + b.plane);
+            off += nl;
+            s.off_r[k] = (int)(off + b.plane);
+            off += nl;
+            s.stride_b[k] = (int)nl;
+            s.off_b[k] = -1;
+            if (k >= 1) {
+                s.off_b[k] = (int)(off + b.plane);
+                off += 3 * nl;
+            }
+            for (int a = 0; a < 3; ++a) s.gbeta[k][a] = L.beta[a];
+        }
+        s.ndense = mg.use_dense ? mg.ndense : 0;
+        s.dense = mg.dense;
+        s.off_rs = (int)off;
+        off += s.ndense;
+        if (off * sizeof(R) > budget) continue;
+        s.off_dense = -1;
+        const size_t nd2 = (size_t)s.ndense * s.ndense;
+        if (s.ndense > 0 && (off + nd2) * sizeof(R) <= budget) {
+            s.off_dense = (int)off;
+            off += nd2;
+        }
+        s.lin = c.opt.p_prolong;
+        s.lds_elems = (int)off;
+        std::vector<SmallOp> ops;
+        gen_small_ops<R>(c, mg, l0, l0, 2, ops);
+        if (ops.size() > (size_t)kSmallMaxOps) continue;
+        if (off * sizeof(R) > 64 * 1024 &&
+            hipFuncSetAttribute(reinterpret_cast<const void *>(&k_p_small_cycle<R>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)(off * sizeof(R))) != hipSuccess) {
+            // the runtime refuses more than 64 KiB: plan again within that
+            (void)hipGetLastError();
+            budget = 64 * 1024;
+            l0 = 0;
+            continue;
+        }
+        HIPCHK(hipMemcpyAsync(mg.ops, ops.data(), sizeof(SmallOp) * ops.size(), hipMemcpyHostToDevice, c.stream));
+        HIPCHK(hipStreamSynchronize(c.stream));
+        mg.small = s;
+        mg.nops = (int)ops.size();
+        mg.small_lds = off * sizeof(R);
+        mg.small_l0 = l0;
+        return;
+    }
+}
+
 template <int DIM, class R>
 void build_hierarchy(stokes_ctx &c, MG<R> &mg, bool cast_level0) {
     Level<R> &L0 = mg.L[0];
@@ -829,6 +937,7 @@ void build_hierarchy(stokes_ctx &c, MG<R> &mg, bool cast_level0) {
         }
     }
     if (mg.use_dense) build_dense<R>(c, mg);
+    plan_small<R>(c, mg);
 }
 
 __global__ void k_minmax(Box b, const double *__restrict__ m0, const double *__restrict__ m1,
@@ -903,6 +1012,7 @@ stokes_options defaults() {
     o.orth = 1;
     o.matvec_z = 1;
     o.p_gamma = 2;
+    o.p_small = 1;
     return o;
 }
 
@@ -930,6 +1040,7 @@ const char *check_grid_opts(const stokes_grid *g, const stokes_options &o) {
     if (o.orth != 1 && o.orth != 2) return "orth must be 1 or 2";
     if (o.matvec_z != 0 && o.matvec_z != 1) return "matvec_z must be 0 or 1";
     if (o.p_gamma != 1 && o.p_gamma != 2) return "p_gamma must be 1 (V-cycle) or 2 (W-cycle)";
+    if (o.p_small != 0 && o.p_small != 1) return "p_small must be 0 or 1";
     return nullptr;
 }
 
@@ -1290,6 +1401,7 @@ stokes_status stokes_solve(stokes_ctx *ctx, const double *const rhs_u[3], const 
     st.ms_total = std::chrono::duration<double, std::milli>(t1 - t0).count();
     st.vcycles = ctx->vcycles;
     st.levels = ctx->opt.precision == 1 ? ctx->mgf.nlev : ctx->mgd.nlev;
+    st.small_level = ctx->opt.precision == 1 ? ctx->mgf.small_l0 : ctx->mgd.small_l0;
     st.sigma = ctx->sigma;
     if (stats) *stats = st;
     return s;

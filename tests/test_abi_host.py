@@ -68,3 +68,15 @@ def test_bad_options_rejected_on_host(S):
     with pytest.raises(S.StokesError) as e:
         S.stokes_setup([1, 2, None], 4, 1e-3, g, o, 8, 16, stream=0)
     assert e.value.status == -3          # workspace too small, detected on the host
+
+
+def test_options_struct_layout_matches_library(S):
+    """The ctypes mirror of stokes_options ends where the C struct ends: the last
+    fields read back with their documented defaults, and a bad value in the last
+    field is rejected by the library's own validation."""
+    o = S.stokes_default_options()
+    assert (o.orth, o.matvec_z, o.p_gamma, o.p_small) == (1, 1, 2, 1)
+    g = S._binding.make_grid(3, (16, 16, 16), (1 / 16,) * 3)
+    assert S.stokes_workspace_size(g, o) > 0
+    o.p_small = 2
+    assert S.stokes_workspace_size(g, o) == 0
