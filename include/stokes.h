@@ -97,6 +97,8 @@ typedef struct {
                             finest, at most 64^3 cells) whose cycle fits in the LDS of one
                             workgroup down to the coarsest as one single-workgroup launch per
                             visit (same passes and arithmetic as 0); 0 one launch per pass */
+    int p_wdepth;        /* levels that use p_gamma coarse cycles: the p_wdepth finest (0 =
+                            all); coarser levels take one (a V-cycle below them) */
 } stokes_options;
 
 typedef struct {
@@ -119,10 +121,11 @@ typedef struct {
 typedef struct stokes_ctx stokes_ctx;
 
 /* Fill *opts with the defaults (FP64, theta 1, automatic sigma, restart 30,
- * max_iters 200, (2,2) smoothing, one velocity cycle and two pressure W-cycles, 40 coarse sweeps,
+ * max_iters 200, (2,2) smoothing, one velocity cycle and three pressure cycles that
+ * are W-cycles on the two finest levels and V-cycles below, 40 coarse sweeps,
  * automatic velocity levels, 1 single-level velocity sweep, piecewise-constant
  * pressure prolongation, diagonal velocity step, one-pass Gram-Schmidt, z-marching
- * matvec). */
+ * matvec, small levels cycled in one workgroup). */
 void stokes_default_options(stokes_options *opts);
 
 /* Bytes of device workspace that stokes_setup needs for this grid and these

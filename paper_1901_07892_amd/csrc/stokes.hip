@@ -344,6 +344,14 @@ void vel_vcycle(stokes_ctx &c, MG<R> &mg, int l, R *const e[3], R *const r[3], b
 }
 
 // ---------------------------------------------------------------- pressure multigrid
+// Coarse cycles per visit of level l: p_gamma on the p_wdepth finest levels (all
+// when p_wdepth = 0), one below; one when the coarse level is solved exactly.
+template <class R>
+int gamma_at(const stokes_ctx &c, const MG<R> &mg, int l) {
+    if (l + 1 >= mg.nlev - 1) return 1;
+    return (c.opt.p_wdepth == 0 || l < c.opt.p_wdepth) ? c.opt.p_gamma : 1;
+}
+
 template <int DIM, class R>
 void p_smooth(stokes_ctx &c, Level<R> &L, R *e, const R *r, int sweeps, bool zero_guess) {
     for (int s = 0; s < sweeps; ++s)
@@ -438,7 +446,7 @@ R *p_vcycle(stokes_ctx &c, MG<R> &mg, int l, R *e, R *r, bool zero_guess) {
     R *ce = p_vcycle<DIM, R>(c, mg, l + 1, C.ep, C.rp, true);
     // W-cycle (p_gamma = 2): a second coarse cycle on the same coarse equation
     // (pointless above the exactly solved coarsest level)
-    for (int g = 1; g < c.opt.p_gamma && l + 1 < mg.nlev - 1; ++g) ce = p_vcycle<DIM, R>(c, mg, l + 1, ce, C.rp, false);
+    for (int g = 1; g < gamma_at(c, mg, l); ++g) ce = p_vcycle<DIM, R>(c, mg, l + 1, ce, C.rp, false);
     if (DIM == 3 && nu2 > 0) {
         sweep(false, ce, &C.b);                    // prolongation folded into the first post-sweep
         for (int s = 1; s < nu2; ++s) sweep(false, nullptr, nullptr);
@@ -834,7 +842,7 @@ void gen_small_ops(const stokes_ctx &c, const MG<R> &mg, int l0, int l, int zg, 
     sweeps(c.opt.nu1, zg);
     ops.push_back({SOP_RESTRICT, rel, 0, 0});
     gen_small_ops<R>(c, mg, l0, l + 1, 1, ops);
-    for (int g = 1; g < c.opt.p_gamma && l + 1 < mg.nlev - 1; ++g) gen_small_ops<R>(c, mg, l0, l + 1, 0, ops);
+    for (int g = 1; g < gamma_at(c, mg, l); ++g) gen_small_ops<R>(c, mg, l0, l + 1, 0, ops);
     ops.push_back({SOP_PROLONG, rel, 0, 0});
     sweeps(c.opt.nu2, 0);
 }
@@ -1003,7 +1011,7 @@ stokes_options defaults() {
     o.nu1 = 2;
     o.nu2 = 2;
     o.vel_cycles = 1;
-    o.p_cycles = 2;
+    o.p_cycles = 3;
     o.coarse_sweeps = 40;
     o.vel_levels = 0;
     o.vel_sweeps = 1;
@@ -1013,6 +1021,7 @@ stokes_options defaults() {
     o.matvec_z = 1;
     o.p_gamma = 2;
     o.p_small = 1;
+    o.p_wdepth = 2;
     return o;
 }
 
@@ -1041,6 +1050,7 @@ const char *check_grid_opts(const stokes_grid *g, const stokes_options &o) {
     if (o.matvec_z != 0 && o.matvec_z != 1) return "matvec_z must be 0 or 1";
     if (o.p_gamma != 1 && o.p_gamma != 2) return "p_gamma must be 1 (V-cycle) or 2 (W-cycle)";
     if (o.p_small != 0 && o.p_small != 1) return "p_small must be 0 or 1";
+    if (o.p_wdepth < 0) return "p_wdepth must be >= 0";
     return nullptr;
 }
 

@@ -75,8 +75,11 @@ def test_options_struct_layout_matches_library(S):
     fields read back with their documented defaults, and a bad value in the last
     field is rejected by the library's own validation."""
     o = S.stokes_default_options()
-    assert (o.orth, o.matvec_z, o.p_gamma, o.p_small) == (1, 1, 2, 1)
+    assert (o.orth, o.matvec_z, o.p_gamma, o.p_small, o.p_wdepth) == (1, 1, 2, 1, 2)
     g = S._binding.make_grid(3, (16, 16, 16), (1 / 16,) * 3)
     assert S.stokes_workspace_size(g, o) > 0
+    o.p_wdepth = -1
+    assert S.stokes_workspace_size(g, o) == 0
+    o.p_wdepth = 0
     o.p_small = 2
     assert S.stokes_workspace_size(g, o) == 0

@@ -4,8 +4,8 @@ arithmetic: after two preconditioned FGMRES iterations the iterates agree to
 rounding, and converged solves take the same number of iterations.  Cases cover
 cubes whose small hierarchy starts at 16^3 with the coarsest dense matrix in
 LDS, a wave-tank shape whose dense matrix (288^2) stays in global memory,
-V- and W-cycles, pre- or post-smoothing only, linear prolongation, FP64 and
-FP32 multigrid."""
+V-cycles, W-cycles at every level or on the finest two, pre- or post-smoothing
+only, linear prolongation, FP64 and FP32 multigrid."""
 import numpy as np
 import pytest
 
@@ -17,11 +17,12 @@ pytestmark = pytest.mark.gpu
 CASES = [("headline_recipe_64cubed", lambda: W.config5(n_cells=64)),
          ("dam_break_64cubed", lambda: W.config3(scale=2)),
          ("wave_tank_256x24x24", lambda: W.config4(scale=4))]
-OPTS = [dict(), dict(p_gamma=1), dict(nu1=0, nu2=2), dict(nu1=3, nu2=1, p_prolong=1)]
+OPTS = [dict(), dict(p_wdepth=0), dict(p_gamma=1), dict(nu1=0, nu2=2, p_wdepth=0),
+        dict(nu1=3, nu2=1, p_prolong=1)]
 
 
 @pytest.mark.parametrize("precision", [0, 1])
-@pytest.mark.parametrize("opts", OPTS, ids=["default", "vcycle", "post_only", "lin_prolong"])
+@pytest.mark.parametrize("opts", OPTS, ids=["default", "wcycle_all", "vcycle", "post_only", "lin_prolong"])
 @pytest.mark.parametrize("name,maker", CASES, ids=[c[0] for c in CASES])
 def test_small_cycle_matches_pass_by_pass(name, maker, opts, precision):
     prob = maker()
