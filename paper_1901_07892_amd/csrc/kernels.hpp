@@ -902,6 +902,138 @@ __global__ void __launch_bounds__(TX *TY) k_p_sweep3b(Box b, int kc, int zero_gu
     }
 }
 
+// Two-barrier fused 3D sweep with the coefficients read once per plane.  Same
+// tiling, rings and result as k_p_sweep3b, but every thread owns one point of
+// the TX x TY tile through both half-sweeps: in the red step of plane k it
+// reads its point's six face coefficients and right-hand side once, updates
+// the point if it is red, and otherwise keeps the seven values in registers
+// for the black step of plane k one step later (a plane later they would no
+// longer be in L2).  The upper z-face coefficient of plane k is the lower one
+// of plane k+1 and is carried over as well.  Threads below the ring size also
+// take one point of the 1-cell halo ring, read directly.  At most 64 VGPRs, so
+// that two 1024-thread blocks share a CU.
+template <class R, int TX, int TY>
+__global__ void __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(8))) k_p_sweep3c(Box b, int kc, int zero_guess, const R *__restrict__ ein,
+        const R *__restrict__ ec, Box cb, int lin, R *__restrict__ eout, const R *__restrict__ r,
+        const R *__restrict__ bx, const R *__restrict__ by, const R *__restrict__ bz) {
+    constexpr int NT = TX * TY;
+    constexpr int EX1 = TX + 2, EY1 = TY + 2, N1 = EX1 * EY1;
+    constexpr int EX2 = TX + 4, EY2 = TY + 4, N2 = EX2 * EY2;
+    constexpr int NRING = N1 - NT;
+    static_assert(NRING <= NT, "ring larger than the tile");
+    __shared__ R oldp[3][N2];
+    __shared__ R newp[3][N1];
+    const int tid = threadIdx.x;
+    const int G = gridDim.x * gridDim.y * gridDim.z;
+    int t = xcd_swizzle(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z), G);
+    const int bx_ = t % gridDim.x;
+    t /= gridDim.x;
+    const int by_ = t % gridDim.y, bz_ = t / gridDim.y;
+    const int i0 = bx_ * TX, j0 = by_ * TY;
+    const int k0 = bz_ * kc, k1 = min(k0 + kc, b.nz);
+    const int sy = b.px, sz = b.plane;
+    const R ix2 = R(b.ihx * b.ihx), iy2 = R(b.ihy * b.ihy), iz2 = R(b.ihz * b.ihz);
+    auto slot = [](int k) { return ((k % 3) + 3) % 3; };
+    auto load_old = [&](int k) {
+        R *dst = oldp[slot(k)];
+        for (int t = tid; t < N2; t += NT) {
+            int i = i0 + (t % EX2) - 2, j = j0 + (t / EX2) - 2;
+            R v = R(0);
+            if (!zero_guess && k >= 0 && k < b.nz && i >= 0 && i < b.nx && j >= 0 && j < b.ny) {
+                int q = box_index(b, i, j, k);
+                v = ein[q];
+                if (ec) v += prolong_value<3, R>(cb, ec, i, j, k, lin);
+            }
+            dst[t] = v;
+        }
+    };
+    // own tile point
+    const int tx = tid % TX, ty = tid / TX;
+    const int i = i0 + tx, j = j0 + ty;
+    const bool own = i < b.nx && j < b.ny;
+    const int o1 = (ty + 1) * EX1 + (tx + 1), o2 = (ty + 2) * EX2 + (tx + 2);
+    // own ring point (tid < NRING): top row, bottom row, left column, right column
+    int rex = 0, rey = 0;
+    if (tid < EX1) { rex = tid; rey = 0; }
+    else if (tid < 2 * EX1) { rex = tid - EX1; rey = EY1 - 1; }
+    else if (tid < 2 * EX1 + TY) { rex = 0; rey = 1 + tid - 2 * EX1; }
+    else { rex = EX1 - 1; rey = 1 + tid - 2 * EX1 - TY; }
+    const int ri = i0 + rex - 1, rj = j0 + rey - 1;
+    const bool ring = tid < NRING && ri >= 0 && ri < b.nx && rj >= 0 && rj < b.ny;
+    const int ro1 = rey * EX1 + rex, ro2 = (rey + 1) * EX2 + (rex + 1);
+    // kept for the black step: weights and right-hand side of the own point
+    R kW = 0, kE = 0, kS = 0, kN = 0, kB = 0, kT = 0, kr = 0;
+    R carryB = 0;          // own point's lower z weight of the next plane
+    bool have_carry = false;
+    load_old(k0 - 2);
+    load_old(k0 - 1);
+    for (int k = k0 - 1; k <= k1; ++k) {
+        load_old(k + 1);
+        __syncthreads();
+        const bool kin = k >= 0 && k < b.nz;
+        const R *om = oldp[slot(k - 1)], *oc = oldp[slot(k)], *op = oldp[slot(k + 1)];
+        R *dst = newp[slot(k)];
+        // red half-sweep of plane k: own tile point
+        {
+            R v = R(0);
+            if (own && kin) {
+                const int q = box_index(b, i, j, k);
+                const R wW = bx[q] * ix2, wE = bx[q + 1] * ix2, wS = by[q] * iy2, wN = by[q + sy] * iy2;
+                const R wB = have_carry ? carryB : bz[q] * iz2;
+                const R wT = bz[q + sz] * iz2;
+                const R rr = r[q];
+                carryB = wT;
+                have_carry = true;
+                if (((i + j + k) & 1) == 0) {
+                    const R dg = wW + wE + wS + wN + wB + wT;
+                    const R off = wW * oc[o2 - 1] + wE * oc[o2 + 1] + wS * oc[o2 - EX2] + wN * oc[o2 + EX2]
+                                + wB * om[o2] + wT * op[o2];
+                    v = dg > R(0) ? (rr + off) / dg : R(0);
+                } else {
+                    kW = wW; kE = wE; kS = wS; kN = wN; kB = wB; kT = wT; kr = rr;
+                    v = oc[o2];
+                }
+            }
+            dst[o1] = v;
+        }
+        // red half-sweep of plane k: own ring point
+        if (tid < NRING) {
+            R v = R(0);
+            if (ring && kin) {
+                if (((ri + rj + k) & 1) == 0) {
+                    const int q = box_index(b, ri, rj, k);
+                    const R wW = bx[q] * ix2, wE = bx[q + 1] * ix2, wS = by[q] * iy2, wN = by[q + sy] * iy2;
+                    const R wB = bz[q] * iz2, wT = bz[q + sz] * iz2;
+                    const R dg = wW + wE + wS + wN + wB + wT;
+                    const R off = wW * oc[ro2 - 1] + wE * oc[ro2 + 1] + wS * oc[ro2 - EX2] + wN * oc[ro2 + EX2]
+                                + wB * om[ro2] + wT * op[ro2];
+                    v = dg > R(0) ? (r[q] + off) / dg : R(0);
+                } else {
+                    v = oc[ro2];
+                }
+            }
+            dst[ro1] = v;
+        }
+        __syncthreads();
+        // black half-sweep of plane k-1 on the tile, written out with the red values
+        const int kk = k - 1;
+        if (kk >= k0 && kk < k1 && own) {
+            const R *nm = newp[slot(kk - 1)], *nc = newp[slot(kk)], *np = newp[slot(kk + 1)];
+            const int q = box_index(b, i, j, kk);
+            R v;
+            if (((i + j + kk) & 1) == 1) {
+                const R dg = kW + kE + kS + kN + kB + kT;
+                const R off = kW * nc[o1 - 1] + kE * nc[o1 + 1] + kS * nc[o1 - EX1] + kN * nc[o1 + EX1]
+                            + kB * nm[o1] + kT * np[o1];
+                v = dg > R(0) ? (kr + off) / dg : R(0);
+            } else {
+                v = nc[o1];
+            }
+            eout[q] = v;
+        }
+    }
+}
+
 // ---------------------------------------------------------------- coefficients
 // Coarse cell viscosity: harmonic mean of the 2^d children.
 template <int DIM, class R>

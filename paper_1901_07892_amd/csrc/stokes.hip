@@ -381,7 +381,7 @@ void p_sweep3_launch(stokes_ctx &c, Level<R> &L, const R *in, R *out, const R *r
         k_p_sweep3<R, TX, TY><<<dim3(gx, gy, gz), TX * TY, 0, c.stream>>>(
             b, kc, zero_guess ? 1 : 0, in, ec, cb ? *cb : b, c.opt.p_prolong, out, r, L.beta[0], L.beta[1], L.beta[2]);
     else
-        k_p_sweep3b<R, TX, TY><<<dim3(gx, gy, gz), TX * TY, 0, c.stream>>>(
+        k_p_sweep3c<R, TX, TY><<<dim3(gx, gy, gz), TX * TY, 0, c.stream>>>(
             b, kc, zero_guess ? 1 : 0, in, ec, cb ? *cb : b, c.opt.p_prolong, out, r, L.beta[0], L.beta[1], L.beta[2]);
 }
 
@@ -651,6 +651,7 @@ stokes_status fgmres(stokes_ctx &c, MG<R> &mg, double tol, stokes_stats &st) {
     st.restarts = 0;
     if (bnorm == 0.0) {
         fill<double>(c, c.xk, c.vlen, 0.0);
+        fill<double>(c, c.vec(c.V, 0), c.vlen, 0.0);   // its residual
         st.rel_res_est = st.rel_res_true = 0.0;
         return STOKES_OK;
     }
@@ -730,6 +731,9 @@ stokes_status fgmres(stokes_ctx &c, MG<R> &mg, double tol, stokes_stats &st) {
         }
         HIPCHK(hipMemcpyAsync(dy, y.data(), sizeof(double) * nj, hipMemcpyHostToDevice, c.stream));
         maxpy(c, 1.0, c.Z, nj, dy, c.xk);
+        // zero-mean pressure before the true residual is formed, so that the
+        // residual left in V[0] on return belongs to the returned iterate
+        remove_p_mean(c, c.xk);
         if (breakdown) {
             apply_fine<DIM>(c, c.xk, c.bk, v0);
             multidot(c, v0, 1, v0, w2, dh);
@@ -1184,10 +1188,9 @@ stokes_status solve_impl(stokes_ctx &c, const double *const rhs_u[3], const doub
     stokes_status s = c.opt.precision == 1 ? fgmres<DIM, float>(c, c.mgf, tol, st)
                                            : fgmres<DIM, double>(c, c.mgd, tol, st);
     if (s < 0) return s;
-    remove_p_mean(c, c.xk);
-    // final residual split into its blocks (plain 2-norm)
+    // final residual split into its blocks (plain 2-norm); fgmres leaves the
+    // residual b - K x of the returned (zero-mean pressure) iterate in V[0]
     double *v0 = c.vec(c.V, 0);
-    apply_fine<DIM>(c, c.xk, c.bk, v0);
     {
         const long long nvel = (long long)DIM * c.fine.stride;
         const unsigned g1 = nblocks_stream(nvel), g2 = nblocks_stream(c.fine.stride), g3 = nblocks_stream(c.vlen);
