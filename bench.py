@@ -39,6 +39,9 @@ def parse():
                     help="first run a plain 1 GiB device copy (reference for HBM counter runs)")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the FP32-multigrid form timed after the plain FP64 solve")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="no solve: turn the rocprofv3 FETCH_SIZE and WRITE_SIZE counter runs of "
+                         "'bench.py --calibrate-copy' into profiles/traffic.json and print a summary")
     ap.add_argument("--verbose", action="store_true")
     return ap.parse_args()
 
@@ -49,6 +52,9 @@ def log(*a):
 
 def main():
     args = parse()
+    if args.traffic_from:
+        traffic_from_counters(*args.traffic_from, n=args.n, precision=args.precision)
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the solve is a single-GPU kernel path "
               "(no multi-GPU sharding is built); use --gpus 1", file=sys.stderr)
@@ -119,7 +125,7 @@ def main():
     n_cells = prob.n_cells
     kms, klaunch, kbytes = S.stokes_profile_read(solver.ctx)
     S.stokes_profile_kernel(solver.ctx, -1)
-    names = {0: "k_apply (matvec)", 1: "k_p_sweep3 (fused pressure RB-GS sweep, finest level)",
+    names = {0: "k_apply3_z (Stokes matvec)", 1: "k_p_sweep3c (fused pressure RB-GS sweep, finest level)",
              2: "k_multidot", 3: "k_maxpy"}
     achieved = kbytes / (kms * 1e-3) / 1e9 if kms > 0 else None
     roofline = {"bound": "hbm", "kernel": names.get(args.prof_kernel),
@@ -268,22 +274,114 @@ def traffic_per_launch(kernel, n, precision):
     return e.get("bytes_per_launch")
 
 
+def _counter_rows(d, counter):
+    import csv
+    rows = []
+    for r in csv.DictReader(open(os.path.join(d, "run_counter_collection.csv"))):
+        if r["Counter_Name"] == counter:
+            rows.append((r["Kernel_Name"], int(r["Grid_Size"]), float(r["Counter_Value"])))
+    return rows
+
+
+def traffic_from_counters(fetch_dir, write_dir, n=256, precision=0):
+    """HBM bytes per launch of the finest fused pressure sweep from two rocprofv3 runs
+    (--pmc FETCH_SIZE, then --pmc WRITE_SIZE) of 'bench.py --calibrate-copy': each
+    counter (KiB per dispatch) is scaled by what it reads for the plain 1 GiB device
+    copy that run starts with.  Writes profiles/traffic.json; prints the summary."""
+    import re
+    fetch, write = _counter_rows(fetch_dir, "FETCH_SIZE"), _counter_rows(write_dir, "WRITE_SIZE")
+    gib_kib = float(1 << 20)
+
+    def calib(rows):
+        v = [c for name, g, c in rows if "copyBuffer" in name and c > 0.25 * gib_kib]
+        if not v:
+            raise SystemExit("no 1 GiB calibration copy in the counter run")
+        return gib_kib / (sum(v) / len(v))
+
+    ff, wf = calib(fetch), calib(write)
+    R = 8 if precision == 0 else 4
+    cells = float(n) ** 3
+    kernels = [  # (label, name pattern, algorithmic bytes per launch on the finest level)
+        ("k_p_sweep3c (finest fused pressure sweep)", r"k_p_sweep3\w*<%s, 64, 16>" % ("double" if R == 8 else "float"),
+         cells * R * 6.0),
+        ("k_apply3_z (Stokes matvec)", r"k_apply3_z<", None),
+        ("k_p_residual_restrict (finest)", r"k_p_residual_restrict<3, %s>" % ("double" if R == 8 else "float"),
+         cells * R * 5.0 + cells / 8 * R),
+        ("k_precond_update_jac", r"k_precond_update_jac<", cells * 8 * 16.0),
+        ("k_precond_div_jac", r"k_precond_div_jac<", cells * 8 * 9.0),
+        ("k_scale", r"k_scale\b", None),
+    ]
+    out = {}
+    lines = []
+    for label, pat, alg in kernels:
+        def pick(rows):
+            m = [(g, c) for name, g, c in rows if re.search(pat, name)]
+            if not m:
+                return None, 0
+            gmax = max(g for g, _ in m)
+            v = [c for g, c in m if g == gmax]
+            return sum(v) / len(v), len(v)
+        fk, nf = pick(fetch)
+        wk, nw = pick(write)
+        if fk is None or wk is None:
+            continue
+        fb, wb = fk * 1024 * ff, wk * 1024 * wf
+        out[label] = (fk, wk, nf, fb, wb, alg)
+        ratio = ("  -> %.2fx algorithmic %.3f GB" % ((fb + wb) / alg, alg / 1e9)) if alg else ""
+        lines.append("  %-44s FETCH %10.1f KiB x %.3f = %.3f GB  WRITE %10.1f KiB x %.3f = %.3f GB  (%d dispatches)%s"
+                     % (label, fk, ff, fb / 1e9, wk, wf, wb / 1e9, nf, ratio))
+    label = kernels[0][0]
+    if label not in out:
+        raise SystemExit("finest sweep not found in the counter runs")
+    fk, wk, nd, fb, wb, alg = out[label]
+    entry = {"kernel": "k_p_sweep3c<%s,64,16> finest level" % ("double" if R == 8 else "float"),
+             "fetch_kib_per_dispatch": fk, "write_kib_per_dispatch": wk, "dispatches": nd,
+             "fetch_factor": ff, "write_factor": wf, "bytes_per_launch": fb + wb,
+             "algorithmic_bytes_per_launch": alg, "kernel_source_hash": kernel_source_hash()}
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    rec = json.load(open(path)) if os.path.exists(path) else {}
+    rec["description"] = ("HBM traffic per launch of the timed kernel from rocprofv3 --pmc FETCH_SIZE and "
+                          "WRITE_SIZE runs, each scaled by the same counter on a plain 1 GiB device copy "
+                          "(bench.py --calibrate-copy); written by bench.py --traffic-from.")
+    rec["commands"] = [
+        "rocprofv3 --pmc FETCH_SIZE --output-format csv -d %s -o run -- python3 -u bench.py --steps 1 "
+        "--warmup 0 --no-cpu-baseline --no-forms --calibrate-copy" % fetch_dir,
+        "rocprofv3 --pmc WRITE_SIZE --output-format csv -d %s -o run -- python3 -u bench.py --steps 1 "
+        "--warmup 0 --no-cpu-baseline --no-forms --calibrate-copy" % write_dir,
+        "python3 bench.py --traffic-from %s %s" % (fetch_dir, write_dir)]
+    rec.setdefault("entries", {})["1/%d/%d" % (n, precision)] = entry
+    with open(path, "w") as f:
+        json.dump(rec, f, indent=1)
+    print("calibration (1 GiB copy): FETCH_SIZE factor %.3f, WRITE_SIZE factor %.3f" % (ff, wf))
+    print("\n".join(lines))
+    print("wrote", path)
+
+
 def cpu_baseline(prob, gpu_iters):
     """The C oracle (OpenMP) on this host, bounded: setup plus ONE FGMRES iteration
-    on the same workload; ms/solve = setup + that iteration's time x the GPU solve's
-    iteration count (both use three pressure V-cycles per preconditioner step)."""
+    on the same 256^3 workload, scaled by the oracle's own iteration count to the
+    same tolerance, taken from a full oracle solve of the same recipe and time step
+    at 128^3 (multigrid-preconditioned iteration counts barely change with the grid)."""
+    import workloads as W
     from oracle import native
     t0 = time.time()
+    small = W.config5(n_cells=prob.n[0] // 2)
+    small.dt = prob.dt
+    _, _, info_s = native.solve_problem(small, tol=prob.tol, p_cycles=3)
+    iters = max(int(info_s["iters"]), 1)
     xu, xp, info = native.solve_problem(prob, max_iters=1, restart=1, p_cycles=3)
     wall = time.time() - t0
     per_iter = info["solve_s"] / max(info["iters"], 1)
-    value = (info["setup_s"] + per_iter * gpu_iters) * 1e3
-    log("cpu baseline: setup %.1fs, 1 iteration %.1fs (wall %.1fs)" % (info["setup_s"], info["solve_s"], wall))
+    value = (info["setup_s"] + per_iter * iters) * 1e3
+    log("cpu baseline: %d oracle iterations at %d^3; 256^3 setup %.1fs, 1 iteration %.1fs (wall %.1fs)"
+        % (iters, small.n[0], info["setup_s"], info["solve_s"], wall))
     return {"value": value, "unit": "ms/solve", "cores": native.num_threads(), "kind": "oracle",
-            "sample": "C oracle (FP64, OpenMP for matvec/BLAS, lexicographic Gauss-Seidel multigrid) "
-                      "on the same %s workload: setup plus 1 FGMRES iteration (%.1f s), scaled to "
-                      "the GPU solve's %d iterations" % (prob.name, info["solve_s"], gpu_iters),
-            "measured_s": wall}
+            "sample": "C oracle (FP64, OpenMP for matvec/BLAS, lexicographic Gauss-Seidel multigrid, three "
+                      "pressure V-cycles per step) on the same %s workload: setup plus 1 FGMRES iteration "
+                      "(%.1f s), scaled to the oracle's %d iterations to tol %.0e on the same recipe and dt at %d^3 "
+                      "(the GPU solve takes %d)" % (prob.name, info["solve_s"], iters, prob.tol, small.n[0],
+                                                   gpu_iters),
+            "oracle_iters": iters, "measured_s": wall}
 
 
 if __name__ == "__main__":
