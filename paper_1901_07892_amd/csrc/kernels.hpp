@@ -1218,11 +1218,13 @@ __global__ void __launch_bounds__(kBlock) k_precond_update(Box b, const R *eu, c
 // Diagonal (point-Jacobi) form of step 1 folded into the glue kernels: when the
 // velocity operator is mass dominated, u~ = D_A^{-1} v_u with dinv the inverse
 // diagonal of A.  Same formulas as k_precond_div / k_precond_update otherwise.
+// The input vector is vs * (vu, vv, vw, rp): the Krylov basis is stored
+// unnormalised with its scale kept aside.
 template <int DIM, class R>
 __global__ void __launch_bounds__(kBlock) k_precond_div_jac(Box b, const double *__restrict__ vu,
         const double *__restrict__ vv, const double *__restrict__ vw, const double *__restrict__ du,
-        const double *__restrict__ dv, const double *__restrict__ dw, const double *__restrict__ rp, double dt,
-        double *__restrict__ q, R *__restrict__ s) {
+        const double *__restrict__ dv, const double *__restrict__ dw, const double *__restrict__ rp, double vs,
+        double dt, double *__restrict__ q, R *__restrict__ s) {
     int idx = box_thread_index();
     if (idx >= b.nb) return;
     int i, j, k;
@@ -1232,7 +1234,7 @@ __global__ void __launch_bounds__(kBlock) k_precond_div_jac(Box b, const double 
         double d = (vu[idx + 1] * du[idx + 1] - vu[idx] * du[idx]) * b.ihx
                  + (vv[idx + b.px] * dv[idx + b.px] - vv[idx] * dv[idx]) * b.ihy;
         if (DIM == 3) d += (vw[idx + b.plane] * dw[idx + b.plane] - vw[idx] * dw[idx]) * b.ihz;
-        qq = rp[idx] + d;
+        qq = vs * (rp[idx] + d);
     }
     q[idx] = qq;
     s[idx] = (R)(-qq / dt);
@@ -1241,7 +1243,7 @@ __global__ void __launch_bounds__(kBlock) k_precond_div_jac(Box b, const double 
 template <int DIM, class R>
 __global__ void __launch_bounds__(kBlock) k_precond_update_jac(Box b, const double *__restrict__ vu,
         const double *__restrict__ vv, const double *__restrict__ vw, const double *__restrict__ du,
-        const double *__restrict__ dv, const double *__restrict__ dw, const R *__restrict__ phi,
+        const double *__restrict__ dv, const double *__restrict__ dw, double vs, const R *__restrict__ phi,
         const double *__restrict__ bx, const double *__restrict__ by, const double *__restrict__ bz,
         const double *__restrict__ mu, const double *__restrict__ q, double dt, double theta,
         double *__restrict__ zu, double *__restrict__ zv, double *__restrict__ zw, double *__restrict__ zp) {
@@ -1251,14 +1253,14 @@ __global__ void __launch_bounds__(kBlock) k_precond_update_jac(Box b, const doub
     decompose(b, idx, i, j, k);
     const double ph = (double)phi[idx];
     double z = 0.0;
-    if (is_ux(b, i, j, k)) z = vu[idx] * du[idx] - dt * bx[idx] * (ph - (double)phi[idx - 1]) * b.ihx;
+    if (is_ux(b, i, j, k)) z = vs * vu[idx] * du[idx] - dt * bx[idx] * (ph - (double)phi[idx - 1]) * b.ihx;
     zu[idx] = z;
     z = 0.0;
-    if (is_vy(b, i, j, k)) z = vv[idx] * dv[idx] - dt * by[idx] * (ph - (double)phi[idx - b.px]) * b.ihy;
+    if (is_vy(b, i, j, k)) z = vs * vv[idx] * dv[idx] - dt * by[idx] * (ph - (double)phi[idx - b.px]) * b.ihy;
     zv[idx] = z;
     if (DIM == 3) {
         z = 0.0;
-        if (is_wz(b, i, j, k)) z = vw[idx] * dw[idx] - dt * bz[idx] * (ph - (double)phi[idx - b.plane]) * b.ihz;
+        if (is_wz(b, i, j, k)) z = vs * vw[idx] * dw[idx] - dt * bz[idx] * (ph - (double)phi[idx - b.plane]) * b.ihz;
         zw[idx] = z;
     }
     z = 0.0;
@@ -1495,28 +1497,38 @@ __global__ void __launch_bounds__(kBlock) k_multidot(long long n, long long psta
 }
 
 // out[m] (=, or += if accumulate) sum over blocks of partial[m * nblk + .], in a
-// fixed order: the result is bitwise reproducible.  One block per m.
+// fixed order: the result is bitwise reproducible.  One block per m.  With
+// mscale != nullptr the sum is multiplied by mscale[m] first.
 __global__ void __launch_bounds__(kBlock) k_reduce_partials(int nblk, const double *__restrict__ partial,
-        double *__restrict__ out, int accumulate) {
+        double *__restrict__ out, int accumulate, const double *__restrict__ mscale) {
     __shared__ double lds[kBlock / 64];
     const int m = blockIdx.x;
     double v[1] = {0.0};
     for (int t = threadIdx.x; t < nblk; t += kBlock) v[0] += partial[(size_t)m * nblk + t];
     block_reduce<1>(v, lds);
-    if (threadIdx.x == 0) out[m] = accumulate ? out[m] + v[0] : v[0];
+    if (threadIdx.x == 0) {
+        const double r = mscale ? v[0] * mscale[m] : v[0];
+        out[m] = accumulate ? out[m] + r : r;
+    }
 }
 
-// w[t] += sign * sum_m c[m] * V_m[t]   (c on the device).  With partial !=
+// p[0] = v (one thread; a device scalar set in stream order)
+__global__ void k_set_scalar(double *__restrict__ p, double v) {
+    if (threadIdx.x == 0) p[0] = v;
+}
+
+// w[t] += sign * sum_m c[m] * s[m] * V_m[t]   (c and the optional per-vector
+// scales s on the device; s = 1 when vscale is nullptr).  With partial !=
 // nullptr also the weighted squared norm of the updated w (weight w2 from
 // pstart on), one partial sum per block.
 template <int NV>
 __global__ void __launch_bounds__(kBlock) k_maxpy(long long n, double sign, const double *__restrict__ V,
-        long long ldv, int nv, const double *__restrict__ c, double *__restrict__ w,
-        long long pstart, double w2, double *__restrict__ partial) {
+        long long ldv, int nv, const double *__restrict__ c, const double *__restrict__ vscale,
+        double *__restrict__ w, long long pstart, double w2, double *__restrict__ partial) {
     __shared__ double lds[kBlock / 64];
     double cc[NV];
 #pragma unroll
-    for (int m = 0; m < NV; ++m) cc[m] = m < nv ? sign * c[m] : 0.0;
+    for (int m = 0; m < NV; ++m) cc[m] = m < nv ? sign * c[m] * (vscale ? vscale[m] : 1.0) : 0.0;
     double nrm[1] = {0.0};
     long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
     long long st = (long long)gridDim.x * kBlock;
@@ -1577,13 +1589,17 @@ __global__ void __launch_bounds__(kBlock) k_partial_sum(long long n, const doubl
     if (threadIdx.x == 0) partial[blockIdx.x] = v[0];
 }
 
-// flags non-finite values in a range
+// flag[0] = 1 if a value of the range is not finite, flag[1] = 1 if one is nonzero
 __global__ void __launch_bounds__(kBlock) k_check_finite(long long n, const double *__restrict__ x, int *__restrict__ flag) {
     long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
     long long st = (long long)gridDim.x * kBlock;
-    bool bad = false;
-    for (; t < n; t += st) bad |= !isfinite(x[t]);
+    bool bad = false, nz = false;
+    for (; t < n; t += st) {
+        bad |= !isfinite(x[t]);
+        nz |= x[t] != 0.0;
+    }
     if (bad) flag[0] = 1;
+    if (nz) flag[1] = 1;     // some entry is nonzero
 }
 
 }  // namespace stk

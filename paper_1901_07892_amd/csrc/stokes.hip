@@ -122,6 +122,7 @@ struct stokes_ctx {
     double unknowns = 0;        // interior unknowns (velocity faces + cells)
     double *V = nullptr, *Z = nullptr, *xk = nullptr, *bk = nullptr, *q = nullptr;
     double *partial = nullptr, *dsc = nullptr;
+    double *vs = nullptr;        // scales of the unnormalised Krylov basis (m + 1)
     int *dflag = nullptr;
     int vcycles = 0;
     double visc_ratio = -1.0;   // max viscous/mass diagonal ratio (automatic velocity levels)
@@ -227,6 +228,7 @@ void carve_all(Carver &cv, stokes_ctx &c) {
     c.q = cv.fields<double>(b, 1);
     c.partial = cv.take<double>((size_t)kRedBlocks * kGroup);
     c.dsc = cv.take<double>(4 * (size_t)(c.m + 8));
+    c.vs = cv.take<double>((size_t)c.m + 2);
     if (d == 3)
         for (int a = 0; a < 4; ++a) c.lf[a] = cv.take<float>((size_t)kLearnedMaxCells);
     c.lstat = cv.take<double>(8);
@@ -521,7 +523,7 @@ R *pressure_cycles(stokes_ctx &c, MG<R> &mg) {
 // Its derivation: with constant coefficients A (dt beta G phi) = G p exactly
 // when p = phi - 2 theta mu dt beta Lap(phi), and beta Lap(phi) ~= s.
 template <int DIM, class R>
-void precond(stokes_ctx &c, MG<R> &mg, double *v, double *z) {
+void precond(stokes_ctx &c, MG<R> &mg, double *v, double vs, double *z) {
     Level<R> &L0 = mg.L[0];
     double *vu[3] = {c.fld(v, 0), c.fld(v, 1), DIM == 3 ? c.fld(v, 2) : nullptr};
     double *zu[3] = {c.fld(z, 0), c.fld(z, 1), DIM == 3 ? c.fld(z, 2) : nullptr};
@@ -530,13 +532,14 @@ void precond(stokes_ctx &c, MG<R> &mg, double *v, double *z) {
         // step 1 as one diagonal step, folded into the divergence and update kernels
         double *d2 = DIM == 3 ? c.dinv[2] : c.dinv[1];
         k_precond_div_jac<DIM, R><<<nblocks_box(c.fine), kBlock, 0, c.stream>>>(
-            c.fine, vu[0], vu[1], DIM == 3 ? vu[2] : vu[1], c.dinv[0], c.dinv[1], d2, vp, c.dt, c.q, L0.rp);
+            c.fine, vu[0], vu[1], DIM == 3 ? vu[2] : vu[1], c.dinv[0], c.dinv[1], d2, vp, vs, c.dt, c.q, L0.rp);
         R *phi = pressure_cycles<DIM, R>(c, mg);
         k_precond_update_jac<DIM, R><<<nblocks_box(c.fine), kBlock, 0, c.stream>>>(
-            c.fine, vu[0], vu[1], DIM == 3 ? vu[2] : vu[1], c.dinv[0], c.dinv[1], d2, phi, c.beta[0], c.beta[1],
+            c.fine, vu[0], vu[1], DIM == 3 ? vu[2] : vu[1], c.dinv[0], c.dinv[1], d2, vs, phi, c.beta[0], c.beta[1],
             DIM == 3 ? c.beta[2] : c.beta[1], c.mu, c.q, c.dt, c.theta, zu[0], zu[1], DIM == 3 ? zu[2] : zu[1], zp);
         return;
     }
+    // the multigrid velocity path reads v as it is (the caller passes vs = 1)
     R *eu[3], *ru[3];
     if (sizeof(R) == sizeof(double)) {
         for (int a = 0; a < 3; ++a) {
@@ -566,32 +569,36 @@ void precond(stokes_ctx &c, MG<R> &mg, double *v, double *z) {
 }
 
 // ---------------------------------------------------------------- BLAS helpers
-// out[0..nv) = <V_m, w>_W for m < nv (W: pressure block weighted by w2)
-void multidot(stokes_ctx &c, const double *V, int nv, const double *w, double w2, double *out) {
+// out[0..nv) = scale[m] * <V_m, w>_W for m < nv (W: pressure block weighted by w2;
+// scale = 1 when nullptr)
+void multidot(stokes_ctx &c, const double *V, int nv, const double *w, double w2, double *out,
+              const double *scale = nullptr) {
     const long long n = c.vlen, pstart = (long long)c.dim * c.fine.stride;
     const unsigned g = nblocks_stream(n);
     for (int m0 = 0; m0 < nv; m0 += kGroup) {
         int cnt = std::min(kGroup, nv - m0);
         ProfScope ps(c, STOKES_PROF_MULTIDOT, (double)(cnt + 1) * c.unknowns * 8.0);
         k_multidot<kGroup><<<g, kBlock, 0, c.stream>>>(n, pstart, w2, V + (size_t)m0 * c.vlen, c.vlen, cnt, w, c.partial);
-        k_reduce_partials<<<cnt, kBlock, 0, c.stream>>>((int)g, c.partial, out + m0, 0);
+        k_reduce_partials<<<cnt, kBlock, 0, c.stream>>>((int)g, c.partial, out + m0, 0, scale ? scale + m0 : nullptr);
     }
 }
 
-// w += sign * sum_m coef[m] V_m   (coef on the device).  With nrm2 != nullptr
-// the weighted squared norm of the result is reduced into nrm2[0].
+// w += sign * sum_m coef[m] vscale[m] V_m   (coef and vscale on the device;
+// vscale = 1 when nullptr).  With nrm2 != nullptr the weighted squared norm of
+// the result is reduced into nrm2[0].
 void maxpy(stokes_ctx &c, double sign, const double *V, int nv, const double *coef, double *w,
-           double w2 = 1.0, double *nrm2 = nullptr) {
+           double w2 = 1.0, double *nrm2 = nullptr, const double *vscale = nullptr) {
     const long long n = c.vlen, pstart = (long long)c.dim * c.fine.stride;
     const unsigned g = nblocks_stream(n);
     for (int m0 = 0; m0 < nv; m0 += kGroup) {
         int cnt = std::min(kGroup, nv - m0);
         bool last = m0 + kGroup >= nv;
         ProfScope ps(c, STOKES_PROF_MAXPY, (double)(cnt + 2) * c.unknowns * 8.0);
-        k_maxpy<kGroup><<<g, kBlock, 0, c.stream>>>(n, sign, V + (size_t)m0 * c.vlen, c.vlen, cnt, coef + m0, w,
-                                                    pstart, w2, (last && nrm2) ? c.partial : nullptr);
+        k_maxpy<kGroup><<<g, kBlock, 0, c.stream>>>(n, sign, V + (size_t)m0 * c.vlen, c.vlen, cnt, coef + m0,
+                                                    vscale ? vscale + m0 : nullptr, w, pstart, w2,
+                                                    (last && nrm2) ? c.partial : nullptr);
     }
-    if (nrm2) k_reduce_partials<<<1, kBlock, 0, c.stream>>>((int)g, c.partial, nrm2, 0);
+    if (nrm2) k_reduce_partials<<<1, kBlock, 0, c.stream>>>((int)g, c.partial, nrm2, 0, nullptr);
 }
 
 void sync_read(stokes_ctx &c, const double *dsrc, double *hdst, int n) {
@@ -629,16 +636,25 @@ void remove_p_mean(stokes_ctx &c, double *x) {
     const long long n = c.fine.stride;
     const unsigned g = nblocks_stream(n);
     k_partial_sum<<<g, kBlock, 0, c.stream>>>(n, p, 0, c.partial);
-    k_reduce_partials<<<1, kBlock, 0, c.stream>>>((int)g, c.partial, c.dsc, 0);
+    k_reduce_partials<<<1, kBlock, 0, c.stream>>>((int)g, c.partial, c.dsc, 0, nullptr);
     k_sub_mean<<<nblocks_box(c.fine), kBlock, 0, c.stream>>>(c.fine, c.dsc, c.fld(x, c.dim));
 }
 
 // ---------------------------------------------------------------- FGMRES
 template <int DIM, class R>
-stokes_status fgmres(stokes_ctx &c, MG<R> &mg, double tol, stokes_stats &st) {
+stokes_status fgmres(stokes_ctx &c, MG<R> &mg, double tol, bool zero_guess, stokes_stats &st) {
     const int m = c.m;
     const double w2 = c.sigma * c.sigma;
     std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1), y(m), hbuf(2 * m + 4);
+    // The Krylov basis is kept unnormalised: v_j = hs[j] * V_j, with the scales
+    // also on the device (c.vs) for the Gram-Schmidt kernels.  This saves one
+    // pass over every new basis vector; the preconditioner is positively
+    // homogeneous, so it takes the scale as an argument.
+    std::vector<double> hs(m + 1, 1.0);
+    auto set_scale = [&](int j, double v) {
+        hs[j] = v;
+        k_set_scalar<<<1, 64, 0, c.stream>>>(c.vs + j, v);
+    };
     auto HH = [&](int i, int j) -> double & { return H[(size_t)i * m + j]; };
     double *dh = c.dsc, *dh2 = c.dsc + (m + 2), *dy = c.dsc + 2 * (m + 2);
 
@@ -657,12 +673,20 @@ stokes_status fgmres(stokes_ctx &c, MG<R> &mg, double tol, stokes_stats &st) {
     }
     double prev = INFINITY;
     stokes_status status = STOKES_NOT_CONVERGED;
+    bool first = true;
     for (;;) {
         double *v0 = c.vec(c.V, 0);
-        apply_fine<DIM>(c, c.xk, c.bk, v0);
-        multidot(c, v0, 1, v0, w2, dh);
         double be2;
-        sync_read(c, dh, &be2, 1);
+        if (first && zero_guess) {
+            // x0 = 0: the residual is b itself
+            HIPCHK(hipMemcpyAsync(v0, c.bk, sizeof(double) * c.vlen, hipMemcpyDeviceToDevice, c.stream));
+            be2 = bn2;
+        } else {
+            apply_fine<DIM>(c, c.xk, c.bk, v0);
+            multidot(c, v0, 1, v0, w2, dh);
+            sync_read(c, dh, &be2, 1);
+        }
+        first = false;
         if (!std::isfinite(be2)) { c.err = "non-finite residual"; return STOKES_ENAN; }
         const double beta = std::sqrt(be2);
         st.rel_res_true = beta / bnorm;
@@ -671,24 +695,29 @@ stokes_status fgmres(stokes_ctx &c, MG<R> &mg, double tol, stokes_stats &st) {
         if (beta >= 0.999 * prev) { status = STOKES_NOT_CONVERGED; break; }   // stagnation across a restart
         prev = beta;
         if (st.iters > 0) st.restarts++;
-        k_scale<<<nblocks_stream(c.vlen), kBlock, 0, c.stream>>>(c.vlen, 1.0 / beta, v0);
+        set_scale(0, 1.0 / beta);
         std::fill(g.begin(), g.end(), 0.0);
         g[0] = beta;
         int nj = 0;
         bool breakdown = false;
         for (int j = 0; j < m && st.iters < c.opt.max_iters; ++j) {
             double *vj = c.vec(c.V, j), *zj = c.vec(c.Z, j), *w = c.vec(c.V, j + 1);
-            precond<DIM, R>(c, mg, vj, zj);
+            if (!c.diag_vel && hs[j] != 1.0) {
+                // the multigrid velocity path reads v_j in many kernels: normalise it
+                k_scale<<<nblocks_stream(c.vlen), kBlock, 0, c.stream>>>(c.vlen, hs[j], vj);
+                set_scale(j, 1.0);
+            }
+            precond<DIM, R>(c, mg, vj, hs[j], zj);
             apply_fine<DIM>(c, zj, nullptr, w);
             // classical Gram-Schmidt: one pass (orth 1) or two (orth 2); the last
             // update pass also reduces the norm of the new vector
-            multidot(c, c.V, j + 1, w, w2, dh);
+            multidot(c, c.V, j + 1, w, w2, dh, c.vs);
             if (c.opt.orth >= 2) {
-                maxpy(c, -1.0, c.V, j + 1, dh, w);
-                multidot(c, c.V, j + 1, w, w2, dh2);
-                maxpy(c, -1.0, c.V, j + 1, dh2, w, w2, dh2 + (j + 1));
+                maxpy(c, -1.0, c.V, j + 1, dh, w, 1.0, nullptr, c.vs);
+                multidot(c, c.V, j + 1, w, w2, dh2, c.vs);
+                maxpy(c, -1.0, c.V, j + 1, dh2, w, w2, dh2 + (j + 1), c.vs);
             } else {
-                maxpy(c, -1.0, c.V, j + 1, dh, w, w2, dh2 + (j + 1));
+                maxpy(c, -1.0, c.V, j + 1, dh, w, w2, dh2 + (j + 1), c.vs);
             }
             HIPCHK(hipMemcpyAsync(hbuf.data(), dh, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, c.stream));
             HIPCHK(hipMemcpyAsync(hbuf.data() + (m + 2), dh2, sizeof(double) * (j + 2), hipMemcpyDeviceToHost, c.stream));
@@ -698,7 +727,7 @@ stokes_status fgmres(stokes_ctx &c, MG<R> &mg, double tol, stokes_stats &st) {
             if (!std::isfinite(hn2)) { c.err = "non-finite Arnoldi vector"; return STOKES_ENAN; }
             double hn = std::sqrt(std::max(hn2, 0.0));
             HH(j + 1, j) = hn;
-            if (hn > 0.0) k_scale<<<nblocks_stream(c.vlen), kBlock, 0, c.stream>>>(c.vlen, 1.0 / hn, w);
+            if (hn > 0.0) set_scale(j + 1, 1.0 / hn);
             for (int i = 0; i < j; ++i) {
                 double t = cs[i] * HH(i, j) + sn[i] * HH(i + 1, j);
                 HH(i + 1, j) = -sn[i] * HH(i, j) + cs[i] * HH(i + 1, j);
@@ -1170,7 +1199,7 @@ stokes_status solve_impl(stokes_ctx &c, const double *const rhs_u[3], const doub
         double *p = c.fld(c.bk, DIM) - c.fine.guard;
         const unsigned g = nblocks_stream(c.fine.stride);
         k_partial_sum<<<g, kBlock, 0, c.stream>>>(c.fine.stride, p, 0, c.partial);
-        k_reduce_partials<<<1, kBlock, 0, c.stream>>>((int)g, c.partial, c.dsc, 0);
+        k_reduce_partials<<<1, kBlock, 0, c.stream>>>((int)g, c.partial, c.dsc, 0, nullptr);
         double s;
         HIPCHK(hipMemcpyAsync(&flag, c.dflag, sizeof(int), hipMemcpyDeviceToHost, c.stream));
         sync_read(c, c.dsc, &s, 1);
@@ -1179,14 +1208,16 @@ stokes_status solve_impl(stokes_ctx &c, const double *const rhs_u[3], const doub
         k_sub_mean<<<nblocks_box(c.fine), kBlock, 0, c.stream>>>(c.fine, c.dsc, c.fld(c.bk, DIM));
     }
     pack_vector<DIM>(c, x_u, x_p, c.xk);
-    k_fill<int><<<1, kBlock, 0, c.stream>>>(1, c.dflag, 0);
+    k_fill<int><<<1, kBlock, 0, c.stream>>>(2, c.dflag, 0);
     k_check_finite<<<nblocks_stream(c.vlen), kBlock, 0, c.stream>>>(c.vlen, c.xk, c.dflag);
-    HIPCHK(hipMemcpyAsync(&flag, c.dflag, sizeof(int), hipMemcpyDeviceToHost, c.stream));
+    int xflag[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(xflag, c.dflag, 2 * sizeof(int), hipMemcpyDeviceToHost, c.stream));
     HIPCHK(hipStreamSynchronize(c.stream));
-    if (flag) { c.err = "non-finite initial guess"; return STOKES_ENAN; }
+    if (xflag[0]) { c.err = "non-finite initial guess"; return STOKES_ENAN; }
+    const bool zero_guess = xflag[1] == 0;
     remove_p_mean(c, c.xk);
-    stokes_status s = c.opt.precision == 1 ? fgmres<DIM, float>(c, c.mgf, tol, st)
-                                           : fgmres<DIM, double>(c, c.mgd, tol, st);
+    stokes_status s = c.opt.precision == 1 ? fgmres<DIM, float>(c, c.mgf, tol, zero_guess, st)
+                                           : fgmres<DIM, double>(c, c.mgd, tol, zero_guess, st);
     if (s < 0) return s;
     // final residual split into its blocks (plain 2-norm); fgmres leaves the
     // residual b - K x of the returned (zero-mean pressure) iterate in V[0]
@@ -1195,11 +1226,11 @@ stokes_status solve_impl(stokes_ctx &c, const double *const rhs_u[3], const doub
         const long long nvel = (long long)DIM * c.fine.stride;
         const unsigned g1 = nblocks_stream(nvel), g2 = nblocks_stream(c.fine.stride), g3 = nblocks_stream(c.vlen);
         k_partial_sum<<<g1, kBlock, 0, c.stream>>>(nvel, v0, 1, c.partial);
-        k_reduce_partials<<<1, kBlock, 0, c.stream>>>((int)g1, c.partial, c.dsc, 0);
+        k_reduce_partials<<<1, kBlock, 0, c.stream>>>((int)g1, c.partial, c.dsc, 0, nullptr);
         k_partial_sum<<<g2, kBlock, 0, c.stream>>>(c.fine.stride, c.fld(v0, DIM) - c.fine.guard, 1, c.partial);
-        k_reduce_partials<<<1, kBlock, 0, c.stream>>>((int)g2, c.partial, c.dsc + 1, 0);
+        k_reduce_partials<<<1, kBlock, 0, c.stream>>>((int)g2, c.partial, c.dsc + 1, 0, nullptr);
         k_partial_sum<<<g3, kBlock, 0, c.stream>>>(c.vlen, c.bk, 1, c.partial);
-        k_reduce_partials<<<1, kBlock, 0, c.stream>>>((int)g3, c.partial, c.dsc + 2, 0);
+        k_reduce_partials<<<1, kBlock, 0, c.stream>>>((int)g3, c.partial, c.dsc + 2, 0, nullptr);
         double h3[3];
         sync_read(c, c.dsc, h3, 3);
         double bn = std::sqrt(h3[2]);
@@ -1247,7 +1278,8 @@ void learned_tuple(stokes_ctx &c, MG<R> &mg, int lc, int cycles, float *f0, floa
     // steps 1-2 of the preconditioner on v = b: u~ and the Poisson right-hand side
     if (c.diag_vel) {
         k_precond_div_jac<3, R><<<nblocks_box(fb), kBlock, 0, c.stream>>>(
-            fb, c.fld(v, 0), c.fld(v, 1), c.fld(v, 2), c.dinv[0], c.dinv[1], c.dinv[2], c.fld(v, 3), c.dt, c.q, L0.rp);
+            fb, c.fld(v, 0), c.fld(v, 1), c.fld(v, 2), c.dinv[0], c.dinv[1], c.dinv[2], c.fld(v, 3), 1.0, c.dt, c.q,
+            L0.rp);
     } else {
         double *z = c.vec(c.Z, 0);
         R *eu[3], *ru[3];

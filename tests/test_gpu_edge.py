@@ -26,6 +26,28 @@ def test_exact_initial_guess_needs_no_iteration():
     assert st == 0 and stats.iters == 0
 
 
+@pytest.mark.parametrize("maker", [lambda: W.config1(scale=2), lambda: W.config3(scale=4)])
+def test_nonzero_initial_guess_reaches_the_same_solution(oracle_lib, maker):
+    """A nonzero guess takes the path that forms b - K x0 (a zero guess copies b);
+    both end at the reference solution and the residual statistics belong to the
+    returned iterate."""
+    prob = maker()
+    if prob.dim == 2:
+        ru, rp = D.solve_problem(prob, A.from_problem(prob))
+    else:
+        ru, rp, _ = oracle_lib.solve_problem(prob, tol=1e-13, max_iters=300)
+    rng = np.random.default_rng(11)
+    x0 = ([0.5 * a + 0.1 * rng.standard_normal(a.shape) * np.abs(a).max() for a in ru[:prob.dim]],
+          0.5 * rp + 0.1 * rng.standard_normal(rp.shape) * np.abs(rp).max())
+    for guess in (None, x0):
+        xu, xp, st, stats = gpu_solve(prob, tol=1e-12, max_iters=400, x0=guess)
+        assert st == 0 or (st == 1 and stats.rel_res_true <= 1e-11), stats.as_dict()
+        assert stats.iters > 0 and stats.rel_res_plain <= 1e-10
+        for c in range(prob.dim):
+            assert rel(xu[c], ru[c]) <= 1e-8
+        assert rel(xp - xp.mean(), rp - rp.mean()) <= 1e-8
+
+
 def test_rhs_p_mean_removed_and_reported():
     prob = W.config1(scale=2)
     prob.rhs_p = prob.rhs_p + 0.25
@@ -126,12 +148,16 @@ def test_well_balanced_still_tank():
                                   dict(vel_levels=1, vel_sweeps=2, vel_smoother=0),
                                   dict(orth=1, p_cycles=2, p_prolong=0),
                                   dict(nu1=0, nu2=2, vel_levels=99, vel_smoother=0),
-                                  dict(nu1=3, nu2=0, vel_levels=99, vel_smoother=0)])
+                                  dict(nu1=3, nu2=0, vel_levels=99, vel_smoother=0),
+                                  dict(orth=2), dict(restart=2), dict(restart=3, orth=2, p_cycles=1),
+                                  dict(restart=2, vel_levels=99, vel_smoother=0)])
 @pytest.mark.parametrize("maker", [lambda: W.config1(), lambda: W.config3(scale=4)])
 def test_solver_variants_match_direct_or_oracle(oracle_lib, opts, maker):
     """Every multigrid/Krylov variant reaches the same solution: full velocity
-    hierarchy, multi-sweep single level, one-pass Gram-Schmidt, constant
-    prolongation, pre- or post-smoothing only."""
+    hierarchy, multi-sweep single level, one- and two-pass Gram-Schmidt,
+    constant prolongation, pre- or post-smoothing only, short restarts (the
+    unnormalised basis and its scales across restarts) with either velocity
+    subsolve."""
     prob = maker()
     if prob.dim == 2:
         sys = A.from_problem(prob)
