@@ -134,6 +134,19 @@ def main():
                 "traffic": traffic_per_launch(args.prof_kernel, args.n, args.precision),
                 "launches": klaunch, "avg_launch_us": kms * 1e3 / max(klaunch, 1),
                 "algorithmic_bytes_per_launch": kbytes / max(klaunch, 1)}
+    # the other kernel classes, one solve each (outside the timed steps)
+    kernels = {names[args.prof_kernel]: {"launches": klaunch, "avg_launch_us": kms * 1e3 / max(klaunch, 1),
+                                         "algorithmic_GBps": achieved}}
+    for kind in (0, 2, 3):
+        if kind == args.prof_kernel:
+            continue
+        S.stokes_profile_kernel(solver.ctx, kind)
+        step()
+        torch.cuda.synchronize()
+        a_ms, a_n, a_b = S.stokes_profile_read(solver.ctx)
+        S.stokes_profile_kernel(solver.ctx, -1)
+        kernels[names[kind]] = {"launches": a_n, "avg_launch_us": a_ms * 1e3 / max(a_n, 1),
+                                "algorithmic_GBps": a_b / (a_ms * 1e-3) / 1e9 if a_ms > 0 else None}
     out = {
         "metric": "ms per Stokes solve to 1e-8 rel. residual, 256^3 rho-ratio 1000",
         "value": ms,
@@ -159,9 +172,11 @@ def main():
         "rel_res_plain": stats.rel_res_plain,
         "vcycles": stats.vcycles,
         "roofline": roofline,
+        "kernels": kernels,
     }
     solver.close()
     del solver
+    out["hbm_stream_copy"] = stream_copy(S)
     if not args.no_forms and args.precision == 0:
         out["forms"] = {"fp32_multigrid": fp32_form(S, prob, rho, mu, rhs_u, rhs_p, xu, xp, overrides,
                                                     ms, args.steps)}
@@ -187,6 +202,8 @@ def fp32_form(S, prob, rho, mu, rhs_u, rhs_p, xu64, xp64, overrides, ms64, steps
     xp = torch.zeros_like(ref_p)
     times = []
     for s in range(steps + 2):
+        if s == 2:
+            S.stokes_profile_kernel(solver.ctx, 1)
         for a in xu:
             a.zero_()
         xp.zero_()
@@ -198,13 +215,20 @@ def fp32_form(S, prob, rho, mu, rhs_u, rhs_p, xu64, xp64, overrides, ms64, steps
             times.append((time.perf_counter() - t) * 1e3)
         if st != 0:
             raise RuntimeError("fp32-multigrid solve did not converge: %s" % stats.as_dict())
+    kms, kn, kb = S.stokes_profile_read(solver.ctx)
+    S.stokes_profile_kernel(solver.ctx, -1)
     solver.close()
+    achieved = kb / (kms * 1e-3) / 1e9 if kms > 0 else None
+    roofline = {"bound": "hbm", "kernel": "k_p_sweep3c<float> (fused pressure RB-GS sweep, finest level)",
+                "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
+                "frac": achieved / 8000.0 if achieved else None, "launches": kn,
+                "avg_launch_us": kms * 1e3 / max(kn, 1), "algorithmic_bytes_per_launch": kb / max(kn, 1)}
     diff = [float(torch.linalg.vector_norm(xu[c] - ref_u[c]) / torch.linalg.vector_norm(ref_u[c])) for c in range(3)]
     diff.append(float(torch.linalg.vector_norm(xp - ref_p) / torch.linalg.vector_norm(ref_p)))
     ms = float(np.mean(times))
     log("fp32-multigrid form: %.2f ms, %d iterations, residual %.2e" % (ms, stats.iters, stats.rel_res_true))
     return {"ms_per_solve": ms, "fgmres_iters": stats.iters, "rel_res_true": stats.rel_res_true,
-            "speedup_vs_fp64": ms64 / ms, "rel_diff_vs_fp64_solution": diff}
+            "speedup_vs_fp64": ms64 / ms, "rel_diff_vs_fp64_solution": diff, "roofline": roofline}
 
 
 def learned_form(S, prob, rho, mu, rhs_u, rhs_p, xu64, xp64, overrides, ms64, steps):
@@ -236,6 +260,21 @@ def learned_form(S, prob, rho, mu, rhs_u, rhs_p, xu64, xp64, overrides, ms64, st
         if st != 0:
             raise RuntimeError("learned-form solve did not converge: %s" % stats.as_dict())
     solver.close()
+    # the network alone: forward passes on the features of the 32^3 level
+    n = meta["grid"]
+    f = [torch.randn((n, n, n), dtype=torch.float32, device="cuda") for _ in range(3)]
+    pred = torch.zeros_like(f[0])
+    for _ in range(3):
+        net.forward(f[0], f[1], f[2], pred)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(20):
+        net.forward(f[0], f[1], f[2], pred)
+    e1.record()
+    torch.cuda.synchronize()
+    fwd_us = e0.elapsed_time(e1) / 20 * 1e3
+    flops = S.stokes_unet_forward_flops(n)
+    tflops = flops / (fwd_us * 1e-6) / 1e12
     net.close()
     diff = [float(torch.linalg.vector_norm(xu[c] - xu64[c]) / torch.linalg.vector_norm(xu64[c])) for c in range(3)]
     diff.append(float(torch.linalg.vector_norm(xp - xp64) / torch.linalg.vector_norm(xp64)))
@@ -245,7 +284,10 @@ def learned_form(S, prob, rho, mu, rhs_u, rhs_p, xu64, xp64, overrides, ms64, st
             "rel_res_true": stats.rel_res_true, "speedup_vs_fp64": ms64 / ms,
             "rel_diff_vs_fp64_solution": diff,
             "training": {k: meta.get(k) for k in ("instances", "epochs", "fine_grid", "level_grid")},
-            "final_val_loss": meta["history"][-1]["val_loss"] if meta.get("history") else None}
+            "final_val_loss": meta["history"][-1]["val_loss"] if meta.get("history") else None,
+            "unet_forward": {"grid": n, "us": fwd_us, "flops": flops,
+                             "roofline": {"bound": "mfma", "achieved": tflops, "peak": 2500.0, "unit": "TFLOP/s",
+                                          "frac": tflops / 2500.0}}}
 
 
 def kernel_source_hash() -> str:
@@ -272,6 +314,40 @@ def traffic_per_launch(kernel, n, precision):
     if not e or e.get("kernel_source_hash") != kernel_source_hash():
         return None
     return e.get("bytes_per_launch")
+
+
+def stream_copy(S):
+    """Practical HBM bandwidth of the library's own streaming copy kernel
+    (stokes_stream_copy): 1 GiB read + 1 GiB written per launch, 10 launches
+    timed with events on the stream they run on."""
+    import torch
+    a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    for _ in range(2):
+        S.stokes_stream_copy(a, b)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        S.stokes_stream_copy(a, b)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 10
+    gbps = 2.0 * a.numel() * 8 / (ms * 1e-3) / 1e9
+    del a, b
+    log("stream copy: %.1f GB/s (%.1f%% of 8 TB/s)" % (gbps, gbps / 80.0))
+    return {"kernel": "k_stream_copy (library)", "bytes_per_launch": 2 * (1 << 30), "avg_launch_us": ms * 1e3,
+            "GBps": gbps, "frac_of_8TBps": gbps / 8000.0}
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def _counter_rows(d, counter):
@@ -377,17 +453,33 @@ def cpu_baseline(prob, gpu_iters):
     iters = max(int(info_s["iters"]), 1)
     xu, xp, info = native.solve_problem(prob, max_iters=1, restart=1, p_cycles=3)
     wall = time.time() - t0
+    # thread scaling of the oracle: a full 64^3 solve of the recipe on all threads and on one
+    tiny = W.config5(n_cells=64)
+    tiny.dt = prob.dt
+    nth = native.num_threads()
+    t1 = time.time()
+    native.solve_problem(tiny, tol=prob.tol, p_cycles=3)
+    t_all = time.time() - t1
+    native.set_threads(1)
+    t1 = time.time()
+    native.solve_problem(tiny, tol=prob.tol, p_cycles=3)
+    t_one = time.time() - t1
+    native.set_threads(nth)
     per_iter = info["solve_s"] / max(info["iters"], 1)
     value = (info["setup_s"] + per_iter * iters) * 1e3
-    log("cpu baseline: %d oracle iterations at %d^3; 256^3 setup %.1fs, 1 iteration %.1fs (wall %.1fs)"
-        % (iters, small.n[0], info["setup_s"], info["solve_s"], wall))
+    log("cpu baseline: %d oracle iterations at %d^3; %d^3 setup %.1fs, 1 iteration %.1fs (wall %.1fs)"
+        % (iters, small.n[0], prob.n[0], info["setup_s"], info["solve_s"], wall))
     return {"value": value, "unit": "ms/solve", "cores": native.num_threads(), "kind": "oracle",
             "sample": "C oracle (FP64, OpenMP for matvec/BLAS, lexicographic Gauss-Seidel multigrid, three "
                       "pressure V-cycles per step) on the same %s workload: setup plus 1 FGMRES iteration "
                       "(%.1f s), scaled to the oracle's %d iterations to tol %.0e on the same recipe and dt at %d^3 "
                       "(the GPU solve takes %d)" % (prob.name, info["solve_s"], iters, prob.tol, small.n[0],
                                                    gpu_iters),
-            "oracle_iters": iters, "measured_s": wall}
+            "oracle_iters": iters, "measured_s": wall,
+            "cpu_model": _cpu_model(), "nproc": os.cpu_count(),
+            "one_core": {"value": value * t_one / t_all, "unit": "ms/solve",
+                         "sample": "the value above times the one-thread / %d-thread time ratio of a full 64^3 "
+                                   "oracle solve of the same recipe (%.2f s / %.2f s)" % (nth, t_one, t_all)}}
 
 
 if __name__ == "__main__":

@@ -174,7 +174,7 @@ stokes_status stokes_solve(stokes_ctx *ctx, const double *const rhs_u[3], const 
 
 /* Measurement hook.  Kernel classes that can be timed: */
 enum {
-    STOKES_PROF_MATVEC = 0,    /* fine-level K x and b - K x (k_apply) */
+    STOKES_PROF_MATVEC = 0,    /* fine-level K x and b - K x (k_apply3_z / k_apply) */
     STOKES_PROF_P_SWEEP = 1,   /* fused 3D red-black pressure sweep on the finest level */
     STOKES_PROF_MULTIDOT = 2,  /* Arnoldi inner products, up to 8 vectors per launch */
     STOKES_PROF_MAXPY = 3      /* Arnoldi vector updates, up to 8 vectors per launch */
@@ -192,6 +192,15 @@ stokes_status stokes_profile_kernel(stokes_ctx *ctx, int kernel);
  * their summed algorithmic bytes. */
 stokes_status stokes_profile_read(stokes_ctx *ctx, double *ms_total, long long *launches, double *bytes);
 
+/* Streaming reference for the measurements: dst[i] = src[i] for i < n, device
+ * pointers that do not overlap, asynchronously on `stream` (a hipStream_t; NULL
+ * = default stream), one read and one write of every element with the
+ * library's own copy kernel (16-byte accesses when both pointers are 16-byte
+ * aligned).  Timing it gives the practical HBM bandwidth next to the nominal
+ * 8 TB/s.  Returns EINVAL for n < 0 or a null pointer with n > 0, EHIP if the
+ * launch fails. */
+stokes_status stokes_stream_copy(const double *src, double *dst, long long n, void *stream);
+
 /* ---------------------------------------------------------------------------
  * Learned form: a 4-level 3D U-Net (channels 16/32/48/64, 3x3x3 convolutions,
  * ReLU, 2x2x2 average pooling, nearest upsampling, additive skips) in BF16 with
@@ -205,6 +214,11 @@ typedef struct stokes_unet stokes_unet;
 
 /* Number of FP32 parameters (all weights as [c_out][27][c_in] layer by layer, then all biases). */
 long long stokes_unet_param_count(void);
+
+/* Floating-point operations of the convolutions of one forward pass at n^3
+ * (two per multiply-add, input channels padded to 16 as computed); 0 for an
+ * invalid n.  Host-only. */
+double stokes_unet_forward_flops(int n);
 
 /* Workspace bytes for an n^3 network (n >= 8, n % 8 == 0), 0 otherwise.  Host-only. */
 size_t stokes_unet_workspace_size(int n);

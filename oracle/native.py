@@ -45,6 +45,8 @@ def lib():
         L.oracle_precond.restype = C.c_int
         L.oracle_num_threads.argtypes = []
         L.oracle_num_threads.restype = C.c_int
+        L.oracle_set_threads.argtypes = [C.c_int]
+        L.oracle_set_threads.restype = None
         _lib = L
     return _lib
 
@@ -138,6 +140,11 @@ def precond(dim, n, h, dt, theta, rho_faces, mu, ru, rp, **opts):
 
 def num_threads() -> int:
     return lib().oracle_num_threads()
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads of the following oracle calls."""
+    lib().oracle_set_threads(int(n))
 
 
 def solve_problem(prob, tol=None, theta=1.0, **opts):

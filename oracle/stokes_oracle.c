@@ -995,3 +995,12 @@ int oracle_num_threads(void) {
     return 1;
 #endif
 }
+
+/* OpenMP threads of the following calls (n < 1: leave unchanged). */
+void oracle_set_threads(int n) {
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

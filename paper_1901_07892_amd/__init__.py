@@ -24,7 +24,9 @@ from ._binding import (  # noqa: F401
     stokes_profile_read,
     stokes_setup,
     stokes_solve,
+    stokes_stream_copy,
     stokes_workspace_size,
     stokes_unet_param_count,
+    stokes_unet_forward_flops,
     stokes_unet_workspace_size,
 )

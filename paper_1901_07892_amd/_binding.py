@@ -85,8 +85,12 @@ def load_library():
     L.stokes_profile_read.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_longlong),
                                       C.POINTER(C.c_double)]
     L.stokes_profile_read.restype = C.c_int
+    L.stokes_stream_copy.argtypes = [dp, dp, C.c_longlong, dp]
+    L.stokes_stream_copy.restype = C.c_int
     L.stokes_unet_param_count.argtypes = []
     L.stokes_unet_param_count.restype = C.c_longlong
+    L.stokes_unet_forward_flops.argtypes = [C.c_int]
+    L.stokes_unet_forward_flops.restype = C.c_double
     L.stokes_unet_workspace_size.argtypes = [C.c_int]
     L.stokes_unet_workspace_size.restype = C.c_size_t
     L.stokes_unet_create.argtypes = [C.c_int, dp, C.c_size_t, dp, C.POINTER(C.c_void_p)]
@@ -219,6 +223,16 @@ def stokes_profile_read(ctx):
     return ms.value, n.value, b.value
 
 
+def stokes_stream_copy(src, dst, stream=None) -> None:
+    """dst[:] = src[:] (float64 device tensors of equal size) with the library's
+    streaming copy kernel, on the current (or given) stream."""
+    if src.dtype != dst.dtype or src.numel() != dst.numel() or not (src.is_contiguous() and dst.is_contiguous()):
+        raise ValueError("src and dst must be contiguous tensors of one size and dtype")
+    st = load_library().stokes_stream_copy(src.data_ptr(), dst.data_ptr(), src.numel(), _stream(stream))
+    if st < 0:
+        raise StokesError(st, "stokes_stream_copy failed")
+
+
 # ---------------------------------------------------------------- convenience wrapper
 class StokesSolver:
     """Owns a workspace tensor and a context for one coefficient set.
@@ -275,6 +289,10 @@ def _fptr(t):
 
 def stokes_unet_param_count() -> int:
     return int(load_library().stokes_unet_param_count())
+
+
+def stokes_unet_forward_flops(n: int) -> float:
+    return float(load_library().stokes_unet_forward_flops(int(n)))
 
 
 def stokes_unet_workspace_size(n: int) -> int:

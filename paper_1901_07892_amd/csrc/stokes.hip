@@ -1484,6 +1484,16 @@ stokes_status stokes_profile_read(stokes_ctx *ctx, double *ms_total, long long *
     return STOKES_OK;
 }
 
+stokes_status stokes_stream_copy(const double *src, double *dst, long long n, void *stream) {
+    if (n < 0 || (n > 0 && (!src || !dst))) return STOKES_EINVAL;
+    if (n == 0) return STOKES_OK;
+    const bool vec2 = ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 15) == 0;
+    const long long work = vec2 ? (n + 1) / 2 : n;
+    const unsigned g = (unsigned)std::max<long long>(1, std::min<long long>((work + kBlock - 1) / kBlock, 16384));
+    k_stream_copy<<<g, kBlock, 0, reinterpret_cast<hipStream_t>(stream)>>>(n, src, dst, vec2 ? 1 : 0);
+    return hipGetLastError() == hipSuccess ? STOKES_OK : STOKES_EHIP;
+}
+
 stokes_status stokes_attach_learned(stokes_ctx *ctx, stokes_unet *net, double stall_ratio) {
     if (!ctx) return STOKES_EINVAL;
     ctx->err.clear();

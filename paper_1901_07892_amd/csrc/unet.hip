@@ -708,6 +708,16 @@ long long stokes_unet_param_count(void) {
     return u.np;
 }
 
+double stokes_unet_forward_flops(int n) {
+    if (n < 8 || n % 8 != 0) return 0.0;
+    double f = 0.0;
+    for (int l = 0; l < kLayers; ++l) {
+        const double m = (double)(n >> kSpec[l].level);
+        f += 2.0 * 27.0 * kSpec[l].cin * kSpec[l].cout * m * m * m;
+    }
+    return f;
+}
+
 size_t stokes_unet_workspace_size(int n) {
     if (n < 8 || n % 8 != 0) return 0;
     stokes_unet u;

@@ -83,3 +83,10 @@ def test_options_struct_layout_matches_library(S):
     o.p_wdepth = 0
     o.p_small = 2
     assert S.stokes_workspace_size(g, o) == 0
+
+
+def test_stream_copy_rejects_bad_arguments_on_host(S):
+    L = S.load_library()
+    assert L.stokes_stream_copy(None, None, -1, None) == -1
+    assert L.stokes_stream_copy(None, None, 5, None) == -1
+    assert L.stokes_stream_copy(None, None, 0, None) == 0

@@ -202,3 +202,22 @@ def test_fp32_multigrid_reaches_fp64_residual(oracle_lib, maker):
     errs = [rel(xu[c], ru[c]) for c in range(prob.dim)] + [rel(xp - xp.mean(), rp - rp.mean())]
     print("fp32-mg", prob.name, "iters", stats.iters, "rel errors vs oracle", ["%.1e" % e for e in errs])
     assert max(errs) <= 1e-5
+
+
+@pytest.mark.parametrize("n,offset", [(1, 0), (1 << 20, 0), ((1 << 20) + 7, 1), (12345, 3)])
+def test_stream_copy_copies_exactly(n, offset):
+    """The measurement reference copy: every element, both aligned (16-byte
+    accesses) and unaligned (8-byte) pointers, odd lengths."""
+    import torch
+    import paper_1901_07892_amd as S
+    print("stream copy", n, offset, flush=True)
+    g = torch.Generator(device="cuda").manual_seed(n)
+    src = torch.randn(n + offset, dtype=torch.float64, device="cuda", generator=g)[offset:]
+    dst_full = torch.full((n + offset + 1,), -1.0, dtype=torch.float64, device="cuda")
+    dst = dst_full[offset:offset + n]
+    S.stokes_stream_copy(src, dst)
+    torch.cuda.synchronize()
+    assert torch.equal(dst, src)
+    assert float(dst_full[offset + n]) == -1.0          # nothing written past the end
+    if offset:
+        assert torch.all(dst_full[:offset] == -1.0)
