@@ -1489,7 +1489,7 @@ stokes_status stokes_stream_copy(const double *src, double *dst, long long n, vo
     if (n == 0) return STOKES_OK;
     const bool vec2 = ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 15) == 0;
     const long long work = vec2 ? (n + 1) / 2 : n;
-    const unsigned g = (unsigned)std::max<long long>(1, std::min<long long>((work + kBlock - 1) / kBlock, 16384));
+    const unsigned g = (unsigned)std::max<long long>(1, std::min<long long>((work + kBlock - 1) / kBlock, 1 << 22));
     k_stream_copy<<<g, kBlock, 0, reinterpret_cast<hipStream_t>(stream)>>>(n, src, dst, vec2 ? 1 : 0);
     return hipGetLastError() == hipSuccess ? STOKES_OK : STOKES_EHIP;
 }
