@@ -911,8 +911,11 @@ __global__ void __launch_bounds__(TX *TY) k_p_sweep3b(Box b, int kc, int zero_gu
 // longer be in L2).  The upper z-face coefficient of plane k is the lower one
 // of plane k+1 and is carried over as well.  Threads below the ring size also
 // take one point of the 1-cell halo ring, read directly.  At most 64 VGPRs, so
-// that two 1024-thread blocks share a CU.
-template <class R, int TX, int TY>
+// that two 1024-thread blocks share a CU.  With EARLY all global loads of a step
+// are issued before its first barrier so that their latencies overlap (one HBM
+// round trip per plane instead of two); that keeps the coefficients live across
+// the barrier and fits the 64 registers only in float.
+template <class R, int TX, int TY, bool EARLY>
 __global__ void __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(8))) k_p_sweep3c(Box b, int kc, int zero_guess, const R *__restrict__ ein,
         const R *__restrict__ ec, Box cb, int lin, R *__restrict__ eout, const R *__restrict__ r,
         const R *__restrict__ bx, const R *__restrict__ by, const R *__restrict__ bz) {
@@ -967,30 +970,73 @@ __global__ void __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(8))
     bool have_carry = false;
     load_old(k0 - 2);
     load_old(k0 - 1);
+    const bool two = tid + NT < N2;
     for (int k = k0 - 1; k <= k1; ++k) {
-        load_old(k + 1);
-        __syncthreads();
         const bool kin = k >= 0 && k < b.nz;
+        const bool ownk = own && kin;
+        const bool ringred = tid < NRING && ring && kin && ((ri + rj + k) & 1) == 0;
+        // raw coefficients of plane k: own point (c*) and red ring point (a*)
+        R cW = 0, cE = 0, cS = 0, cN = 0, cB = 0, cT = 0, cr = 0;
+        R aW = 0, aE = 0, aS = 0, aN = 0, aB = 0, aT = 0, ar = 0;
+        auto load_own = [&]() {
+            if (ownk) {
+                const int q = box_index(b, i, j, k);
+                cW = bx[q]; cE = bx[q + 1]; cS = by[q]; cN = by[q + sy];
+                if (!have_carry) cB = bz[q];
+                cT = bz[q + sz]; cr = r[q];
+            }
+        };
+        auto load_ring = [&]() {
+            if (ringred) {
+                const int q = box_index(b, ri, rj, k);
+                aW = bx[q]; aE = bx[q + 1]; aS = by[q]; aN = by[q + sy]; aB = bz[q]; aT = bz[q + sz]; ar = r[q];
+            }
+        };
+        if constexpr (EARLY) {
+            // all of the step's global loads before the barrier, so that their
+            // latencies overlap: old plane k+1 first (its LDS stores wait only
+            // for it), then the coefficients (used after the barrier)
+            auto old_at = [&](int t) -> R {
+                int ii = i0 + (t % EX2) - 2, jj = j0 + (t / EX2) - 2;
+                R v = R(0);
+                const int kn = k + 1;
+                if (!zero_guess && kn >= 0 && kn < b.nz && ii >= 0 && ii < b.nx && jj >= 0 && jj < b.ny) {
+                    int q = box_index(b, ii, jj, kn);
+                    v = ein[q];
+                    if (ec) v += prolong_value<3, R>(cb, ec, ii, jj, kn, lin);
+                }
+                return v;
+            };
+            const R v0 = old_at(tid);
+            const R v1 = two ? old_at(tid + NT) : R(0);
+            load_own();
+            load_ring();
+            R *d = oldp[slot(k + 1)];
+            d[tid] = v0;
+            if (two) d[tid + NT] = v1;
+        } else {
+            load_old(k + 1);
+        }
+        __syncthreads();
         const R *om = oldp[slot(k - 1)], *oc = oldp[slot(k)], *op = oldp[slot(k + 1)];
         R *dst = newp[slot(k)];
         // red half-sweep of plane k: own tile point
         {
+            if constexpr (!EARLY) load_own();
             R v = R(0);
-            if (own && kin) {
-                const int q = box_index(b, i, j, k);
-                const R wW = bx[q] * ix2, wE = bx[q + 1] * ix2, wS = by[q] * iy2, wN = by[q + sy] * iy2;
-                const R wB = have_carry ? carryB : bz[q] * iz2;
-                const R wT = bz[q + sz] * iz2;
-                const R rr = r[q];
+            if (ownk) {
+                const R wW = cW * ix2, wE = cE * ix2, wS = cS * iy2, wN = cN * iy2;
+                const R wB = have_carry ? carryB : cB * iz2;
+                const R wT = cT * iz2;
                 carryB = wT;
                 have_carry = true;
                 if (((i + j + k) & 1) == 0) {
                     const R dg = wW + wE + wS + wN + wB + wT;
                     const R off = wW * oc[o2 - 1] + wE * oc[o2 + 1] + wS * oc[o2 - EX2] + wN * oc[o2 + EX2]
                                 + wB * om[o2] + wT * op[o2];
-                    v = dg > R(0) ? (rr + off) / dg : R(0);
+                    v = dg > R(0) ? (cr + off) / dg : R(0);
                 } else {
-                    kW = wW; kE = wE; kS = wS; kN = wN; kB = wB; kT = wT; kr = rr;
+                    kW = wW; kE = wE; kS = wS; kN = wN; kB = wB; kT = wT; kr = cr;
                     v = oc[o2];
                 }
             }
@@ -998,16 +1044,16 @@ __global__ void __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(8))
         }
         // red half-sweep of plane k: own ring point
         if (tid < NRING) {
+            if constexpr (!EARLY) load_ring();
             R v = R(0);
             if (ring && kin) {
-                if (((ri + rj + k) & 1) == 0) {
-                    const int q = box_index(b, ri, rj, k);
-                    const R wW = bx[q] * ix2, wE = bx[q + 1] * ix2, wS = by[q] * iy2, wN = by[q + sy] * iy2;
-                    const R wB = bz[q] * iz2, wT = bz[q + sz] * iz2;
+                if (ringred) {
+                    const R wW = aW * ix2, wE = aE * ix2, wS = aS * iy2, wN = aN * iy2;
+                    const R wB = aB * iz2, wT = aT * iz2;
                     const R dg = wW + wE + wS + wN + wB + wT;
                     const R off = wW * oc[ro2 - 1] + wE * oc[ro2 + 1] + wS * oc[ro2 - EX2] + wN * oc[ro2 + EX2]
                                 + wB * om[ro2] + wT * op[ro2];
-                    v = dg > R(0) ? (r[q] + off) / dg : R(0);
+                    v = dg > R(0) ? (ar + off) / dg : R(0);
                 } else {
                     v = oc[ro2];
                 }

@@ -383,7 +383,7 @@ void p_sweep3_launch(stokes_ctx &c, Level<R> &L, const R *in, R *out, const R *r
         k_p_sweep3<R, TX, TY><<<dim3(gx, gy, gz), TX * TY, 0, c.stream>>>(
             b, kc, zero_guess ? 1 : 0, in, ec, cb ? *cb : b, c.opt.p_prolong, out, r, L.beta[0], L.beta[1], L.beta[2]);
     else
-        k_p_sweep3c<R, TX, TY><<<dim3(gx, gy, gz), TX * TY, 0, c.stream>>>(
+        k_p_sweep3c<R, TX, TY, sizeof(R) == 4><<<dim3(gx, gy, gz), TX * TY, 0, c.stream>>>(
             b, kc, zero_guess ? 1 : 0, in, ec, cb ? *cb : b, c.opt.p_prolong, out, r, L.beta[0], L.beta[1], L.beta[2]);
 }
 
