@@ -359,7 +359,7 @@ def _counter_rows(d, counter):
     return rows
 
 
-def traffic_from_counters(fetch_dir, write_dir, n=256, precision=0):
+def traffic_from_counters(fetch_dir, write_dir, n=256, precision=0, path=None):
     """HBM bytes per launch of the finest fused pressure sweep from two rocprofv3 runs
     (--pmc FETCH_SIZE, then --pmc WRITE_SIZE) of 'bench.py --calibrate-copy': each
     counter (KiB per dispatch) is scaled by what it reads for the plain 1 GiB device
@@ -384,7 +384,7 @@ def traffic_from_counters(fetch_dir, write_dir, n=256, precision=0):
     R = 8 if precision == 0 else 4
     cells = float(n) ** 3
     kernels = [  # (label, name pattern, algorithmic bytes per launch on the finest level)
-        ("k_p_sweep3c (finest fused pressure sweep)", r"k_p_sweep3\w*<%s, 64, 16>" % ("double" if R == 8 else "float"),
+        ("k_p_sweep3c (finest fused pressure sweep)", r"k_p_sweep3\w*<%s, 64, 16(, \w+)?>" % ("double" if R == 8 else "float"),
          cells * R * 6.0),
         ("k_apply3_z (Stokes matvec)", r"k_apply3_z<", None),
         ("k_p_residual_restrict (finest)", r"k_p_residual_restrict<3, %s>" % ("double" if R == 8 else "float"),
@@ -420,7 +420,7 @@ def traffic_from_counters(fetch_dir, write_dir, n=256, precision=0):
              "fetch_kib_per_dispatch": fk, "write_kib_per_dispatch": wk, "dispatches": nd,
              "fetch_factor": ff, "write_factor": wf, "bytes_per_launch": fb + wb,
              "algorithmic_bytes_per_launch": alg, "kernel_source_hash": kernel_source_hash()}
-    path = os.path.join(ROOT, "profiles", "traffic.json")
+    path = path or os.path.join(ROOT, "profiles", "traffic.json")
     rec = json.load(open(path)) if os.path.exists(path) else {}
     rec["description"] = ("HBM traffic per launch of the timed kernel from rocprofv3 --pmc FETCH_SIZE and "
                           "WRITE_SIZE runs, each scaled by the same counter on a plain 1 GiB device copy "
@@ -437,6 +437,7 @@ def traffic_from_counters(fetch_dir, write_dir, n=256, precision=0):
     print("calibration (1 GiB copy): FETCH_SIZE factor %.3f, WRITE_SIZE factor %.3f" % (ff, wf))
     print("\n".join(lines))
     print("wrote", path)
+    return entry
 
 
 def cpu_baseline(prob, gpu_iters):
