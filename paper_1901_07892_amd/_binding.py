@@ -60,8 +60,7 @@ def load_library():
     if _lib is not None:
         return _lib
     if not os.path.exists(_LIB_PATH):
-        raise ImportError("libstokes.so is not built; run __graft_entry__.build() or "
-                          "python paper_1901_07892_amd/build.py")
+        raise ImportError("libstokes.so is not built; run python paper_1901_07892_amd/build.py")
     L = C.CDLL(_LIB_PATH)
     dp = C.c_void_p
     L.stokes_default_options.argtypes = [C.POINTER(StokesOptions)]

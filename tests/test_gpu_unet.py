@@ -145,9 +145,9 @@ def test_learned_tuple_normalisation():
 
 @pytest.mark.parametrize("stall", [0.9, 0.0])
 def test_learned_form_reaches_fp64_tolerance(stall):
-    """An untrained network attached as the learned stage: the FP64 residual is
-    still the judge, the answer matches the plain solve, and with stall_ratio 0
-    the fallback to plain multigrid is taken and reported."""
+    """An untrained network attached as the learned stage: the FP64 residual check
+    still decides convergence, the answer matches the plain solve, and with
+    stall_ratio 0 the fallback to plain multigrid is taken and reported."""
     import workloads as W
     import paper_1901_07892_amd as S
     from tests.gpu_util import gpu_solve, rel
