@@ -457,6 +457,81 @@ __global__ void __launch_bounds__(kBlock) k_p_residual_restrict(Box fb, Box cb, 
     rc[idx] = acc * (DIM == 3 ? R(0.125) : R(0.25));
 }
 
+// 3D residual + restriction marching in z: a thread owns one coarse column
+// (I, J) and a chunk of kc coarse planes; the fine values of its 2x2 fine
+// columns at the four planes a coarse plane needs (2K-1 .. 2K+2) stay in
+// registers, so each fine plane is read once instead of twice (the per-cell
+// kernel above re-reads the planes shared with the coarse cells below and
+// above) and the upper z coefficient of plane 2K+1 is reused.  Same formulas
+// and summation order as k_p_residual_restrict.
+template <class R, int TX, int TY>
+__global__ void __launch_bounds__(TX *TY) k_p_residual_restrict3_z(Box fb, Box cb, int kc,
+        const R *__restrict__ e, const R *__restrict__ r, const R *__restrict__ bx,
+        const R *__restrict__ by, const R *__restrict__ bz, R *__restrict__ rc) {
+    const int G = gridDim.x * gridDim.y * gridDim.z;
+    int t = xcd_swizzle(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z), G);
+    const int bx_ = t % gridDim.x;
+    t /= gridDim.x;
+    const int by_ = t % gridDim.y, bz_ = t / gridDim.y;
+    const int I = bx_ * TX + (int)(threadIdx.x % TX), J = by_ * TY + (int)(threadIdx.x / TX);
+    if (I >= cb.nx || J >= cb.ny) return;
+    const int K0 = bz_ * kc, K1 = min(K0 + kc, cb.nz);
+    if (K0 >= K1) return;
+    const int sy = fb.px, sz = fb.plane;
+    const R ix2 = R(fb.ihx * fb.ihx), iy2 = R(fb.ihy * fb.ihy), iz2 = R(fb.ihz * fb.ihz);
+    // fine columns c = di + 2 dj at offsets co[c] from the (2I, 2J) column
+    const int co[4] = {0, 1, sy, sy + 1};
+    int q = box_index(fb, 2 * I, 2 * J, 2 * K0);     // fine point (2I, 2J, 2K)
+    // e of the four columns at planes 2K-1 (em), 2K (ea), 2K+1 (eb), 2K+2 (ep); the
+    // guard plane below plane 0 and the padding plane nz hold zeros
+    R em[4], ea[4], eb[4], ep[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        em[c] = e[q + co[c] - sz];
+        ea[c] = e[q + co[c]];
+        eb[c] = e[q + co[c] + sz];
+        ep[c] = e[q + co[c] + 2 * sz];
+    }
+    for (int K = K0; K < K1; ++K, q += 2 * sz) {
+        R acc = 0;
+#pragma unroll
+        for (int dk = 0; dk < 2; ++dk) {
+            const R *lo = dk == 0 ? em : ea;
+            const R *ce = dk == 0 ? ea : eb;
+            const R *hi = dk == 0 ? eb : ep;
+#pragma unroll
+            for (int dj = 0; dj < 2; ++dj)
+#pragma unroll
+                for (int di = 0; di < 2; ++di) {
+                    const int c = di + 2 * dj;
+                    const int p = q + co[c] + dk * sz;
+                    const R eW = di == 1 ? ce[c - 1] : e[p - 1];
+                    const R eE = di == 0 ? ce[c + 1] : e[p + 1];
+                    const R eS = dj == 1 ? ce[c - 2] : e[p - sy];
+                    const R eN = dj == 0 ? ce[c + 2] : e[p + sy];
+                    const R wW = bx[p] * ix2, wE = bx[p + 1] * ix2;
+                    const R wS = by[p] * iy2, wN = by[p + sy] * iy2;
+                    R off = wW * eW + wE * eE + wS * eS + wN * eN;
+                    R dg = wW + wE + wS + wN;
+                    const R wB = bz[p] * iz2, wT = bz[p + sz] * iz2;
+                    off += wB * lo[c] + wT * hi[c];
+                    dg += wB + wT;
+                    acc += r[p] - (dg * ce[c] - off);
+                }
+        }
+        rc[box_index(cb, I, J, K)] = acc * R(0.125);
+        if (K + 1 < K1) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                em[c] = eb[c];
+                ea[c] = ep[c];
+                eb[c] = e[q + co[c] + 3 * sz];
+                ep[c] = e[q + co[c] + 4 * sz];
+            }
+        }
+    }
+}
+
 // Prolonged coarse correction at fine cell (i,j,k).  lin == 0: the parent's
 // value (piecewise constant).  lin == 1: bi/trilinear interpolation between the
 // cell centres, weights 3/4 (parent) and 1/4 (the coarse neighbour on the

@@ -444,7 +444,18 @@ R *p_vcycle(stokes_ctx &c, MG<R> &mg, int l, R *e, R *r, bool zero_guess) {
     }
     Level<R> &C = mg.L[l + 1];
     const R *bz = DIM == 3 ? L.beta[2] : L.beta[1];
-    k_p_residual_restrict<DIM, R><<<nblocks_box(C.b), kBlock, 0, c.stream>>>(L.b, C.b, cur, r, L.beta[0], L.beta[1], bz, C.rp);
+    if (DIM == 3 && (long long)L.b.nx * L.b.ny * L.b.nz >= (1LL << 21)) {
+        // z-marching form: each fine plane read once
+        constexpr int TX = 64, TY = 4;
+        const int gx = (C.b.nx + TX - 1) / TX, gy = (C.b.ny + TY - 1) / TY;
+        int kc = C.b.nz;
+        while (kc > 2 && (long long)gx * gy * ((C.b.nz + kc - 1) / kc) < 1024) kc = (kc + 1) / 2;
+        const int gz = (C.b.nz + kc - 1) / kc;
+        k_p_residual_restrict3_z<R, TX, TY><<<dim3(gx, gy, gz), TX * TY, 0, c.stream>>>(
+            L.b, C.b, kc, cur, r, L.beta[0], L.beta[1], bz, C.rp);
+    } else {
+        k_p_residual_restrict<DIM, R><<<nblocks_box(C.b), kBlock, 0, c.stream>>>(L.b, C.b, cur, r, L.beta[0], L.beta[1], bz, C.rp);
+    }
     R *ce = p_vcycle<DIM, R>(c, mg, l + 1, C.ep, C.rp, true);
     // W-cycle (p_gamma = 2): a second coarse cycle on the same coarse equation
     // (pointless above the exactly solved coarsest level)
