@@ -874,122 +874,31 @@ __global__ void __launch_bounds__(TX *TY) k_p_sweep3(Box b, int kc, int zero_gue
     }
 }
 
-// Two-barrier form of the fused 3D sweep (used on the largest levels, where
-// 1024-thread tiles keep the halo fraction low): one full red-black
-// Gauss-Seidel sweep of -L_rho e = r in 3D, both colours in one launch.  A block owns a TX x TY column of cells and a chunk of KC planes,
-// marching in z with rings of three planes in LDS: the old values (tile plus a
-// 2-cell x-y halo) and the values after the red half-sweep (tile plus 1).  Red
-// points of the 1-cell halo ring and of the planes next to the chunk are
-// recomputed by every block that needs them, so blocks are independent and the
-// result equals the global two-pass sweep.  Input and output are separate
-// arrays (ein is never written), so blocks never race.  With zero_guess the old
-// values are taken as zero (ein is not read).  With ec != nullptr the old value
-// is ein + the prolonged coarse correction ec: the prolongation of a coarse
-// correction (see prolong_value) is folded into the sweep that follows it.
-template <class R, int TX, int TY>
-__global__ void __launch_bounds__(TX *TY) k_p_sweep3b(Box b, int kc, int zero_guess, const R *__restrict__ ein,
-        const R *__restrict__ ec, Box cb, int lin, R *__restrict__ eout, const R *__restrict__ r,
-        const R *__restrict__ bx, const R *__restrict__ by, const R *__restrict__ bz) {
-    constexpr int NT = TX * TY;
-    constexpr int EX1 = TX + 2, EY1 = TY + 2, N1 = EX1 * EY1;
-    constexpr int EX2 = TX + 4, EY2 = TY + 4, N2 = EX2 * EY2;
-    __shared__ R oldp[3][N2];
-    __shared__ R newp[3][N1];
-    const int tid = threadIdx.x;
-    // logical tile from the XCD-swizzled linear block id, z slowest
-    const int G = gridDim.x * gridDim.y * gridDim.z;
-    int t = xcd_swizzle(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z), G);
-    const int bx_ = t % gridDim.x;
-    t /= gridDim.x;
-    const int by_ = t % gridDim.y, bz_ = t / gridDim.y;
-    const int i0 = bx_ * TX, j0 = by_ * TY;
-    const int k0 = bz_ * kc, k1 = min(k0 + kc, b.nz);
-    const int sy = b.px, sz = b.plane;
-    const R ix2 = R(b.ihx * b.ihx), iy2 = R(b.ihy * b.ihy), iz2 = R(b.ihz * b.ihz);
-    auto slot = [](int k) { return ((k % 3) + 3) % 3; };
-    auto load_old = [&](int k) {
-        R *dst = oldp[slot(k)];
-        for (int t = tid; t < N2; t += NT) {
-            int i = i0 + (t % EX2) - 2, j = j0 + (t / EX2) - 2;
-            R v = R(0);
-            if (!zero_guess && k >= 0 && k < b.nz && i >= 0 && i < b.nx && j >= 0 && j < b.ny) {
-                int q = box_index(b, i, j, k);
-                v = ein[q];
-                if (ec) v += prolong_value<3, R>(cb, ec, i, j, k, lin);
-            }
-            dst[t] = v;
-        }
-    };
-    load_old(k0 - 2);
-    load_old(k0 - 1);
-    for (int k = k0 - 1; k <= k1; ++k) {
-        load_old(k + 1);
-        __syncthreads();
-        // red half-sweep on plane k over the tile plus a 1-cell ring
-        {
-            const R *om = oldp[slot(k - 1)], *oc = oldp[slot(k)], *op = oldp[slot(k + 1)];
-            R *dst = newp[slot(k)];
-            for (int t = tid; t < N1; t += NT) {
-                int ex = t % EX1, ey = t / EX1;
-                int i = i0 + ex - 1, j = j0 + ey - 1;
-                R v = R(0);
-                if (k >= 0 && k < b.nz && i >= 0 && i < b.nx && j >= 0 && j < b.ny) {
-                    int o2 = (ey + 1) * EX2 + (ex + 1);
-                    if (((i + j + k) & 1) == 0) {
-                        int q = box_index(b, i, j, k);
-                        R wW = bx[q] * ix2, wE = bx[q + 1] * ix2, wS = by[q] * iy2, wN = by[q + sy] * iy2;
-                        R wB = bz[q] * iz2, wT = bz[q + sz] * iz2;
-                        R dg = wW + wE + wS + wN + wB + wT;
-                        R off = wW * oc[o2 - 1] + wE * oc[o2 + 1] + wS * oc[o2 - EX2] + wN * oc[o2 + EX2]
-                              + wB * om[o2] + wT * op[o2];
-                        v = dg > R(0) ? (r[q] + off) / dg : R(0);
-                    } else {
-                        v = oc[o2];
-                    }
-                }
-                dst[t] = v;
-            }
-        }
-        __syncthreads();
-        // black half-sweep on plane k-1 over the tile, written out with the red values
-        const int kk = k - 1;
-        if (kk >= k0 && kk < k1) {
-            const R *nm = newp[slot(kk - 1)], *nc = newp[slot(kk)], *np = newp[slot(kk + 1)];
-            int tx = tid % TX, ty = tid / TX;
-            int i = i0 + tx, j = j0 + ty;
-            if (i < b.nx && j < b.ny) {
-                int o1 = (ty + 1) * EX1 + (tx + 1);
-                int q = box_index(b, i, j, kk);
-                R v;
-                if (((i + j + kk) & 1) == 1) {
-                    R wW = bx[q] * ix2, wE = bx[q + 1] * ix2, wS = by[q] * iy2, wN = by[q + sy] * iy2;
-                    R wB = bz[q] * iz2, wT = bz[q + sz] * iz2;
-                    R dg = wW + wE + wS + wN + wB + wT;
-                    R off = wW * nc[o1 - 1] + wE * nc[o1 + 1] + wS * nc[o1 - EX1] + wN * nc[o1 + EX1]
-                          + wB * nm[o1] + wT * np[o1];
-                    v = dg > R(0) ? (r[q] + off) / dg : R(0);
-                } else {
-                    v = nc[o1];
-                }
-                eout[q] = v;
-            }
-        }
-    }
-}
 
-// Two-barrier fused 3D sweep with the coefficients read once per plane.  Same
-// tiling, rings and result as k_p_sweep3b, but every thread owns one point of
-// the TX x TY tile through both half-sweeps: in the red step of plane k it
-// reads its point's six face coefficients and right-hand side once, updates
-// the point if it is red, and otherwise keeps the seven values in registers
-// for the black step of plane k one step later (a plane later they would no
-// longer be in L2).  The upper z-face coefficient of plane k is the lower one
-// of plane k+1 and is carried over as well.  Threads below the ring size also
-// take one point of the 1-cell halo ring, read directly.  At most 64 VGPRs, so
-// that two 1024-thread blocks share a CU.  With EARLY all global loads of a step
-// are issued before its first barrier so that their latencies overlap (one HBM
-// round trip per plane instead of two); that keeps the coefficients live across
-// the barrier and fits the 64 registers only in float.
+// Two-barrier form of the fused 3D sweep, used on the largest levels (1024-thread
+// tiles keep the halo fraction low): one full red-black Gauss-Seidel sweep of
+// -L_rho e = r, both colours in one launch.  A block owns a TX x TY column of
+// cells and a chunk of kc planes and marches in z with rings of three planes in
+// LDS: the old values (tile plus a 2-cell x-y halo) and the values after the red
+// half-sweep (tile plus 1).  Step k loads old plane k+1, does the red half-sweep
+// of plane k and the black half-sweep of plane k-1.  Red points of the 1-cell
+// halo ring and of the planes next to the chunk are recomputed by every block
+// that needs them, so blocks are independent and the result equals the global
+// two-pass sweep; input and output are separate arrays, so blocks never race.
+// With zero_guess the old values are taken as zero (ein is not read); with
+// ec != nullptr the old value is ein + the prolonged coarse correction (see
+// prolong_value), so the prolongation is folded into the sweep that follows it.
+// Every thread owns one point of the tile through both half-sweeps: in the red
+// step of plane k it reads its point's six face coefficients and right-hand side
+// once, updates the point if it is red, and otherwise keeps the seven values in
+// registers for the black step of plane k one step later (a plane later they
+// would no longer be in L2).  The upper z-face coefficient of plane k is the
+// lower one of plane k+1 and is carried over as well.  Threads below the ring
+// size also take one point of the 1-cell halo ring, read directly.  At most 64
+// VGPRs, so that two 1024-thread blocks share a CU.  With EARLY all global loads
+// of a step are issued before its first barrier so that their latencies overlap
+// (one HBM round trip per plane instead of two); that keeps the coefficients
+// live across the barrier and fits the 64 registers only in float.
 template <class R, int TX, int TY, bool EARLY>
 __global__ void __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(8))) k_p_sweep3c(Box b, int kc, int zero_guess, const R *__restrict__ ein,
         const R *__restrict__ ec, Box cb, int lin, R *__restrict__ eout, const R *__restrict__ r,

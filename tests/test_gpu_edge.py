@@ -188,7 +188,7 @@ def test_viscous_dominated_uses_velocity_multigrid(precision):
 
 
 @pytest.mark.parametrize("maker", [lambda: W.config2(scale=2), lambda: W.config3(scale=2),
-                                   lambda: W.config4(scale=4)])
+                                   lambda: W.config4(scale=4), lambda: W.config5(n_cells=96)])
 def test_fp32_multigrid_reaches_fp64_residual(oracle_lib, maker):
     """Multigrid in FP32 inside FP64 FGMRES: the recomputed FP64 residual meets tol
     (1e-8); the error against the FP64 oracle is printed for the record."""

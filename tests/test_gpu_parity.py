@@ -109,6 +109,8 @@ def test_solve_matches_direct(name, maker, precision):
     ("config3_64", lambda: W.config3(scale=2)),
     ("config4_256x24x24", lambda: W.config4(scale=4)),
     ("config5_64", lambda: W.config5(n_cells=64)),
+    # finest level of 884,736 cells: the pipelined fused sweep (levels between 2^18 and 2^20 cells)
+    ("config5_96", lambda: W.config5(n_cells=96)),
 ])
 def test_solve_matches_oracle_fgmres(oracle_lib, name, maker):
     prob = maker()
