@@ -221,3 +221,41 @@ def test_stream_copy_copies_exactly(n, offset):
     assert float(dst_full[offset + n]) == -1.0          # nothing written past the end
     if offset:
         assert torch.all(dst_full[:offset] == -1.0)
+
+
+def test_profile_hook_counts_launches_and_bytes():
+    """The measurement hook behind the bench's roofline: the finest fused sweep
+    runs (nu1 + nu2) times per pressure cycle, p_cycles cycles per FGMRES
+    iteration, each launch moving 6 fields (and 1/8 of one more when it folds
+    the prolongation); the matvec runs once per iteration plus once for the
+    final true residual (a zero guess skips the first); reading resets."""
+    import torch
+    import paper_1901_07892_amd as S
+    prob = W.config3()                     # 128^3: the finest level uses the fused sweep
+    s = solver_for(prob)
+    rhs_u = [to_dev(f) for f in prob.rhs_u[:3]]
+    rhs_p = to_dev(prob.rhs_p)
+    xu = [torch.zeros_like(f) for f in rhs_u]
+    xp = torch.zeros_like(rhs_p)
+    S.stokes_profile_kernel(s.ctx, S._binding.PROF_P_SWEEP)
+    st, stats = s.solve(rhs_u, rhs_p, prob.tol, xu, xp)
+    torch.cuda.synchronize()
+    ms, n, by = S.stokes_profile_read(s.ctx)
+    o = s.opts
+    cycles = stats.iters * o.p_cycles
+    assert st == 0 and n == cycles * (o.nu1 + o.nu2) and ms > 0.0
+    cells = float(np.prod(prob.n))
+    assert by == pytest.approx(cycles * ((o.nu1 + o.nu2) * 6.0 + 0.125) * cells * 8.0, rel=1e-12)
+    assert S.stokes_profile_read(s.ctx) == (0.0, 0, 0.0)
+    S.stokes_profile_kernel(s.ctx, S._binding.PROF_MATVEC)
+    for a in xu:
+        a.zero_()
+    xp.zero_()
+    st, stats = s.solve(rhs_u, rhs_p, prob.tol, xu, xp)
+    torch.cuda.synchronize()
+    ms, n, by = S.stokes_profile_read(s.ctx)
+    assert n == stats.iters + 1 and ms > 0.0
+    S.stokes_profile_kernel(s.ctx, -1)
+    with pytest.raises(S.StokesError):
+        S.stokes_profile_kernel(s.ctx, 17)
+    s.close()
