@@ -72,7 +72,8 @@ typedef struct {
     int max_iters;       /* total FGMRES iterations allowed */
     int nu1, nu2;        /* pre- and post-smoothing sweeps per V-cycle level */
     int vel_cycles;      /* velocity V-cycles per preconditioner application (>= 0) */
-    int p_cycles;        /* pressure V-cycles per preconditioner application (>= 1) */
+    int p_cycles;        /* pressure cycles in the first preconditioner application of each
+                            FGMRES restart cycle (>= 1), 0 = automatic: 4 for 3D FP64, else 3 */
     int coarse_sweeps;   /* smoothing sweeps on the coarsest velocity level (and on the
                             coarsest pressure level when it is too big for a dense solve) */
     int vel_levels;      /* velocity multigrid levels.  0 = automatic: a single level (the
@@ -99,6 +100,9 @@ typedef struct {
                             visit (same passes and arithmetic as 0); 0 one launch per pass */
     int p_wdepth;        /* levels that use p_gamma coarse cycles: the p_wdepth finest (0 =
                             all); coarser levels take one (a V-cycle below them) */
+    int p_cycles_next;   /* pressure cycles in the later applications (>= 1), 0 = automatic:
+                            6 for 3D FP64 when p_cycles is automatic, else p_cycles (FGMRES is
+                            flexible, so the preconditioner may change between iterations) */
 } stokes_options;
 
 typedef struct {
@@ -121,8 +125,9 @@ typedef struct {
 typedef struct stokes_ctx stokes_ctx;
 
 /* Fill *opts with the defaults (FP64, theta 1, automatic sigma, restart 30,
- * max_iters 200, (2,2) smoothing, one velocity cycle and three pressure cycles that
- * are W-cycles on the two finest levels and V-cycles below, 40 coarse sweeps,
+ * max_iters 200, (2,2) smoothing, one velocity cycle and an automatic number of
+ * pressure cycles (4 then 6 for 3D FP64, otherwise 3) that are W-cycles on
+ * the two finest levels and V-cycles below, 40 coarse sweeps,
  * automatic velocity levels, 1 single-level velocity sweep, piecewise-constant
  * pressure prolongation, diagonal velocity step, one-pass Gram-Schmidt, z-marching
  * matvec, small levels cycled in one workgroup). */

@@ -125,6 +125,8 @@ struct stokes_ctx {
     double *vs = nullptr;        // scales of the unnormalised Krylov basis (m + 1)
     int *dflag = nullptr;
     int vcycles = 0;
+    int cyc_first = 3, cyc_next = 3;   // pressure cycles: first / later applications of a restart cycle
+    int cyc_now = 3;                    // cycles of the current application
     double visc_ratio = -1.0;   // max viscous/mass diagonal ratio (automatic velocity levels)
     bool diag_vel = false;      // velocity subsolve is one diagonal step (see stokes_options.vel_smoother)
     // learned stage: network, the level it runs on, feature/prediction buffers
@@ -505,7 +507,7 @@ void learned_guess(stokes_ctx &c, MG<R> &mg, R *phi0) {
     }
 }
 
-// Pressure subsolve of the preconditioner: p_cycles cycles on -L_rho phi = r
+// Pressure subsolve of the preconditioner: cyc_now cycles on -L_rho phi = r
 // (level 0 right-hand side already in L0.rp), from zero or from the learned
 // guess.  Returns the array holding phi.
 template <int DIM, class R>
@@ -517,7 +519,7 @@ R *pressure_cycles(stokes_ctx &c, MG<R> &mg) {
         learned_guess<R>(c, mg, phi);
         zero = false;
     }
-    for (int cyc = 0; cyc < c.opt.p_cycles; ++cyc) {
+    for (int cyc = 0; cyc < c.cyc_now; ++cyc) {
         phi = p_vcycle<DIM, R>(c, mg, 0, phi, L0.rp, zero && cyc == 0);
         c.vcycles++;
     }
@@ -718,6 +720,7 @@ stokes_status fgmres(stokes_ctx &c, MG<R> &mg, double tol, bool zero_guess, stok
                 k_scale<<<nblocks_stream(c.vlen), kBlock, 0, c.stream>>>(c.vlen, hs[j], vj);
                 set_scale(j, 1.0);
             }
+            c.cyc_now = j == 0 ? c.cyc_first : c.cyc_next;
             precond<DIM, R>(c, mg, vj, hs[j], zj);
             apply_fine<DIM>(c, zj, nullptr, w);
             // classical Gram-Schmidt: one pass (orth 1) or two (orth 2); the last
@@ -1055,7 +1058,7 @@ stokes_options defaults() {
     o.nu1 = 2;
     o.nu2 = 2;
     o.vel_cycles = 1;
-    o.p_cycles = 3;
+    o.p_cycles = 0;
     o.coarse_sweeps = 40;
     o.vel_levels = 0;
     o.vel_sweeps = 1;
@@ -1066,6 +1069,7 @@ stokes_options defaults() {
     o.p_gamma = 2;
     o.p_small = 1;
     o.p_wdepth = 2;
+    o.p_cycles_next = 0;
     return o;
 }
 
@@ -1084,7 +1088,7 @@ const char *check_grid_opts(const stokes_grid *g, const stokes_options &o) {
     if (o.restart < 1 || o.restart > 200) return "restart must be in [1, 200]";
     if (o.max_iters < 1) return "max_iters must be >= 1";
     if (o.nu1 < 0 || o.nu2 < 0 || o.nu1 + o.nu2 < 1) return "nu1, nu2 >= 0 with nu1 + nu2 >= 1";
-    if (o.vel_cycles < 0 || o.p_cycles < 1) return "vel_cycles >= 0 and p_cycles >= 1";
+    if (o.vel_cycles < 0 || o.p_cycles < 0 || o.p_cycles_next < 0) return "vel_cycles, p_cycles and p_cycles_next must be >= 0";
     if (o.coarse_sweeps < 1) return "coarse_sweeps must be >= 1";
     if (o.vel_levels < 0) return "vel_levels must be >= 0";
     if (o.vel_sweeps < 1) return "vel_sweeps must be >= 1";
@@ -1105,6 +1109,14 @@ void init_ctx_shape(stokes_ctx &c, const stokes_grid *g, const stokes_options &o
     c.nf = g->dim + 1;
     c.m = o.restart;
     c.theta = o.visc_scale;
+    // automatic pressure-cycle schedule: in 3D FP64 a lighter first application
+    // and stronger later ones reach the tolerance in two FGMRES iterations on the
+    // density-ratio-1000 workloads; the FP32 cycles cannot, nor do the 2D
+    // hierarchies, and those keep three cycles per application
+    const bool two_step = o.precision == 0 && g->dim == 3;
+    c.cyc_first = o.p_cycles > 0 ? o.p_cycles : (two_step ? 4 : 3);
+    c.cyc_next = o.p_cycles_next > 0 ? o.p_cycles_next : (o.p_cycles > 0 ? o.p_cycles : (two_step ? 6 : 3));
+    c.cyc_now = c.cyc_first;
     c.fine = make_box(g->dim, g->n[0], g->n[1], g->dim == 3 ? g->n[2] : 1, g->h[0], g->h[1],
                       g->dim == 3 ? g->h[2] : g->h[0]);
     {

@@ -59,7 +59,7 @@ def test_bad_grids_rejected_on_host(S, dim, n, h):
 def test_bad_options_rejected_on_host(S):
     g = S._binding.make_grid(2, (8, 8, 1), (1, 1, 1))
     o = S.stokes_default_options()
-    o.p_cycles = 0
+    o.p_cycles = -1
     assert S.stokes_workspace_size(g, o) == 0
     o = S.stokes_default_options()
     with pytest.raises(S.StokesError) as e:
@@ -75,13 +75,16 @@ def test_options_struct_layout_matches_library(S):
     fields read back with their documented defaults, and a bad value in the last
     field is rejected by the library's own validation."""
     o = S.stokes_default_options()
-    assert (o.orth, o.matvec_z, o.p_gamma, o.p_small, o.p_wdepth) == (1, 1, 2, 1, 2)
+    assert (o.orth, o.matvec_z, o.p_gamma, o.p_small, o.p_wdepth, o.p_cycles, o.p_cycles_next) == (1, 1, 2, 1, 2, 0, 0)
     g = S._binding.make_grid(3, (16, 16, 16), (1 / 16,) * 3)
     assert S.stokes_workspace_size(g, o) > 0
     o.p_wdepth = -1
     assert S.stokes_workspace_size(g, o) == 0
     o.p_wdepth = 0
     o.p_small = 2
+    assert S.stokes_workspace_size(g, o) == 0
+    o.p_small = 1
+    o.p_cycles_next = -1
     assert S.stokes_workspace_size(g, o) == 0
 
 

@@ -225,14 +225,15 @@ def test_stream_copy_copies_exactly(n, offset):
 
 def test_profile_hook_counts_launches_and_bytes():
     """The measurement hook behind the bench's roofline: the finest fused sweep
-    runs (nu1 + nu2) times per pressure cycle, p_cycles cycles per FGMRES
-    iteration, each launch moving 6 fields (and 1/8 of one more when it folds
-    the prolongation); the matvec runs once per iteration plus once for the
-    final true residual (a zero guess skips the first); reading resets."""
+    runs (nu1 + nu2) times per pressure cycle, p_cycles cycles in the first
+    preconditioner application and p_cycles_next in each later one, each launch
+    moving 6 fields (and 1/8 of one more when it folds the prolongation); the
+    matvec runs once per iteration plus once for the final true residual (a
+    zero guess skips the first); reading resets."""
     import torch
     import paper_1901_07892_amd as S
     prob = W.config3()                     # 128^3: the finest level uses the fused sweep
-    s = solver_for(prob)
+    s = solver_for(prob, p_cycles=2, p_cycles_next=5)
     rhs_u = [to_dev(f) for f in prob.rhs_u[:3]]
     rhs_p = to_dev(prob.rhs_p)
     xu = [torch.zeros_like(f) for f in rhs_u]
@@ -242,7 +243,8 @@ def test_profile_hook_counts_launches_and_bytes():
     torch.cuda.synchronize()
     ms, n, by = S.stokes_profile_read(s.ctx)
     o = s.opts
-    cycles = stats.iters * o.p_cycles
+    cycles = 2 + 5 * (stats.iters - 1)
+    assert stats.vcycles == cycles
     assert st == 0 and n == cycles * (o.nu1 + o.nu2) and ms > 0.0
     cells = float(np.prod(prob.n))
     assert by == pytest.approx(cycles * ((o.nu1 + o.nu2) * 6.0 + 0.125) * cells * 8.0, rel=1e-12)
