@@ -387,7 +387,7 @@ def traffic_from_counters(fetch_dir, write_dir, n=256, precision=0, path=None):
         ("k_p_sweep3c (finest fused pressure sweep)", r"k_p_sweep3\w*<%s, 64, 16(, \w+)?>" % ("double" if R == 8 else "float"),
          cells * R * 6.0),
         ("k_apply3_z (Stokes matvec)", r"k_apply3_z<", None),
-        ("k_p_residual_restrict (finest)", r"k_p_residual_restrict<3, %s>" % ("double" if R == 8 else "float"),
+        ("k_p_residual_restrict3_z (finest)", r"k_p_residual_restrict3_z<%s" % ("double" if R == 8 else "float"),
          cells * R * 5.0 + cells / 8 * R),
         ("k_precond_update_jac", r"k_precond_update_jac<", cells * 8 * 16.0),
         ("k_precond_div_jac", r"k_precond_div_jac<", cells * 8 * 9.0),
