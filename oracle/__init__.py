@@ -14,6 +14,9 @@ Contents
                    O4  projection preconditioner, lexicographic Gauss-Seidel
                        multigrid for both subsolves
   native.py        ctypes loader for liboracle.so (built with gcc + OpenMP)
+  coefficients.py  the coefficient step: smoothed Heaviside, two-step property
+                   law, face densities from level sets averaged onto faces
+  unet.py          the learned stage's network (forward pass)
 
 Parity of the GPU solve is measured on the solution of the linear system,
 never on iterates.  The multigrid inside O4 has no parity of its own

@@ -56,6 +56,10 @@ class Problem:
     phi: Optional[np.ndarray] = None        # cell level sets, kept for tests
     rho_flow_faces: Optional[List[Optional[np.ndarray]]] = None
     seed: Optional[int] = None
+    psi: Optional[List[np.ndarray]] = None  # cell level set of each solid (solid where < 0)
+    rho_solid: Optional[List[float]] = None # density of each solid
+    rho_air: float = RHO_AIR                # gas density of this problem
+    heaviside_cells: float = N_CELLS        # Heaviside half-width in cells of hx
 
     @property
     def n_cells(self) -> int:
@@ -254,12 +258,12 @@ def _materials(dim, n, h, phi_fn, solids, rho_air=RHO_AIR, n_cells=N_CELLS):
         rho_flow[ax] = two_stage(RHO_WATER, rho_air, hf, [])
         rho_faces[ax] = two_stage(RHO_WATER, rho_air, hf,
                                   [(rs, heaviside(face_average(ps, ax), eps)) for ps, rs in psis])
-    return phi, mu, rho_faces, rho_flow
+    return phi, mu, rho_faces, rho_flow, psis
 
 
 def make_problem(name, dim, n, h, dt, tol, phi_fn, solids, seed, rho_air=RHO_AIR,
                  rhs_rng=None, rhs_scale_by_mass=False):
-    phi, mu, rho_faces, rho_flow = _materials(dim, n, h, phi_fn, solids, rho_air=rho_air)
+    phi, mu, rho_faces, rho_flow, psis = _materials(dim, n, h, phi_fn, solids, rho_air=rho_air)
     rng = rhs_rng if rhs_rng is not None else np.random.Generator(np.random.PCG64(seed))
     rhs_u, _ = fourier_rhs(rng, dim, n, h)
     if rhs_scale_by_mass:
@@ -268,7 +272,8 @@ def make_problem(name, dim, n, h, dt, tol, phi_fn, solids, seed, rho_air=RHO_AIR
     rhs_p = np.zeros(cell_shape(n))
     return Problem(name=name, dim=dim, n=tuple(n), h=tuple(h), dt=dt, rho_faces=rho_faces,
                    mu=mu, rhs_u=rhs_u, rhs_p=rhs_p, tol=tol, phi=phi,
-                   rho_flow_faces=rho_flow, seed=seed)
+                   rho_flow_faces=rho_flow, seed=seed, psi=[ps for ps, _ in psis],
+                   rho_solid=[float(rs) for _, rs in psis], rho_air=rho_air)
 
 
 def _grid(dim, cells, lengths):
