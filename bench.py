@@ -177,6 +177,7 @@ def main():
     solver.close()
     del solver
     out["hbm_stream_copy"] = stream_copy(S)
+    out["coefficient_step"] = coefficient_step(S, prob)
     if not args.no_forms and args.precision == 0:
         out["forms"] = {"fp32_multigrid": fp32_form(S, prob, rho, mu, rhs_u, rhs_p, xu, xp, overrides,
                                                     ms, args.steps)}
@@ -338,6 +339,42 @@ def stream_copy(S):
     log("stream copy: %.1f GB/s (%.1f%% of 8 TB/s)" % (gbps, gbps / 80.0))
     return {"kernel": "k_stream_copy (library)", "bytes_per_launch": 2 * (1 << 30), "avg_launch_us": ms * 1e3,
             "GBps": gbps, "frac_of_8TBps": gbps / 8000.0}
+
+
+def coefficient_step(S, prob, launches=20):
+    """The step before the solve on the same instance: face densities and cell
+    viscosity from its level sets (stokes_coefficients), timed with events on
+    the stream it runs on.  Algorithmic bytes: every level set read once, every
+    output written once."""
+    import torch
+    import workloads as W
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    n, dim = prob.n, prob.dim
+    phi = dev(prob.phi)
+    psi = [dev(p) for p in prob.psi]
+    rho = [torch.empty(W.face_shape(n, ax), dtype=torch.float64, device="cuda") for ax in range(dim)]
+    mu = torch.empty(W.cell_shape(n), dtype=torch.float64, device="cuda")
+    grid = S._binding.make_grid(dim, n, prob.h)
+    fl = S.make_fluids(W.RHO_WATER, prob.rho_air, W.MU_WATER, W.MU_AIR, prob.heaviside_cells)
+    mus = [W.MU_SOLID] * len(psi)
+    run = lambda: S.stokes_coefficients(grid, fl, phi, psi, prob.rho_solid, mus, rho, mu)
+    for _ in range(3):
+        run()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(launches):
+        run()
+    e1.record()
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) / launches * 1e3
+    nbytes = 8.0 * ((1 + len(psi)) * mu.numel() + mu.numel() + sum(r.numel() for r in rho))
+    err = max([float((mu.cpu().numpy() - prob.mu).__abs__().max() / prob.mu.max())] +
+              [float((r.cpu().numpy() - pr).__abs__().max() / pr.max()) for r, pr in zip(rho, prob.rho_faces)])
+    gbps = nbytes / (us * 1e-6) / 1e9
+    log("coefficient step: %.1f us, %.0f GB/s (%d solids), max rel diff vs generator %.1e" % (us, gbps, len(psi), err))
+    return {"kernel": "k_coefficients<%d>" % len(psi), "solids": len(psi), "avg_launch_us": us,
+            "bytes_per_launch": nbytes, "GBps": gbps, "frac_of_8TBps": gbps / 8000.0,
+            "max_rel_diff_vs_generator": err}
 
 
 def _cpu_model():

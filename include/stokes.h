@@ -207,6 +207,49 @@ stokes_status stokes_profile_read(stokes_ctx *ctx, double *ms_total, long long *
 stokes_status stokes_stream_copy(const double *src, double *dst, long long n, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * Coefficient step (Sec. 4.1, eqs. eq_heaviside, eq_ls_flow, eq_ls_solid;
+ * Sec. 4.2.2 for the face density): the rho_face and mu_cell that
+ * stokes_setup takes, computed on the device from signed-distance level sets.
+ *
+ *   H(x) = 0 for x < -eps, 1 for x > eps, (1 + x/eps + sin(pi x/eps)/pi)/2
+ *          between, with eps = n_cells * hx (the grid is taken as isotropic);
+ *   flowing phase  z = z_liquid + (z_gas - z_liquid) H(phi)   (liquid: phi < 0);
+ *   each solid q   z = z_s[q] + (z - z_s[q]) H(psi_q)        (solid: psi_q < 0),
+ *                  applied in the order given.
+ *
+ * mu_cell uses the cell level sets.  A face uses the level sets averaged onto
+ * it: the mean of its two cells, or the one cell of a boundary face (every
+ * face of the output arrays is written, wall faces included).
+ * rho_flow_face, if not NULL, receives the flowing-phase density alone (no
+ * solid) on the same faces, as the well-balanced gravity force needs (Sec. 4.3).
+ * --------------------------------------------------------------------------- */
+#define STOKES_MAX_SOLIDS 8
+
+typedef struct {
+    double rho_liquid, rho_gas;   /* > 0 */
+    double mu_liquid, mu_gas;     /* >= 0 */
+    double n_cells;               /* Heaviside half-width in cells of hx, > 0 */
+} stokes_fluids;
+
+/* phi          device, cell layout (Nz, Ny, Nx): liquid/gas level set
+ * n_solids     0..STOKES_MAX_SOLIDS
+ * psi          HOST array of n_solids DEVICE pointers, each a cell-layout level set
+ * rho_solid, mu_solid   HOST arrays of n_solids values (> 0, >= 0)
+ * rho_face[3]  device outputs in the face layouts (rho_face[2] ignored in 2D)
+ * mu_cell      device output, cell layout
+ * rho_flow_face  NULL, or device outputs like rho_face
+ * stream       hipStream_t (as void*); asynchronous, no workspace, no allocation.
+ * Grids need >= 1 cell per axis and fewer than 2^31 points (Nx+1)(Ny+1)(Nz+1)
+ * (ESHAPE otherwise).  EINVAL for a NULL required pointer, a non-positive or
+ * non-finite density, spacing or n_cells, a negative viscosity or n_solids out
+ * of range; EHIP if the launch fails.  Outputs must not overlap the inputs. */
+stokes_status stokes_coefficients(const stokes_grid *grid, const stokes_fluids *fluids,
+                                  const double *phi, int n_solids, const double *const *psi,
+                                  const double *rho_solid, const double *mu_solid,
+                                  double *const rho_face[3], double *mu_cell,
+                                  double *const rho_flow_face[3], void *stream);
+
+/* ---------------------------------------------------------------------------
  * Learned form: a 4-level 3D U-Net (channels 16/32/48/64, 3x3x3 convolutions,
  * ReLU, 2x2x2 average pooling, nearest upsampling, additive skips) in BF16 with
  * FP32 accumulation on the matrix cores (v_mfma_f32_16x16x16_bf16), with its

@@ -25,6 +25,10 @@ from ._binding import (  # noqa: F401
     stokes_setup,
     stokes_solve,
     stokes_stream_copy,
+    StokesFluids,
+    MAX_SOLIDS,
+    make_fluids,
+    stokes_coefficients,
     stokes_workspace_size,
     stokes_unet_param_count,
     stokes_unet_forward_flops,

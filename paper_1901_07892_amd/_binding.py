@@ -28,6 +28,14 @@ class StokesGrid(C.Structure):
     _fields_ = [("dim", C.c_int), ("n", C.c_int * 3), ("h", C.c_double * 3)]
 
 
+class StokesFluids(C.Structure):
+    _fields_ = [("rho_liquid", C.c_double), ("rho_gas", C.c_double), ("mu_liquid", C.c_double),
+                ("mu_gas", C.c_double), ("n_cells", C.c_double)]
+
+
+MAX_SOLIDS = 8
+
+
 class StokesOptions(C.Structure):
     _fields_ = [("precision", C.c_int), ("visc_scale", C.c_double), ("cont_scale", C.c_double),
                 ("restart", C.c_int), ("max_iters", C.c_int), ("nu1", C.c_int), ("nu2", C.c_int),
@@ -86,6 +94,10 @@ def load_library():
     L.stokes_profile_read.restype = C.c_int
     L.stokes_stream_copy.argtypes = [dp, dp, C.c_longlong, dp]
     L.stokes_stream_copy.restype = C.c_int
+    L.stokes_coefficients.argtypes = [C.POINTER(StokesGrid), C.POINTER(StokesFluids), dp, C.c_int,
+                                      C.POINTER(C.c_void_p), C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                      C.c_void_p * 3, dp, C.POINTER(C.c_void_p * 3), dp]
+    L.stokes_coefficients.restype = C.c_int
     L.stokes_unet_param_count.argtypes = []
     L.stokes_unet_param_count.restype = C.c_longlong
     L.stokes_unet_forward_flops.argtypes = [C.c_int]
@@ -230,6 +242,39 @@ def stokes_stream_copy(src, dst, stream=None) -> None:
     st = load_library().stokes_stream_copy(src.data_ptr(), dst.data_ptr(), src.numel(), _stream(stream))
     if st < 0:
         raise StokesError(st, "stokes_stream_copy failed")
+
+
+def make_fluids(rho_liquid, rho_gas, mu_liquid, mu_gas, n_cells) -> StokesFluids:
+    f = StokesFluids()
+    f.rho_liquid, f.rho_gas, f.mu_liquid, f.mu_gas, f.n_cells = (
+        float(rho_liquid), float(rho_gas), float(mu_liquid), float(mu_gas), float(n_cells))
+    return f
+
+
+def stokes_coefficients(grid, fluids, phi, psi, rho_solid, mu_solid, rho_face, mu_cell,
+                        rho_flow_face=None, stream=None) -> None:
+    """Face densities and cell viscosity from level sets on the device.
+
+    ``psi`` is a list of solid level sets (device tensors, cell layout) with
+    ``rho_solid`` / ``mu_solid`` lists of their properties; ``rho_face`` (and
+    ``rho_flow_face`` when given) are lists of 2 or 3 face-layout output tensors.
+    """
+    L = load_library()
+    ns = len(psi)
+    if len(rho_solid) != ns or len(mu_solid) != ns:
+        raise ValueError("psi, rho_solid and mu_solid must have one entry per solid")
+    cap = max(ns, 1)
+    ps = (C.c_void_p * cap)(*[_ptr(t) for t in psi])
+    rs = (C.c_double * cap)(*[float(v) for v in rho_solid])
+    ms = (C.c_double * cap)(*[float(v) for v in mu_solid])
+    flow = C.byref(_ptr3(list(rho_flow_face) + [None] * 3)) if rho_flow_face is not None else None
+    st = L.stokes_coefficients(C.byref(grid), C.byref(fluids), _ptr(phi), ns,
+                               C.cast(ps, C.POINTER(C.c_void_p)) if ns else None,
+                               C.cast(rs, C.POINTER(C.c_double)) if ns else None,
+                               C.cast(ms, C.POINTER(C.c_double)) if ns else None,
+                               _ptr3(list(rho_face) + [None] * 3), _ptr(mu_cell), flow, _stream(stream))
+    if st < 0:
+        raise StokesError(st, "stokes_coefficients failed")
 
 
 # ---------------------------------------------------------------- convenience wrapper

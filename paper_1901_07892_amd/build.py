@@ -7,7 +7,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = [os.path.join(HERE, "csrc", "stokes.hip"), os.path.join(HERE, "csrc", "unet.hip")]
+SRC = [os.path.join(HERE, "csrc", f) for f in ("stokes.hip", "unet.hip", "coef.hip")]
 LIB = os.path.join(HERE, "libstokes.so")
 
 HIPCC_FLAGS = [
@@ -19,7 +19,7 @@ HIPCC_FLAGS = [
 
 
 def build(verbose: bool = False) -> str:
-    """Compile csrc/stokes.hip and csrc/unet.hip into libstokes.so (always recompiles)."""
+    """Compile the HIP sources of csrc/ into libstokes.so (always recompiles)."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     tmp = LIB + ".tmp"
     cmd = [hipcc] + HIPCC_FLAGS + ["-I", os.path.join(ROOT, "include"), "-o", tmp] + SRC

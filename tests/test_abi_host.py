@@ -93,3 +93,37 @@ def test_stream_copy_rejects_bad_arguments_on_host(S):
     assert L.stokes_stream_copy(None, None, -1, None) == -1
     assert L.stokes_stream_copy(None, None, 5, None) == -1
     assert L.stokes_stream_copy(None, None, 0, None) == 0
+
+
+def test_coefficients_reject_bad_arguments_on_host(S):
+    """Every argument check of stokes_coefficients returns before any HIP call
+    (the pointers below are never dereferenced)."""
+    B = S._binding
+    g3 = B.make_grid(3, (8, 8, 8), (1 / 8,) * 3)
+    ok = B.make_fluids(1000.0, 1.0, 1e-3, 1.8e-5, 1.5)
+    fake = [0x1000, 0x2000, 0x3000]
+
+    def call(grid=g3, fluids=ok, phi=0x4000, psi=(), rs=(), ms=(), rho=fake, mu=0x5000, flow=None):
+        with pytest.raises(S.StokesError) as e:
+            S.stokes_coefficients(grid, fluids, phi, list(psi), list(rs), list(ms), rho, mu, flow, stream=0)
+        return e.value.status
+
+    assert call(grid=B.make_grid(4, (8, 8, 8), (1, 1, 1))) == -1
+    assert call(grid=B.make_grid(3, (8, 0, 8), (1, 1, 1))) == -2
+    assert call(grid=B.make_grid(3, (2000, 2000, 2000), (1, 1, 1))) == -2
+    assert call(grid=B.make_grid(3, (8, 8, 8), (1, -1, 1))) == -1
+    assert call(phi=None) == -1
+    assert call(mu=None) == -1
+    assert call(rho=[0x1000, None, 0x3000]) == -1
+    assert call(rho=[0x1000, 0x2000, None]) == -1                 # 3D needs rho_z
+    assert call(flow=[0x1000, 0x2000, None]) == -1
+    for bad in (B.make_fluids(0.0, 1.0, 1e-3, 1e-5, 1.5), B.make_fluids(1e3, 1.0, -1e-3, 1e-5, 1.5),
+                B.make_fluids(1e3, float("nan"), 1e-3, 1e-5, 1.5), B.make_fluids(1e3, 1.0, 1e-3, 1e-5, 0.0)):
+        assert call(fluids=bad) == -1
+    assert call(psi=[0x6000], rs=[-5.0], ms=[1e-3]) == -1
+    assert call(psi=[None], rs=[500.0], ms=[1e-3]) == -1
+    assert call(psi=[0x6000] * (S.MAX_SOLIDS + 1), rs=[500.0] * (S.MAX_SOLIDS + 1),
+                ms=[1e-3] * (S.MAX_SOLIDS + 1)) == -1
+    L = S.load_library()
+    assert L.stokes_coefficients(ctypes.byref(g3), ctypes.byref(ok), 0x4000, -1, None, None, None,
+                                 B._ptr3(fake), 0x5000, None, None) == -1

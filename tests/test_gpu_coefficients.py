@@ -1,0 +1,145 @@
+"""Parity of the device coefficient step (stokes_coefficients) with the oracle
+(oracle/coefficients.py): face densities, cell viscosity and flow-only face
+densities from level sets, element by element.
+
+Tolerance: the two sides evaluate the same closed forms in FP64 and differ
+only in rounding (the sine of the band formula, fused multiply-adds), so an
+output may differ by a few units in the last place of the largest material
+constant it mixes: |gpu - oracle| <= 1e-13 * max|constants|.  Outside every
+Heaviside band the law reduces to adding zero or a product with 1, and the
+values are compared bit for bit."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import coefficients as OC
+from tests.gpu_util import rel, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+def _guarded(shape):
+    """Output tensor inside a NaN-filled buffer, to catch writes out of bounds."""
+    import torch
+    n = int(np.prod(shape))
+    buf = torch.full((n + 128,), float("nan"), dtype=torch.float64, device="cuda")
+    return buf, buf[64:64 + n].view(*shape)
+
+
+def _run(dim, n, h, phi, psis, rho_s, mu_s, fluids, flow=True):
+    import torch
+    import paper_1901_07892_amd as S
+    grid = S._binding.make_grid(dim, n, h)
+    fl = S.make_fluids(*fluids)
+    bufs, rho, frho = [], [], []
+    for ax in range(dim):
+        b, t = _guarded(W.face_shape(n, ax))
+        bufs.append(b)
+        rho.append(t)
+        if flow:
+            b, t = _guarded(W.face_shape(n, ax))
+            bufs.append(b)
+            frho.append(t)
+    b, mu = _guarded(W.cell_shape(n))
+    bufs.append(b)
+    phid = to_dev(phi)
+    psid = [to_dev(p) for p in psis]
+    print("stokes_coefficients dim=%d n=%s solids=%d flow=%d" % (dim, tuple(n), len(psis), flow), flush=True)
+    S.stokes_coefficients(grid, fl, phid, psid, rho_s, mu_s, rho, mu, frho if flow else None)
+    torch.cuda.synchronize()
+    for b in bufs:
+        g = to_host(b)
+        assert np.all(np.isnan(g[:64])) and np.all(np.isnan(g[-64:])), "write outside an output array"
+    return [to_host(t) for t in rho], to_host(mu), [to_host(t) for t in frho]
+
+
+def _check(dim, n, h, phi, psis, rho_s, mu_s, fluids, flow=True):
+    rho_l, rho_g, mu_l, mu_g, nc = fluids
+    rho, mu, frho = _run(dim, n, h, phi, psis, rho_s, mu_s, fluids, flow)
+    orho, omu, oflow = OC.coefficients(dim, h, phi, psis, rho_s, mu_s, rho_l, rho_g, mu_l, mu_g, nc)
+    rscale = max([rho_l, rho_g] + list(rho_s))
+    mscale = max([mu_l, mu_g] + list(mu_s))
+    np.testing.assert_allclose(mu, omu, rtol=0, atol=1e-13 * mscale)
+    for ax in range(dim):
+        np.testing.assert_allclose(rho[ax], orho[ax], rtol=0, atol=1e-13 * rscale)
+        if flow:
+            np.testing.assert_allclose(frho[ax], oflow[ax], rtol=0, atol=1e-13 * max(rho_l, rho_g))
+    # far from every interface the values are exact
+    eps = nc * h[0]
+    far = np.abs(phi) > 2 * eps
+    for ps in psis:
+        far &= np.abs(ps) > 2 * eps
+    assert np.array_equal(mu[far], omu[far])
+    return rho, mu
+
+
+def _fluids(p):
+    return (W.RHO_WATER, p.rho_air, W.MU_WATER, W.MU_AIR, p.heaviside_cells)
+
+
+@pytest.mark.parametrize("maker", [W.config1, W.config2, lambda: W.config3(), lambda: W.config5(scale=2)],
+                         ids=["config1_64sq", "config2_512sq", "config3_128cube", "config5_128cube"])
+def test_coefficients_match_oracle_on_workloads(maker):
+    p = maker()
+    _check(p.dim, p.n, p.h, p.phi, p.psi, p.rho_solid, [W.MU_SOLID] * len(p.psi), _fluids(p))
+
+
+def _smooth_field(rng, n, h, dim, scale):
+    xs = [(np.arange(m) + 0.5) * hh for m, hh in zip(n, h)]
+    Z, Y, X = np.meshgrid(xs[2], xs[1], xs[0], indexing="ij")
+    f = rng.uniform(-0.5, 0.5) * np.ones_like(X)
+    for _ in range(4):
+        k = rng.integers(-3, 4, size=3) * 2 * np.pi
+        f += scale * rng.uniform(0.2, 1.0) * np.cos(k[0] * X + k[1] * Y + (k[2] * Z if dim == 3 else 0)
+                                                   + rng.uniform(0, 2 * np.pi))
+    return f
+
+
+@pytest.mark.parametrize("dim,n,ns,flow", [
+    (3, (37, 19, 32), 2, True),      # nz a multiple of the z chunk: a chunk holding only the top z-face
+    (3, (5, 3, 17), 1, False),
+    (3, (64, 48, 33), 8, True),      # the most solids
+    (3, (1, 1, 1), 0, True),         # one cell: every face is a boundary face
+    (2, (33, 17, 1), 3, True),
+    (2, (200, 3, 1), 0, False),
+])
+def test_coefficients_ragged_grids(dim, n, ns, flow):
+    rng = np.random.default_rng(1000 + sum(n) + ns)
+    h = (1.0 / max(n[:dim]),) * 3
+    # level sets of O(1) slope so that many cells fall in the Heaviside band
+    phi = _smooth_field(rng, n, h, dim, 0.05)
+    psis = [_smooth_field(rng, n, h, dim, 0.05) + 0.03 for _ in range(ns)]
+    rho_s = list(rng.uniform(300.0, 1200.0, ns))
+    mu_s = list(rng.uniform(1e-4, 1e-2, ns))
+    _check(dim, n, h, phi, psis, rho_s, mu_s, (1000.0, 1.2, 1e-3, 1.8e-5, 1.5), flow)
+
+
+def test_coefficients_headline_instance():
+    """256^3 headline instance (seed 900000), the launch the benchmark times."""
+    p = W.config5()
+    rho, mu = _check(p.dim, p.n, p.h, p.phi, p.psi, p.rho_solid, [W.MU_SOLID] * len(p.psi), _fluids(p))
+    # and equal to the generator's coefficients the solve benchmarks use
+    assert rel(mu, p.mu) < 1e-14
+    for ax in range(3):
+        assert rel(rho[ax], p.rho_faces[ax]) < 1e-14
+
+
+def test_device_coefficients_feed_the_solver():
+    """Coefficients built on the device give the same solution as the
+    generator's (config 1 at 64^2, tol 1e-12)."""
+    import torch
+    import paper_1901_07892_amd as S
+    p = W.config1()
+    rho, mu, _ = _run(p.dim, p.n, p.h, p.phi, p.psi, p.rho_solid, [W.MU_SOLID] * len(p.psi), _fluids(p), False)
+    out = []
+    for r, m in ((rho, mu), (p.rho_faces[:2], p.mu)):
+        s = S.StokesSolver(2, p.n, p.h, [to_dev(a) for a in r], to_dev(m), p.dt)
+        xu = [torch.zeros_like(to_dev(f)) for f in p.rhs_u[:2]]
+        xp = torch.zeros_like(to_dev(p.rhs_p))
+        st, _ = s.solve([to_dev(f) for f in p.rhs_u[:2]], to_dev(p.rhs_p), 1e-12, xu, xp)
+        torch.cuda.synchronize()
+        assert st == 0
+        out.append([to_host(a) for a in xu] + [to_host(xp)])
+        s.close()
+    for a, b in zip(*out):
+        assert rel(a, b) < 1e-10
