@@ -15,8 +15,9 @@
 //
 // One HBM-bound pass: each thread owns one (i, j) point of the
 // (Nx+1) x (Ny+1) index plane and marches over a chunk of z planes, keeping
-// the level sets of the plane below in registers; the x- and y-neighbours are
-// the neighbouring threads' loads and come from cache.  Per point it writes
+// the level sets of the plane below in registers and loading the next plane
+// one step ahead; the x- and y-neighbours are the neighbouring threads' loads
+// and come from cache.  Per point it writes
 // the viscosity of cell (i, j, k), the x-face i, the y-face j and the z-face k
 // that exist there, directly in the caller's C-order layouts.
 #include "../../include/stokes.h"
@@ -29,7 +30,7 @@
 namespace {
 
 constexpr int kCoefBlock = 256;
-constexpr int kCoefPlanes = 16;   // z planes per block
+constexpr int kCoefPlanes = 8;    // z planes per block
 
 struct CoefArgs {
     int nx, ny, nz, dim;
@@ -58,6 +59,10 @@ __device__ inline double material(double zl, double zg, const double *zs, double
     return z;
 }
 
+// Outputs are written once and consumed by a later call (the solver's setup),
+// so they are stored with the non-temporal hint.
+__device__ inline void put(double *p, double v) { __builtin_nontemporal_store(v, p); }
+
 template <int NS>
 __global__ void __launch_bounds__(kCoefBlock) k_coefficients(CoefArgs a, const double *__restrict__ phi,
         double *__restrict__ rx, double *__restrict__ ry, double *__restrict__ rz, double *__restrict__ mu,
@@ -80,15 +85,27 @@ __global__ void __launch_bounds__(kCoefBlock) k_coefficients(CoefArgs a, const d
 #pragma unroll
         for (int q = 0; q < NS; ++q) sb[q] = a.psi[q][o];
     }
+    // own, west and south level sets of the next plane, loaded one plane ahead so
+    // that their latency overlaps the current plane's arithmetic and stores
+    const long long roww = iw + (long long)nx * cj, rows = ci + (long long)nx * js;
+    double nfc, nfw, nfs, nsc[NS > 0 ? NS : 1], nsw[NS > 0 ? NS : 1], nss[NS > 0 ? NS : 1];
+    {
+        const long long pk = plane * min(k0, nz - 1);
+        nfc = phi[rowc + pk]; nfw = phi[roww + pk]; nfs = phi[rows + pk];
+#pragma unroll
+        for (int q = 0; q < NS; ++q) { nsc[q] = a.psi[q][rowc + pk]; nsw[q] = a.psi[q][roww + pk]; nss[q] = a.psi[q][rows + pk]; }
+    }
     for (int k = k0; k < k1; ++k) {
-        const int ck = min(k, nz - 1);
-        const long long oc = rowc + plane * ck;
-        const long long ow = iw + (long long)nx * cj + plane * ck;
-        const long long os = ci + (long long)nx * js + plane * ck;
-        const double fc = phi[oc], fw = phi[ow], fs = phi[os];
+        const double fc = nfc, fw = nfw, fs = nfs;
         double sc[NS > 0 ? NS : 1], sw[NS > 0 ? NS : 1], ss[NS > 0 ? NS : 1];
 #pragma unroll
-        for (int q = 0; q < NS; ++q) { sc[q] = a.psi[q][oc]; sw[q] = a.psi[q][ow]; ss[q] = a.psi[q][os]; }
+        for (int q = 0; q < NS; ++q) { sc[q] = nsc[q]; sw[q] = nsw[q]; ss[q] = nss[q]; }
+        if (k + 1 < k1) {
+            const long long pk = plane * min(k + 1, nz - 1);
+            nfc = phi[rowc + pk]; nfw = phi[roww + pk]; nfs = phi[rows + pk];
+#pragma unroll
+            for (int q = 0; q < NS; ++q) { nsc[q] = a.psi[q][rowc + pk]; nsw[q] = a.psi[q][roww + pk]; nss[q] = a.psi[q][rows + pk]; }
+        }
         if (k == 0) {                         // the plane below the first is the first (mirror)
             fb = fc;
 #pragma unroll
@@ -97,27 +114,27 @@ __global__ void __launch_bounds__(kCoefBlock) k_coefficients(CoefArgs a, const d
         const bool in_z = k < nz;
         double t[NS > 0 ? NS : 1], fl;
         if (in_z && i < nx && j < ny)
-            mu[i + (long long)nx * j + plane * k] = material<NS>(a.mu_l, a.mu_g, a.mu_s, fc, sc, a.eps, fl);
+            put(mu + i + (long long)nx * j + plane * k, material<NS>(a.mu_l, a.mu_g, a.mu_s, fc, sc, a.eps, fl));
         if (in_z && j < ny) {                 // x-face i (i = 0 and nx take their one cell)
 #pragma unroll
             for (int q = 0; q < NS; ++q) t[q] = 0.5 * (sw[q] + sc[q]);
             const long long o = i + (long long)px * (j + (long long)ny * k);
-            rx[o] = material<NS>(a.rho_l, a.rho_g, a.rho_s, 0.5 * (fw + fc), t, a.eps, fl);
-            if (fx) fx[o] = fl;
+            put(rx + o, material<NS>(a.rho_l, a.rho_g, a.rho_s, 0.5 * (fw + fc), t, a.eps, fl));
+            if (fx) put(fx + o, fl);
         }
         if (in_z && i < nx) {                 // y-face j
 #pragma unroll
             for (int q = 0; q < NS; ++q) t[q] = 0.5 * (ss[q] + sc[q]);
             const long long o = i + (long long)nx * (j + (long long)py * k);
-            ry[o] = material<NS>(a.rho_l, a.rho_g, a.rho_s, 0.5 * (fs + fc), t, a.eps, fl);
-            if (fy) fy[o] = fl;
+            put(ry + o, material<NS>(a.rho_l, a.rho_g, a.rho_s, 0.5 * (fs + fc), t, a.eps, fl));
+            if (fy) put(fy + o, fl);
         }
         if (a.dim == 3 && i < nx && j < ny) { // z-face k (k = 0 and nz take their one cell)
 #pragma unroll
             for (int q = 0; q < NS; ++q) t[q] = 0.5 * (sb[q] + sc[q]);
             const long long o = i + (long long)nx * j + plane * k;
-            rz[o] = material<NS>(a.rho_l, a.rho_g, a.rho_s, 0.5 * (fb + fc), t, a.eps, fl);
-            if (fz) fz[o] = fl;
+            put(rz + o, material<NS>(a.rho_l, a.rho_g, a.rho_s, 0.5 * (fb + fc), t, a.eps, fl));
+            if (fz) put(fz + o, fl);
         }
         fb = fc;
 #pragma unroll

@@ -143,3 +143,43 @@ def test_device_coefficients_feed_the_solver():
         s.close()
     for a, b in zip(*out):
         assert rel(a, b) < 1e-10
+
+
+def test_well_balanced_tank_from_device_coefficients():
+    """Sec. 4.3's well-balanced gravity in 3D, built on the device end to end:
+    the coefficient step gives rho (with the solid) for the operator and the
+    flow-only rho for the force f_z = rho_flow g; the solve must return u = 0
+    and the discrete hydrostatic pressure p_k - p_(k-1) = hz rho_flow(z-face k) g.
+    Negative control: the force from the full density (solid included) is not
+    balanced and drives a flow many orders larger."""
+    import torch
+    import paper_1901_07892_amd as S
+    p = W.config3(scale=2)                      # 64^3 with config 3's sphere (rho_s 700)
+    g = -9.81
+    # a flat water surface z = 0.55: the flow density then depends on z only, so the
+    # force is a discrete gradient and the fluid stays at rest
+    _, _, Z = W.cell_coords(p.n, p.h)
+    phi = Z - 0.55
+    rho, mu, flow = _run(p.dim, p.n, p.h, phi, p.psi, p.rho_solid, [W.MU_SOLID] * len(p.psi), _fluids(p))
+    s = S.StokesSolver(3, p.n, p.h, [to_dev(a) for a in rho], to_dev(mu), p.dt)
+    umax = []
+    for src in (flow, rho):
+        fz = src[2] * g
+        fz[0] = 0.0
+        fz[-1] = 0.0
+        rhs_u = [to_dev(np.zeros_like(rho[0])), to_dev(np.zeros_like(rho[1])), to_dev(fz)]
+        xu = [torch.zeros_like(f) for f in rhs_u]
+        xp = torch.zeros_like(to_dev(p.rhs_p))
+        st, stats = s.solve(rhs_u, to_dev(p.rhs_p), 1e-13, xu, xp)
+        torch.cuda.synchronize()
+        assert st == 0, stats.as_dict()
+        umax.append(max(float(a.abs().max()) for a in xu) / (abs(g) * p.dt))
+        if src is flow:
+            ph = np.zeros(W.cell_shape(p.n))
+            for k in range(1, p.n[2]):
+                ph[k] = ph[k - 1] + p.h[2] * flow[2][k] * g
+            got = to_host(xp)
+            assert rel(got - got.mean(), ph - ph.mean()) <= 1e-11
+    s.close()
+    assert umax[0] <= 1e-9
+    assert umax[1] > 1e4 * max(umax[0], 1e-14)
