@@ -17,6 +17,9 @@ Contents
   coefficients.py  the coefficient step: smoothed Heaviside, two-step property
                    law, face densities from level sets averaged onto faces
   unet.py          the learned stage's network (forward pass)
+  rigid.py         rigid-body constraint projection after the solve: four-point
+                   kernel interpolation and spreading with wall mirrors,
+                   prescribed or free-body (momentum-redistributed) motion
 
 Parity of the GPU solve is measured on the solution of the linear system,
 never on iterates.  The multigrid inside O4 has no parity of its own
