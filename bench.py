@@ -178,6 +178,7 @@ def main():
     del solver
     out["hbm_stream_copy"] = stream_copy(S)
     out["coefficient_step"] = coefficient_step(S, prob)
+    out["rigid_projection"] = rigid_step(S, prob, xu)
     if not args.no_forms and args.precision == 0:
         out["forms"] = {"fp32_multigrid": fp32_form(S, prob, rho, mu, rhs_u, rhs_p, xu, xp, overrides,
                                                     ms, args.steps)}
@@ -375,6 +376,40 @@ def coefficient_step(S, prob, launches=20):
     return {"kernel": "k_coefficients<%d>" % len(psi), "solids": len(psi), "avg_launch_us": us,
             "bytes_per_launch": nbytes, "GBps": gbps, "frac_of_8TBps": gbps / 8000.0,
             "max_rel_diff_vs_generator": err}
+
+
+def rigid_step(S, prob, u, reps=10):
+    """The step after the solve on the same instance: the free-body rigid
+    projection of each solid (markers at the solid's cell centres) applied to
+    the solved velocity, timed on the host around the call (it synchronises
+    once to read the momentum sums)."""
+    import time
+    import torch
+    import workloads as W
+    Xc, Yc, Zc = W.cell_coords(prob.n, prob.h)
+    grid = S._binding.make_grid(prob.dim, prob.n, prob.h)
+    dV = float(np.prod(prob.h))
+    bodies = []
+    for q, psi in enumerate(prob.psi):
+        m = psi < 0
+        X = torch.from_numpy(np.ascontiguousarray(np.stack([Xc[m], Yc[m], Zc[m]], 1))).cuda()
+        ws = torch.empty(S.stokes_rigid_workspace_size(3, X.shape[0]), dtype=torch.uint8, device="cuda")
+        xc = X.mean(0).tolist()
+        uu = [a.clone() for a in u]
+        S.stokes_rigid_projection(grid, uu, X, dV, 1, S.make_body(xc), ws)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            uu = [a.clone() for a in u]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            b = S.stokes_rigid_projection(grid, uu, X, dV, 1, S.make_body(xc), ws)
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - t0) * 1e3)
+        bodies.append({"markers": int(X.shape[0]), "ms": float(np.median(ts)), "u_r": list(b.u_r),
+                       "w_r": list(b.w_r)})
+        log("rigid projection of solid %d: %d markers, %.3f ms" % (q, X.shape[0], bodies[-1]["ms"]))
+    return {"bodies": bodies, "note": "free body, markers at the solid's cell centres, on the solved velocity"}
 
 
 def _cpu_model():

@@ -250,6 +250,51 @@ stokes_status stokes_coefficients(const stokes_grid *grid, const stokes_fluids *
                                   double *const rho_flow_face[3], void *stream);
 
 /* ---------------------------------------------------------------------------
+ * Rigid-body constraint projection after the solve (Sec. 4.2.5, eqs.
+ * eq_velocity_correction, eq_prescribed_velocity, eq_linear_conservation and
+ * eq_angular_conservation; interpolation and spreading of Sec. 3.3):
+ *
+ *     u <- u + S (U_b - J u),   U_b = U_r + W_r x (X - x_com)  at each marker X,
+ *
+ * J interpolates the face velocities onto the body's Lagrangian markers with
+ * the four-point regularised delta function of Peskin (2002), delta_h(x) =
+ * prod_d phi(x_d / h_d) / h_d, times the cell volume; S spreads marker values
+ * back with the same kernel times the marker volume dV.  Near a no-slip wall
+ * stencil points beyond the wall take the odd mirror image of the interior and
+ * wall-normal points on the wall hold zero, with S the exact adjoint of J.
+ * free_body = 0: (U_r, W_r) are the caller's (prescribed motion).  free_body = 1:
+ * they are computed from the momentum of J u over the markers,
+ *     M U_r = sum (J u) dV,  I W_r = sum R x (J u) dV,  R = X - x_com,
+ *     M = n dV,  I = sum (|R|^2 Id - R (x) R) dV,
+ * and returned in *body.  In 2D, W_r is the rotation rate about z (w_r[0]) and
+ * I = sum |R|^2 dV.
+ * --------------------------------------------------------------------------- */
+typedef struct {
+    double x_com[3];   /* centre of mass (rotation centre) */
+    double u_r[3];     /* linear velocity: input (prescribed) or output (free body) */
+    double w_r[3];     /* angular velocity: input or output; 2D uses w_r[0] only */
+} stokes_body;
+
+/* Workspace bytes for n_markers markers in dim dimensions; 0 if invalid.  Host-only. */
+size_t stokes_rigid_workspace_size(int dim, long long n_markers);
+
+/* u[3]       device face velocities in the solver's layouts (u[2] ignored in 2D),
+ *            corrected in place; plain device memory (hipMalloc), as the
+ *            correction is added with device atomics
+ * X          device marker positions, n_markers x dim, each inside [0, n h]
+ * dV         marker volume (> 0)
+ * workspace  device buffer of ws_bytes >= stokes_rigid_workspace_size(dim, n_markers)
+ * Blocks until the momentum sums are on the host (it synchronises the stream
+ * once); the correction itself is queued after them.  EINVAL for NULL pointers,
+ * bad dV or body values, a marker outside the domain (then u is untouched), a
+ * free body without markers or whose markers are collinear (singular inertia);
+ * ESHAPE for fewer than 2 cells along an axis; ENOMEM for a small workspace;
+ * EHIP if a HIP call fails.  Several bodies: one call per body. */
+stokes_status stokes_rigid_projection(const stokes_grid *grid, double *const u[3], long long n_markers,
+                                      const double *X, double dV, int free_body, stokes_body *body,
+                                      void *workspace, size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------
  * Learned form: a 4-level 3D U-Net (channels 16/32/48/64, 3x3x3 convolutions,
  * ReLU, 2x2x2 average pooling, nearest upsampling, additive skips) in BF16 with
  * FP32 accumulation on the matrix cores (v_mfma_f32_16x16x16_bf16), with its

@@ -29,6 +29,10 @@ from ._binding import (  # noqa: F401
     MAX_SOLIDS,
     make_fluids,
     stokes_coefficients,
+    StokesBody,
+    make_body,
+    stokes_rigid_workspace_size,
+    stokes_rigid_projection,
     stokes_workspace_size,
     stokes_unet_param_count,
     stokes_unet_forward_flops,

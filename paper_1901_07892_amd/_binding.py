@@ -36,6 +36,13 @@ class StokesFluids(C.Structure):
 MAX_SOLIDS = 8
 
 
+class StokesBody(C.Structure):
+    _fields_ = [("x_com", C.c_double * 3), ("u_r", C.c_double * 3), ("w_r", C.c_double * 3)]
+
+    def as_dict(self):
+        return {"x_com": list(self.x_com), "u_r": list(self.u_r), "w_r": list(self.w_r)}
+
+
 class StokesOptions(C.Structure):
     _fields_ = [("precision", C.c_int), ("visc_scale", C.c_double), ("cont_scale", C.c_double),
                 ("restart", C.c_int), ("max_iters", C.c_int), ("nu1", C.c_int), ("nu2", C.c_int),
@@ -98,6 +105,11 @@ def load_library():
                                       C.POINTER(C.c_void_p), C.POINTER(C.c_double), C.POINTER(C.c_double),
                                       C.c_void_p * 3, dp, C.POINTER(C.c_void_p * 3), dp]
     L.stokes_coefficients.restype = C.c_int
+    L.stokes_rigid_workspace_size.argtypes = [C.c_int, C.c_longlong]
+    L.stokes_rigid_workspace_size.restype = C.c_size_t
+    L.stokes_rigid_projection.argtypes = [C.POINTER(StokesGrid), C.c_void_p * 3, C.c_longlong, dp, C.c_double,
+                                          C.c_int, C.POINTER(StokesBody), dp, C.c_size_t, dp]
+    L.stokes_rigid_projection.restype = C.c_int
     L.stokes_unet_param_count.argtypes = []
     L.stokes_unet_param_count.restype = C.c_longlong
     L.stokes_unet_forward_flops.argtypes = [C.c_int]
@@ -275,6 +287,35 @@ def stokes_coefficients(grid, fluids, phi, psi, rho_solid, mu_solid, rho_face, m
                                _ptr3(list(rho_face) + [None] * 3), _ptr(mu_cell), flow, _stream(stream))
     if st < 0:
         raise StokesError(st, "stokes_coefficients failed")
+
+
+def make_body(x_com, u_r=(0.0, 0.0, 0.0), w_r=(0.0, 0.0, 0.0)) -> StokesBody:
+    b = StokesBody()
+    for d in range(3):
+        b.x_com[d] = float(x_com[d]) if d < len(x_com) else 0.0
+        b.u_r[d] = float(u_r[d]) if d < len(u_r) else 0.0
+        b.w_r[d] = float(w_r[d]) if d < len(w_r) else 0.0
+    return b
+
+
+def stokes_rigid_workspace_size(dim: int, n_markers: int) -> int:
+    return int(load_library().stokes_rigid_workspace_size(int(dim), int(n_markers)))
+
+
+def stokes_rigid_projection(grid, u, X, dV, free_body, body, workspace, stream=None) -> StokesBody:
+    """Correct the face velocities ``u`` (list of device tensors, in place) for the
+    rigid body whose markers are the rows of ``X`` (device tensor, n x dim);
+    returns ``body`` with the free-body velocities filled in."""
+    L = load_library()
+    n = int(X.shape[0]) if X is not None else 0
+    st = L.stokes_rigid_projection(C.byref(grid), _ptr3(list(u) + [None] * 3), n,
+                                   _ptr(X) if n else None, float(dV), int(bool(free_body)), C.byref(body),
+                                   workspace.data_ptr() if workspace is not None else None,
+                                   workspace.numel() * workspace.element_size() if workspace is not None else 0,
+                                   _stream(stream))
+    if st < 0:
+        raise StokesError(st, "stokes_rigid_projection failed")
+    return body
 
 
 # ---------------------------------------------------------------- convenience wrapper

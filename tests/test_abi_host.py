@@ -127,3 +127,32 @@ def test_coefficients_reject_bad_arguments_on_host(S):
     L = S.load_library()
     assert L.stokes_coefficients(ctypes.byref(g3), ctypes.byref(ok), 0x4000, -1, None, None, None,
                                  B._ptr3(fake), 0x5000, None, None) == -1
+
+
+def test_rigid_projection_rejects_bad_arguments_on_host(S):
+    """Argument checks of stokes_rigid_projection return before any HIP call."""
+    B = S._binding
+    g = B.make_grid(3, (8, 8, 8), (1 / 8,) * 3)
+    u = [0x1000, 0x2000, 0x3000]
+    L = S.load_library()
+
+    def call(grid=g, uu=u, n=10, X=0x4000, dV=1e-3, free=1, body=None, ws=0x5000, wsb=1 << 20):
+        b = body if body is not None else B.make_body((0.5, 0.5, 0.5))
+        return L.stokes_rigid_projection(ctypes.byref(grid), B._ptr3(uu), n, X, dV, free, ctypes.byref(b),
+                                         ws, wsb, None)
+
+    assert S.stokes_rigid_workspace_size(3, 10) == (10 * 3 + 13) * 8
+    assert S.stokes_rigid_workspace_size(5, 10) == 0 and S.stokes_rigid_workspace_size(2, -1) == 0
+    assert call(grid=B.make_grid(4, (8, 8, 8), (1, 1, 1))) == -1
+    assert call(grid=B.make_grid(3, (8, 1, 8), (1, 1, 1))) == -2
+    assert call(grid=B.make_grid(3, (8, 8, 8), (1, 0, 1))) == -1
+    assert call(uu=[0x1000, None, 0x3000]) == -1
+    assert call(n=-1) == -1
+    assert call(X=None) == -1
+    assert call(ws=None) == -1
+    assert call(wsb=8) == -3
+    assert call(dV=0.0) == -1 and call(dV=float("inf")) == -1
+    assert call(free=2) == -1
+    assert call(body=B.make_body((0.5, float("nan"), 0.5))) == -1
+    assert call(n=0, free=1) == -1                     # a free body needs markers
+    assert call(n=0, free=0) == 0                      # nothing to do, no device work
