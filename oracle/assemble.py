@@ -303,3 +303,38 @@ def from_problem(prob, theta: float = 1.0) -> System:
     """Assemble the system of a ``workloads.Problem`` (all walls)."""
     g = OGrid(prob.dim, tuple(prob.n), tuple(prob.h))
     return assemble(g, prob.rho_faces, prob.mu, prob.dt, theta)
+
+
+def explicit_rhs(g: OGrid, rho_faces: Sequence[np.ndarray], mu_cell: np.ndarray, dt: float,
+                 theta: float, u_n: Sequence[np.ndarray],
+                 rho_force: Optional[Sequence[np.ndarray]] = None,
+                 gravity: Sequence[float] = (0.0, 0.0, 0.0)) -> List[np.ndarray]:
+    """Momentum right-hand side of one time step built from the old velocity.
+
+    Moving the explicit terms of the paper's discrete momentum equations to the
+    right (Sec. 4.2.2, eq_nc_discrete_momentum; eq_c_discrete_momentum with the
+    old density as ``rho_faces``) gives, with the viscous term split as
+    theta (new) + (1 - theta) (old) (theta = 1/2: Crank-Nicolson),
+
+        f = (rho/dt) u^n + (1 - theta) L_mu u^n + rho_force g
+
+    on every interior face (0 on wall-normal faces), where L_mu is the same
+    strain-rate operator as in the system matrix (built here from ``mu_cell``,
+    the old viscosity) and rho_force is the density of the gravity force (the
+    flow-only density for the well-balanced form, Sec. 4.3).  The convective
+    term is the caller's.
+    """
+    asm = Assembler(g)
+    d = g.dim
+    L = asm.viscous(np.asarray(mu_cell, dtype=np.float64))
+    S = [asm.select(c) for c in range(d)]
+    mask = [S[c].T @ S[c] for c in range(d)]             # keep interior faces, zero wall-normal ones
+    un = [mask[c] @ np.asarray(u_n[c], dtype=np.float64).ravel() for c in range(d)]
+    out = []
+    for c in range(d):
+        f = np.asarray(rho_faces[c], dtype=np.float64).ravel() / dt * un[c]
+        f = f + (1.0 - theta) * sum(L[c][e] @ un[e] for e in range(d))
+        if rho_force is not None:
+            f = f + np.asarray(rho_force[c], dtype=np.float64).ravel() * gravity[c]
+        out.append((mask[c] @ f).reshape(g.comp_shape(c)))
+    return out

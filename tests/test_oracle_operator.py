@@ -197,3 +197,54 @@ def test_pressure_poisson_spectrum():
     assert abs(ev[0]) < 1e-12 * ev[-1]
     assert ev[1] > 1e-8 * ev[-1]
     np.testing.assert_allclose(np.abs(vec[:, 0]), 1.0 / 8.0, rtol=1e-10)
+
+
+def _rhs_grid(dim):
+    n = (10, 12, 9) if dim == 3 else (10, 12, 1)
+    return A.OGrid(dim, n, (0.1, 1 / 12, 0.11))
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_explicit_rhs_special_cases(dim):
+    """Zero old velocity leaves only the gravity term; theta = 1 leaves the mass
+    term and gravity; wall-normal entries are written as zero."""
+    g = _rhs_grid(dim)
+    rng = np.random.default_rng(40 + dim)
+    rho = [rng.uniform(1, 1000, g.comp_shape(c)) for c in range(dim)]
+    rf = [rng.uniform(1, 1000, g.comp_shape(c)) for c in range(dim)]
+    mu = rng.uniform(1e-5, 1e-3, g.cell_shape())
+    un = [rng.standard_normal(g.comp_shape(c)) for c in range(dim)]
+    gv = (0.3, -9.81, 1.7)
+    f0 = A.explicit_rhs(g, rho, mu, 1e-3, 0.5, [np.zeros_like(a) for a in un], rf, gv)
+    f1 = A.explicit_rhs(g, rho, mu, 1e-3, 1.0, un, rf, gv)
+    for c in range(dim):
+        inner = [slice(None)] * 3
+        inner[2 - c] = slice(1, -1)
+        inner = tuple(inner)
+        np.testing.assert_allclose(f0[c][inner], (rf[c] * gv[c])[inner], rtol=1e-15)
+        np.testing.assert_allclose(f1[c][inner], (rho[c] / 1e-3 * un[c] + rf[c] * gv[c])[inner], rtol=1e-14)
+        for end in (0, -1):
+            sl = [slice(None)] * 3
+            sl[2 - c] = end
+            assert np.all(f0[c][tuple(sl)] == 0) and np.all(f1[c][tuple(sl)] == 0)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_explicit_rhs_viscous_part_of_shear_profiles(dim):
+    """Constant mu, u = u(y) only (v = w = 0): the viscous part of the x-rows is
+    mu u'' exactly for rows whose neighbours are interior: 0 for a linear
+    profile, -2 mu for y(1 - y); a linear profile through zero at y = 0 is also
+    exact next to that wall (the ghost is its odd reflection)."""
+    g = _rhs_grid(dim)
+    mu0 = 2.5e-3
+    mu = np.full(g.cell_shape(), mu0)
+    rho = [np.zeros(g.comp_shape(c)) for c in range(dim)]
+    _, Yc, _ = W.face_coords(g.n, g.h, 0)
+    for prof, want in ((Yc, 0.0), (Yc * (1.0 - Yc), -2.0 * mu0)):
+        un = [prof] + [np.zeros(g.comp_shape(c)) for c in range(1, dim)]
+        f = A.explicit_rhs(g, rho, mu, 1.0, 0.0, un)
+        rows = slice(0 if want == 0.0 else 1, -1)        # y rows (the top wall row differs)
+        # x rows 2..nx-2: their x-neighbours are interior faces (the profile is cut to zero on
+        # the x-walls, where u is wall-normal)
+        zs = slice(1, -1) if dim == 3 else slice(None)   # in 3D the z-walls' ghosts see u too
+        np.testing.assert_allclose(f[0][zs, rows, 2:-2], want, rtol=0, atol=1e-12)
