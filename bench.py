@@ -179,6 +179,7 @@ def main():
     out["hbm_stream_copy"] = stream_copy(S)
     out["coefficient_step"] = coefficient_step(S, prob)
     out["rigid_projection"] = rigid_step(S, prob, xu)
+    out["explicit_rhs"] = explicit_rhs_step(S, prob, rho, mu, xu)
     if not args.no_forms and args.precision == 0:
         out["forms"] = {"fp32_multigrid": fp32_form(S, prob, rho, mu, rhs_u, rhs_p, xu, xp, overrides,
                                                     ms, args.steps)}
@@ -376,6 +377,34 @@ def coefficient_step(S, prob, launches=20):
     return {"kernel": "k_coefficients<%d>" % len(psi), "solids": len(psi), "avg_launch_us": us,
             "bytes_per_launch": nbytes, "GBps": gbps, "frac_of_8TBps": gbps / 8000.0,
             "max_rel_diff_vs_generator": err}
+
+
+def explicit_rhs_step(S, prob, rho, mu, u, launches=20):
+    """The right-hand side of the next step from the solved velocity
+    (stokes_explicit_rhs: mass term, Crank-Nicolson explicit viscous half,
+    well-balanced gravity from the flow-only density), timed with events on its
+    stream.  Algorithmic bytes: u^n (3), rho (3), rho_flow (3), mu read, f (3)
+    written, each once."""
+    import torch
+    grid = S._binding.make_grid(prob.dim, prob.n, prob.h)
+    rf = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in prob.rho_flow_faces[:prob.dim]]
+    f = [torch.empty_like(a) for a in u]
+    gv = (0.0, 0.0, -9.81)
+    run = lambda: S.stokes_explicit_rhs(grid, rho, mu, prob.dt, 0.5, u, f, rf, gv)
+    for _ in range(3):
+        run()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(launches):
+        run()
+    e1.record()
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) / launches * 1e3
+    nbytes = 8.0 * (4 * sum(a.numel() for a in u) + mu.numel())     # u^n, rho, rho_flow, f; mu
+    gbps = nbytes / (us * 1e-6) / 1e9
+    log("explicit rhs: %.1f us, %.0f GB/s" % (us, gbps))
+    return {"kernel": "k_explicit_rhs", "theta": 0.5, "avg_launch_us": us, "bytes_per_launch": nbytes,
+            "GBps": gbps, "frac_of_8TBps": gbps / 8000.0}
 
 
 def rigid_step(S, prob, u, reps=10):

@@ -250,6 +250,34 @@ stokes_status stokes_coefficients(const stokes_grid *grid, const stokes_fluids *
                                   double *const rho_flow_face[3], void *stream);
 
 /* ---------------------------------------------------------------------------
+ * Explicit momentum right-hand side of one time step (Sec. 4.2.2,
+ * eq_nc_discrete_momentum, and eq_c_discrete_momentum with the old density;
+ * Sec. 4.3 for the gravity force):
+ *
+ *     f = (rho/dt) u^n + (1 - theta) L_mu u^n + rho_force g   on interior faces,
+ *
+ * L_mu the strain-rate operator of the solve (same edge viscosities and wall
+ * rules), theta the implicit fraction of the following stokes_solve (1/2: the
+ * paper's Crank-Nicolson split, which the solver takes as visc_scale).  With
+ * rho = the level-set density this is the non-conservative scheme's
+ * right-hand side, with the old density the conservative one's; rho_force = the
+ * flow-only density gives the well-balanced gravity force.  The convective term
+ * is the caller's (add it to f).
+ *   rho_face[3], mu_cell, u_n[3]  device inputs in the solver's layouts
+ *                                 (wall-normal entries of u_n are read as 0)
+ *   rho_force[3], gravity[3]      NULL for no gravity term; gravity is a host array
+ *   f[3]                          device output (wall-normal entries written as 0)
+ * Asynchronous on stream; no workspace.  EINVAL for NULL pointers, dt <= 0,
+ * theta outside [0, 1] or a non-finite gravity; ESHAPE for fewer than 2 cells
+ * along an axis or 2^31 - 256 points (Nx+1)(Ny+1)(Nz+1) or more; EHIP if the
+ * launch fails.  f must not overlap the inputs.
+ * --------------------------------------------------------------------------- */
+stokes_status stokes_explicit_rhs(const stokes_grid *grid, const double *const rho_face[3],
+                                  const double *mu_cell, double dt, double theta,
+                                  const double *const u_n[3], const double *const rho_force[3],
+                                  const double gravity[3], double *const f[3], void *stream);
+
+/* ---------------------------------------------------------------------------
  * Rigid-body constraint projection after the solve (Sec. 4.2.5, eqs.
  * eq_velocity_correction, eq_prescribed_velocity, eq_linear_conservation and
  * eq_angular_conservation; interpolation and spreading of Sec. 3.3):

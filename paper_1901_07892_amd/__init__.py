@@ -30,6 +30,7 @@ from ._binding import (  # noqa: F401
     make_fluids,
     stokes_coefficients,
     StokesBody,
+    stokes_explicit_rhs,
     make_body,
     stokes_rigid_workspace_size,
     stokes_rigid_projection,

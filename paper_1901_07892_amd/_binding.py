@@ -105,6 +105,10 @@ def load_library():
                                       C.POINTER(C.c_void_p), C.POINTER(C.c_double), C.POINTER(C.c_double),
                                       C.c_void_p * 3, dp, C.POINTER(C.c_void_p * 3), dp]
     L.stokes_coefficients.restype = C.c_int
+    L.stokes_explicit_rhs.argtypes = [C.POINTER(StokesGrid), C.c_void_p * 3, dp, C.c_double, C.c_double,
+                                      C.c_void_p * 3, C.POINTER(C.c_void_p * 3), C.POINTER(C.c_double * 3),
+                                      C.c_void_p * 3, dp]
+    L.stokes_explicit_rhs.restype = C.c_int
     L.stokes_rigid_workspace_size.argtypes = [C.c_int, C.c_longlong]
     L.stokes_rigid_workspace_size.restype = C.c_size_t
     L.stokes_rigid_projection.argtypes = [C.POINTER(StokesGrid), C.c_void_p * 3, C.c_longlong, dp, C.c_double,
@@ -287,6 +291,19 @@ def stokes_coefficients(grid, fluids, phi, psi, rho_solid, mu_solid, rho_face, m
                                _ptr3(list(rho_face) + [None] * 3), _ptr(mu_cell), flow, _stream(stream))
     if st < 0:
         raise StokesError(st, "stokes_coefficients failed")
+
+
+def stokes_explicit_rhs(grid, rho_face, mu_cell, dt, theta, u_n, f, rho_force=None, gravity=None,
+                        stream=None) -> None:
+    """f = (rho/dt) u^n + (1 - theta) L_mu u^n (+ rho_force g) on the device."""
+    L = load_library()
+    pad = lambda ts: list(ts) + [None] * 3
+    rf = C.byref(_ptr3(pad(rho_force))) if rho_force is not None else None
+    gv = C.byref((C.c_double * 3)(*[float(x) for x in (list(gravity) + [0.0] * 3)[:3]])) if gravity is not None else None
+    st = L.stokes_explicit_rhs(C.byref(grid), _ptr3(pad(rho_face)), _ptr(mu_cell), float(dt), float(theta),
+                               _ptr3(pad(u_n)), rf, gv, _ptr3(pad(f)), _stream(stream))
+    if st < 0:
+        raise StokesError(st, "stokes_explicit_rhs failed")
 
 
 def make_body(x_com, u_r=(0.0, 0.0, 0.0), w_r=(0.0, 0.0, 0.0)) -> StokesBody:

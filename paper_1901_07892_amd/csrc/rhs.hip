@@ -1,0 +1,201 @@
+// Explicit momentum right-hand side of one time step.
+//
+// Moving the explicit terms of the discrete momentum equations to the right
+// (Sec. 4.2.2, eq_nc_discrete_momentum, and eq_c_discrete_momentum with the old
+// density), with the viscous term split as theta (new) + (1 - theta) (old),
+// gives on every interior face
+//     f = (rho/dt) u^n + (1 - theta) L_mu u^n + rho_force g,
+// L_mu u = div[mu (grad u + grad u^T)] the strain-rate operator of the solve
+// (shear viscosity on cell edges = harmonic mean of the four cells around the
+// edge, out-of-domain cells mirrored; no-slip walls: wall-normal velocity zero,
+// tangential ghost = minus the interior value).  theta = 1/2 is the paper's
+// Crank-Nicolson split; rho_force is the flow-only density for the
+// well-balanced gravity force (Sec. 4.3).  The convective term is the caller's.
+//
+// One thread per point (i, j, k) of the (Nx+1)(Ny+1)(Nz+1) index space, which
+// holds the x-face i, the y-face j and the z-face k of cell (i, j, k); all
+// arrays are the caller's C-order layouts, neighbours come from cache.
+#include "../../include/stokes.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+namespace {
+
+constexpr int kRhsBlock = 256;
+
+struct RhsArgs {
+    int dim, nx, ny, nz;
+    double ihx, ihy, ihz;
+    double idt, expl;        // 1/dt, 1 - theta
+    double g[3];
+    const double *u, *v, *w, *mu;
+    const double *rx, *ry, *rz;      // density of the mass term
+    const double *fx, *fy, *fz;      // density of the gravity force (may be null)
+};
+
+struct Fields {
+    const RhsArgs &a;
+    __device__ int cx(int i) const { return min(max(i, 0), a.nx - 1); }
+    __device__ int cy(int j) const { return min(max(j, 0), a.ny - 1); }
+    __device__ int cz(int k) const { return min(max(k, 0), a.nz - 1); }
+    __device__ double M(int i, int j, int k) const {        // cell viscosity, mirrored outside
+        return a.mu[cx(i) + a.nx * (cy(j) + a.ny * cz(k))];
+    }
+    // harmonic mean of four viscosities, 4 / (1/p + 1/q + 1/r + 1/s), with one
+    // division: 4 pq rs / ((p + q) rs + (r + s) pq); 0 if any of them is 0
+    __device__ static double hm4(double p, double q, double r, double s) {
+        const double pq = p * q, rs = r * s;
+        const double num = pq * rs;
+        return num == 0.0 ? 0.0 : 4.0 * num / ((p + q) * rs + (r + s) * pq);
+    }
+    __device__ double Mxy(int i, int j, int k) const {
+        return hm4(M(i - 1, j - 1, k), M(i, j - 1, k), M(i - 1, j, k), M(i, j, k));
+    }
+    __device__ double Mxz(int i, int j, int k) const {
+        return hm4(M(i - 1, j, k - 1), M(i, j, k - 1), M(i - 1, j, k), M(i, j, k));
+    }
+    __device__ double Myz(int i, int j, int k) const {
+        return hm4(M(i, j - 1, k - 1), M(i, j, k - 1), M(i, j - 1, k), M(i, j, k));
+    }
+    // velocity components with the wall rules: wall-normal entries read as 0,
+    // tangential ghosts beyond a wall are minus the mirrored interior value
+    __device__ double U(int i, int j, int k) const {
+        if (i <= 0 || i >= a.nx) return 0.0;
+        double s = 1.0;
+        if (j < 0) { j = -1 - j; s = -s; } else if (j >= a.ny) { j = 2 * a.ny - 1 - j; s = -s; }
+        if (a.dim == 3) { if (k < 0) { k = -1 - k; s = -s; } else if (k >= a.nz) { k = 2 * a.nz - 1 - k; s = -s; } }
+        return s * a.u[i + (a.nx + 1) * (j + a.ny * k)];
+    }
+    __device__ double V(int i, int j, int k) const {
+        if (j <= 0 || j >= a.ny) return 0.0;
+        double s = 1.0;
+        if (i < 0) { i = -1 - i; s = -s; } else if (i >= a.nx) { i = 2 * a.nx - 1 - i; s = -s; }
+        if (a.dim == 3) { if (k < 0) { k = -1 - k; s = -s; } else if (k >= a.nz) { k = 2 * a.nz - 1 - k; s = -s; } }
+        return s * a.v[i + a.nx * (j + (a.ny + 1) * k)];
+    }
+    __device__ double W(int i, int j, int k) const {
+        if (a.dim != 3 || k <= 0 || k >= a.nz) return 0.0;
+        double s = 1.0;
+        if (i < 0) { i = -1 - i; s = -s; } else if (i >= a.nx) { i = 2 * a.nx - 1 - i; s = -s; }
+        if (j < 0) { j = -1 - j; s = -s; } else if (j >= a.ny) { j = 2 * a.ny - 1 - j; s = -s; }
+        return s * a.w[i + a.nx * (j + a.ny * k)];
+    }
+};
+
+__global__ void __launch_bounds__(kRhsBlock) k_explicit_rhs(RhsArgs a, double *__restrict__ ox,
+                                                            double *__restrict__ oy, double *__restrict__ oz) {
+    const int px = a.nx + 1, py = a.ny + 1, pz = a.dim == 3 ? a.nz + 1 : 1;
+    // blocks are dealt to the 8 XCDs round-robin; give each XCD a contiguous range
+    // of rows so that the neighbouring rows and planes a block reads share its L2
+    const int G = gridDim.x, b = blockIdx.x, q8 = G >> 3, r8 = G & 7, x8 = b & 7, l8 = b >> 3;
+    const int bs = x8 < r8 ? x8 * (q8 + 1) + l8 : r8 * (q8 + 1) + (x8 - r8) * q8 + l8;
+    const int p = bs * kRhsBlock + threadIdx.x;
+    if (p >= px * py * pz) return;
+    const int i = p % px, j = (p / px) % py, k = p / (px * py);
+    const Fields F{a};
+    const double hx = a.ihx, hy = a.ihy, hz = a.ihz;
+    const bool three = a.dim == 3;
+    // x-face i of row (j, k)
+    if (j < a.ny && k < a.nz) {
+        double r = 0.0;
+        if (i > 0 && i < a.nx) {
+            const double u0 = F.U(i, j, k);
+            double L = 2.0 * hx * hx * (F.M(i, j, k) * (F.U(i + 1, j, k) - u0) - F.M(i - 1, j, k) * (u0 - F.U(i - 1, j, k)));
+            L += hy * (F.Mxy(i, j + 1, k) * ((F.U(i, j + 1, k) - u0) * hy + (F.V(i, j + 1, k) - F.V(i - 1, j + 1, k)) * hx) -
+                       F.Mxy(i, j, k) * ((u0 - F.U(i, j - 1, k)) * hy + (F.V(i, j, k) - F.V(i - 1, j, k)) * hx));
+            if (three)
+                L += hz * (F.Mxz(i, j, k + 1) * ((F.U(i, j, k + 1) - u0) * hz + (F.W(i, j, k + 1) - F.W(i - 1, j, k + 1)) * hx) -
+                           F.Mxz(i, j, k) * ((u0 - F.U(i, j, k - 1)) * hz + (F.W(i, j, k) - F.W(i - 1, j, k)) * hx));
+            const int o = i + px * (j + a.ny * k);
+            r = a.rx[o] * a.idt * u0 + a.expl * L;
+            if (a.fx) r += a.fx[o] * a.g[0];
+        }
+        ox[i + px * (j + a.ny * k)] = r;
+    }
+    // y-face j of column (i, k)
+    if (i < a.nx && k < a.nz) {
+        double r = 0.0;
+        if (j > 0 && j < a.ny) {
+            const double v0 = F.V(i, j, k);
+            double L = 2.0 * hy * hy * (F.M(i, j, k) * (F.V(i, j + 1, k) - v0) - F.M(i, j - 1, k) * (v0 - F.V(i, j - 1, k)));
+            L += hx * (F.Mxy(i + 1, j, k) * ((F.V(i + 1, j, k) - v0) * hx + (F.U(i + 1, j, k) - F.U(i + 1, j - 1, k)) * hy) -
+                       F.Mxy(i, j, k) * ((v0 - F.V(i - 1, j, k)) * hx + (F.U(i, j, k) - F.U(i, j - 1, k)) * hy));
+            if (three)
+                L += hz * (F.Myz(i, j, k + 1) * ((F.V(i, j, k + 1) - v0) * hz + (F.W(i, j, k + 1) - F.W(i, j - 1, k + 1)) * hy) -
+                           F.Myz(i, j, k) * ((v0 - F.V(i, j, k - 1)) * hz + (F.W(i, j, k) - F.W(i, j - 1, k)) * hy));
+            const int o = i + a.nx * (j + py * k);
+            r = a.ry[o] * a.idt * v0 + a.expl * L;
+            if (a.fy) r += a.fy[o] * a.g[1];
+        }
+        oy[i + a.nx * (j + py * k)] = r;
+    }
+    // z-face k of column (i, j)
+    if (three && i < a.nx && j < a.ny) {
+        double r = 0.0;
+        if (k > 0 && k < a.nz) {
+            const double w0 = F.W(i, j, k);
+            double L = 2.0 * hz * hz * (F.M(i, j, k) * (F.W(i, j, k + 1) - w0) - F.M(i, j, k - 1) * (w0 - F.W(i, j, k - 1)));
+            L += hx * (F.Mxz(i + 1, j, k) * ((F.W(i + 1, j, k) - w0) * hx + (F.U(i + 1, j, k) - F.U(i + 1, j, k - 1)) * hz) -
+                       F.Mxz(i, j, k) * ((w0 - F.W(i - 1, j, k)) * hx + (F.U(i, j, k) - F.U(i, j, k - 1)) * hz));
+            L += hy * (F.Myz(i, j + 1, k) * ((F.W(i, j + 1, k) - w0) * hy + (F.V(i, j + 1, k) - F.V(i, j + 1, k - 1)) * hz) -
+                       F.Myz(i, j, k) * ((w0 - F.W(i, j - 1, k)) * hy + (F.V(i, j, k) - F.V(i, j, k - 1)) * hz));
+            const int o = i + a.nx * (j + a.ny * k);
+            r = a.rz[o] * a.idt * w0 + a.expl * L;
+            if (a.fz) r += a.fz[o] * a.g[2];
+        }
+        oz[i + a.nx * (j + a.ny * k)] = r;
+    }
+}
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+}  // namespace
+
+extern "C" stokes_status stokes_explicit_rhs(const stokes_grid *grid, const double *const rho_face[3],
+        const double *mu_cell, double dt, double theta, const double *const u_n[3],
+        const double *const rho_force[3], const double gravity[3], double *const f[3], void *stream) {
+    if (!grid || !rho_face || !mu_cell || !u_n || !f) return STOKES_EINVAL;
+    const int dim = grid->dim;
+    if (dim != 2 && dim != 3) return STOKES_EINVAL;
+    for (int d = 0; d < dim; ++d) {
+        if (grid->n[d] < 2) return STOKES_ESHAPE;
+        if (!finite_pos(grid->h[d])) return STOKES_EINVAL;
+        if (!rho_face[d] || !u_n[d] || !f[d] || (rho_force && !rho_force[d])) return STOKES_EINVAL;
+    }
+    if (!finite_pos(dt) || !std::isfinite(theta) || theta < 0.0 || theta > 1.0) return STOKES_EINVAL;
+    if (rho_force && (!gravity || !std::isfinite(gravity[0]) || !std::isfinite(gravity[1]) ||
+                      (dim == 3 && !std::isfinite(gravity[2]))))
+        return STOKES_EINVAL;
+    const long long nz = dim == 3 ? grid->n[2] : 1;
+    const long long pts = (long long)(grid->n[0] + 1) * (grid->n[1] + 1) * (dim == 3 ? nz + 1 : 1);
+    if (pts >= (1LL << 31) - kRhsBlock) return STOKES_ESHAPE;   // 32-bit point and array indices
+    RhsArgs a{};
+    a.dim = dim;
+    a.nx = grid->n[0];
+    a.ny = grid->n[1];
+    a.nz = (int)nz;
+    a.ihx = 1.0 / grid->h[0];
+    a.ihy = 1.0 / grid->h[1];
+    a.ihz = dim == 3 ? 1.0 / grid->h[2] : 0.0;
+    a.idt = 1.0 / dt;
+    a.expl = 1.0 - theta;
+    a.u = u_n[0];
+    a.v = u_n[1];
+    a.w = dim == 3 ? u_n[2] : nullptr;
+    a.mu = mu_cell;
+    a.rx = rho_face[0];
+    a.ry = rho_face[1];
+    a.rz = dim == 3 ? rho_face[2] : nullptr;
+    if (rho_force) {
+        a.fx = rho_force[0];
+        a.fy = rho_force[1];
+        a.fz = dim == 3 ? rho_force[2] : nullptr;
+        for (int d = 0; d < 3; ++d) a.g[d] = d < dim ? gravity[d] : 0.0;
+    }
+    const unsigned blocks = (unsigned)((pts + kRhsBlock - 1) / kRhsBlock);
+    k_explicit_rhs<<<blocks, kRhsBlock, 0, reinterpret_cast<hipStream_t>(stream)>>>(a, f[0], f[1],
+                                                                                   dim == 3 ? f[2] : nullptr);
+    return hipGetLastError() == hipSuccess ? STOKES_OK : STOKES_EHIP;
+}

@@ -156,3 +156,25 @@ def test_rigid_projection_rejects_bad_arguments_on_host(S):
     assert call(body=B.make_body((0.5, float("nan"), 0.5))) == -1
     assert call(n=0, free=1) == -1                     # a free body needs markers
     assert call(n=0, free=0) == 0                      # nothing to do, no device work
+
+
+def test_explicit_rhs_rejects_bad_arguments_on_host(S):
+    B = S._binding
+    g = B.make_grid(3, (8, 8, 8), (1 / 8,) * 3)
+    p3 = [0x1000, 0x2000, 0x3000]
+
+    def call(grid=g, rho=p3, mu=0x4000, dt=1e-3, theta=0.5, un=p3, f=p3, rf=None, gv=None):
+        with pytest.raises(S.StokesError) as e:
+            S.stokes_explicit_rhs(grid, rho, mu, dt, theta, un, f, rf, gv, stream=0)
+        return e.value.status
+
+    assert call(grid=B.make_grid(4, (8, 8, 8), (1, 1, 1))) == -1
+    assert call(grid=B.make_grid(3, (8, 8, 1), (1, 1, 1))) == -2
+    assert call(mu=None) == -1
+    assert call(rho=[0x1000, None, 0x3000]) == -1
+    assert call(un=[0x1000, 0x2000, None]) == -1
+    assert call(f=[None, 0x2000, 0x3000]) == -1
+    assert call(dt=0.0) == -1 and call(dt=float("nan")) == -1
+    assert call(theta=-0.1) == -1 and call(theta=1.5) == -1
+    assert call(rf=p3, gv=(0.0, float("inf"), 0.0)) == -1
+    assert call(rf=[0x1000, None, 0x3000], gv=(0, 0, -9.81)) == -1
