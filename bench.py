@@ -493,6 +493,12 @@ def traffic_from_counters(fetch_dir, write_dir, n=256, precision=0, path=None):
         ("k_precond_update_jac", r"k_precond_update_jac<", cells * 8 * 16.0),
         ("k_precond_div_jac", r"k_precond_div_jac<", cells * 8 * 9.0),
         ("k_scale", r"k_scale\b", None),
+        # the steps around the solve (the headline instance has two solids)
+        ("k_coefficients<2> (coefficient step)", r"k_coefficients<2>",
+         8.0 * (4 * cells + 3 * (n + 1) * float(n) ** 2)),
+        ("k_explicit_rhs (explicit right-hand side)", r"k_explicit_rhs", 8.0 * (12 * (n + 1) * float(n) ** 2 + cells)),
+        ("k_rigid_interp (rigid projection gather)", r"k_rigid_interp<3>", None),
+        ("k_rigid_spread (rigid projection scatter)", r"k_rigid_spread<3>", None),
     ]
     out = {}
     lines = []
