@@ -149,6 +149,127 @@ __global__ void __launch_bounds__(kRhsBlock) k_explicit_rhs(RhsArgs a, double *_
     }
 }
 
+// 3D form: a block owns a TX x TY tile of cells and a chunk of z planes and
+// marches in z with a three-plane LDS ring of u, v, w and mu on the tile plus a
+// one-cell halo, filled with the wall rules already applied (wall-normal
+// entries 0, tangential ghosts odd, viscosity mirrored), so that every plane is
+// read from memory once per block and the stencil reads LDS without branches.
+// Each thread writes the x-, y- and z-face rows of its cell (i, j, k); the
+// wall-normal faces beyond the last cell of a row, column or stack (i = Nx,
+// j = Ny, k = Nz) hold zero and are written by that last cell's thread.
+constexpr int kZX = 64, kZY = 8, kZC = 16;
+constexpr int kHX = kZX + 2, kHY = kZY + 2, kHP = kHX * kHY;
+
+__global__ void __launch_bounds__(kZX *kZY) k_explicit_rhs3_z(RhsArgs a, double *__restrict__ ox,
+                                                              double *__restrict__ oy, double *__restrict__ oz) {
+    __shared__ double sU[3][kHP], sV[3][kHP], sW[3][kHP], sM[3][kHP];
+    const Fields F{a};
+    const int tid = threadIdx.x;
+    const int i0 = blockIdx.x * kZX, j0 = blockIdx.y * kZY;
+    const int k0 = blockIdx.z * kZC, k1 = min(k0 + kZC, a.nz);
+    auto slot = [](int k) { return (k + 3) % 3; };                     // k >= -1
+    auto load = [&](int k) {                                           // plane k, -1 <= k <= nz
+        const int sl = slot(k);
+        for (int t = tid; t < kHP; t += kZX * kZY) {
+            const int gi = i0 - 1 + t % kHX, gj = j0 - 1 + t / kHX;
+            double u = 0.0, v = 0.0, w = 0.0, m = 0.0;
+            if (gi >= -1 && gi <= a.nx && gj >= -1 && gj <= a.ny) {
+                u = F.U(gi, gj, k);
+                v = F.V(gi, gj, k);
+                w = F.W(gi, gj, k);
+                m = F.M(gi, gj, k);
+            }
+            sU[sl][t] = u;
+            sV[sl][t] = v;
+            sW[sl][t] = w;
+            sM[sl][t] = m;
+        }
+    };
+    const int tx = tid % kZX, ty = tid / kZX;
+    const int i = i0 + tx, j = j0 + ty;
+    const bool own = i < a.nx && j < a.ny;
+    const int c = (ty + 1) * kHX + (tx + 1);
+    const double hx = a.ihx, hy = a.ihy, hz = a.ihz;
+    load(k0 - 1);
+    load(k0);
+    for (int k = k0; k < k1; ++k) {
+        load(k + 1);
+        __syncthreads();
+        if (own) {
+            const int sm = slot(k - 1), s0 = slot(k), sp = slot(k + 1);
+            const int ss[3] = {sm, s0, sp};
+            auto Us = [&](int di, int dj, int dk) { return sU[ss[dk + 1]][c + di + dj * kHX]; };
+            auto Vs = [&](int di, int dj, int dk) { return sV[ss[dk + 1]][c + di + dj * kHX]; };
+            auto Ws = [&](int di, int dj, int dk) { return sW[ss[dk + 1]][c + di + dj * kHX]; };
+            auto Ms = [&](int di, int dj, int dk) { return sM[ss[dk + 1]][c + di + dj * kHX]; };
+            auto Mxy = [&](int di, int dj) {
+                return Fields::hm4(Ms(di - 1, dj - 1, 0), Ms(di, dj - 1, 0), Ms(di - 1, dj, 0), Ms(di, dj, 0));
+            };
+            auto Mxz = [&](int di, int dk) {
+                return Fields::hm4(Ms(di - 1, 0, dk - 1), Ms(di, 0, dk - 1), Ms(di - 1, 0, dk), Ms(di, 0, dk));
+            };
+            auto Myz = [&](int dj, int dk) {
+                return Fields::hm4(Ms(0, dj - 1, dk - 1), Ms(0, dj, dk - 1), Ms(0, dj - 1, dk), Ms(0, dj, dk));
+            };
+            // x-face i
+            {
+                double r = 0.0;
+                if (i > 0) {
+                    const double u0 = Us(0, 0, 0);
+                    double L = 2.0 * hx * hx * (Ms(0, 0, 0) * (Us(1, 0, 0) - u0) - Ms(-1, 0, 0) * (u0 - Us(-1, 0, 0)));
+                    L += hy * (Mxy(0, 1) * ((Us(0, 1, 0) - u0) * hy + (Vs(0, 1, 0) - Vs(-1, 1, 0)) * hx) -
+                               Mxy(0, 0) * ((u0 - Us(0, -1, 0)) * hy + (Vs(0, 0, 0) - Vs(-1, 0, 0)) * hx));
+                    L += hz * (Mxz(0, 1) * ((Us(0, 0, 1) - u0) * hz + (Ws(0, 0, 1) - Ws(-1, 0, 1)) * hx) -
+                               Mxz(0, 0) * ((u0 - Us(0, 0, -1)) * hz + (Ws(0, 0, 0) - Ws(-1, 0, 0)) * hx));
+                    const int o = i + (a.nx + 1) * (j + a.ny * k);
+                    r = a.rx[o] * a.idt * u0 + a.expl * L;
+                    if (a.fx) r += a.fx[o] * a.g[0];
+                }
+                const int o = i + (a.nx + 1) * (j + a.ny * k);
+                ox[o] = r;
+                if (i == a.nx - 1) ox[o + 1] = 0.0;            // wall face i = nx
+            }
+            // y-face j
+            {
+                double r = 0.0;
+                if (j > 0) {
+                    const double v0 = Vs(0, 0, 0);
+                    double L = 2.0 * hy * hy * (Ms(0, 0, 0) * (Vs(0, 1, 0) - v0) - Ms(0, -1, 0) * (v0 - Vs(0, -1, 0)));
+                    L += hx * (Mxy(1, 0) * ((Vs(1, 0, 0) - v0) * hx + (Us(1, 0, 0) - Us(1, -1, 0)) * hy) -
+                               Mxy(0, 0) * ((v0 - Vs(-1, 0, 0)) * hx + (Us(0, 0, 0) - Us(0, -1, 0)) * hy));
+                    L += hz * (Myz(0, 1) * ((Vs(0, 0, 1) - v0) * hz + (Ws(0, 0, 1) - Ws(0, -1, 1)) * hy) -
+                               Myz(0, 0) * ((v0 - Vs(0, 0, -1)) * hz + (Ws(0, 0, 0) - Ws(0, -1, 0)) * hy));
+                    const int o = i + a.nx * (j + (a.ny + 1) * k);
+                    r = a.ry[o] * a.idt * v0 + a.expl * L;
+                    if (a.fy) r += a.fy[o] * a.g[1];
+                }
+                const int o = i + a.nx * (j + (a.ny + 1) * k);
+                oy[o] = r;
+                if (j == a.ny - 1) oy[o + a.nx] = 0.0;         // wall face j = ny
+            }
+            // z-face k
+            {
+                double r = 0.0;
+                if (k > 0) {
+                    const double w0 = Ws(0, 0, 0);
+                    double L = 2.0 * hz * hz * (Ms(0, 0, 0) * (Ws(0, 0, 1) - w0) - Ms(0, 0, -1) * (w0 - Ws(0, 0, -1)));
+                    L += hx * (Mxz(1, 0) * ((Ws(1, 0, 0) - w0) * hx + (Us(1, 0, 0) - Us(1, 0, -1)) * hz) -
+                               Mxz(0, 0) * ((w0 - Ws(-1, 0, 0)) * hx + (Us(0, 0, 0) - Us(0, 0, -1)) * hz));
+                    L += hy * (Myz(1, 0) * ((Ws(0, 1, 0) - w0) * hy + (Vs(0, 1, 0) - Vs(0, 1, -1)) * hz) -
+                               Myz(0, 0) * ((w0 - Ws(0, -1, 0)) * hy + (Vs(0, 0, 0) - Vs(0, 0, -1)) * hz));
+                    const int o = i + a.nx * (j + a.ny * k);
+                    r = a.rz[o] * a.idt * w0 + a.expl * L;
+                    if (a.fz) r += a.fz[o] * a.g[2];
+                }
+                const int o = i + a.nx * (j + a.ny * k);
+                oz[o] = r;
+                if (k == a.nz - 1) oz[o + a.nx * a.ny] = 0.0;  // wall face k = nz
+            }
+        }
+        __syncthreads();
+    }
+}
+
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
 }  // namespace
@@ -194,8 +315,13 @@ extern "C" stokes_status stokes_explicit_rhs(const stokes_grid *grid, const doub
         a.fz = dim == 3 ? rho_force[2] : nullptr;
         for (int d = 0; d < 3; ++d) a.g[d] = d < dim ? gravity[d] : 0.0;
     }
-    const unsigned blocks = (unsigned)((pts + kRhsBlock - 1) / kRhsBlock);
-    k_explicit_rhs<<<blocks, kRhsBlock, 0, reinterpret_cast<hipStream_t>(stream)>>>(a, f[0], f[1],
-                                                                                   dim == 3 ? f[2] : nullptr);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (dim == 3) {
+        const dim3 g((a.nx + kZX - 1) / kZX, (a.ny + kZY - 1) / kZY, (a.nz + kZC - 1) / kZC);
+        k_explicit_rhs3_z<<<g, kZX * kZY, 0, s>>>(a, f[0], f[1], f[2]);
+    } else {
+        const unsigned blocks = (unsigned)((pts + kRhsBlock - 1) / kRhsBlock);
+        k_explicit_rhs<<<blocks, kRhsBlock, 0, s>>>(a, f[0], f[1], nullptr);
+    }
     return hipGetLastError() == hipSuccess ? STOKES_OK : STOKES_EHIP;
 }
