@@ -403,7 +403,7 @@ def explicit_rhs_step(S, prob, rho, mu, u, launches=20):
     nbytes = 8.0 * (4 * sum(a.numel() for a in u) + mu.numel())     # u^n, rho, rho_flow, f; mu
     gbps = nbytes / (us * 1e-6) / 1e9
     log("explicit rhs: %.1f us, %.0f GB/s" % (us, gbps))
-    return {"kernel": "k_explicit_rhs", "theta": 0.5, "avg_launch_us": us, "bytes_per_launch": nbytes,
+    return {"kernel": "k_explicit_rhs3_z", "theta": 0.5, "avg_launch_us": us, "bytes_per_launch": nbytes,
             "GBps": gbps, "frac_of_8TBps": gbps / 8000.0}
 
 
