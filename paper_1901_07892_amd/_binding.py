@@ -50,7 +50,7 @@ class StokesOptions(C.Structure):
                 ("vel_levels", C.c_int), ("vel_sweeps", C.c_int), ("p_prolong", C.c_int),
                 ("vel_smoother", C.c_int), ("orth", C.c_int), ("matvec_z", C.c_int),
                 ("p_gamma", C.c_int), ("p_small", C.c_int),
-                ("p_wdepth", C.c_int), ("p_cycles_next", C.c_int)]
+                ("p_wdepth", C.c_int), ("p_cycles_next", C.c_int), ("p_nu_second", C.c_int)]
 
 
 class StokesStats(C.Structure):

@@ -127,6 +127,7 @@ struct stokes_ctx {
     int vcycles = 0;
     int cyc_first = 3, cyc_next = 3;   // pressure cycles: first / later applications of a restart cycle
     int cyc_now = 3;                    // cycles of the current application
+    int nu_sec1 = 2, nu_sec2 = 2;       // pre-/post-smoothing sweeps on the second pressure level
     double visc_ratio = -1.0;   // max viscous/mass diagonal ratio (automatic velocity levels)
     bool diag_vel = false;      // velocity subsolve is one diagonal step (see stokes_options.vel_smoother)
     // learned stage: network, the level it runs on, feature/prediction buffers
@@ -356,6 +357,10 @@ int gamma_at(const stokes_ctx &c, const MG<R> &mg, int l) {
     return (c.opt.p_wdepth == 0 || l < c.opt.p_wdepth) ? c.opt.p_gamma : 1;
 }
 
+// Pre- and post-smoothing sweeps of pressure level l.
+inline int p_nu_pre(const stokes_ctx &c, int l) { return l == 1 ? c.nu_sec1 : c.opt.nu1; }
+inline int p_nu_post(const stokes_ctx &c, int l) { return l == 1 ? c.nu_sec2 : c.opt.nu2; }
+
 template <int DIM, class R>
 void p_smooth(stokes_ctx &c, Level<R> &L, R *e, const R *r, int sweeps, bool zero_guess) {
     for (int s = 0; s < sweeps; ++s)
@@ -437,7 +442,7 @@ R *p_vcycle(stokes_ctx &c, MG<R> &mg, int l, R *e, R *r, bool zero_guess) {
         }
         return cur;
     }
-    const int nu1 = c.opt.nu1, nu2 = c.opt.nu2;
+    const int nu1 = p_nu_pre(c, l), nu2 = p_nu_post(c, l);
     if (zero_guess && nu1 == 0) fill<R>(c, cur - L.b.guard, L.b.stride, R(0));
     if (DIM == 3) {
         for (int s = 0; s < nu1; ++s) sweep(zero_guess && s == 0, nullptr, nullptr);
@@ -885,13 +890,13 @@ void gen_small_ops(const stokes_ctx &c, const MG<R> &mg, int l0, int l, int zg, 
     }
     // with a zero guess and no pre-smoothing the iterate must read as zero (at
     // the first level the launch leaves it zero by not loading it)
-    if (zg == 1 && c.opt.nu1 == 0) ops.push_back({SOP_ZERO, rel, 0, 0});
-    sweeps(c.opt.nu1, zg);
+    if (zg == 1 && p_nu_pre(c, l) == 0) ops.push_back({SOP_ZERO, rel, 0, 0});
+    sweeps(p_nu_pre(c, l), zg);
     ops.push_back({SOP_RESTRICT, rel, 0, 0});
     gen_small_ops<R>(c, mg, l0, l + 1, 1, ops);
     for (int g = 1; g < gamma_at(c, mg, l); ++g) gen_small_ops<R>(c, mg, l0, l + 1, 0, ops);
     ops.push_back({SOP_PROLONG, rel, 0, 0});
-    sweeps(c.opt.nu2, 0);
+    sweeps(p_nu_post(c, l), 0);
 }
 
 // Picks the finest level (below the finest) from which the whole 3D cycle fits
@@ -1070,6 +1075,7 @@ stokes_options defaults() {
     o.p_small = 1;
     o.p_wdepth = 2;
     o.p_cycles_next = 0;
+    o.p_nu_second = 0;
     return o;
 }
 
@@ -1098,6 +1104,7 @@ const char *check_grid_opts(const stokes_grid *g, const stokes_options &o) {
     if (o.matvec_z != 0 && o.matvec_z != 1) return "matvec_z must be 0 or 1";
     if (o.p_gamma != 1 && o.p_gamma != 2) return "p_gamma must be 1 (V-cycle) or 2 (W-cycle)";
     if (o.p_small != 0 && o.p_small != 1) return "p_small must be 0 or 1";
+    if (o.p_nu_second < 0) return "p_nu_second must be >= 0";
     if (o.p_wdepth < 0) return "p_wdepth must be >= 0";
     return nullptr;
 }
@@ -1117,6 +1124,12 @@ void init_ctx_shape(stokes_ctx &c, const stokes_grid *g, const stokes_options &o
     c.cyc_first = o.p_cycles > 0 ? o.p_cycles : (two_step ? 4 : 3);
     c.cyc_next = o.p_cycles_next > 0 ? o.p_cycles_next : (o.p_cycles > 0 ? o.p_cycles : (two_step ? 6 : 3));
     c.cyc_now = c.cyc_first;
+    // smoothing on the second pressure level: with W-cycles it is cycled twice per
+    // visit of the finest level, and in FP64 one sweep on each side is enough there
+    // (same iteration counts, fewer sweeps); FP32 multigrid keeps nu1/nu2
+    const bool sec_auto = o.precision == 0 && o.p_gamma == 2;
+    c.nu_sec1 = o.p_nu_second > 0 ? o.p_nu_second : (sec_auto ? std::min(o.nu1, 1) : o.nu1);
+    c.nu_sec2 = o.p_nu_second > 0 ? o.p_nu_second : (sec_auto ? std::min(o.nu2, 1) : o.nu2);
     c.fine = make_box(g->dim, g->n[0], g->n[1], g->dim == 3 ? g->n[2] : 1, g->h[0], g->h[1],
                       g->dim == 3 ? g->h[2] : g->h[0]);
     {

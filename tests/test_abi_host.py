@@ -75,7 +75,8 @@ def test_options_struct_layout_matches_library(S):
     fields read back with their documented defaults, and a bad value in the last
     field is rejected by the library's own validation."""
     o = S.stokes_default_options()
-    assert (o.orth, o.matvec_z, o.p_gamma, o.p_small, o.p_wdepth, o.p_cycles, o.p_cycles_next) == (1, 1, 2, 1, 2, 0, 0)
+    assert (o.orth, o.matvec_z, o.p_gamma, o.p_small, o.p_wdepth, o.p_cycles, o.p_cycles_next, o.p_nu_second) == \
+        (1, 1, 2, 1, 2, 0, 0, 0)
     g = S._binding.make_grid(3, (16, 16, 16), (1 / 16,) * 3)
     assert S.stokes_workspace_size(g, o) > 0
     o.p_wdepth = -1
@@ -86,6 +87,11 @@ def test_options_struct_layout_matches_library(S):
     o.p_small = 1
     o.p_cycles_next = -1
     assert S.stokes_workspace_size(g, o) == 0
+    o.p_cycles_next = 0
+    o.p_nu_second = -1
+    assert S.stokes_workspace_size(g, o) == 0
+    o.p_nu_second = 3
+    assert S.stokes_workspace_size(g, o) > 0
 
 
 def test_stream_copy_rejects_bad_arguments_on_host(S):
