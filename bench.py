@@ -370,8 +370,8 @@ def coefficient_step(S, prob, launches=20):
     torch.cuda.synchronize()
     us = e0.elapsed_time(e1) / launches * 1e3
     nbytes = 8.0 * ((1 + len(psi)) * mu.numel() + mu.numel() + sum(r.numel() for r in rho))
-    err = max([float((mu.cpu().numpy() - prob.mu).__abs__().max() / prob.mu.max())] +
-              [float((r.cpu().numpy() - pr).__abs__().max() / pr.max()) for r, pr in zip(rho, prob.rho_faces)])
+    err = max([float(np.abs(mu.cpu().numpy() - prob.mu).max() / prob.mu.max())] +
+              [float(np.abs(r.cpu().numpy() - pr).max() / pr.max()) for r, pr in zip(rho, prob.rho_faces)])
     gbps = nbytes / (us * 1e-6) / 1e9
     log("coefficient step: %.1f us, %.0f GB/s (%d solids), max rel diff vs generator %.1e" % (us, gbps, len(psi), err))
     return {"kernel": "k_coefficients<%d>" % len(psi), "solids": len(psi), "avg_launch_us": us,
