@@ -3,7 +3,7 @@ passes of the pass-by-pass cycle (p_small = 0) in the same order with the same
 arithmetic: after two preconditioned FGMRES iterations the iterates agree to
 rounding, and converged solves take the same number of iterations.  Cases cover
 cubes whose small hierarchy starts at 16^3 with the coarsest dense matrix in
-LDS, a wave-tank shape whose dense matrix (288^2) stays in global memory,
+LDS (at 32^3 that is the second level, with its own smoothing counts), a wave-tank shape whose dense matrix (288^2) stays in global memory,
 V-cycles, W-cycles at every level or on the finest two, pre- or post-smoothing
 only, linear prolongation, FP64 and FP32 multigrid."""
 import numpy as np
@@ -16,7 +16,10 @@ pytestmark = pytest.mark.gpu
 
 CASES = [("headline_recipe_64cubed", lambda: W.config5(n_cells=64)),
          ("dam_break_64cubed", lambda: W.config3(scale=2)),
-         ("wave_tank_256x24x24", lambda: W.config4(scale=4))]
+         ("wave_tank_256x24x24", lambda: W.config4(scale=4)),
+         # the small-level kernel starts at the second level here, so its pass list
+         # carries that level's own smoothing counts (p_nu_second)
+         ("headline_recipe_32cubed", lambda: W.config5(n_cells=32))]
 OPTS = [dict(), dict(p_wdepth=0), dict(p_gamma=1), dict(nu1=0, nu2=2, p_wdepth=0),
         dict(nu1=3, nu2=1, p_prolong=1)]
 
