@@ -12,9 +12,11 @@
 // Crank-Nicolson split; rho_force is the flow-only density for the
 // well-balanced gravity force (Sec. 4.3).  The convective term is the caller's.
 //
-// One thread per point (i, j, k) of the (Nx+1)(Ny+1)(Nz+1) index space, which
-// holds the x-face i, the y-face j and the z-face k of cell (i, j, k); all
-// arrays are the caller's C-order layouts, neighbours come from cache.
+// Two kernels: in 3D, a z-marching one with the old velocity and viscosity in a
+// three-plane LDS ring (k_explicit_rhs3_z, below); in 2D, one thread per point
+// (i, j) of the (Nx+1)(Ny+1) index space, which holds the x-face i and the
+// y-face j of cell (i, j), neighbours from cache (k_explicit_rhs2).  All arrays
+// are the caller's C-order layouts.
 #include "../../include/stokes.h"
 
 #include <hip/hip_runtime.h>
@@ -53,12 +55,6 @@ struct Fields {
     __device__ double Mxy(int i, int j, int k) const {
         return hm4(M(i - 1, j - 1, k), M(i, j - 1, k), M(i - 1, j, k), M(i, j, k));
     }
-    __device__ double Mxz(int i, int j, int k) const {
-        return hm4(M(i - 1, j, k - 1), M(i, j, k - 1), M(i - 1, j, k), M(i, j, k));
-    }
-    __device__ double Myz(int i, int j, int k) const {
-        return hm4(M(i, j - 1, k - 1), M(i, j, k - 1), M(i, j - 1, k), M(i, j, k));
-    }
     // velocity components with the wall rules: wall-normal entries read as 0,
     // tangential ghosts beyond a wall are minus the mirrored interior value
     __device__ double U(int i, int j, int k) const {
@@ -84,68 +80,41 @@ struct Fields {
     }
 };
 
-__global__ void __launch_bounds__(kRhsBlock) k_explicit_rhs(RhsArgs a, double *__restrict__ ox,
-                                                            double *__restrict__ oy, double *__restrict__ oz) {
-    const int px = a.nx + 1, py = a.ny + 1, pz = a.dim == 3 ? a.nz + 1 : 1;
-    // blocks are dealt to the 8 XCDs round-robin; give each XCD a contiguous range
-    // of rows so that the neighbouring rows and planes a block reads share its L2
-    const int G = gridDim.x, b = blockIdx.x, q8 = G >> 3, r8 = G & 7, x8 = b & 7, l8 = b >> 3;
-    const int bs = x8 < r8 ? x8 * (q8 + 1) + l8 : r8 * (q8 + 1) + (x8 - r8) * q8 + l8;
-    const int p = bs * kRhsBlock + threadIdx.x;
-    if (p >= px * py * pz) return;
-    const int i = p % px, j = (p / px) % py, k = p / (px * py);
+__global__ void __launch_bounds__(kRhsBlock) k_explicit_rhs2(RhsArgs a, double *__restrict__ ox,
+                                                             double *__restrict__ oy) {
+    const int px = a.nx + 1, py = a.ny + 1;
+    const int p = blockIdx.x * kRhsBlock + threadIdx.x;
+    if (p >= px * py) return;
+    const int i = p % px, j = p / px;
     const Fields F{a};
-    const double hx = a.ihx, hy = a.ihy, hz = a.ihz;
-    const bool three = a.dim == 3;
-    // x-face i of row (j, k)
-    if (j < a.ny && k < a.nz) {
+    const double hx = a.ihx, hy = a.ihy;
+    // x-face i of row j
+    if (j < a.ny) {
         double r = 0.0;
         if (i > 0 && i < a.nx) {
-            const double u0 = F.U(i, j, k);
-            double L = 2.0 * hx * hx * (F.M(i, j, k) * (F.U(i + 1, j, k) - u0) - F.M(i - 1, j, k) * (u0 - F.U(i - 1, j, k)));
-            L += hy * (F.Mxy(i, j + 1, k) * ((F.U(i, j + 1, k) - u0) * hy + (F.V(i, j + 1, k) - F.V(i - 1, j + 1, k)) * hx) -
-                       F.Mxy(i, j, k) * ((u0 - F.U(i, j - 1, k)) * hy + (F.V(i, j, k) - F.V(i - 1, j, k)) * hx));
-            if (three)
-                L += hz * (F.Mxz(i, j, k + 1) * ((F.U(i, j, k + 1) - u0) * hz + (F.W(i, j, k + 1) - F.W(i - 1, j, k + 1)) * hx) -
-                           F.Mxz(i, j, k) * ((u0 - F.U(i, j, k - 1)) * hz + (F.W(i, j, k) - F.W(i - 1, j, k)) * hx));
-            const int o = i + px * (j + a.ny * k);
+            const double u0 = F.U(i, j, 0);
+            double L = 2.0 * hx * hx * (F.M(i, j, 0) * (F.U(i + 1, j, 0) - u0) - F.M(i - 1, j, 0) * (u0 - F.U(i - 1, j, 0)));
+            L += hy * (F.Mxy(i, j + 1, 0) * ((F.U(i, j + 1, 0) - u0) * hy + (F.V(i, j + 1, 0) - F.V(i - 1, j + 1, 0)) * hx) -
+                       F.Mxy(i, j, 0) * ((u0 - F.U(i, j - 1, 0)) * hy + (F.V(i, j, 0) - F.V(i - 1, j, 0)) * hx));
+            const int o = i + px * j;
             r = a.rx[o] * a.idt * u0 + a.expl * L;
             if (a.fx) r += a.fx[o] * a.g[0];
         }
-        ox[i + px * (j + a.ny * k)] = r;
+        ox[i + px * j] = r;
     }
-    // y-face j of column (i, k)
-    if (i < a.nx && k < a.nz) {
+    // y-face j of column i
+    if (i < a.nx) {
         double r = 0.0;
         if (j > 0 && j < a.ny) {
-            const double v0 = F.V(i, j, k);
-            double L = 2.0 * hy * hy * (F.M(i, j, k) * (F.V(i, j + 1, k) - v0) - F.M(i, j - 1, k) * (v0 - F.V(i, j - 1, k)));
-            L += hx * (F.Mxy(i + 1, j, k) * ((F.V(i + 1, j, k) - v0) * hx + (F.U(i + 1, j, k) - F.U(i + 1, j - 1, k)) * hy) -
-                       F.Mxy(i, j, k) * ((v0 - F.V(i - 1, j, k)) * hx + (F.U(i, j, k) - F.U(i, j - 1, k)) * hy));
-            if (three)
-                L += hz * (F.Myz(i, j, k + 1) * ((F.V(i, j, k + 1) - v0) * hz + (F.W(i, j, k + 1) - F.W(i, j - 1, k + 1)) * hy) -
-                           F.Myz(i, j, k) * ((v0 - F.V(i, j, k - 1)) * hz + (F.W(i, j, k) - F.W(i, j - 1, k)) * hy));
-            const int o = i + a.nx * (j + py * k);
+            const double v0 = F.V(i, j, 0);
+            double L = 2.0 * hy * hy * (F.M(i, j, 0) * (F.V(i, j + 1, 0) - v0) - F.M(i, j - 1, 0) * (v0 - F.V(i, j - 1, 0)));
+            L += hx * (F.Mxy(i + 1, j, 0) * ((F.V(i + 1, j, 0) - v0) * hx + (F.U(i + 1, j, 0) - F.U(i + 1, j - 1, 0)) * hy) -
+                       F.Mxy(i, j, 0) * ((v0 - F.V(i - 1, j, 0)) * hx + (F.U(i, j, 0) - F.U(i, j - 1, 0)) * hy));
+            const int o = i + a.nx * j;
             r = a.ry[o] * a.idt * v0 + a.expl * L;
             if (a.fy) r += a.fy[o] * a.g[1];
         }
-        oy[i + a.nx * (j + py * k)] = r;
-    }
-    // z-face k of column (i, j)
-    if (three && i < a.nx && j < a.ny) {
-        double r = 0.0;
-        if (k > 0 && k < a.nz) {
-            const double w0 = F.W(i, j, k);
-            double L = 2.0 * hz * hz * (F.M(i, j, k) * (F.W(i, j, k + 1) - w0) - F.M(i, j, k - 1) * (w0 - F.W(i, j, k - 1)));
-            L += hx * (F.Mxz(i + 1, j, k) * ((F.W(i + 1, j, k) - w0) * hx + (F.U(i + 1, j, k) - F.U(i + 1, j, k - 1)) * hz) -
-                       F.Mxz(i, j, k) * ((w0 - F.W(i - 1, j, k)) * hx + (F.U(i, j, k) - F.U(i, j, k - 1)) * hz));
-            L += hy * (F.Myz(i, j + 1, k) * ((F.W(i, j + 1, k) - w0) * hy + (F.V(i, j + 1, k) - F.V(i, j + 1, k - 1)) * hz) -
-                       F.Myz(i, j, k) * ((w0 - F.W(i, j - 1, k)) * hy + (F.V(i, j, k) - F.V(i, j, k - 1)) * hz));
-            const int o = i + a.nx * (j + a.ny * k);
-            r = a.rz[o] * a.idt * w0 + a.expl * L;
-            if (a.fz) r += a.fz[o] * a.g[2];
-        }
-        oz[i + a.nx * (j + a.ny * k)] = r;
+        oy[i + a.nx * j] = r;
     }
 }
 
@@ -321,7 +290,7 @@ extern "C" stokes_status stokes_explicit_rhs(const stokes_grid *grid, const doub
         k_explicit_rhs3_z<<<g, kZX * kZY, 0, s>>>(a, f[0], f[1], f[2]);
     } else {
         const unsigned blocks = (unsigned)((pts + kRhsBlock - 1) / kRhsBlock);
-        k_explicit_rhs<<<blocks, kRhsBlock, 0, s>>>(a, f[0], f[1], nullptr);
+        k_explicit_rhs2<<<blocks, kRhsBlock, 0, s>>>(a, f[0], f[1]);
     }
     return hipGetLastError() == hipSuccess ? STOKES_OK : STOKES_EHIP;
 }
