@@ -104,11 +104,12 @@ typedef struct {
                             6 for 3D FP64 when p_cycles is automatic, else p_cycles (FGMRES is
                             flexible, so the preconditioner may change between iterations) */
     int p_nu_second;     /* pre- and post-smoothing sweeps on the second-finest pressure level
-                            (>= 0; the third-finest keeps nu1 / nu2).  0 = automatic: with FP64
-                            multigrid and W-cycles (those levels are cycled twice and four times
-                            per visit of the finest) at most one sweep on each side of the second
-                            (min(nu1, 1), min(nu2, 1)) and one pre-smoothing sweep on the third
-                            (min(nu1, 1)); otherwise nu1 / nu2 */
+                            (>= 0; the coarser levels keep nu1 / nu2).  0 = automatic: with FP64
+                            multigrid and W-cycles (the second level is cycled twice per visit of
+                            the finest, the third and fourth four times) at most one sweep on
+                            each side of the second (min(nu1, 1), min(nu2, 1)) and one
+                            pre-smoothing sweep on the third and fourth (min(nu1, 1)); otherwise
+                            nu1 / nu2 */
 } stokes_options;
 
 typedef struct {
@@ -137,7 +138,8 @@ typedef struct stokes_ctx stokes_ctx;
  * automatic velocity levels, 1 single-level velocity sweep, piecewise-constant
  * pressure prolongation, diagonal velocity step, one-pass Gram-Schmidt, z-marching
  * matvec, small levels cycled in one workgroup, in FP64 one sweep on each side on
- * the second-finest pressure level and one pre-smoothing sweep on the third). */
+ * the second-finest pressure level and one pre-smoothing sweep on the third and
+ * fourth). */
 void stokes_default_options(stokes_options *opts);
 
 /* Bytes of device workspace that stokes_setup needs for this grid and these

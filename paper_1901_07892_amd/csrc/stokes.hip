@@ -128,7 +128,7 @@ struct stokes_ctx {
     int cyc_first = 3, cyc_next = 3;   // pressure cycles: first / later applications of a restart cycle
     int cyc_now = 3;                    // cycles of the current application
     int nu_sec1 = 2, nu_sec2 = 2;       // pre-/post-smoothing sweeps on the second pressure level
-    int nu_third1 = 2;                  // pre-smoothing sweeps on the third pressure level
+    int nu_mid1 = 2;                    // pre-smoothing sweeps on the third and fourth pressure levels
     double visc_ratio = -1.0;   // max viscous/mass diagonal ratio (automatic velocity levels)
     bool diag_vel = false;      // velocity subsolve is one diagonal step (see stokes_options.vel_smoother)
     // learned stage: network, the level it runs on, feature/prediction buffers
@@ -359,7 +359,7 @@ int gamma_at(const stokes_ctx &c, const MG<R> &mg, int l) {
 }
 
 // Pre- and post-smoothing sweeps of pressure level l.
-inline int p_nu_pre(const stokes_ctx &c, int l) { return l == 1 ? c.nu_sec1 : l == 2 ? c.nu_third1 : c.opt.nu1; }
+inline int p_nu_pre(const stokes_ctx &c, int l) { return l == 1 ? c.nu_sec1 : (l == 2 || l == 3) ? c.nu_mid1 : c.opt.nu1; }
 inline int p_nu_post(const stokes_ctx &c, int l) { return l == 1 ? c.nu_sec2 : c.opt.nu2; }
 
 template <int DIM, class R>
@@ -1125,14 +1125,15 @@ void init_ctx_shape(stokes_ctx &c, const stokes_grid *g, const stokes_options &o
     c.cyc_first = o.p_cycles > 0 ? o.p_cycles : (two_step ? 4 : 3);
     c.cyc_next = o.p_cycles_next > 0 ? o.p_cycles_next : (o.p_cycles > 0 ? o.p_cycles : (two_step ? 6 : 3));
     c.cyc_now = c.cyc_first;
-    // smoothing on the second and third pressure levels: with W-cycles they are
-    // cycled twice and four times per visit of the finest level, and in FP64 one
-    // sweep on each side of the second and one pre-smoothing sweep on the third are
-    // enough there (same iteration counts, fewer sweeps); FP32 multigrid keeps nu1/nu2
+    // smoothing below the finest pressure level: with W-cycles on the two finest
+    // levels the second is cycled twice and the third and fourth four times per visit
+    // of the finest, and in FP64 one sweep on each side of the second and one
+    // pre-smoothing sweep on the third and fourth are enough (same iteration counts,
+    // fewer sweeps); FP32 multigrid keeps nu1/nu2
     const bool sec_auto = o.precision == 0 && o.p_gamma == 2;
     c.nu_sec1 = o.p_nu_second > 0 ? o.p_nu_second : (sec_auto ? std::min(o.nu1, 1) : o.nu1);
     c.nu_sec2 = o.p_nu_second > 0 ? o.p_nu_second : (sec_auto ? std::min(o.nu2, 1) : o.nu2);
-    c.nu_third1 = o.p_nu_second == 0 && sec_auto ? std::min(o.nu1, 1) : o.nu1;
+    c.nu_mid1 = o.p_nu_second == 0 && sec_auto ? std::min(o.nu1, 1) : o.nu1;
     c.fine = make_box(g->dim, g->n[0], g->n[1], g->dim == 3 ? g->n[2] : 1, g->h[0], g->h[1],
                       g->dim == 3 ? g->h[2] : g->h[0]);
     {
