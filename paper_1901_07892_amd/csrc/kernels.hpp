@@ -1144,7 +1144,10 @@ __global__ void __launch_bounds__(kBlock) k_edge_mu(Box b, const R *__restrict__
 // comp 0,1,2: face arrays normal to x,y,z; comp 3: cell array.
 // mode 0: copy, 1: reciprocal (beta = 1/rho), 2: multiply by s.
 // Only interior unknowns are copied (faces: interior faces; with keep_walls the
-// wall faces too); everything else in the box is written as 0.
+// wall faces too); everything else in the box is written as 0.  With flag, the
+// values read are checked on the way: flag[0] = 1 if one is not finite, flag[1] =
+// 1 if one is nonzero (one vector store per block at most, after a block-wide
+// OR; the flags are read first so that later blocks mostly skip the store).
 __device__ inline bool api_index(const Box &b, int comp, int i, int j, int k, int &a) {
     int ex = b.nx + (comp == 0), ey = b.ny + (comp == 1), ez = b.nz + (comp == 2);
     if (i >= ex || j >= ey || k >= ez) return false;
@@ -1153,21 +1156,32 @@ __device__ inline bool api_index(const Box &b, int comp, int i, int j, int k, in
 }
 
 __global__ void __launch_bounds__(kBlock) k_pack(Box b, int comp, int mode, int keep_walls, double s,
-        const double *__restrict__ src, double *__restrict__ dst) {
-    int idx = box_thread_index();
-    if (idx >= b.nb) return;
-    int i, j, k, a;
-    decompose(b, idx, i, j, k);
-    double val = 0.0;
-    if (api_index(b, comp, i, j, k, a)) {
-        bool wall = (comp == 0 && (i == 0 || i == b.nx)) || (comp == 1 && (j == 0 || j == b.ny)) ||
-                    (comp == 2 && (k == 0 || k == b.nz));
-        if (!wall || keep_walls) {
-            double x = src[a];
-            val = mode == 0 ? x : mode == 1 ? 1.0 / x : s * x;
+        const double *__restrict__ src, double *__restrict__ dst, int *__restrict__ flag) {
+    const int idx = box_thread_index();
+    bool bad = false, nz = false;
+    if (idx < b.nb) {
+        int i, j, k, a;
+        decompose(b, idx, i, j, k);
+        double val = 0.0;
+        if (api_index(b, comp, i, j, k, a)) {
+            bool wall = (comp == 0 && (i == 0 || i == b.nx)) || (comp == 1 && (j == 0 || j == b.ny)) ||
+                        (comp == 2 && (k == 0 || k == b.nz));
+            if (!wall || keep_walls) {
+                double x = src[a];
+                bad = !isfinite(x);
+                nz = x != 0.0;
+                val = mode == 0 ? x : mode == 1 ? 1.0 / x : s * x;
+            }
+        }
+        dst[idx] = val;
+    }
+    if (flag) {                       // uniform: every thread of the block takes both barriers
+        const bool any_bad = __syncthreads_or(bad), any_nz = __syncthreads_or(nz);
+        if (threadIdx.x == 0) {
+            if (any_bad && flag[0] == 0) flag[0] = 1;
+            if (any_nz && flag[1] == 0) flag[1] = 1;
         }
     }
-    dst[idx] = val;
 }
 
 __global__ void __launch_bounds__(kBlock) k_unpack(Box b, int comp, const double *__restrict__ src,
@@ -1637,19 +1651,6 @@ __global__ void __launch_bounds__(kBlock) k_partial_sum(long long n, const doubl
     }
     block_reduce<1>(v, lds);
     if (threadIdx.x == 0) partial[blockIdx.x] = v[0];
-}
-
-// flag[0] = 1 if a value of the range is not finite, flag[1] = 1 if one is nonzero
-__global__ void __launch_bounds__(kBlock) k_check_finite(long long n, const double *__restrict__ x, int *__restrict__ flag) {
-    long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
-    long long st = (long long)gridDim.x * kBlock;
-    bool bad = false, nz = false;
-    for (; t < n; t += st) {
-        bad |= !isfinite(x[t]);
-        nz |= x[t] != 0.0;
-    }
-    if (bad) flag[0] = 1;
-    if (nz) flag[1] = 1;     // some entry is nonzero
 }
 
 }  // namespace stk

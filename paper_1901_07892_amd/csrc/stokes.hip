@@ -301,6 +301,15 @@ VelCoef<double> fine_coef(const stokes_ctx &c) {
     return v;
 }
 
+// dst[0, n) = src[0, n) (n > 0) with the streaming-copy kernel: 16-byte
+// non-temporal accesses when both are 16-byte aligned, one pair per thread.
+inline void stream_copy(const double *src, double *dst, long long n, hipStream_t stream) {
+    const bool vec2 = ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 15) == 0;
+    const long long work = vec2 ? (n + 1) / 2 : n;
+    const unsigned g = (unsigned)std::max<long long>(1, std::min<long long>((work + kBlock - 1) / kBlock, 1 << 22));
+    k_stream_copy<<<g, kBlock, 0, stream>>>(n, src, dst, vec2 ? 1 : 0);
+}
+
 template <class R>
 void fill(stokes_ctx &c, R *p, long long n, R v) {
     k_fill<R><<<nblocks_stream(n), kBlock, 0, c.stream>>>(n, p, v);
@@ -698,7 +707,7 @@ stokes_status fgmres(stokes_ctx &c, MG<R> &mg, double tol, bool zero_guess, stok
         double be2;
         if (first && zero_guess) {
             // x0 = 0: the residual is b itself
-            HIPCHK(hipMemcpyAsync(v0, c.bk, sizeof(double) * c.vlen, hipMemcpyDeviceToDevice, c.stream));
+            stream_copy(c.bk, v0, c.vlen, c.stream);
             be2 = bn2;
         } else {
             apply_fine<DIM>(c, c.xk, c.bk, v0);
@@ -1150,10 +1159,10 @@ stokes_status setup_impl(stokes_ctx &c, const double *const rho[3], const double
     const unsigned gb = nblocks_box(b);
     HIPCHK(hipMemsetAsync(c.ws, 0, c.ws_need, c.stream));
     for (int a = 0; a < DIM; ++a) {
-        k_pack<<<gb, kBlock, 0, c.stream>>>(b, a, 2, 0, 1.0 / c.dt, rho[a], c.mass[a]);
-        k_pack<<<gb, kBlock, 0, c.stream>>>(b, a, 1, 0, 1.0, rho[a], c.beta[a]);
+        k_pack<<<gb, kBlock, 0, c.stream>>>(b, a, 2, 0, 1.0 / c.dt, rho[a], c.mass[a], nullptr);
+        k_pack<<<gb, kBlock, 0, c.stream>>>(b, a, 1, 0, 1.0, rho[a], c.beta[a], nullptr);
     }
-    k_pack<<<gb, kBlock, 0, c.stream>>>(b, 3, 0, 0, 1.0, mu, c.mu);
+    k_pack<<<gb, kBlock, 0, c.stream>>>(b, 3, 0, 0, 1.0, mu, c.mu, nullptr);
     k_check_coef<<<gb, kBlock, 0, c.stream>>>(b, c.mass[0], c.mass[1], DIM == 3 ? c.mass[2] : c.mass[1], c.mu, c.dflag);
     int flag = 0;
     HIPCHK(hipMemcpyAsync(&flag, c.dflag, sizeof(int), hipMemcpyDeviceToHost, c.stream));
@@ -1209,12 +1218,14 @@ stokes_status setup_impl(stokes_ctx &c, const double *const rho[3], const double
     return STOKES_OK;
 }
 
+// Packs (u, p) into the box vector vb; with flag, flag[0] is set if a value is
+// not finite and flag[1] if one is nonzero (the caller clears both first).
 template <int DIM>
-void pack_vector(stokes_ctx &c, const double *const u[3], const double *p, double *vb) {
+void pack_vector(stokes_ctx &c, const double *const u[3], const double *p, double *vb, int *flag = nullptr) {
     const Box &b = c.fine;
     const unsigned gb = nblocks_box(b);
-    for (int a = 0; a < DIM; ++a) k_pack<<<gb, kBlock, 0, c.stream>>>(b, a, 0, 0, 1.0, u[a], c.fld(vb, a));
-    k_pack<<<gb, kBlock, 0, c.stream>>>(b, 3, 0, 0, 1.0, p, c.fld(vb, DIM));
+    for (int a = 0; a < DIM; ++a) k_pack<<<gb, kBlock, 0, c.stream>>>(b, a, 0, 0, 1.0, u[a], c.fld(vb, a), flag);
+    k_pack<<<gb, kBlock, 0, c.stream>>>(b, 3, 0, 0, 1.0, p, c.fld(vb, DIM), flag);
 }
 
 template <int DIM>
@@ -1230,9 +1241,9 @@ stokes_status solve_impl(stokes_ctx &c, const double *const rhs_u[3], const doub
                          double *const x_u[3], double *x_p, stokes_stats &st) {
     c.vcycles = 0;
     c.learned_active = c.net != nullptr;
-    pack_vector<DIM>(c, rhs_u, rhs_p, c.bk);
-    k_fill<int><<<1, kBlock, 0, c.stream>>>(1, c.dflag, 0);
-    k_check_finite<<<nblocks_stream(c.vlen), kBlock, 0, c.stream>>>(c.vlen, c.bk, c.dflag);
+    // dflag[0..1]: right-hand side not finite / nonzero; dflag[2..3]: the same for x
+    k_fill<int><<<1, kBlock, 0, c.stream>>>(4, c.dflag, 0);
+    pack_vector<DIM>(c, rhs_u, rhs_p, c.bk, c.dflag);
     int flag = 0;
     // mean of rhs_p
     {
@@ -1247,11 +1258,9 @@ stokes_status solve_impl(stokes_ctx &c, const double *const rhs_u[3], const doub
         st.g_mean = s / ((double)c.fine.nx * c.fine.ny * c.fine.nz);
         k_sub_mean<<<nblocks_box(c.fine), kBlock, 0, c.stream>>>(c.fine, c.dsc, c.fld(c.bk, DIM));
     }
-    pack_vector<DIM>(c, x_u, x_p, c.xk);
-    k_fill<int><<<1, kBlock, 0, c.stream>>>(2, c.dflag, 0);
-    k_check_finite<<<nblocks_stream(c.vlen), kBlock, 0, c.stream>>>(c.vlen, c.xk, c.dflag);
+    pack_vector<DIM>(c, x_u, x_p, c.xk, c.dflag + 2);
     int xflag[2] = {0, 0};
-    HIPCHK(hipMemcpyAsync(xflag, c.dflag, 2 * sizeof(int), hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(hipMemcpyAsync(xflag, c.dflag + 2, 2 * sizeof(int), hipMemcpyDeviceToHost, c.stream));
     HIPCHK(hipStreamSynchronize(c.stream));
     if (xflag[0]) { c.err = "non-finite initial guess"; return STOKES_ENAN; }
     const bool zero_guess = xflag[1] == 0;
@@ -1527,10 +1536,7 @@ stokes_status stokes_profile_read(stokes_ctx *ctx, double *ms_total, long long *
 stokes_status stokes_stream_copy(const double *src, double *dst, long long n, void *stream) {
     if (n < 0 || (n > 0 && (!src || !dst))) return STOKES_EINVAL;
     if (n == 0) return STOKES_OK;
-    const bool vec2 = ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 15) == 0;
-    const long long work = vec2 ? (n + 1) / 2 : n;
-    const unsigned g = (unsigned)std::max<long long>(1, std::min<long long>((work + kBlock - 1) / kBlock, 1 << 22));
-    k_stream_copy<<<g, kBlock, 0, reinterpret_cast<hipStream_t>(stream)>>>(n, src, dst, vec2 ? 1 : 0);
+    stream_copy(src, dst, n, reinterpret_cast<hipStream_t>(stream));
     return hipGetLastError() == hipSuccess ? STOKES_OK : STOKES_EHIP;
 }
 

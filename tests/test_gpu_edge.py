@@ -68,6 +68,58 @@ def test_nan_rhs_reports_enan():
     assert e.value.status == -5
 
 
+@pytest.mark.parametrize("where", ["rhs_w", "rhs_p_inf", "x0_u_nan", "x0_p_inf"])
+def test_non_finite_input_reports_enan(where):
+    """A non-finite value in any packed field of the right-hand side or of the
+    initial guess (3D: u, v, w, p; the first and the last field packed) gives
+    ENAN and leaves the guess arrays untouched."""
+    import torch
+    import paper_1901_07892_amd as S
+    prob = W.config3(scale=4)
+    x0u = [np.zeros(W.face_shape(prob.n, c)) for c in range(3)]
+    x0p = np.zeros(W.cell_shape(prob.n))
+    if where == "rhs_w":
+        prob.rhs_u[2][3, 2, 1] = np.nan
+    elif where == "rhs_p_inf":
+        prob.rhs_p[-1, -1, -1] = np.inf
+    elif where == "x0_u_nan":
+        x0u[0][2, 3, 4] = np.nan
+    else:
+        x0p[-1, -1, -1] = -np.inf
+    s = solver_for(prob)
+    xu = [to_dev(a) for a in x0u]
+    xp = to_dev(x0p)
+    with pytest.raises(S.StokesError) as e:
+        s.solve([to_dev(f) for f in prob.rhs_u[:3]], to_dev(prob.rhs_p), prob.tol, xu, xp)
+    torch.cuda.synchronize()
+    s.close()
+    assert e.value.status == -5, e.value
+    np.testing.assert_array_equal(to_host(xp), x0p)
+    for c in range(3):
+        np.testing.assert_array_equal(to_host(xu[c]), x0u[c])
+
+
+@pytest.mark.parametrize("field", ["u_first", "p_last"])
+def test_guess_zero_but_one_entry_is_not_taken_for_zero(oracle_lib, field):
+    """The zero-guess decision sees every packed value: a guess that is zero but
+    for one entry (in the first or the last field packed) takes the b - K x0 path
+    and ends at the reference solution; taken for zero, the returned iterate
+    would keep that entry's offset."""
+    prob = W.config3(scale=4)
+    ru, rp, _ = oracle_lib.solve_problem(prob, tol=1e-13, max_iters=300)
+    x0u = [np.zeros_like(a) for a in ru[:3]]
+    x0p = np.zeros_like(rp)
+    if field == "u_first":
+        x0u[0][0, 0, 1] = 10.0 * np.abs(ru[0]).max() + 1.0
+    else:
+        x0p[-1, -1, -1] = 10.0 * np.abs(rp).max() + 1.0
+    xu, xp, st, stats = gpu_solve(prob, tol=1e-12, max_iters=400, x0=(x0u, x0p))
+    assert st == 0 or (st == 1 and stats.rel_res_true <= 1e-11), stats.as_dict()
+    for c in range(3):
+        assert rel(xu[c], ru[c]) <= 1e-8
+    assert rel(xp - xp.mean(), rp - rp.mean()) <= 1e-8
+
+
 def test_max_iters_not_converged_returns_best_iterate():
     prob = W.config1(scale=2)
     xu, xp, st, stats = gpu_solve(prob, tol=1e-14, max_iters=1)
