@@ -1148,49 +1148,53 @@ __global__ void __launch_bounds__(kBlock) k_edge_mu(Box b, const R *__restrict__
 // values read are checked on the way: flag[0] = 1 if one is not finite, flag[1] =
 // 1 if one is nonzero (one vector store per block at most, after a block-wide
 // OR; the flags are read first so that later blocks mostly skip the store).
-__device__ inline bool api_index(const Box &b, int comp, int i, int j, int k, int &a) {
-    int ex = b.nx + (comp == 0), ey = b.ny + (comp == 1), ez = b.nz + (comp == 2);
-    if (i >= ex || j >= ey || k >= ez) return false;
-    a = i + ex * (j + ey * k);
-    return true;
-}
+// Row form: a block of 64 x kPackRows threads takes kPackRows rows (j, k) of the
+// box, one wavefront per row, each lane stepping over x in strides of 64, so no
+// thread divides a flat point index.
+constexpr int kPackRows = 4;
 
-__global__ void __launch_bounds__(kBlock) k_pack(Box b, int comp, int mode, int keep_walls, double s,
+__global__ void __launch_bounds__(64 * kPackRows) k_pack(Box b, int comp, int mode, int keep_walls, double s,
         const double *__restrict__ src, double *__restrict__ dst, int *__restrict__ flag) {
-    const int idx = box_thread_index();
+    const int r = blockIdx.x * kPackRows + threadIdx.y;     // row j + py k
     bool bad = false, nz = false;
-    if (idx < b.nb) {
-        int i, j, k, a;
-        decompose(b, idx, i, j, k);
-        double val = 0.0;
-        if (api_index(b, comp, i, j, k, a)) {
-            bool wall = (comp == 0 && (i == 0 || i == b.nx)) || (comp == 1 && (j == 0 || j == b.ny)) ||
-                        (comp == 2 && (k == 0 || k == b.nz));
-            if (!wall || keep_walls) {
-                double x = src[a];
-                bad = !isfinite(x);
-                nz = x != 0.0;
+    if (r < b.py * b.pz) {
+        const int k = r / b.py, j = r - k * b.py;
+        const int ex = b.nx + (comp == 0), ey = b.ny + (comp == 1), ez = b.nz + (comp == 2);
+        const bool row_in = j < ey && k < ez;
+        const bool row_wall = (comp == 1 && (j == 0 || j == b.ny)) || (comp == 2 && (k == 0 || k == b.nz));
+        const double *sr = src + (row_in ? ex * (j + ey * k) : 0);
+        double *dr = dst + r * b.px;
+        for (int i = threadIdx.x; i < b.px; i += 64) {
+            double val = 0.0;
+            if (row_in && i < ex && (keep_walls || !(row_wall || (comp == 0 && (i == 0 || i == b.nx))))) {
+                const double x = sr[i];
+                bad |= !isfinite(x);
+                nz |= x != 0.0;
                 val = mode == 0 ? x : mode == 1 ? 1.0 / x : s * x;
             }
+            dr[i] = val;
         }
-        dst[idx] = val;
     }
     if (flag) {                       // uniform: every thread of the block takes both barriers
         const bool any_bad = __syncthreads_or(bad), any_nz = __syncthreads_or(nz);
-        if (threadIdx.x == 0) {
+        if (threadIdx.x == 0 && threadIdx.y == 0) {
             if (any_bad && flag[0] == 0) flag[0] = 1;
             if (any_nz && flag[1] == 0) flag[1] = 1;
         }
     }
 }
 
-__global__ void __launch_bounds__(kBlock) k_unpack(Box b, int comp, const double *__restrict__ src,
+// Box -> caller layout for every point of the caller's array (wall faces included).
+__global__ void __launch_bounds__(64 * kPackRows) k_unpack(Box b, int comp, const double *__restrict__ src,
         double *__restrict__ dst) {
-    int idx = box_thread_index();
-    if (idx >= b.nb) return;
-    int i, j, k, a;
-    decompose(b, idx, i, j, k);
-    if (api_index(b, comp, i, j, k, a)) dst[a] = src[idx];
+    const int r = blockIdx.x * kPackRows + threadIdx.y;
+    if (r >= b.py * b.pz) return;
+    const int k = r / b.py, j = r - k * b.py;
+    const int ex = b.nx + (comp == 0), ey = b.ny + (comp == 1), ez = b.nz + (comp == 2);
+    if (j >= ey || k >= ez) return;
+    double *dr = dst + ex * (j + ey * k);
+    const double *sr = src + r * b.px;
+    for (int i = threadIdx.x; i < ex; i += 64) dr[i] = sr[i];
 }
 
 // Flags non-physical coefficients: rho <= 0 or non-finite on interior faces, mu < 0

@@ -301,6 +301,9 @@ VelCoef<double> fine_coef(const stokes_ctx &c) {
     return v;
 }
 
+// blocks of the row-form layout conversion kernels (kPackRows box rows each)
+inline unsigned nblocks_rows(const Box &b) { return (unsigned)((b.py * b.pz + kPackRows - 1) / kPackRows); }
+
 // dst[0, n) = src[0, n) (n > 0) with the streaming-copy kernel: 16-byte
 // non-temporal accesses when both are 16-byte aligned, one pair per thread.
 inline void stream_copy(const double *src, double *dst, long long n, hipStream_t stream) {
@@ -1159,10 +1162,10 @@ stokes_status setup_impl(stokes_ctx &c, const double *const rho[3], const double
     const unsigned gb = nblocks_box(b);
     HIPCHK(hipMemsetAsync(c.ws, 0, c.ws_need, c.stream));
     for (int a = 0; a < DIM; ++a) {
-        k_pack<<<gb, kBlock, 0, c.stream>>>(b, a, 2, 0, 1.0 / c.dt, rho[a], c.mass[a], nullptr);
-        k_pack<<<gb, kBlock, 0, c.stream>>>(b, a, 1, 0, 1.0, rho[a], c.beta[a], nullptr);
+        k_pack<<<nblocks_rows(b), dim3(64, kPackRows), 0, c.stream>>>(b, a, 2, 0, 1.0 / c.dt, rho[a], c.mass[a], nullptr);
+        k_pack<<<nblocks_rows(b), dim3(64, kPackRows), 0, c.stream>>>(b, a, 1, 0, 1.0, rho[a], c.beta[a], nullptr);
     }
-    k_pack<<<gb, kBlock, 0, c.stream>>>(b, 3, 0, 0, 1.0, mu, c.mu, nullptr);
+    k_pack<<<nblocks_rows(b), dim3(64, kPackRows), 0, c.stream>>>(b, 3, 0, 0, 1.0, mu, c.mu, nullptr);
     k_check_coef<<<gb, kBlock, 0, c.stream>>>(b, c.mass[0], c.mass[1], DIM == 3 ? c.mass[2] : c.mass[1], c.mu, c.dflag);
     int flag = 0;
     HIPCHK(hipMemcpyAsync(&flag, c.dflag, sizeof(int), hipMemcpyDeviceToHost, c.stream));
@@ -1223,17 +1226,15 @@ stokes_status setup_impl(stokes_ctx &c, const double *const rho[3], const double
 template <int DIM>
 void pack_vector(stokes_ctx &c, const double *const u[3], const double *p, double *vb, int *flag = nullptr) {
     const Box &b = c.fine;
-    const unsigned gb = nblocks_box(b);
-    for (int a = 0; a < DIM; ++a) k_pack<<<gb, kBlock, 0, c.stream>>>(b, a, 0, 0, 1.0, u[a], c.fld(vb, a), flag);
-    k_pack<<<gb, kBlock, 0, c.stream>>>(b, 3, 0, 0, 1.0, p, c.fld(vb, DIM), flag);
+    for (int a = 0; a < DIM; ++a) k_pack<<<nblocks_rows(b), dim3(64, kPackRows), 0, c.stream>>>(b, a, 0, 0, 1.0, u[a], c.fld(vb, a), flag);
+    k_pack<<<nblocks_rows(b), dim3(64, kPackRows), 0, c.stream>>>(b, 3, 0, 0, 1.0, p, c.fld(vb, DIM), flag);
 }
 
 template <int DIM>
 void unpack_vector(stokes_ctx &c, double *vb, double *const u[3], double *p) {
     const Box &b = c.fine;
-    const unsigned gb = nblocks_box(b);
-    for (int a = 0; a < DIM; ++a) k_unpack<<<gb, kBlock, 0, c.stream>>>(b, a, c.fld(vb, a), u[a]);
-    k_unpack<<<gb, kBlock, 0, c.stream>>>(b, 3, c.fld(vb, DIM), p);
+    for (int a = 0; a < DIM; ++a) k_unpack<<<nblocks_rows(b), dim3(64, kPackRows), 0, c.stream>>>(b, a, c.fld(vb, a), u[a]);
+    k_unpack<<<nblocks_rows(b), dim3(64, kPackRows), 0, c.stream>>>(b, 3, c.fld(vb, DIM), p);
 }
 
 template <int DIM>
