@@ -1265,7 +1265,7 @@ stokes_status solve_impl(stokes_ctx &c, const double *const rhs_u[3], const doub
     HIPCHK(hipStreamSynchronize(c.stream));
     if (xflag[0]) { c.err = "non-finite initial guess"; return STOKES_ENAN; }
     const bool zero_guess = xflag[1] == 0;
-    remove_p_mean(c, c.xk);
+    if (!zero_guess) remove_p_mean(c, c.xk);     // an all-zero guess has zero mean
     stokes_status s = c.opt.precision == 1 ? fgmres<DIM, float>(c, c.mgf, tol, zero_guess, st)
                                            : fgmres<DIM, double>(c, c.mgd, tol, zero_guess, st);
     if (s < 0) return s;
