@@ -53,7 +53,7 @@ typedef enum {
     STOKES_ESHAPE = -2,         /* grid unsupported (e.g. fewer than 2 cells along an axis) */
     STOKES_ENOMEM = -3,         /* workspace smaller than stokes_workspace_size() */
     STOKES_EHIP = -4,           /* a HIP runtime call failed */
-    STOKES_ENAN = -5            /* NaN or Inf in the right-hand side or the residual */
+    STOKES_ENAN = -5            /* NaN or Inf in the right-hand side, the guess or the residual */
 } stokes_status;
 
 typedef struct {
@@ -182,7 +182,9 @@ stokes_status stokes_apply(stokes_ctx *ctx, const double *const x_u[3], const do
  * reported in stats->g_mean.  x holds the initial guess on entry (its wall
  * entries ignored) and the solution on exit (p with zero mean); the residual is
  * recomputed in FP64 before returning.  Blocks until done.  stats may be NULL.
- * Returns OK, NOT_CONVERGED (best iterate in x), BREAKDOWN, ENAN, EINVAL or EHIP. */
+ * Returns OK, NOT_CONVERGED (best iterate in x), BREAKDOWN, ENAN, EINVAL or EHIP.
+ * ENAN: a NaN or Inf among the values read (the right-hand side, or the initial
+ * guess; x is then left untouched), or a non-finite residual during the solve. */
 stokes_status stokes_solve(stokes_ctx *ctx, const double *const rhs_u[3], const double *rhs_p,
                            double tol, double *const x_u[3], double *x_p, stokes_stats *stats);
 
