@@ -1625,6 +1625,17 @@ __global__ void __launch_bounds__(kBlock) k_stream_copy(long long n, const doubl
     }
 }
 
+// x[0, n) = 0 (x 16-byte aligned) with 16-byte non-temporal stores, one pair per
+// thread of a full grid (grid stride beyond it).
+__global__ void __launch_bounds__(kBlock) k_zero(long long n, double *__restrict__ x) {
+    const long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+    const long long st = (long long)gridDim.x * kBlock;
+    stream_d2 *x2 = reinterpret_cast<stream_d2 *>(x);
+    const stream_d2 z = {0.0, 0.0};
+    for (long long u = t; u < n / 2; u += st) __builtin_nontemporal_store(z, x2 + u);
+    if (t == 0 && (n & 1)) x[n - 1] = 0.0;
+}
+
 // x[t] *= s
 __global__ void __launch_bounds__(kBlock) k_scale(long long n, double s, double *__restrict__ x) {
     long long t = (long long)blockIdx.x * kBlock + threadIdx.x;

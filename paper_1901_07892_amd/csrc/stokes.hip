@@ -108,6 +108,7 @@ struct stokes_ctx {
     hipStream_t stream = nullptr;
     char *ws = nullptr;
     size_t ws_bytes = 0, ws_need = 0;
+    int v_clear = 0, z_clear = 0;       // leading Krylov vectors V, Z zero-filled since setup
     int dim = 3, nf = 4;
     Box fine;
     // fine-level FP64 operator
@@ -316,6 +317,29 @@ inline void stream_copy(const double *src, double *dst, long long n, hipStream_t
 template <class R>
 void fill(stokes_ctx &c, R *p, long long n, R v) {
     k_fill<R><<<nblocks_stream(n), kBlock, 0, c.stream>>>(n, p, v);
+}
+
+// V[0, nv) and Z[0, nz) zero-filled before their first use after setup.  The
+// workspace clear at setup leaves the Krylov vectors out (they are most of the
+// workspace: 2 m + 1 vectors for restart length m), and a solve that converges
+// in a few iterations touches only the first few of them.
+void touch_krylov(stokes_ctx &c, int nv, int nz) {
+    auto zero = [&](double *x, long long n) {
+        if (reinterpret_cast<uintptr_t>(x) & 15) { fill<double>(c, x, n, 0.0); return; }
+        const long long work = (n + 1) / 2;
+        const unsigned g = (unsigned)std::max<long long>(1, std::min<long long>((work + kBlock - 1) / kBlock, 1 << 22));
+        k_zero<<<g, kBlock, 0, c.stream>>>(n, x);
+    };
+    nv = std::min(nv, c.m + 1);
+    nz = std::min(nz, c.m);
+    if (nv > c.v_clear) {
+        zero(c.vec(c.V, c.v_clear), (long long)(nv - c.v_clear) * c.vlen);
+        c.v_clear = nv;
+    }
+    if (nz > c.z_clear) {
+        zero(c.vec(c.Z, c.z_clear), (long long)(nz - c.z_clear) * c.vlen);
+        c.z_clear = nz;
+    }
 }
 
 // ---------------------------------------------------------------- velocity multigrid
@@ -705,6 +729,7 @@ stokes_status fgmres(stokes_ctx &c, MG<R> &mg, double tol, bool zero_guess, stok
     double prev = INFINITY;
     stokes_status status = STOKES_NOT_CONVERGED;
     bool first = true;
+    touch_krylov(c, 1, 0);
     for (;;) {
         double *v0 = c.vec(c.V, 0);
         double be2;
@@ -732,6 +757,7 @@ stokes_status fgmres(stokes_ctx &c, MG<R> &mg, double tol, bool zero_guess, stok
         int nj = 0;
         bool breakdown = false;
         for (int j = 0; j < m && st.iters < c.opt.max_iters; ++j) {
+            touch_krylov(c, j + 2, j + 1);
             double *vj = c.vec(c.V, j), *zj = c.vec(c.Z, j), *w = c.vec(c.V, j + 1);
             if (!c.diag_vel && hs[j] != 1.0) {
                 // the multigrid velocity path reads v_j in many kernels: normalise it
@@ -1160,7 +1186,14 @@ template <int DIM>
 stokes_status setup_impl(stokes_ctx &c, const double *const rho[3], const double *mu) {
     const Box &b = c.fine;
     const unsigned gb = nblocks_box(b);
-    HIPCHK(hipMemsetAsync(c.ws, 0, c.ws_need, c.stream));
+    // everything but the Krylov vectors (cleared on first use, touch_krylov)
+    {
+        const size_t vb = (size_t)(reinterpret_cast<char *>(c.V) - c.ws);
+        const size_t ze = (size_t)(reinterpret_cast<char *>(c.Z + (size_t)c.vlen * c.m) - c.ws);
+        HIPCHK(hipMemsetAsync(c.ws, 0, vb, c.stream));
+        HIPCHK(hipMemsetAsync(c.ws + ze, 0, c.ws_need - ze, c.stream));
+        c.v_clear = c.z_clear = 0;
+    }
     for (int a = 0; a < DIM; ++a) {
         k_pack<<<nblocks_rows(b), dim3(64, kPackRows), 0, c.stream>>>(b, a, 2, 0, 1.0 / c.dt, rho[a], c.mass[a], nullptr);
         k_pack<<<nblocks_rows(b), dim3(64, kPackRows), 0, c.stream>>>(b, a, 1, 0, 1.0, rho[a], c.beta[a], nullptr);
@@ -1331,6 +1364,7 @@ void learned_tuple(stokes_ctx &c, MG<R> &mg, int lc, int cycles, float *f0, floa
             fb, c.fld(v, 0), c.fld(v, 1), c.fld(v, 2), c.dinv[0], c.dinv[1], c.dinv[2], c.fld(v, 3), 1.0, c.dt, c.q,
             L0.rp);
     } else {
+        touch_krylov(c, 0, 1);
         double *z = c.vec(c.Z, 0);
         R *eu[3], *ru[3];
         if (sizeof(R) == sizeof(double)) {
@@ -1449,6 +1483,7 @@ stokes_status stokes_apply(stokes_ctx *ctx, const double *const x_u[3], const do
         return STOKES_EINVAL;
     }
     try {
+        touch_krylov(*ctx, 2, 0);
         double *vin = ctx->vec(ctx->V, 0), *vout = ctx->vec(ctx->V, 1 % (ctx->m + 1));
         if (d == 3) {
             pack_vector<3>(*ctx, x_u, x_p, vin);

@@ -120,6 +120,54 @@ def test_guess_zero_but_one_entry_is_not_taken_for_zero(oracle_lib, field):
     assert rel(xp - xp.mean(), rp - rp.mean()) <= 1e-8
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_workspace_contents_do_not_matter(precision):
+    """Nothing reads workspace memory the library has not written: setup on a
+    workspace full of NaN gives bitwise the same matvec and solves as on a zeroed
+    one (restart length 2 at tol 1e-12, so the solve restarts and every Krylov
+    vector is used, then a second solve from a nonzero guess)."""
+    import torch
+    import paper_1901_07892_amd as S
+    B = S._binding
+    prob = W.config3(scale=4)
+    rho = [to_dev(r) for r in prob.rho_faces[:3]]
+    mu = to_dev(prob.mu)
+    grid = B.make_grid(3, prob.n, prob.h)
+    opts = B.stokes_default_options()
+    opts.restart = 2
+    opts.precision = precision
+    nbytes = B.stokes_workspace_size(grid, opts)
+    rng = np.random.default_rng(5)
+    xin = [rng.standard_normal(W.face_shape(prob.n, c)) for c in range(3)]
+    pin = rng.standard_normal(W.cell_shape(prob.n))
+    runs = []
+    for value in (0.0, float("nan")):
+        ws = torch.full((nbytes // 8 + 1,), value, dtype=torch.float64, device="cuda")
+        ctx = B.stokes_setup(rho, mu, prob.dt, grid, opts, ws.data_ptr(), nbytes)
+        out = []
+        yu = [torch.empty_like(to_dev(a)) for a in xin]
+        yp = torch.empty_like(to_dev(pin))
+        B.stokes_apply(ctx, [to_dev(a) for a in xin], to_dev(pin), yu, yp)
+        out += [to_host(a) for a in yu] + [to_host(yp)]
+        xu = [torch.zeros_like(to_dev(f)) for f in prob.rhs_u[:3]]
+        xp = torch.zeros_like(to_dev(prob.rhs_p))
+        for solve in range(2):
+            st, stats = B.stokes_solve(ctx, [to_dev(f) for f in prob.rhs_u[:3]], to_dev(prob.rhs_p), 1e-12, xu, xp)
+            torch.cuda.synchronize()
+            assert st in (0, 1), stats.as_dict()
+            if solve == 0:
+                assert stats.restarts >= 1, stats.as_dict()
+            out += [to_host(a) for a in xu] + [to_host(xp), np.array([stats.iters, stats.rel_res_true])]
+            for a in xu:                      # second solve: guess = half the solution
+                a.mul_(0.5)
+            xp.mul_(0.5)
+        B.stokes_destroy(ctx)
+        runs.append(out)
+    for a, b in zip(*runs):
+        assert np.all(np.isfinite(a))
+        np.testing.assert_array_equal(a, b)
+
+
 def test_max_iters_not_converged_returns_best_iterate():
     prob = W.config1(scale=2)
     xu, xp, st, stats = gpu_solve(prob, tol=1e-14, max_iters=1)
