@@ -26,6 +26,7 @@ constexpr int kMaxLev = 24;
 constexpr int kDenseMax = 2048;     // largest coarsest pressure level solved densely
 constexpr int kRedBlocks = 2048;    // blocks of the streaming reduction kernels
 constexpr int kGroup = 8;           // vectors per multidot / maxpy launch
+static_assert(kGroup >= 3, "c.partial holds the 3 partials per block of the setup min/max");
 constexpr int kLearnedMaxCells = 1 << 18;   // largest level (64^3) the learned stage may run on
 constexpr int kSmallMaxOps = 4096;          // passes of one small-level cycle
 
@@ -1210,7 +1211,7 @@ stokes_status setup_impl(stokes_ctx &c, const double *const rho[3], const double
     k_edge_mu<DIM, double><<<gb, kBlock, 0, c.stream>>>(b, c.mu, c.mxy, c.mxz, c.myz);
     if (c.opt.vel_levels == 0) {
         // automatic velocity hierarchy: smoother only when the operator is mass dominated
-        const int nbk = 256;
+        const int nbk = kRedBlocks;
         k_visc_ratio<DIM><<<nbk, kBlock, 0, c.stream>>>(b, fine_coef(c), c.partial);
         std::vector<double> h(nbk);
         HIPCHK(hipMemcpyAsync(h.data(), c.partial, sizeof(double) * nbk, hipMemcpyDeviceToHost, c.stream));
@@ -1232,7 +1233,7 @@ stokes_status setup_impl(stokes_ctx &c, const double *const rho[3], const double
     if (c.opt.cont_scale > 0.0) {
         c.sigma = c.opt.cont_scale;
     } else {
-        const int nbk = 256;
+        const int nbk = kRedBlocks;        // 3 partials per block: fits c.partial (kRedBlocks * kGroup)
         k_minmax<<<nbk, kBlock, 0, c.stream>>>(b, c.mass[0], c.mass[1], DIM == 3 ? c.mass[2] : c.mass[1], c.mu, c.partial);
         std::vector<double> h(3 * nbk);
         HIPCHK(hipMemcpyAsync(h.data(), c.partial, sizeof(double) * h.size(), hipMemcpyDeviceToHost, c.stream));
