@@ -1145,16 +1145,17 @@ __global__ void __launch_bounds__(kBlock) k_edge_mu(Box b, const R *__restrict__
 // mode 0: copy, 1: reciprocal (beta = 1/rho), 2: multiply by s.
 // Only interior unknowns are copied (faces: interior faces; with keep_walls the
 // wall faces too); everything else in the box is written as 0.  With flag, the
-// values read are checked on the way: flag[0] = 1 if one is not finite, flag[1] =
-// 1 if one is nonzero (one vector store per block at most, after a block-wide
-// OR; the flags are read first so that later blocks mostly skip the store).
+// values read are checked on the way (one vector store per block at most, after
+// a block-wide OR; the flags are read first so that later blocks mostly skip the
+// store): check 0, flag[0] = 1 if one is not finite and flag[1] = 1 if one is
+// nonzero; check 1 (a viscosity), flag[0] = 1 if one is negative or not finite.
 // Row form: a block of 64 x kPackRows threads takes kPackRows rows (j, k) of the
 // box, one wavefront per row, each lane stepping over x in strides of 64, so no
 // thread divides a flat point index.
 constexpr int kPackRows = 4;
 
 __global__ void __launch_bounds__(64 * kPackRows) k_pack(Box b, int comp, int mode, int keep_walls, double s,
-        const double *__restrict__ src, double *__restrict__ dst, int *__restrict__ flag) {
+        const double *__restrict__ src, double *__restrict__ dst, int *__restrict__ flag, int check) {
     const int r = blockIdx.x * kPackRows + threadIdx.y;     // row j + py k
     bool bad = false, nz = false;
     if (r < b.py * b.pz) {
@@ -1168,7 +1169,7 @@ __global__ void __launch_bounds__(64 * kPackRows) k_pack(Box b, int comp, int mo
             double val = 0.0;
             if (row_in && i < ex && (keep_walls || !(row_wall || (comp == 0 && (i == 0 || i == b.nx))))) {
                 const double x = sr[i];
-                bad |= !isfinite(x);
+                bad |= check ? !(x >= 0.0) || !isfinite(x) : !isfinite(x);
                 nz |= x != 0.0;
                 val = mode == 0 ? x : mode == 1 ? 1.0 / x : s * x;
             }
@@ -1179,7 +1180,7 @@ __global__ void __launch_bounds__(64 * kPackRows) k_pack(Box b, int comp, int mo
         const bool any_bad = __syncthreads_or(bad), any_nz = __syncthreads_or(nz);
         if (threadIdx.x == 0 && threadIdx.y == 0) {
             if (any_bad && flag[0] == 0) flag[0] = 1;
-            if (any_nz && flag[1] == 0) flag[1] = 1;
+            if (!check && any_nz && flag[1] == 0) flag[1] = 1;
         }
     }
 }
@@ -1197,21 +1198,36 @@ __global__ void __launch_bounds__(64 * kPackRows) k_unpack(Box b, int comp, cons
     for (int i = threadIdx.x; i < ex; i += 64) dr[i] = sr[i];
 }
 
-// Flags non-physical coefficients: rho <= 0 or non-finite on interior faces, mu < 0
-// or non-finite on cells.  flag[0] is set to 1 on failure (vector store).
-__global__ void __launch_bounds__(kBlock) k_check_coef(Box b, const double *__restrict__ rx,
-        const double *__restrict__ ry, const double *__restrict__ rz, const double *__restrict__ mu,
+// Face densities of one component -> mass = rho/dt and beta = 1/rho in one pass
+// over rho, in the row form of k_pack: interior faces only, everything else in
+// the box written as 0.  flag[0] = 1 if an interior mass value is not > 0 or not
+// finite (one vector store per block at most, after a block-wide OR).
+__global__ void __launch_bounds__(64 * kPackRows) k_pack_rho(Box b, int comp, double inv_dt,
+        const double *__restrict__ src, double *__restrict__ mass, double *__restrict__ beta,
         int *__restrict__ flag) {
-    int idx = box_thread_index();
-    if (idx >= b.nb) return;
-    int i, j, k;
-    decompose(b, idx, i, j, k);
+    const int r = blockIdx.x * kPackRows + threadIdx.y;     // row j + py k
     bool bad = false;
-    if (is_ux(b, i, j, k)) bad |= !(rx[idx] > 0.0) || !isfinite(rx[idx]);
-    if (is_vy(b, i, j, k)) bad |= !(ry[idx] > 0.0) || !isfinite(ry[idx]);
-    if (b.dim == 3 && is_wz(b, i, j, k)) bad |= !(rz[idx] > 0.0) || !isfinite(rz[idx]);
-    if (is_cell(b, i, j, k)) bad |= !(mu[idx] >= 0.0) || !isfinite(mu[idx]);
-    if (bad) flag[0] = 1;
+    if (r < b.py * b.pz) {
+        const int k = r / b.py, j = r - k * b.py;
+        const int ex = b.nx + (comp == 0), ey = b.ny + (comp == 1), ez = b.nz + (comp == 2);
+        const bool row_in = j < ey && k < ez;
+        const bool row_wall = (comp == 1 && (j == 0 || j == b.ny)) || (comp == 2 && (k == 0 || k == b.nz));
+        const double *sr = src + (row_in ? ex * (j + ey * k) : 0);
+        double *mr = mass + r * b.px, *br = beta + r * b.px;
+        for (int i = threadIdx.x; i < b.px; i += 64) {
+            double m = 0.0, be = 0.0;
+            if (row_in && i < ex && !(row_wall || (comp == 0 && (i == 0 || i == b.nx)))) {
+                const double x = sr[i];
+                m = inv_dt * x;
+                be = 1.0 / x;
+                bad |= !(m > 0.0) || !isfinite(m);
+            }
+            mr[i] = m;
+            br[i] = be;
+        }
+    }
+    const bool any_bad = __syncthreads_or(bad);
+    if (threadIdx.x == 0 && threadIdx.y == 0 && any_bad && flag[0] == 0) flag[0] = 1;
 }
 
 // ---------------------------------------------------------------- preconditioner glue

@@ -1196,11 +1196,10 @@ stokes_status setup_impl(stokes_ctx &c, const double *const rho[3], const double
         c.v_clear = c.z_clear = 0;
     }
     for (int a = 0; a < DIM; ++a) {
-        k_pack<<<nblocks_rows(b), dim3(64, kPackRows), 0, c.stream>>>(b, a, 2, 0, 1.0 / c.dt, rho[a], c.mass[a], nullptr);
-        k_pack<<<nblocks_rows(b), dim3(64, kPackRows), 0, c.stream>>>(b, a, 1, 0, 1.0, rho[a], c.beta[a], nullptr);
+        k_pack_rho<<<nblocks_rows(b), dim3(64, kPackRows), 0, c.stream>>>(b, a, 1.0 / c.dt, rho[a], c.mass[a],
+                                                                          c.beta[a], c.dflag);
     }
-    k_pack<<<nblocks_rows(b), dim3(64, kPackRows), 0, c.stream>>>(b, 3, 0, 0, 1.0, mu, c.mu, nullptr);
-    k_check_coef<<<gb, kBlock, 0, c.stream>>>(b, c.mass[0], c.mass[1], DIM == 3 ? c.mass[2] : c.mass[1], c.mu, c.dflag);
+    k_pack<<<nblocks_rows(b), dim3(64, kPackRows), 0, c.stream>>>(b, 3, 0, 0, 1.0, mu, c.mu, c.dflag, 1);
     int flag = 0;
     HIPCHK(hipMemcpyAsync(&flag, c.dflag, sizeof(int), hipMemcpyDeviceToHost, c.stream));
     HIPCHK(hipStreamSynchronize(c.stream));
@@ -1260,8 +1259,9 @@ stokes_status setup_impl(stokes_ctx &c, const double *const rho[3], const double
 template <int DIM>
 void pack_vector(stokes_ctx &c, const double *const u[3], const double *p, double *vb, int *flag = nullptr) {
     const Box &b = c.fine;
-    for (int a = 0; a < DIM; ++a) k_pack<<<nblocks_rows(b), dim3(64, kPackRows), 0, c.stream>>>(b, a, 0, 0, 1.0, u[a], c.fld(vb, a), flag);
-    k_pack<<<nblocks_rows(b), dim3(64, kPackRows), 0, c.stream>>>(b, 3, 0, 0, 1.0, p, c.fld(vb, DIM), flag);
+    for (int a = 0; a < DIM; ++a)
+        k_pack<<<nblocks_rows(b), dim3(64, kPackRows), 0, c.stream>>>(b, a, 0, 0, 1.0, u[a], c.fld(vb, a), flag, 0);
+    k_pack<<<nblocks_rows(b), dim3(64, kPackRows), 0, c.stream>>>(b, 3, 0, 0, 1.0, p, c.fld(vb, DIM), flag, 0);
 }
 
 template <int DIM>

@@ -184,6 +184,40 @@ def test_nonpositive_density_rejected():
     assert e.value.status == -1
 
 
+@pytest.mark.parametrize("case", ["rho_w_zero", "rho_u_nan", "rho_v_negative", "mu_negative", "mu_nan",
+                                  "rho_wall_zero_accepted"])
+def test_setup_checks_coefficients(case):
+    """Setup rejects (EINVAL) a density that is not > 0 or not finite on an interior
+    face of any component and a viscosity that is negative or not finite, before
+    anything else is built; wall-normal faces are not read, so a zero there is
+    accepted (3D)."""
+    import paper_1901_07892_amd as S
+    prob = W.config3(scale=8)
+    rho = [a.copy() for a in prob.rho_faces[:3]]
+    mu = prob.mu.copy()
+    if case == "rho_w_zero":
+        rho[2][3, 2, 1] = 0.0
+    elif case == "rho_u_nan":
+        rho[0][1, 2, 3] = np.nan
+    elif case == "rho_v_negative":
+        rho[1][-1, 4, -1] = -1.0
+    elif case == "mu_negative":
+        mu[-1, -1, -1] = -1e-3
+    elif case == "mu_nan":
+        mu[0, 0, 0] = np.nan
+    else:
+        rho[0][2, 3, 0] = 0.0            # x = 0 wall face
+        rho[2][-1, 1, 1] = 0.0           # z = top wall face
+    prob.rho_faces = rho + [None] * (3 - len(rho))
+    prob.mu = mu
+    if case == "rho_wall_zero_accepted":
+        solver_for(prob).close()
+        return
+    with pytest.raises(S.StokesError) as e:
+        solver_for(prob)
+    assert e.value.status == -1, e.value
+
+
 def test_small_workspace_rejected():
     import torch
     import paper_1901_07892_amd as S
