@@ -191,7 +191,8 @@ stokes_status stokes_solve(stokes_ctx *ctx, const double *const rhs_u[3], const 
 /* Measurement hook.  Kernel classes that can be timed: */
 enum {
     STOKES_PROF_MATVEC = 0,    /* fine-level K x and b - K x (k_apply3_z / k_apply) */
-    STOKES_PROF_P_SWEEP = 1,   /* fused 3D red-black pressure sweep on the finest level */
+    STOKES_PROF_P_SWEEP = 1,   /* fused 3D red-black pressure sweep on the finest level: 6 fields
+                                  (5 from a zero guess) + 1/8 field with a folded prolongation */
     STOKES_PROF_MULTIDOT = 2,  /* Arnoldi inner products, up to 8 vectors per launch */
     STOKES_PROF_MAXPY = 3      /* Arnoldi vector updates, up to 8 vectors per launch */
 };

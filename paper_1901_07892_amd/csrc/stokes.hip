@@ -422,8 +422,10 @@ void p_sweep3_launch(stokes_ctx &c, Level<R> &L, const R *in, R *out, const R *r
     while (kc > 8 && (long long)gx * gy * ((b.nz + kc - 1) / kc) < min_blocks) kc = (kc + 1) / 2;
     int gz = (b.nz + kc - 1) / kc;
     const double cells = (double)b.nx * b.ny * b.nz;
-    // old and new iterate, right-hand side, three face coefficients (+ coarse correction)
-    ProfScope ps(c, STOKES_PROF_P_SWEEP, cells * sizeof(R) * (6.0 + (ec ? 0.125 : 0.0)), b.nx == c.fine.nx);
+    // new iterate, right-hand side, three face coefficients, the old iterate unless
+    // the sweep starts from zero (+ 1/8 field for a folded coarse correction)
+    ProfScope ps(c, STOKES_PROF_P_SWEEP, cells * sizeof(R) * ((zero_guess ? 5.0 : 6.0) + (ec ? 0.125 : 0.0)),
+                 b.nx == c.fine.nx);
     if (PIPE)
         k_p_sweep3<R, TX, TY><<<dim3(gx, gy, gz), TX * TY, 0, c.stream>>>(
             b, kc, zero_guess ? 1 : 0, in, ec, cb ? *cb : b, c.opt.p_prolong, out, r, L.beta[0], L.beta[1], L.beta[2]);
