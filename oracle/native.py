@@ -43,6 +43,8 @@ def lib():
         L.oracle_solve.restype = C.c_int
         L.oracle_precond.argtypes = [C.c_int, ip, dp, C.c_double, C.c_double, pp, dp, ip, pp, pp]
         L.oracle_precond.restype = C.c_int
+        L.oracle_auto_sigma.argtypes = [C.c_int, ip, dp, C.c_double, C.c_double, pp, dp, dp]
+        L.oracle_auto_sigma.restype = C.c_int
         L.oracle_num_threads.argtypes = []
         L.oracle_num_threads.restype = C.c_int
         L.oracle_set_threads.argtypes = [C.c_int]
@@ -136,6 +138,17 @@ def precond(dim, n, h, dt, theta, rho_faces, mu, ru, rp, **opts):
     if rc != 0:
         raise ValueError("oracle_precond failed")
     return zs[:3], zs[3]
+
+
+def auto_sigma(prob, theta=1.0) -> float:
+    """The oracle's continuity weight of the residual norm for a ``workloads.Problem``."""
+    rho = [_c(r) for r in (list(prob.rho_faces[:prob.dim]) + [None] * 3)[:3]]
+    ni, hd = _grid_args(prob.dim, prob.n, prob.h)
+    out = C.c_double()
+    rc = lib().oracle_auto_sigma(prob.dim, ni, hd, prob.dt, theta, _parr(rho), _dp(_c(prob.mu)), C.byref(out))
+    if rc != 0:
+        raise ValueError("oracle_auto_sigma failed")
+    return out.value
 
 
 def num_threads() -> int:

@@ -897,6 +897,21 @@ int oracle_apply(int dim, const int *n, const double *h, double dt, double theta
     return 0;
 }
 
+/* The continuity weight auto_sigma picks for these coefficients (*out). */
+int oracle_auto_sigma(int dim, const int *n, const double *h, double dt, double theta,
+                      double *const rho[3], const double *mu, double *out) {
+    Grid g;
+    if (make_grid(&g, dim, n, h)) return -1;
+    Level L;
+    memset(&L, 0, sizeof(L));
+    L.g = g;
+    L.nu = n_u(&g); L.nv = n_v(&g); L.nw = n_w(&g); L.nc = n_c(&g);
+    for (int a = 0; a < 3; ++a) L.rho[a] = a < dim ? rho[a] : NULL;
+    L.mu = (double *)mu;
+    *out = auto_sigma(&L, dt, theta);
+    return 0;
+}
+
 /* Solve K x = (f, g) to ||b - K x||_s <= tol ||b||_s, where ||(a, c)||_s^2 =
  * ||a||^2 + sigma^2 ||c||^2 weights the continuity rows (cont_scale > 0 gives
  * sigma; 0 picks auto_sigma; 1 is the plain 2-norm).  x holds the initial guess
