@@ -176,8 +176,10 @@ stokes_status stokes_apply(stokes_ctx *ctx, const double *const x_u[3], const do
  * theta * max(mu) * (pi/l)^2.  This balances the momentum rows (scale rho/dt)
  * against the continuity rows (scale 1/h) at the slowest pressure mode; in the
  * plain 2-norm the system's condition number is near 1e14 and the pressure is
- * barely determined.  With rhs_p = 0, convergence in this norm implies
- * convergence in the plain 2-norm.
+ * barely determined.  With rhs_p = 0 and sigma >= 1 (every workload here has
+ * sigma > 1e4), convergence in this norm implies convergence in the plain
+ * 2-norm (stats->rel_res_plain reports it either way); with sigma < 1 the
+ * continuity rows are under-weighted and the plain residual can exceed tol.
  * The mean of rhs_p (incompatible with walls everywhere) is removed first and
  * reported in stats->g_mean.  x holds the initial guess on entry (its wall
  * entries ignored) and the solution on exit (p with zero mean); the residual is
@@ -233,7 +235,7 @@ stokes_status stokes_stream_copy(const double *src, double *dst, long long n, vo
  * it: the mean of its two cells, or the one cell of a boundary face (every
  * face of the output arrays is written, wall faces included).
  * rho_flow_face, if not NULL, receives the flowing-phase density alone (no
- * solid) on the same faces, as the well-balanced gravity force needs (Sec. 4.3).
+ * solid) on the same faces, as the well-balanced gravity force needs (Sec. 5).
  * --------------------------------------------------------------------------- */
 #define STOKES_MAX_SOLIDS 8
 
@@ -264,7 +266,7 @@ stokes_status stokes_coefficients(const stokes_grid *grid, const stokes_fluids *
 /* ---------------------------------------------------------------------------
  * Explicit momentum right-hand side of one time step (Sec. 4.2.2,
  * eq_nc_discrete_momentum, and eq_c_discrete_momentum with the old density;
- * Sec. 4.3 for the gravity force):
+ * Sec. 5 for the gravity force):
  *
  *     f = (rho/dt) u^n + (1 - theta) L_mu u^n + rho_force g   on interior faces,
  *
@@ -407,6 +409,46 @@ stokes_status stokes_attach_learned(stokes_ctx *ctx, stokes_unet *net, double st
  * and scaled to zero mean and unit RMS (phi_c).  Blocks until done. */
 stokes_status stokes_learned_tuple(stokes_ctx *ctx, const double *const rhs_u[3], const double *rhs_p, int n,
                                    int cycles, float *f0, float *f1, float *s_c, float *phi_c);
+
+/* ---------------------------------------------------------------------------
+ * Test hook: one kernel of the pressure multigrid on the finest level, run on
+ * caller data exactly as the cycle launches it.  The operator is the pressure
+ * Poisson operator of the projection step, -L_rho = -D beta G with beta =
+ * 1/rho on interior faces and Neumann walls (Sec. 4.2.4 names the projection
+ * preconditioner; the multigrid is this library's subsolve for it).
+ *   STOKES_POP_SWEEP          one red-black Gauss-Seidel sweep of -L_rho e = r
+ *                             (cells with i+j+k even first, then odd), in the
+ *                             form the cycle uses on this level: the fused
+ *                             z-marching kernel on 3D levels of more than 2^18
+ *                             cells, two colour passes otherwise;
+ *   STOKES_POP_SWEEP_FLAT     the same sweep as two one-thread-per-point passes;
+ *   STOKES_POP_RESTRICT       out (cells of the next-coarser level) = the mean
+ *                             over the 2^d children of r - (-L_rho) e, in the
+ *                             cycle's form (z-marching on 3D levels of at least
+ *                             2^21 cells);
+ *   STOKES_POP_RESTRICT_FLAT  the same with the one-thread-per-coarse-cell kernel.
+ * e_in, r   device cell arrays (Nz, Ny, Nx) of the grid; e_in NULL starts a
+ *           sweep from zero
+ * ec        NULL, or (sweeps with e_in only) a device cell array of the
+ *           next-coarser level whose prolongation (piecewise constant, or
+ *           trilinear with p_prolong = 1) is added to e_in before the sweep, as
+ *           the cycle does after its coarse-grid correction
+ * out       device cell array of the fine level (sweeps) or the next-coarser
+ *           level (restriction)
+ * With FP32 multigrid the inputs are rounded to float on the way in and the
+ * result widened on the way out.  Uses the context's level buffers (not
+ * concurrently with a solve on the same context); blocks until done.  EINVAL for
+ * an unknown op, a missing pointer, ec without e_in, or a coarse operand on a
+ * grid that has no coarser level; EHIP if a HIP call fails.
+ * --------------------------------------------------------------------------- */
+enum {
+    STOKES_POP_SWEEP = 0,
+    STOKES_POP_SWEEP_FLAT = 1,
+    STOKES_POP_RESTRICT = 2,
+    STOKES_POP_RESTRICT_FLAT = 3
+};
+stokes_status stokes_pressure_op(stokes_ctx *ctx, int op, const double *e_in, const double *r, const double *ec,
+                                 double *out);
 
 /* Release the host-side context (the workspace stays the caller's). NULL is a no-op. */
 void stokes_destroy(stokes_ctx *ctx);

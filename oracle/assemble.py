@@ -321,7 +321,7 @@ def explicit_rhs(g: OGrid, rho_faces: Sequence[np.ndarray], mu_cell: np.ndarray,
     on every interior face (0 on wall-normal faces), where L_mu is the same
     strain-rate operator as in the system matrix (built here from ``mu_cell``,
     the old viscosity) and rho_force is the density of the gravity force (the
-    flow-only density for the well-balanced form, Sec. 4.3).  The convective
+    flow-only density for the well-balanced form, Sec. 5).  The convective
     term is the caller's.
     """
     asm = Assembler(g)

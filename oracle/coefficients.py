@@ -20,7 +20,7 @@ What is computed (plain definitions, FP64, vectorised numpy):
   an interior face taking the mean of its two cells and a boundary face the
   one cell it touches (a mirror ghost);
 * the flow-only face density (no solid), which the well-balanced gravity
-  force uses (Sec. 4.3).
+  force uses (Sec. 5).
 
 Layouts are C order with x fastest: cell fields (Nz, Ny, Nx), x-faces
 (Nz, Ny, Nx+1), y-faces (Nz, Ny+1, Nx), z-faces (Nz+1, Ny, Nx).  In 2D

@@ -143,6 +143,8 @@ def load_library():
     L.stokes_attach_learned.restype = C.c_int
     L.stokes_learned_tuple.argtypes = [C.c_void_p, C.c_void_p * 3, dp, C.c_int, C.c_int, dp, dp, dp, dp]
     L.stokes_learned_tuple.restype = C.c_int
+    L.stokes_pressure_op.argtypes = [C.c_void_p, C.c_int, dp, dp, dp, dp]
+    L.stokes_pressure_op.restype = C.c_int
     _lib = L
     return L
 
@@ -248,6 +250,19 @@ def stokes_profile_read(ctx):
     ms, n, b = C.c_double(), C.c_longlong(), C.c_double()
     load_library().stokes_profile_read(ctx, C.byref(ms), C.byref(n), C.byref(b))
     return ms.value, n.value, b.value
+
+
+POP_SWEEP, POP_SWEEP_FLAT, POP_RESTRICT, POP_RESTRICT_FLAT = 0, 1, 2, 3
+
+
+def stokes_pressure_op(ctx, op: int, e_in, r, ec, out) -> None:
+    """One pressure-multigrid kernel of the finest level on caller cell arrays
+    (device float64 tensors; ``e_in`` None = from zero, ``ec`` None = no coarse
+    correction).  Blocks until done."""
+    L = load_library()
+    st = L.stokes_pressure_op(ctx, int(op), _ptr(e_in), _ptr(r), _ptr(ec), _ptr(out))
+    if st != 0:
+        raise StokesError(st, L.stokes_last_error(ctx).decode())
 
 
 def stokes_stream_copy(src, dst, stream=None) -> None:
@@ -366,6 +381,9 @@ class StokesSolver:
 
     def solve(self, rhs_u, rhs_p, tol, x_u, x_p):
         return stokes_solve(self.ctx, rhs_u, rhs_p, tol, x_u, x_p)
+
+    def pressure_op(self, op, e_in, r, ec, out):
+        return stokes_pressure_op(self.ctx, op, e_in, r, ec, out)
 
     def close(self):
         if self.ctx:

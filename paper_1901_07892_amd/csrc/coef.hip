@@ -10,7 +10,7 @@
 // cell centres from the cell level sets; density on each face from the level
 // sets averaged onto that face (Sec. 4.2.2), an interior face taking the mean
 // of its two cells and a boundary face the one cell it touches.  The flow-only
-// face density (no solid) that the well-balanced gravity force uses (Sec. 4.3)
+// face density (no solid) that the well-balanced gravity force uses (Sec. 5)
 // comes out of the same pass.
 //
 // One HBM-bound pass: each thread owns one (i, j) point of the

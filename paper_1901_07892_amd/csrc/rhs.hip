@@ -10,7 +10,7 @@
 // edge, out-of-domain cells mirrored; no-slip walls: wall-normal velocity zero,
 // tangential ghost = minus the interior value).  theta = 1/2 is the paper's
 // Crank-Nicolson split; rho_force is the flow-only density for the
-// well-balanced gravity force (Sec. 4.3).  The convective term is the caller's.
+// well-balanced gravity force (Sec. 5).  The convective term is the caller's.
 //
 // Two kernels: in 3D, a z-marching one with the old velocity and viscosity in a
 // three-plane LDS ring (k_explicit_rhs3_z, below); in 2D, one thread per point

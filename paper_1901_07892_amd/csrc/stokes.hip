@@ -446,6 +446,48 @@ void p_sweep3(stokes_ctx &c, Level<R> &L, const R *in, R *out, const R *r, bool 
         p_sweep3_launch<R, 32, 8, true>(c, L, in, out, r, zero_guess, ec, cb, 2048);
 }
 
+// Coarse right-hand side rc = average over the 2^d children of r - (-L_rho) e,
+// from level L to the next-coarser level C.  3D levels of at least 2^21 cells
+// use the z-marching kernel (each fine plane read once), the others (or all
+// with flat_only) the per-cell kernel; same formulas and summation order.
+template <int DIM, class R>
+void p_residual_restrict(stokes_ctx &c, const Level<R> &L, const Level<R> &C, const R *e, const R *r, R *rc,
+                         bool flat_only) {
+    const R *bz = DIM == 3 ? L.beta[2] : L.beta[1];
+    if (DIM == 3 && !flat_only && (long long)L.b.nx * L.b.ny * L.b.nz >= (1LL << 21)) {
+        constexpr int TX = 64, TY = 4;
+        const int gx = (C.b.nx + TX - 1) / TX, gy = (C.b.ny + TY - 1) / TY;
+        int kc = C.b.nz;
+        while (kc > 2 && (long long)gx * gy * ((C.b.nz + kc - 1) / kc) < 1024) kc = (kc + 1) / 2;
+        const int gz = (C.b.nz + kc - 1) / kc;
+        k_p_residual_restrict3_z<R, TX, TY><<<dim3(gx, gy, gz), TX * TY, 0, c.stream>>>(
+            L.b, C.b, kc, e, r, L.beta[0], L.beta[1], bz, rc);
+    } else {
+        k_p_residual_restrict<DIM, R><<<nblocks_box(C.b), kBlock, 0, c.stream>>>(L.b, C.b, e, r, L.beta[0], L.beta[1], bz, rc);
+    }
+}
+
+// One red-black Gauss-Seidel sweep of -L_rho e = r on level L, starting from
+// *cur (zero when zg; plus the prolonged coarse correction ec of level cb when
+// ec != nullptr).  Levels of at most 64^3 cells (and every 2D level, or all
+// with flat_only) take two flat colour passes in place; larger 3D levels the
+// fused z-marching kernel from *cur into *spare, after which the two pointers
+// are swapped, so *cur always names the array that holds the new iterate.
+template <int DIM, class R>
+void p_level_sweep(stokes_ctx &c, Level<R> &L, R *&cur, R *&spare, const R *r, bool zg, const R *ec, const Box *cb,
+                   bool flat_only) {
+    // levels of at most 64^3 cells are latency-bound: two flat colour passes beat
+    // a z-marching launch there
+    const bool flat = DIM == 2 || flat_only || (long long)L.b.nx * L.b.ny * L.b.nz <= (1LL << 18);
+    if (flat) {
+        if (ec) k_p_prolong_add<DIM, R><<<nblocks_box(L.b), kBlock, 0, c.stream>>>(L.b, *cb, c.opt.p_prolong, ec, cur);
+        p_smooth<DIM, R>(c, L, cur, r, 1, zg);
+        return;
+    }
+    p_sweep3<R>(c, L, cur, spare, r, zg, ec, cb);
+    std::swap(cur, spare);
+}
+
 // V-cycle on -L_rho e = r at level l.  Returns the array that holds the new
 // iterate: e itself, or (3D, after an odd number of fused sweeps) the level's
 // other buffer.
@@ -459,17 +501,8 @@ R *p_vcycle(stokes_ctx &c, MG<R> &mg, int l, R *e, R *r, bool zero_guess) {
     Level<R> &L = mg.L[l];
     R *cur = e;
     R *spare = (e == L.ep) ? L.ep2 : L.ep;
-    // Levels of at most 64^3 cells are latency-bound: two flat colour passes (in
-    // place) beat a z-marching launch there.
-    const bool flat = (long long)L.b.nx * L.b.ny * L.b.nz <= (1LL << 18);
     auto sweep = [&](bool zg, const R *ec, const Box *cb) {
-        if (flat) {
-            if (ec) k_p_prolong_add<DIM, R><<<nblocks_box(L.b), kBlock, 0, c.stream>>>(L.b, *cb, c.opt.p_prolong, ec, cur);
-            p_smooth<DIM, R>(c, L, cur, r, 1, zg);
-            return;
-        }
-        p_sweep3<R>(c, L, cur, spare, r, zg, ec, cb);
-        std::swap(cur, spare);
+        p_level_sweep<DIM, R>(c, L, cur, spare, r, zg, ec, cb, false);
     };
     if (l == mg.nlev - 1) {
         if (mg.use_dense) {
@@ -490,19 +523,7 @@ R *p_vcycle(stokes_ctx &c, MG<R> &mg, int l, R *e, R *r, bool zero_guess) {
         p_smooth<DIM, R>(c, L, cur, r, nu1, zero_guess);
     }
     Level<R> &C = mg.L[l + 1];
-    const R *bz = DIM == 3 ? L.beta[2] : L.beta[1];
-    if (DIM == 3 && (long long)L.b.nx * L.b.ny * L.b.nz >= (1LL << 21)) {
-        // z-marching form: each fine plane read once
-        constexpr int TX = 64, TY = 4;
-        const int gx = (C.b.nx + TX - 1) / TX, gy = (C.b.ny + TY - 1) / TY;
-        int kc = C.b.nz;
-        while (kc > 2 && (long long)gx * gy * ((C.b.nz + kc - 1) / kc) < 1024) kc = (kc + 1) / 2;
-        const int gz = (C.b.nz + kc - 1) / kc;
-        k_p_residual_restrict3_z<R, TX, TY><<<dim3(gx, gy, gz), TX * TY, 0, c.stream>>>(
-            L.b, C.b, kc, cur, r, L.beta[0], L.beta[1], bz, C.rp);
-    } else {
-        k_p_residual_restrict<DIM, R><<<nblocks_box(C.b), kBlock, 0, c.stream>>>(L.b, C.b, cur, r, L.beta[0], L.beta[1], bz, C.rp);
-    }
+    p_residual_restrict<DIM, R>(c, L, C, cur, r, C.rp, false);
     R *ce = p_vcycle<DIM, R>(c, mg, l + 1, C.ep, C.rp, true);
     // W-cycle (p_gamma = 2): a second coarse cycle on the same coarse equation
     // (pointless above the exactly solved coarsest level)
@@ -1403,6 +1424,57 @@ void learned_tuple(stokes_ctx &c, MG<R> &mg, int lc, int cycles, float *f0, floa
     learned_static<R>(c, mg, lc, f0, f1);
 }
 
+// One pressure-multigrid kernel of the finest level on caller data (the test
+// hook stokes_pressure_op): the caller's cell arrays are packed into the level's
+// arrays (through an FP64 staging field and a cast with FP32 multigrid), the
+// kernel runs as the cycle launches it (or in its flat form), and the result is
+// unpacked into the caller's cell layout.
+template <int DIM, class R>
+void pressure_op(stokes_ctx &c, MG<R> &mg, int op, const double *e_in, const double *r_in, const double *ec_in,
+                 double *out) {
+    Level<R> &L = mg.L[0];
+    double *stage = c.q - c.fine.guard;     // one FP64 field of the fine box, guards included
+    auto load = [&](const Box &b, const double *src, R *dst) {
+        if constexpr (sizeof(R) == sizeof(double)) {
+            k_pack<<<nblocks_rows(b), dim3(64, kPackRows), 0, c.stream>>>(b, 3, 0, 0, 1.0, src,
+                                                                          reinterpret_cast<double *>(dst), nullptr, 0);
+        } else {
+            fill<double>(c, stage, b.stride, 0.0);
+            k_pack<<<nblocks_rows(b), dim3(64, kPackRows), 0, c.stream>>>(b, 3, 0, 0, 1.0, src, stage + b.guard,
+                                                                          nullptr, 0);
+            k_cast<double, R><<<nblocks_stream(b.stride), kBlock, 0, c.stream>>>(b.stride, stage, dst - b.guard);
+        }
+    };
+    auto store = [&](const Box &b, const R *src, double *dst) {
+        if constexpr (sizeof(R) == sizeof(double)) {
+            k_unpack<<<nblocks_rows(b), dim3(64, kPackRows), 0, c.stream>>>(b, 3, reinterpret_cast<const double *>(src), dst);
+        } else {
+            k_cast<R, double><<<nblocks_stream(b.stride), kBlock, 0, c.stream>>>(b.stride, src - b.guard, stage);
+            k_unpack<<<nblocks_rows(b), dim3(64, kPackRows), 0, c.stream>>>(b, 3, stage + b.guard, dst);
+        }
+    };
+    const bool flat = op == STOKES_POP_SWEEP_FLAT || op == STOKES_POP_RESTRICT_FLAT;
+    load(L.b, r_in, L.rp);
+    if (e_in) load(L.b, e_in, L.ep);
+    if (op == STOKES_POP_SWEEP || op == STOKES_POP_SWEEP_FLAT) {
+        const R *ec = nullptr;
+        const Box *cb = nullptr;
+        if (ec_in) {
+            Level<R> &C = mg.L[1];
+            load(C.b, ec_in, C.ep);
+            ec = C.ep;
+            cb = &C.b;
+        }
+        R *cur = L.ep, *spare = L.ep2;
+        p_level_sweep<DIM, R>(c, L, cur, spare, L.rp, e_in == nullptr, ec, cb, flat);
+        store(L.b, cur, out);
+    } else {
+        Level<R> &C = mg.L[1];
+        p_residual_restrict<DIM, R>(c, L, C, L.ep, L.rp, C.rp, flat);
+        store(C.b, C.rp, out);
+    }
+}
+
 }  // namespace
 
 // ====================================================================== C-ABI
@@ -1625,6 +1697,35 @@ stokes_status stokes_learned_tuple(stokes_ctx *ctx, const double *const rhs_u[3]
         pack_vector<3>(*ctx, rhs_u, rhs_p, ctx->bk);
         if (ctx->opt.precision == 1) learned_tuple<float>(*ctx, ctx->mgf, lc, cycles, f0, f1, s_c, phi_c);
         else learned_tuple<double>(*ctx, ctx->mgd, lc, cycles, f0, f1, s_c, phi_c);
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        HIPCHK(hipGetLastError());
+    } catch (const HipError &e) {
+        ctx->err = std::string("HIP error in ") + e.what + ": " + hipGetErrorString(e.e);
+        return STOKES_EHIP;
+    }
+    return STOKES_OK;
+}
+
+stokes_status stokes_pressure_op(stokes_ctx *ctx, int op, const double *e_in, const double *r, const double *ec,
+                                 double *out) {
+    if (!ctx) return STOKES_EINVAL;
+    ctx->err.clear();
+    if (op < STOKES_POP_SWEEP || op > STOKES_POP_RESTRICT_FLAT) { ctx->err = "unknown op"; return STOKES_EINVAL; }
+    const bool restrict_op = op == STOKES_POP_RESTRICT || op == STOKES_POP_RESTRICT_FLAT;
+    if (!r || !out || (restrict_op && (!e_in || ec)) || (ec && !e_in)) {
+        ctx->err = "bad array pointers for this op";
+        return STOKES_EINVAL;
+    }
+    const int nlev = ctx->opt.precision == 1 ? ctx->mgf.nlev : ctx->mgd.nlev;
+    if ((restrict_op || ec) && nlev < 2) { ctx->err = "the grid has no coarser level"; return STOKES_EINVAL; }
+    try {
+        if (ctx->dim == 3) {
+            if (ctx->opt.precision == 1) pressure_op<3, float>(*ctx, ctx->mgf, op, e_in, r, ec, out);
+            else pressure_op<3, double>(*ctx, ctx->mgd, op, e_in, r, ec, out);
+        } else {
+            if (ctx->opt.precision == 1) pressure_op<2, float>(*ctx, ctx->mgf, op, e_in, r, ec, out);
+            else pressure_op<2, double>(*ctx, ctx->mgd, op, e_in, r, ec, out);
+        }
         HIPCHK(hipStreamSynchronize(ctx->stream));
         HIPCHK(hipGetLastError());
     } catch (const HipError &e) {

@@ -146,7 +146,7 @@ def test_device_coefficients_feed_the_solver():
 
 
 def test_well_balanced_tank_from_device_coefficients():
-    """Sec. 4.3's well-balanced gravity in 3D, built on the device end to end:
+    """Sec. 5's well-balanced gravity in 3D, built on the device end to end:
     the coefficient step gives rho (with the solid) for the operator and the
     flow-only rho for the force f_z = rho_flow g; the solve must return u = 0
     and the discrete hydrostatic pressure p_k - p_(k-1) = hz rho_flow(z-face k) g.

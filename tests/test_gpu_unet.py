@@ -144,46 +144,59 @@ def test_learned_tuple_normalisation():
 
 
 @pytest.mark.parametrize("stall", [0.9, 0.0])
-def test_learned_form_reaches_fp64_tolerance(stall):
+def test_learned_form_matches_oracle(oracle_lib, stall):
     """An untrained network attached as the learned stage: the FP64 residual check
-    still decides convergence, the answer matches the plain solve, and with
-    stall_ratio 0 the fallback to plain multigrid is taken and reported."""
+    still decides convergence, the answer matches the oracle's FGMRES solution at
+    tol 1e-13 (relative L2 <= 1e-9 per field), and with stall_ratio 0 the fallback
+    to plain multigrid is taken and reported."""
     import workloads as W
     import paper_1901_07892_amd as S
-    from tests.gpu_util import gpu_solve, rel
+    from tests.gpu_util import rel
     prob = W.config5(n_cells=64, seed=7)
+    print("learned form vs oracle", prob.n, "stall", stall, flush=True)
+    ou, op, info = oracle_lib.solve_problem(prob, tol=1e-13, max_iters=400)
+    assert info["status"] == 0 or info["rel_res_true"] <= 1e-12, info
     net = S.UNet(32, seed=1)
-    s = _learned_solver(prob, net, stall)
-    xu, xp, st, stats = _solve_with(s, prob, 1e-10)
-    assert st == 0 and stats.rel_res_true <= 1e-10, stats.as_dict()
+    s = _learned_solver(prob, net, stall, max_iters=400)
+    xu, xp, st, stats = _solve_with(s, prob, 1e-13)
+    print("  learned(untrained) status %d iters %d res %.2e fell_back %d; oracle iters %d" %
+          (st, stats.iters, stats.rel_res_true, stats.fell_back, info["iters"]), flush=True)
+    assert st == 0 or (st == 1 and stats.rel_res_true <= 1e-12), stats.as_dict()
     if stall == 0.0:
         assert stats.fell_back == 1
-    ru, rp, st2, stats2 = gpu_solve(prob, tol=1e-10)
-    for c in range(3):
-        assert rel(xu[c], ru[c]) <= 1e-6
-    assert rel(xp, rp) <= 1e-6
-    print("learned(untrained) iters %d fell_back %d; plain iters %d" % (stats.iters, stats.fell_back, stats2.iters))
+    errs = [rel(xu[c], ou[c]) for c in range(3)] + [rel(xp - xp.mean(), op - op.mean())]
+    print("  rel errors per field", ["%.2e" % e for e in errs], flush=True)
+    assert max(errs) <= 1e-9, errs
     s.close()
     net.close()
 
 
-def test_trained_learned_form_on_headline_recipe():
-    """With the committed trained weights: the learned form converges to tol on a
-    fresh 128^3 instance (seed outside the training range)."""
+def test_trained_learned_form_on_headline_instance(oracle_lib):
+    """With the committed trained weights, on the 256^3 headline instance at tol 1e-8:
+    the learned form converges, and the oracle's operator with its own continuity
+    weight confirms the residual in the weighted and the plain 2-norm."""
     import workloads as W
     import paper_1901_07892_amd as S
     from paper_1901_07892_amd import learned
-    from tests.gpu_util import gpu_solve
     p, meta = learned.load_params()
     if p is None:
         pytest.skip("no trained weights in the package")
-    prob = W.config5(n_cells=128, seed=900001)
+    prob = W.config5()
+    print("trained learned form", prob.n, flush=True)
     net = S.UNet(32)
     net.set_params(p)
     s = _learned_solver(prob, net)
     xu, xp, st, stats = _solve_with(s, prob, prob.tol)
+    print("  status %d iters %d res %.2e fell_back %d" % (st, stats.iters, stats.rel_res_true, stats.fell_back),
+          flush=True)
     assert st == 0 and stats.rel_res_true <= prob.tol
-    _, _, _, plain = gpu_solve(prob)
-    print("trained learned form: iters %d (plain %d), fell_back %d" % (stats.iters, plain.iters, stats.fell_back))
+    sigma = oracle_lib.auto_sigma(prob)
+    yu, yp = oracle_lib.apply_problem(prob, xu, xp)
+    r2 = sum(np.sum((prob.rhs_u[c] - yu[c]) ** 2) for c in range(3))
+    b2 = sum(np.sum(prob.rhs_u[c] ** 2) for c in range(3))
+    rp2 = np.sum(yp ** 2)                                   # rhs_p = 0
+    plain, weighted = np.sqrt((r2 + rp2) / b2), np.sqrt((r2 + sigma ** 2 * rp2) / b2)
+    print("  oracle residual plain %.2e weighted %.2e" % (plain, weighted), flush=True)
+    assert plain <= prob.tol and weighted <= 1.01 * prob.tol
     s.close()
     net.close()
