@@ -127,10 +127,13 @@ ORACLE_CASES = [
     ("config5_64", lambda: W.config5(n_cells=64)),
     # finest level of 884,736 cells: the pipelined fused sweep (levels between 2^18 and 2^20 cells)
     ("config5_96", lambda: W.config5(n_cells=96)),
-    # the stated sizes of configs 3 and 4: the finest levels run the 64x16 fused sweep and
-    # the z-marching residual + restriction, and 128^3 / 512x48x48 the fused sweep too
+    # config 3 at its stated 128^3: the finest level runs the 64x16 fused sweep and the
+    # z-marching residual + restriction
     ("config3_128", lambda: W.config3()),
-    ("config4_1024x96x96", lambda: W.config4()),
+    # config 4's geometry at half its stated size per axis (1,179,648 cells: the 64x16
+    # fused sweep on the finest level); the stated size is checked below by the
+    # oracle's operator, as its oracle FGMRES at tol 1e-13 takes minutes of host time
+    ("config4_512x48x48", lambda: W.config4(scale=2)),
 ]
 
 
@@ -161,9 +164,24 @@ def _oracle_residuals(oracle_lib, prob, xu, xp):
     return plain, weighted, sigma
 
 
+def test_config4_full_size_residual_by_oracle(oracle_lib):
+    """Config 4 at its stated 1024x96x96, FP64 at tol 1e-13: the oracle's operator and
+    its own continuity weight confirm the residual of the GPU solution in both norms
+    (with the kernel-level parity at this size in test_gpu_pressure_ops.py)."""
+    prob = W.config4()
+    print("config 4 full size", prob.n, flush=True)
+    xu, xp, st, stats = gpu_solve(prob, tol=1e-13, max_iters=400)
+    print("  status", st, "iters", stats.iters, "res", stats.rel_res_true, flush=True)
+    _converged_or_stagnated(st, stats)
+    plain, weighted, _ = _oracle_residuals(oracle_lib, prob, xu, xp)
+    print("  oracle residual plain %.2e weighted %.2e" % (plain, weighted), flush=True)
+    assert plain <= 1e-12 and weighted <= 1e-12
+
+
 FP32_CASES = [
     ("config2_512", lambda: W.config2()),
     ("config3_128", lambda: W.config3()),
+    ("config4_512x48x48", lambda: W.config4(scale=2)),
     ("config4_1024x96x96", lambda: W.config4()),
 ]
 
@@ -177,6 +195,8 @@ def test_fp32_multigrid_at_stated_sizes(oracle_lib, name, maker):
     print("FP32 multigrid", name, prob.n, "tol", prob.tol, flush=True)
     if prob.dim == 2:
         ru, rp = D.solve_problem(prob, A.from_problem(prob))
+    elif name == "config4_1024x96x96":
+        ru = rp = None           # residual only at the stated size (see above)
     else:
         ru, rp, _ = _oracle_solution(oracle_lib, name, prob)
     xu, xp, st, stats = gpu_solve(prob, precision=1)
@@ -185,6 +205,8 @@ def test_fp32_multigrid_at_stated_sizes(oracle_lib, name, maker):
     plain, weighted, _ = _oracle_residuals(oracle_lib, prob, xu, xp)
     print("  oracle residual plain %.2e weighted %.2e" % (plain, weighted), flush=True)
     assert plain <= 1.01 * prob.tol and weighted <= 1.01 * prob.tol
+    if ru is None:
+        return
     errs = [rel(xu[c], ru[c]) for c in range(prob.dim)] + [rel(xp - xp.mean(), rp - rp.mean())]
     print("  FP32 multigrid: rel error per field vs the oracle's FP64 solution",
           ["%.2e" % e for e in errs], flush=True)
