@@ -336,6 +336,27 @@ stokes_status stokes_rigid_projection(const stokes_grid *grid, double *const u[3
                                       const double *X, double dV, int free_body, stokes_body *body,
                                       void *workspace, size_t ws_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * projection as stokes_rigid_projection, same arguments and results, without a
+ * workspace.  Its scratch (the interpolated marker velocities and the block
+ * partials of the momentum sums) is a fixed array inside the library, one per
+ * GPU, held until the process ends: 8 * (3 * STOKES_RIGID_NOALLOC_MAX_MARKERS +
+ * 13 * 1024) bytes, about 12.7 MB.  The call allocates nothing (no hipMalloc,
+ * hipFree or host heap); it reads the array's device address once per GPU with
+ * hipGetSymbolAddress, on the current device, which must be the device of u, X
+ * and stream.  Every entry of the scratch is written before it is read, so
+ * nothing carries over between calls; but calls that overlap on one GPU (other
+ * host threads, other streams) share the array and race: serialise them.
+ * ENOMEM (with stokes_last_error(NULL) naming the limit) for more than
+ * STOKES_RIGID_NOALLOC_MAX_MARKERS markers, before any GPU work; the other
+ * errors as for stokes_rigid_projection, EHIP also if the symbol address cannot
+ * be read. */
+#define STOKES_RIGID_NOALLOC_MAX_MARKERS 524288
+stokes_status stokes_rigid_projection_noalloc(const stokes_grid *grid, double *const u[3], long long n_markers,
+                                              const double *X, double dV, int free_body, stokes_body *body,
+                                              void *stream);
+
 /* ---------------------------------------------------------------------------
  * Learned form: a 4-level 3D U-Net (channels 16/32/48/64, 3x3x3 convolutions,
  * ReLU, 2x2x2 average pooling, nearest upsampling, additive skips) in BF16 with
@@ -454,7 +475,8 @@ stokes_status stokes_pressure_op(stokes_ctx *ctx, int op, const double *e_in, co
 void stokes_destroy(stokes_ctx *ctx);
 
 /* Message describing the last failure on this context ("" if none).  With
- * ctx == NULL, the message of the last failed stokes_setup in this thread. */
+ * ctx == NULL, the message of the last failed stokes_setup (or
+ * stokes_rigid_projection_noalloc) in this thread. */
 const char *stokes_last_error(const stokes_ctx *ctx);
 
 #ifdef __cplusplus

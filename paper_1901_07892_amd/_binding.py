@@ -114,6 +114,9 @@ def load_library():
     L.stokes_rigid_projection.argtypes = [C.POINTER(StokesGrid), C.c_void_p * 3, C.c_longlong, dp, C.c_double,
                                           C.c_int, C.POINTER(StokesBody), dp, C.c_size_t, dp]
     L.stokes_rigid_projection.restype = C.c_int
+    L.stokes_rigid_projection_noalloc.argtypes = [C.POINTER(StokesGrid), C.c_void_p * 3, C.c_longlong, dp,
+                                                  C.c_double, C.c_int, C.POINTER(StokesBody), dp]
+    L.stokes_rigid_projection_noalloc.restype = C.c_int
     L.stokes_unet_param_count.argtypes = []
     L.stokes_unet_param_count.restype = C.c_longlong
     L.stokes_unet_forward_flops.argtypes = [C.c_int]
@@ -347,6 +350,21 @@ def stokes_rigid_projection(grid, u, X, dV, free_body, body, workspace, stream=N
                                    _stream(stream))
     if st < 0:
         raise StokesError(st, "stokes_rigid_projection failed")
+    return body
+
+
+RIGID_NOALLOC_MAX_MARKERS = 524288
+
+
+def stokes_rigid_projection_noalloc(grid, u, X, dV, free_body, body, stream=None) -> StokesBody:
+    """stokes_rigid_projection without a workspace (the library's fixed scratch)."""
+    L = load_library()
+    n = int(X.shape[0]) if X is not None else 0
+    st = L.stokes_rigid_projection_noalloc(C.byref(grid), _ptr3(list(u) + [None] * 3), n,
+                                           _ptr(X) if n else None, float(dV), int(bool(free_body)), C.byref(body),
+                                           _stream(stream))
+    if st < 0:
+        raise StokesError(st, "stokes_rigid_projection_noalloc failed: " + L.stokes_last_error(None).decode())
     return body
 
 

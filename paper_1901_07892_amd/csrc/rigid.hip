@@ -27,7 +27,10 @@
 
 #include <algorithm>
 #include <cmath>
-#include <vector>
+#include <mutex>
+
+// Sets the message stokes_last_error(NULL) returns in this thread (stokes.hip).
+void stk_set_thread_error(const char *msg);
 
 namespace {
 
@@ -197,22 +200,45 @@ __global__ void __launch_bounds__(kRigidBlock) k_rigid_spread(RigidGrid g, long 
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
-}  // namespace
+// Host copy of the block partials (per thread, so that no call allocates).
+thread_local double t_partials[kRigidMaxBlocks * kSums];
 
-extern "C" size_t stokes_rigid_workspace_size(int dim, long long n_markers) {
-    if ((dim != 2 && dim != 3) || n_markers < 0) return 0;
-    const long long blocks = std::min<long long>(std::max<long long>((n_markers + kRigidBlock - 1) / kRigidBlock, 1),
-                                                 kRigidMaxBlocks);
-    return (size_t)(n_markers * dim + blocks * kSums) * sizeof(double);
+// Scratch of the allocation-free entry point: the interpolated marker
+// velocities (n_markers x dim) and the block partials, in a file-scope device
+// array that every GPU the library runs on holds until the process ends.  Host
+// code never uses the array's name as an address: each device's address comes
+// from hipGetSymbolAddress, taken once per device with that device current.
+constexpr long long kScratchMarkers = STOKES_RIGID_NOALLOC_MAX_MARKERS;
+constexpr size_t kScratchDoubles = (size_t)kScratchMarkers * 3 + (size_t)kRigidMaxBlocks * kSums;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t scratch_of_current_device(double **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = static_cast<double *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
 }
 
-extern "C" stokes_status stokes_rigid_projection(const stokes_grid *grid, double *const u[3], long long n_markers,
-        const double *X, double dV, int free_body, stokes_body *body, void *workspace, size_t ws_bytes,
-        void *stream) {
+// Argument checks shared by both entry points; fills g.  STOKES_OK means "go on".
+stokes_status rigid_check(const stokes_grid *grid, double *const u[3], long long n_markers, double dV,
+                          int free_body, const stokes_body *body, RigidGrid &g) {
     if (!grid || !u || !body || n_markers < 0) return STOKES_EINVAL;
     const int dim = grid->dim;
     if (dim != 2 && dim != 3) return STOKES_EINVAL;
-    RigidGrid g{};
+    g = RigidGrid{};
     g.dim = dim;
     for (int d = 0; d < 3; ++d) {
         g.n[d] = d < dim ? grid->n[d] : 1;
@@ -229,16 +255,17 @@ extern "C" stokes_status stokes_rigid_projection(const stokes_grid *grid, double
     for (int d = 0; d < 3; ++d)
         if (!std::isfinite(body->x_com[d]) || !std::isfinite(body->u_r[d]) || !std::isfinite(body->w_r[d]))
             return STOKES_EINVAL;
-    if (n_markers == 0) {
-        if (free_body) return STOKES_EINVAL;           // a free body needs markers
-        return STOKES_OK;
-    }
-    if (!X || !workspace || ws_bytes < stokes_rigid_workspace_size(dim, n_markers)) {
-        return !X || !workspace ? STOKES_EINVAL : STOKES_ENOMEM;
-    }
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (n_markers == 0 && free_body) return STOKES_EINVAL;   // a free body needs markers
+    return STOKES_OK;
+}
+
+// The projection itself, with its scratch given: JU (n_markers x dim) and the
+// block partials (at most kRigidMaxBlocks x kSums) after it.  Neither needs
+// clearing: every entry is written before it is read.
+stokes_status rigid_impl(const RigidGrid &g, double *const u[3], long long n_markers, const double *X, double dV,
+                         int free_body, stokes_body *body, double *JU, hipStream_t s) {
+    const int dim = g.dim;
     const int blocks = (int)std::min<long long>((n_markers + kRigidBlock - 1) / kRigidBlock, kRigidMaxBlocks);
-    double *JU = static_cast<double *>(workspace);
     double *partial = JU + n_markers * dim;
     const double *x = body->x_com;
     if (dim == 3)
@@ -248,8 +275,8 @@ extern "C" stokes_status stokes_rigid_projection(const stokes_grid *grid, double
         k_rigid_interp<2><<<blocks, kRigidBlock, 0, s>>>(g, n_markers, X, x[0], x[1], 0.0, dV, u[0], u[1], nullptr,
                                                          JU, partial);
     if (hipGetLastError() != hipSuccess) return STOKES_EHIP;
-    std::vector<double> hp((size_t)blocks * kSums);
-    if (hipMemcpyAsync(hp.data(), partial, hp.size() * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+    double *hp = t_partials;
+    if (hipMemcpyAsync(hp, partial, (size_t)blocks * kSums * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
         return STOKES_EHIP;
     double S[kSums] = {0.0};
@@ -293,4 +320,45 @@ extern "C" stokes_status stokes_rigid_projection(const stokes_grid *grid, double
         body->w_r[d] = wr[d];
     }
     return STOKES_OK;
+}
+
+}  // namespace
+
+extern "C" size_t stokes_rigid_workspace_size(int dim, long long n_markers) {
+    if ((dim != 2 && dim != 3) || n_markers < 0) return 0;
+    const long long blocks = std::min<long long>(std::max<long long>((n_markers + kRigidBlock - 1) / kRigidBlock, 1),
+                                                 kRigidMaxBlocks);
+    return (size_t)(n_markers * dim + blocks * kSums) * sizeof(double);
+}
+
+extern "C" stokes_status stokes_rigid_projection(const stokes_grid *grid, double *const u[3], long long n_markers,
+        const double *X, double dV, int free_body, stokes_body *body, void *workspace, size_t ws_bytes,
+        void *stream) {
+    RigidGrid g;
+    stokes_status st = rigid_check(grid, u, n_markers, dV, free_body, body, g);
+    if (st != STOKES_OK || n_markers == 0) return st;
+    if (!X || !workspace || ws_bytes < stokes_rigid_workspace_size(g.dim, n_markers)) {
+        return !X || !workspace ? STOKES_EINVAL : STOKES_ENOMEM;
+    }
+    return rigid_impl(g, u, n_markers, X, dV, free_body, body, static_cast<double *>(workspace),
+                      reinterpret_cast<hipStream_t>(stream));
+}
+
+extern "C" stokes_status stokes_rigid_projection_noalloc(const stokes_grid *grid, double *const u[3],
+        long long n_markers, const double *X, double dV, int free_body, stokes_body *body, void *stream) {
+    RigidGrid g;
+    stokes_status st = rigid_check(grid, u, n_markers, dV, free_body, body, g);
+    if (st != STOKES_OK || n_markers == 0) return st;
+    if (!X) return STOKES_EINVAL;
+    if (n_markers > kScratchMarkers) {
+        stk_set_thread_error("stokes_rigid_projection_noalloc: more markers than its fixed scratch holds "
+                             "(STOKES_RIGID_NOALLOC_MAX_MARKERS = 524288)");
+        return STOKES_ENOMEM;
+    }
+    double *ws = nullptr;
+    if (scratch_of_current_device(&ws) != hipSuccess) {
+        stk_set_thread_error("stokes_rigid_projection_noalloc: hipGetSymbolAddress of the scratch array failed");
+        return STOKES_EHIP;
+    }
+    return rigid_impl(g, u, n_markers, X, dV, free_body, body, ws, reinterpret_cast<hipStream_t>(stream));
 }

@@ -1743,3 +1743,6 @@ const char *stokes_last_error(const stokes_ctx *ctx) {
 }
 
 }  // extern "C"
+
+// Message for stokes_last_error(NULL) from the other source files of the library.
+void stk_set_thread_error(const char *msg) { g_setup_error = msg ? msg : ""; }
