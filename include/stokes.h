@@ -264,6 +264,38 @@ stokes_status stokes_coefficients(const stokes_grid *grid, const stokes_fluids *
                                   double *const rho_flow_face[3], void *stream);
 
 /* ---------------------------------------------------------------------------
+ * Face-density transport of the conservative scheme (Sec. 4.2.2, eqs. eq_rk1,
+ * eq_rk2 and eq_rk3): the face densities that stokes_setup takes, advanced
+ * from rho_n by three-stage SSP-RK3,
+ *     rho1 = rho_n - dt R(u1, rho_n)
+ *     rho2 = 3/4 rho_n + 1/4 rho1 - 1/4 dt R(u2, rho1)
+ *     rho  = 1/3 rho_n + 2/3 rho2 - 2/3 dt R(u3, rho2),
+ * with R(u, rho) the divergence of u_adv rho_lim over each face's control
+ * volume (one cell long in every direction, centred on the face): u_adv on a
+ * control-volume face is the mean of the two nearest velocities normal to it,
+ * rho_lim the cubic upwind value limited by CUI (Waterson and Deconinck 2007),
+ * densities beyond a wall mirror the interior, and nothing crosses a wall
+ * (wall-normal velocities are zero).  Wall-normal faces are not transported:
+ * they hold rho_n.  The stage velocities are the caller's (the paper takes u^n,
+ * then extrapolations of u^n, u^{n-1} and the latest iterate).
+ *   rho_n[3]     device face densities in the solver's layouts (rho_n[2] NULL in 2D)
+ *   u_stage[9]   device face velocities of the three stages: stage s, component c
+ *                at u_stage[3 s + c] (the c = 2 entries NULL in 2D); wall-normal
+ *                entries must be 0
+ *   rho_out[3]   device outputs in the same layouts; must not overlap the inputs
+ *   workspace    device buffer of ws_bytes >= stokes_density_workspace_size(grid)
+ *                (the second stage's densities)
+ * Asynchronous on stream (three launches).  EINVAL for a NULL pointer, dt <= 0 or
+ * a bad spacing; ESHAPE for fewer than 2 cells along an axis or 2^40 points or
+ * more; ENOMEM for a small workspace; EHIP if a launch fails.
+ * --------------------------------------------------------------------------- */
+size_t stokes_density_workspace_size(const stokes_grid *grid);
+
+stokes_status stokes_density_rk3(const stokes_grid *grid, double dt, const double *const rho_n[3],
+                                 const double *const u_stage[9], double *const rho_out[3],
+                                 void *workspace, size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------
  * Explicit momentum right-hand side of one time step (Sec. 4.2.2,
  * eq_nc_discrete_momentum, and eq_c_discrete_momentum with the old density;
  * Sec. 5 for the gravity force):

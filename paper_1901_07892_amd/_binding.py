@@ -146,6 +146,11 @@ def load_library():
     L.stokes_attach_learned.restype = C.c_int
     L.stokes_learned_tuple.argtypes = [C.c_void_p, C.c_void_p * 3, dp, C.c_int, C.c_int, dp, dp, dp, dp]
     L.stokes_learned_tuple.restype = C.c_int
+    L.stokes_density_workspace_size.argtypes = [C.POINTER(StokesGrid)]
+    L.stokes_density_workspace_size.restype = C.c_size_t
+    L.stokes_density_rk3.argtypes = [C.POINTER(StokesGrid), C.c_double, C.c_void_p * 3, C.c_void_p * 9,
+                                     C.c_void_p * 3, dp, C.c_size_t, dp]
+    L.stokes_density_rk3.restype = C.c_int
     L.stokes_pressure_op.argtypes = [C.c_void_p, C.c_int, dp, dp, dp, dp]
     L.stokes_pressure_op.restype = C.c_int
     _lib = L
@@ -253,6 +258,27 @@ def stokes_profile_read(ctx):
     ms, n, b = C.c_double(), C.c_longlong(), C.c_double()
     load_library().stokes_profile_read(ctx, C.byref(ms), C.byref(n), C.byref(b))
     return ms.value, n.value, b.value
+
+
+def stokes_density_workspace_size(grid: StokesGrid) -> int:
+    return int(load_library().stokes_density_workspace_size(C.byref(grid)))
+
+
+def stokes_density_rk3(grid, dt, rho_n, u_stages, rho_out, workspace, stream=None) -> None:
+    """SSP-RK3 face-density transport: ``u_stages`` is a list of three velocity
+    lists (one per stage); all arrays are device float64 tensors."""
+    L = load_library()
+    us = (C.c_void_p * 9)()
+    for st in range(3):
+        for c, t in enumerate(list(u_stages[st])[:3]):
+            us[3 * st + c] = _ptr(t)
+    st = L.stokes_density_rk3(C.byref(grid), float(dt), _ptr3(list(rho_n) + [None] * 3), us,
+                              _ptr3(list(rho_out) + [None] * 3),
+                              workspace.data_ptr() if workspace is not None else None,
+                              workspace.numel() * workspace.element_size() if workspace is not None else 0,
+                              _stream(stream))
+    if st != 0:
+        raise StokesError(st, "stokes_density_rk3 failed")
 
 
 POP_SWEEP, POP_SWEEP_FLAT, POP_RESTRICT, POP_RESTRICT_FLAT = 0, 1, 2, 3

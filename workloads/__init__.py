@@ -429,3 +429,43 @@ def random_vector(problem_or_n, dim, seed):
             xs.append(None)
     p = rng.standard_normal(cell_shape(n))
     return xs, p
+
+
+def stream_velocity(n, h, dim, seed, n_modes=4, margin=0):
+    """Seeded face velocities with zero discrete divergence on the MAC grid and zero
+    wall-normal entries: the discrete curl of smooth random stream functions on the
+    grid nodes / edges (a few sine modes each), optionally vanishing within
+    `margin` cells of every wall; normalised to max |u| = 1."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    nx, ny, nz = n[0], n[1], (n[2] if dim == 3 else 1)
+    u = [np.zeros(face_shape((nx, ny, nz), c)) for c in range(dim)]
+    planes = [(0, 1)] if dim == 2 else [(0, 1), (0, 2), (1, 2)]
+    for a, b in planes:
+        shape = [nz, ny, nx]
+        shape[2 - a] += 1
+        shape[2 - b] += 1
+        coords = []
+        for ax in range(3):
+            m = shape[2 - ax]
+            if ax in (a, b):
+                coords.append(np.arange(m) / (m - 1))          # node positions in [0, 1]
+            else:
+                coords.append((np.arange(m) + 0.5) / m)       # cell positions
+        psi = np.zeros(shape)                                  # (z, y, x)
+        for _ in range(n_modes):
+            kx, ky, kz = rng.integers(1, 4, size=3)
+            ph = rng.uniform(0, 2 * np.pi)
+            amp = rng.standard_normal()
+            fx = np.sin(np.pi * kx * coords[0])
+            fy = np.sin(np.pi * ky * coords[1])
+            fz = np.cos(np.pi * kz * coords[2] + ph) if dim == 3 else np.ones(1)
+            psi += amp * fz[:, None, None] * fy[None, :, None] * fx[None, None, :]
+        for ax in (a, b):
+            m = psi.shape[2 - ax]
+            idx = np.arange(m)
+            keep = ((idx > margin) & (idx < m - 1 - margin)).astype(float)
+            psi *= np.expand_dims(keep, [k for k in range(3) if k != 2 - ax])
+        u[a] += np.diff(psi, axis=2 - b) / h[b]
+        u[b] -= np.diff(psi, axis=2 - a) / h[a]
+    top = max(float(np.abs(x).max()) for x in u)
+    return [x / top for x in u]
