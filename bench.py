@@ -191,6 +191,7 @@ def main():
     out["coefficient_step"] = coefficient_step(S, prob)
     out["rigid_projection"] = rigid_step(S, prob, xu)
     out["explicit_rhs"] = explicit_rhs_step(S, prob, rho, mu, xu)
+    out["density_transport"] = density_transport_step(S, prob, xu)
     if not args.no_forms and args.precision == 0:
         out["forms"] = {"fp32_multigrid": fp32_form(S, prob, rho, mu, rhs_u, rhs_p, xu, xp, overrides,
                                                     ms, args.steps)}
@@ -419,6 +420,39 @@ def explicit_rhs_step(S, prob, rho, mu, u, launches=20):
     log("explicit rhs: %.1f us, %.0f GB/s" % (us, gbps))
     return {"kernel": "k_explicit_rhs3_z", "theta": 0.5, "avg_launch_us": us, "bytes_per_launch": nbytes,
             "GBps": gbps, "frac_of_8TBps": gbps / 8000.0}
+
+
+def density_transport_step(S, prob, u, reps=10):
+    """SSP-RK3 face-density transport (three launches) on the instance's face densities,
+    with the solved velocity as every stage's advecting velocity; algorithmic bytes =
+    every face array each stage must read or write once (stage 1: rho_n, u, out;
+    stages 2 and 3: rho_n, the stage density, u, out)."""
+    import torch
+    dev = torch.device("cuda:0")
+    rho = [torch.from_numpy(np.ascontiguousarray(prob.rho_faces[c])).to(dev) for c in range(3)]
+    out = [torch.empty_like(a) for a in rho]
+    grid = S._binding.make_grid(3, prob.n, prob.h)
+    ws = torch.empty(S.stokes_density_workspace_size(grid), dtype=torch.uint8, device=dev)
+    umax = max(float(a.abs().max()) for a in u)
+    dt = 0.3 * min(prob.h) / max(umax, 1e-30)
+    stages = [u, u, u]
+    for _ in range(2):
+        S.stokes_density_rk3(grid, dt, rho, stages, out, ws)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        S.stokes_density_rk3(grid, dt, rho, stages, out, ws)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    faces = sum(float(a.numel()) for a in rho)
+    nbytes = 8.0 * faces * (3 + 4 + 4)
+    moved = max(float((out[c] - rho[c]).abs().max()) for c in range(3))
+    log("density transport (SSP-RK3, 3 launches): %.3f ms, %.0f GB/s algorithmic" % (ms, nbytes / (ms * 1e-3) / 1e9))
+    return {"kernel": "k_rk3_stage x 3", "ms_per_update": ms, "bytes_per_update": nbytes,
+            "GBps": nbytes / (ms * 1e-3) / 1e9, "frac_of_8TBps": nbytes / (ms * 1e-3) / 8e12,
+            "cfl": 0.3, "max_density_change": moved}
 
 
 def rigid_step(S, prob, u, reps=10):

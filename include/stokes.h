@@ -286,8 +286,8 @@ stokes_status stokes_coefficients(const stokes_grid *grid, const stokes_fluids *
  *   workspace    device buffer of ws_bytes >= stokes_density_workspace_size(grid)
  *                (the second stage's densities)
  * Asynchronous on stream (three launches).  EINVAL for a NULL pointer, dt <= 0 or
- * a bad spacing; ESHAPE for fewer than 2 cells along an axis or 2^40 points or
- * more; ENOMEM for a small workspace; EHIP if a launch fails.
+ * a bad spacing; ESHAPE for fewer than 2 cells along an axis or a face array of
+ * 2^31 entries or more; ENOMEM for a small workspace; EHIP if a launch fails.
  * --------------------------------------------------------------------------- */
 size_t stokes_density_workspace_size(const stokes_grid *grid);
 

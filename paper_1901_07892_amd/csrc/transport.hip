@@ -17,16 +17,16 @@
 //   - densities beyond a wall mirror the interior (homogeneous Neumann);
 //   - wall-normal faces are not transported and hold rho_n in every stage.
 //
-// GPU mapping: one launch per stage, one thread per point (i, j, k) of the
-// (Nx+1)(Ny+1)(Nz+1) index space, which owns the x-face i, the y-face j and the
-// z-face k of cell (i, j, k) -- all in the caller's C-order layouts; stencil
-// neighbours come from cache.  Every control-volume face flux is evaluated by
-// both faces that share it, in the same arithmetic, so the update is exactly
-// conservative in the same sense as its definition.
+// GPU mapping: one launch per stage, one thread per face (blockIdx.y is the
+// component), in the caller's C-order layouts; stencil neighbours come from
+// cache.  Every control-volume face flux is evaluated by both faces that share
+// it, in the same arithmetic, so the update is exactly conservative in the same
+// sense as its definition.
 #include "../../include/stokes.h"
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 namespace {
@@ -48,84 +48,78 @@ struct StageArgs {
 // extent of component c's array along axis d
 __device__ __host__ inline int ext(const TrGrid &g, int c, int d) { return g.n[d] + (c == d ? 1 : 0); }
 
-__device__ inline long long lin(const TrGrid &g, int c, int i, int j, int k) {
-    return (long long)i + (long long)ext(g, c, 0) * ((long long)j + (long long)ext(g, c, 1) * k);
-}
-
+// CUI-limited face value from far-upwind U, upwind C and downwind D.  The
+// normalised upwind value r = (C - U) / (D - U) only selects the branch, so the
+// comparisons are made on N = C - U and A = D - U with A's sign folded in
+// (no division); each branch's value U + f(r) A is written without r:
+// 3 r A = 3 N, (5/6 r + 1/3) A = 5/6 N + A/3, A, and N.
 __device__ inline double cui(double U, double C, double D) {
-    const double den = D - U;
-    if (den == 0.0) return C;
-    const double r = (C - U) / den;
-    double f = r;
-    if (r > 0.0 && r <= 2.0 / 13.0) f = 3.0 * r;
-    else if (r > 2.0 / 13.0 && r <= 0.8) f = (5.0 / 6.0) * r + 1.0 / 3.0;
-    else if (r > 0.8 && r < 1.0) f = 1.0;
-    return U + f * den;
+    const double A = D - U, N = C - U;
+    if (A == 0.0) return C;
+    const double An = fabs(A), Nn = A > 0.0 ? N : -N;
+    if (Nn <= 0.0 || Nn >= An) return C;                   // r <= 0 or r >= 1: upwind
+    if (13.0 * Nn <= 2.0 * An) return U + 3.0 * N;         // 0 < r <= 2/13
+    if (5.0 * Nn <= 4.0 * An) return U + (5.0 / 6.0) * N + A / 3.0;   // 2/13 < r <= 4/5
+    return D;                                              // 4/5 < r < 1
 }
 
-// density of component c at index m along d from the face (i, j, k), mirrored
-// beyond a wall (about the wall face along c itself, about the wall across it)
-__device__ inline double rho_at(const TrGrid &g, const double *rc, int c, int d, const int p[3], int m) {
-    const int E = ext(g, c, d);
-    int mm = m;
-    if (c == d) mm = m < 0 ? -m : (m > E - 1 ? 2 * (E - 1) - m : m);
-    else mm = m < 0 ? -m - 1 : (m > E - 1 ? 2 * E - 1 - m : m);
-    int q[3] = {p[0], p[1], p[2]};
-    q[d] = mm;
-    return rc[lin(g, c, q[0], q[1], q[2])];
+// Index of entry m along d (mirrored beyond a wall: about the wall face along the
+// component's own axis, about the wall across it) for an array of extent E.
+__device__ inline int mirror(int m, int E, bool face_axis) {
+    if (face_axis) return m < 0 ? -m : (m > E - 1 ? 2 * (E - 1) - m : m);
+    return m < 0 ? -m - 1 : (m > E - 1 ? 2 * E - 1 - m : m);
 }
 
-// advective velocity on the control-volume face between entries m-1 and m
-// along d of the interior c-face p
-__device__ inline double adv(const TrGrid &g, const double *const u[3], int c, int d, const int p[3], int m) {
-    if (d == c) {
-        if (m == 0 || m == ext(g, c, d)) return 0.0;
-        int q0[3] = {p[0], p[1], p[2]}, q1[3] = {p[0], p[1], p[2]};
-        q0[d] = m - 1;
-        q1[d] = m;
-        return 0.5 * (u[d][lin(g, d, q0[0], q0[1], q0[2])] + u[d][lin(g, d, q1[0], q1[1], q1[2])]);
-    }
-    int q0[3] = {p[0], p[1], p[2]}, q1[3] = {p[0], p[1], p[2]};
-    q0[c] -= 1;
-    q0[d] = m;
-    q1[d] = m;
-    return 0.5 * (u[d][lin(g, d, q0[0], q0[1], q0[2])] + u[d][lin(g, d, q1[0], q1[1], q1[2])]);
-}
-
-__device__ inline double flux(const TrGrid &g, const double *const u[3], const double *rc, int c, int d,
-                              const int p[3], int m) {
-    const double a = adv(g, u, c, d, p, m);
-    double lim;
-    if (a > 0.0) lim = cui(rho_at(g, rc, c, d, p, m - 2), rho_at(g, rc, c, d, p, m - 1), rho_at(g, rc, c, d, p, m));
-    else lim = cui(rho_at(g, rc, c, d, p, m + 1), rho_at(g, rc, c, d, p, m), rho_at(g, rc, c, d, p, m - 1));
-    return a * lim;
-}
-
+// One thread per c-face (blockIdx.y = c): out = a_n rho_n + a_s rho_s - c_dt R on
+// interior faces, rho_n on wall-normal ones.  32-bit indices (the host checks
+// that every array has fewer than 2^31 entries).
 __global__ void __launch_bounds__(kTrBlock) k_rk3_stage(TrGrid g, StageArgs s) {
-    const long long px = g.n[0] + 1, py = g.n[1] + 1, pz = g.dim == 3 ? g.n[2] + 1 : 1;
-    const long long t = (long long)blockIdx.x * kTrBlock + threadIdx.x;
-    if (t >= px * py * pz) return;
-    const int i = (int)(t % px), j = (int)((t / px) % py), k = (int)(t / (px * py));
-    const int p[3] = {i, j, k};
-    for (int c = 0; c < g.dim; ++c) {
-        // does point (i, j, k) hold a c-face?
-        bool has = true;
-        for (int d = 0; d < g.dim; ++d)
-            if (p[d] >= ext(g, c, d)) has = false;
-        if (!has) continue;
-        const long long q = lin(g, c, i, j, k);
-        const double rn = s.rn[c][q];
-        if (p[c] == 0 || p[c] == g.n[c]) {          // wall-normal face: not transported
-            s.out[c][q] = rn;
-            continue;
-        }
-        double R = 0.0;
-        for (int d = 0; d < g.dim; ++d) {
-            const int m = p[d];
-            R += (flux(g, s.u, s.rs[c], c, d, p, m + 1) - flux(g, s.u, s.rs[c], c, d, p, m)) * g.ih[d];
-        }
-        s.out[c][q] = s.a_n * rn + s.a_s * s.rs[c][q] - s.c_dt * R;
+    const int c = blockIdx.y;
+    const int E0 = ext(g, c, 0), E1 = ext(g, c, 1), E2 = g.dim == 3 ? ext(g, c, 2) : 1;
+    const int t = blockIdx.x * kTrBlock + threadIdx.x;
+    if (t >= E0 * E1 * E2) return;
+    const int p[3] = {t % E0, (t / E0) % E1, t / (E0 * E1)};
+    const double *rc = s.rs[c];
+    const double rn = s.rn[c][t];
+    if (p[c] == 0 || p[c] == g.n[c]) {                  // wall-normal face: not transported
+        s.out[c][t] = rn;
+        return;
     }
+    const int Ec[3] = {E0, E1, E2};
+    const int st[3] = {1, E0, E0 * E1};
+    double R = 0.0;
+    for (int d = 0; d < g.dim; ++d) {
+        const int m = p[d], E = Ec[d];
+        const bool fa = d == c;
+        const int base = t - m * st[d];
+        // densities at m-2 .. m+2 along d
+        double r5[5];
+#pragma unroll
+        for (int o = 0; o < 5; ++o) r5[o] = rc[base + mirror(m - 2 + o, E, fa) * st[d]];
+        // advective velocities on the control-volume faces m (lower) and m+1 (upper)
+        double alo, ahi;
+        const double *ud = s.u[d];
+        if (fa) {
+            // c-faces around the cell centres m-1 | m and m | m+1; zero beyond the walls
+            const int sd = st[d];
+            const double uc = ud[t];
+            alo = m == 0 ? 0.0 : 0.5 * (ud[t - sd] + uc);
+            ahi = m == E - 1 ? 0.0 : 0.5 * (uc + ud[t + sd]);
+        } else {
+            // d-faces of the cells p[c]-1 and p[c] at edge index m and m+1 along d
+            const int Ed[3] = {g.n[0] + (d == 0), g.n[1] + (d == 1), g.dim == 3 ? g.n[2] + (d == 2) : 1};
+            const int sd1 = 1, sd2 = Ed[0], sd3 = Ed[0] * Ed[1];
+            const int sdd[3] = {sd1, sd2, sd3};
+            const int q = p[0] * sdd[0] + p[1] * sdd[1] + p[2] * sdd[2];   // the d-face at cell p[c], index m
+            const int qm = q - sdd[c];                                     // cell p[c] - 1
+            alo = 0.5 * (ud[qm] + ud[q]);
+            ahi = 0.5 * (ud[qm + sdd[d]] + ud[q + sdd[d]]);
+        }
+        const double flo = alo * (alo > 0.0 ? cui(r5[0], r5[1], r5[2]) : cui(r5[3], r5[2], r5[1]));
+        const double fhi = ahi * (ahi > 0.0 ? cui(r5[1], r5[2], r5[3]) : cui(r5[4], r5[3], r5[2]));
+        R += (fhi - flo) * g.ih[d];
+    }
+    s.out[c][t] = s.a_n * rn + s.a_s * rc[t] - s.c_dt * R;
 }
 
 size_t face_count(const stokes_grid *g, int c) {
@@ -159,14 +153,11 @@ extern "C" stokes_status stokes_density_rk3(const stokes_grid *grid, double dt, 
         g.n[a] = a < dim ? grid->n[a] : 1;
         g.ih[a] = 0.0;
     }
-    long long pts = 1;
     for (int a = 0; a < dim; ++a) {
         if (grid->n[a] < 2) return STOKES_ESHAPE;
         if (!(grid->h[a] > 0.0) || !std::isfinite(grid->h[a])) return STOKES_EINVAL;
         g.ih[a] = 1.0 / grid->h[a];
-        pts *= (long long)grid->n[a] + 1;
     }
-    if (pts >= (1LL << 40)) return STOKES_ESHAPE;
     for (int c = 0; c < dim; ++c) {
         if (!rho_n[c] || !rho_out[c]) return STOKES_EINVAL;
         for (int st = 0; st < 3; ++st)
@@ -185,7 +176,11 @@ extern "C" stokes_status stokes_density_rk3(const stokes_grid *grid, double dt, 
         }
     }
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    const unsigned blocks = (unsigned)((pts + kTrBlock - 1) / kTrBlock);
+    // one thread per face of the largest component array
+    long long most = 0;
+    for (int c = 0; c < dim; ++c) most = std::max<long long>(most, (long long)face_count(grid, c));
+    if (most >= (1LL << 31)) return STOKES_ESHAPE;
+    const unsigned blocks = (unsigned)((most + kTrBlock - 1) / kTrBlock);
     auto stage = [&](double a_n, double a_s, double c_dt, const double *const rs[3], int st, double *const out[3]) {
         StageArgs a{};
         a.a_n = a_n;
@@ -197,7 +192,7 @@ extern "C" stokes_status stokes_density_rk3(const stokes_grid *grid, double dt, 
             a.u[c] = c < dim ? u_stage[3 * st + c] : nullptr;
             a.out[c] = c < dim ? out[c] : nullptr;
         }
-        k_rk3_stage<<<blocks, kTrBlock, 0, s>>>(g, a);
+        k_rk3_stage<<<dim3(blocks, dim), kTrBlock, 0, s>>>(g, a);
     };
     stage(0.0, 1.0, dt, rho_n, 0, rho_out);
     stage(0.75, 0.25, 0.25 * dt, rho_out, 1, r2);
