@@ -20,7 +20,16 @@ harmonic averaging), with out-of-domain cells mirrored.
 
 Boundaries: a wall axis has no-slip walls (normal velocity zero and not an
 unknown; tangential ghost = -interior, i.e. zero wall value); the pressure
-gradient lives only on interior faces.  A periodic axis wraps.
+gradient lives only on interior faces.  A periodic axis wraps.  With
+``open_top`` the upper end of the vertical axis (y in 2D, z in 3D) is the wave
+tank's open top (Sec. 7.1: zero pressure and zero tangential velocity there):
+the normal velocity on the top faces is an unknown, the pressure ghost above
+the top is minus the cell below (zero pressure on the face, so the gradient on
+the top face is -2 p / h), the tangential ghosts keep the no-slip rule, and the
+normal viscous stress in the ghost cell above is likewise minus the cell below
+(zero normal stress on the face: with zero tangential velocity on the top,
+continuity gives d w / d z = 0 there; equivalently the normal velocity above the
+top mirrors the one below it).
 
 The matrix is built from 1D staggered difference operators combined with
 Kronecker products (C order, x fastest), which is a literal transcription of
@@ -42,6 +51,11 @@ class OGrid:
     n: Tuple[int, int, int]
     h: Tuple[float, float, float]
     periodic: Tuple[bool, bool, bool] = (False, False, False)
+    open_top: bool = False                 # upper end of axis dim-1: zero pressure, open
+
+    @property
+    def vert(self) -> int:
+        return self.dim - 1
 
     def nf(self, axis: int) -> int:
         """Number of face positions along ``axis``."""
@@ -60,11 +74,14 @@ class OGrid:
 # --------------------------------------------------------------------------
 # 1D staggered operators along one axis with N cells
 # --------------------------------------------------------------------------
-def _d1(N: int, h: float, periodic: bool):
+def _d1(N: int, h: float, periodic: bool, open_hi: bool = False):
     """Return the 1D building blocks along one axis.
 
     f2c : faces -> cells, (f[i+1] - f[i]) / h
-    c2f : cells -> faces, (c[i] - c[i-1]) / h; zero rows on wall faces
+    c2f : cells -> faces, (c[i] - c[i-1]) / h; zero rows on wall faces; on an
+          open upper end (open_hi) the pressure ghost is -c[N-1]: -2 c[N-1] / h
+    c2fv: the same for the normal viscous stress (equal to c2f: on an open upper
+          end its ghost is also minus the cell below, zero normal stress on the face)
     t2e : cell-positioned tangential values -> face-positioned edges,
           (t[i] - t[i-1]) / h, with ghost t = -interior beyond a wall
     e2t : face-positioned edges -> cell positions, (e[i+1] - e[i]) / h
@@ -108,8 +125,11 @@ def _d1(N: int, h: float, periodic: bool):
             hi = min(i, N - 1)
             avg[i, lo] += 0.5
             avg[i, hi] += 0.5
+    if open_hi and not periodic:
+        c2f[N, N - 1] -= 2.0 / h
+    c2fv = c2f.copy()
     cv = lambda m: sp.csr_matrix(m)
-    return dict(f2c=cv(f2c), c2f=cv(c2f), t2e=cv(t2e), e2t=cv(e2t), avg=cv(avg),
+    return dict(f2c=cv(f2c), c2f=cv(c2f), c2fv=cv(c2fv), t2e=cv(t2e), e2t=cv(e2t), avg=cv(avg),
                 Ic=sp.identity(N, format="csr"), If=sp.identity(nf, format="csr"))
 
 
@@ -126,7 +146,7 @@ class Assembler:
         ax = []
         for a in range(3):
             if a < g.dim:
-                ax.append(_d1(g.n[a], g.h[a], g.periodic[a]))
+                ax.append(_d1(g.n[a], g.h[a], g.periodic[a], g.open_top and a == g.dim - 1))
             else:
                 one = sp.identity(1, format="csr")
                 ax.append(dict(Ic=one, If=one))
@@ -187,7 +207,7 @@ class Assembler:
         for c in range(d):
             # normal stress 2 mu du_c/dx_c at cells, differenced back to c-faces
             f2c = self._op_along(c, "f2c", self._pos(c))
-            c2f = self._op_along(c, "c2f", self._pos(None))
+            c2f = self._op_along(c, "c2fv", self._pos(None))
             # c2f on a wall axis has zero rows on wall faces; the interior stencil
             # (tau[i] - tau[i-1]) / h is what the momentum row needs.
             L[c][c] = c2f @ sp.diags(2.0 * mu) @ f2c
@@ -223,8 +243,9 @@ class Assembler:
             sl = [slice(None)] * 3
             sl[2 - comp] = 0
             mask[tuple(sl)] = False
-            sl[2 - comp] = -1
-            mask[tuple(sl)] = False
+            if not (g.open_top and comp == g.dim - 1):      # the open top's faces are unknowns
+                sl[2 - comp] = -1
+                mask[tuple(sl)] = False
         idx = np.flatnonzero(mask.ravel())
         S = sp.csr_matrix((np.ones(idx.size), (np.arange(idx.size), idx)),
                           shape=(idx.size, mask.size))
@@ -299,9 +320,9 @@ def pressure_laplacian(g: OGrid, rho_faces: Sequence[np.ndarray]) -> sp.csr_matr
     return -sum(terms[1:], terms[0])
 
 
-def from_problem(prob, theta: float = 1.0) -> System:
-    """Assemble the system of a ``workloads.Problem`` (all walls)."""
-    g = OGrid(prob.dim, tuple(prob.n), tuple(prob.h))
+def from_problem(prob, theta: float = 1.0, open_top: bool = False) -> System:
+    """Assemble the system of a ``workloads.Problem`` (all walls, or the open top)."""
+    g = OGrid(prob.dim, tuple(prob.n), tuple(prob.h), open_top=open_top)
     return assemble(g, prob.rho_faces, prob.mu, prob.dt, theta)
 
 
