@@ -30,7 +30,8 @@
  *   - Every array pointer (coefficients, right-hand sides, solutions and the
  *     workspace) is a DEVICE pointer owned by the caller.  The library never
  *     allocates device memory: everything it keeps lives in the workspace.
- *   - Wall-normal face entries are ignored on input and written as 0 on output.
+ *   - Wall-normal face entries are ignored on input and written as 0 on output
+ *     (the faces of an open top, see stokes_options.open_top, are not walls).
  *   - Work is queued on the caller's HIP stream (passed as void*; NULL is the
  *     default stream).  A context belongs to one stream and is not thread-safe.
  *   - Negative status codes mean nothing was written to the outputs.  No C++
@@ -110,6 +111,17 @@ typedef struct {
                             each side of the second (min(nu1, 1), min(nu2, 1)) and one
                             pre-smoothing sweep on the third and fourth (min(nu1, 1)); otherwise
                             nu1 / nu2 */
+    int open_top;        /* 1: the upper end of the vertical axis (y = Ly in 2D, z = Lz in 3D) is
+                            the wave tank's open top (Sec. 7.1): zero pressure and zero tangential
+                            velocity there, and the vertical velocity on its faces (index Ny in 2D,
+                            Nz in 3D of v / w) is an unknown, read from the right-hand side and the
+                            guess and written in the solution.  The pressure ghost above the top
+                            is minus the cell below (p = 0 on the face) and so is the normal
+                            viscous stress (d w / d z = 0 on the face, from continuity with zero
+                            tangential velocity); the pressure has no free constant, so neither
+                            rhs_p nor p is made mean-free.  Needs the single-level diagonal
+                            velocity step (a mass-dominated operator, as at every workload here;
+                            EINVAL otherwise).  0 (default): walls everywhere. */
 } stokes_options;
 
 typedef struct {
@@ -294,6 +306,53 @@ size_t stokes_density_workspace_size(const stokes_grid *grid);
 stokes_status stokes_density_rk3(const stokes_grid *grid, double dt, const double *const rho_n[3],
                                  const double *const u_stage[9], double *const rho_out[3],
                                  void *workspace, size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Wave-tank boundaries (Sec. 7.1, "Stokes wave theory and numerics"): the
+ * inflow on the x = 0 side and, with stokes_options.open_top, the open top.
+ * The vertical axis is y in 2D and z in 3D; the tank bottom is at 0, the still
+ * level at the depth d, and the wave travels along +x.
+ *
+ * stokes_wave_inflow evaluates the second-order Stokes wave (eqs.
+ * eq_stokes_eta, eq_stokes_u, eq_stokes_v; height H, wavelength lambda,
+ * k = 2 pi / lambda, angular frequency omega, gravity g) on x = 0 at time t,
+ * restricted to the liquid by 1 - H~(phi), phi = -eta(0, t) + (height above the
+ * still level), with H~ the smoothed Heaviside of eq. eq_heaviside_normal_bdry
+ * of half-width n_cells sqrt(h_x h_vertical):
+ *   u_n  device (Nz, Ny) (2D: Ny): the normal velocity of the x-faces at x = 0
+ *        (at the faces' heights, cell centres);
+ *   u_t  device (Nz+1, Ny) (2D: Ny+1): the vertical velocity on the wall at the
+ *        vertical faces' heights (nodes).
+ * The lateral velocity of the wave (3D) is 0.  Asynchronous on stream.  EINVAL
+ * for a NULL pointer or a parameter that is not positive and finite (H may be
+ * 0); ESHAPE for fewer than 2 cells along an axis.
+ *
+ * stokes_inflow_lift moves Dirichlet inflow data on x = 0 (u_n, u_t in the
+ * layouts above) to the right-hand side: in place, rhs_u and rhs_p (device,
+ * the caller's layouts) lose the contribution of the boundary values to the
+ * rows next to the wall -- the continuity of the cells (0, j, k) (-u_n / h_x),
+ * the normal viscous stress of the x-faces i = 1, and the wall-edge shear
+ * stress of the tangential faces i = 0 (with the tangential ghost 2 u_t minus
+ * the interior, and the variation of u_n along the wall) -- with the context's
+ * viscosities and theta.  Solve with the lifted right-hand side, then put u_n
+ * into the solution's x-faces at x = 0 (the solver writes wall faces as 0).
+ * Asynchronous on the context's stream.  EINVAL for a NULL pointer, EHIP if the
+ * launch fails.
+ * --------------------------------------------------------------------------- */
+typedef struct {
+    double height;       /* H, peak to peak (>= 0) */
+    double depth;        /* d: still level above the bottom (> 0) */
+    double wavelength;   /* lambda (> 0) */
+    double omega;        /* angular frequency (> 0), e.g. from omega^2 = g k tanh(k d) */
+    double gravity;      /* g (> 0) */
+    double n_cells;      /* half-width of the boundary Heaviside in cells (> 0) */
+} stokes_wave;
+
+stokes_status stokes_wave_inflow(const stokes_grid *grid, const stokes_wave *wave, double t,
+                                 double *u_n, double *u_t, void *stream);
+
+stokes_status stokes_inflow_lift(stokes_ctx *ctx, const double *u_n, const double *u_t,
+                                 double *const rhs_u[3], double *rhs_p);
 
 /* ---------------------------------------------------------------------------
  * Explicit momentum right-hand side of one time step (Sec. 4.2.2,

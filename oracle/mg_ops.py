@@ -36,17 +36,34 @@ from typing import Sequence
 import numpy as np
 
 
-def betas(dim: int, rho_faces: Sequence[np.ndarray]):
-    """beta = 1/rho on every interior face; wall faces hold 0 (no flux)."""
+def betas(dim: int, rho_faces: Sequence[np.ndarray], open_top: bool = False):
+    """beta = 1/rho on every interior face; wall faces hold 0 (no flux).  With the
+    open top (the upper end of the vertical axis, zero pressure on its faces) the
+    top faces keep 1/rho: ``apply`` gives them the Dirichlet flux."""
     out = []
     for c in range(dim):
         b = 1.0 / np.asarray(rho_faces[c], dtype=np.float64)
         sl = [slice(None)] * 3
-        for end in (0, -1):
+        ends = (0,) if (open_top and c == dim - 1) else (0, -1)
+        for end in ends:
             sl[2 - c] = end
             b[tuple(sl)] = 0.0
         out.append(b)
     return out
+
+
+def _top(dim, beta):
+    """beta on the open top's faces (array of the top cells' shape) or None."""
+    v = dim - 1
+    sl = [slice(None)] * 3
+    sl[2 - v] = -1
+    return beta[v][tuple(sl)]
+
+
+def _top_cells(dim):
+    sl = [slice(None)] * 3
+    sl[2 - (dim - 1)] = -1
+    return tuple(sl)
 
 
 def _face_slices(c: int):
@@ -61,8 +78,11 @@ def _face_slices(c: int):
     return tuple(lo), tuple(hi), tuple(fi)
 
 
-def apply(dim: int, h: Sequence[float], beta: Sequence[np.ndarray], e: np.ndarray) -> np.ndarray:
-    """y = -L_rho e = -D beta G e on cells (flux form, zero flux through walls)."""
+def apply(dim: int, h: Sequence[float], beta: Sequence[np.ndarray], e: np.ndarray,
+          open_top: bool = False) -> np.ndarray:
+    """y = -L_rho e = -D beta G e on cells (flux form, zero flux through walls).  On
+    the open top the pressure is zero on the face, half a cell above the top cells'
+    centres: the flux through it is beta (0 - e) / (h / 2)."""
     e = np.asarray(e, dtype=np.float64)
     y = np.zeros_like(e)
     for c in range(dim):
@@ -70,17 +90,27 @@ def apply(dim: int, h: Sequence[float], beta: Sequence[np.ndarray], e: np.ndarra
         F = beta[c][fi] * (e[hi] - e[lo]) / h[c]
         y[lo] -= F / h[c]
         y[hi] += F / h[c]
+    if open_top:
+        v = dim - 1
+        tc = _top_cells(dim)
+        F = _top(dim, beta) * (0.0 - e[tc]) / (0.5 * h[v])
+        y[tc] -= F / h[v]
     return y
 
 
-def diagonal(dim: int, h: Sequence[float], beta: Sequence[np.ndarray], shape) -> np.ndarray:
-    """Diagonal of -L_rho: the sum of beta/h^2 over each cell's interior faces."""
+def diagonal(dim: int, h: Sequence[float], beta: Sequence[np.ndarray], shape,
+             open_top: bool = False) -> np.ndarray:
+    """Diagonal of -L_rho: the sum of beta/h^2 over each cell's interior faces (and
+    2 beta/h^2 for an open-top face)."""
     d = np.zeros(shape)
     for c in range(dim):
         lo, hi, fi = _face_slices(c)
         w = beta[c][fi] / (h[c] * h[c])
         d[lo] += w
         d[hi] += w
+    if open_top:
+        v = dim - 1
+        d[_top_cells(dim)] += 2.0 * _top(dim, beta) / (h[v] * h[v])
     return d
 
 
@@ -89,25 +119,25 @@ def colour_mask(shape, colour: int) -> np.ndarray:
     return ((i + j + k) % 2) == colour
 
 
-def gs_colour(dim, h, beta, e, r, colour):
+def gs_colour(dim, h, beta, e, r, colour, open_top=False):
     """One colour of red-black Gauss-Seidel for -L_rho e = r (returns a new array)."""
     e = np.array(e, dtype=np.float64, copy=True)
-    d = diagonal(dim, h, beta, e.shape)
-    off = d * e - apply(dim, h, beta, e)          # sum_nb w_nb e_nb
+    d = diagonal(dim, h, beta, e.shape, open_top)
+    off = d * e - apply(dim, h, beta, e, open_top)          # sum_nb w_nb e_nb
     m = colour_mask(e.shape, colour)
     e[m] = (r[m] + off[m]) / d[m]
     return e
 
 
-def rb_gs_sweep(dim, h, beta, e, r):
+def rb_gs_sweep(dim, h, beta, e, r, open_top=False):
     """One red-black Gauss-Seidel sweep, colour 0 ((i+j+k) even) first."""
-    e = gs_colour(dim, h, beta, e, r, 0)
-    return gs_colour(dim, h, beta, e, r, 1)
+    e = gs_colour(dim, h, beta, e, r, 0, open_top)
+    return gs_colour(dim, h, beta, e, r, 1, open_top)
 
 
-def residual_restrict(dim, h, beta, e, r) -> np.ndarray:
+def residual_restrict(dim, h, beta, e, r, open_top=False) -> np.ndarray:
     """Mean over the 2^d children of r - (-L_rho) e (even cell counts)."""
-    res = np.asarray(r, dtype=np.float64) - apply(dim, h, beta, e)
+    res = np.asarray(r, dtype=np.float64) - apply(dim, h, beta, e, open_top)
     nz, ny, nx = res.shape
     if dim == 3:
         return res.reshape(nz // 2, 2, ny // 2, 2, nx // 2, 2).mean(axis=(1, 3, 5))

@@ -36,6 +36,11 @@ class StokesFluids(C.Structure):
 MAX_SOLIDS = 8
 
 
+class StokesWave(C.Structure):
+    _fields_ = [("height", C.c_double), ("depth", C.c_double), ("wavelength", C.c_double),
+                ("omega", C.c_double), ("gravity", C.c_double), ("n_cells", C.c_double)]
+
+
 class StokesBody(C.Structure):
     _fields_ = [("x_com", C.c_double * 3), ("u_r", C.c_double * 3), ("w_r", C.c_double * 3)]
 
@@ -50,7 +55,8 @@ class StokesOptions(C.Structure):
                 ("vel_levels", C.c_int), ("vel_sweeps", C.c_int), ("p_prolong", C.c_int),
                 ("vel_smoother", C.c_int), ("orth", C.c_int), ("matvec_z", C.c_int),
                 ("p_gamma", C.c_int), ("p_small", C.c_int),
-                ("p_wdepth", C.c_int), ("p_cycles_next", C.c_int), ("p_nu_second", C.c_int)]
+                ("p_wdepth", C.c_int), ("p_cycles_next", C.c_int), ("p_nu_second", C.c_int),
+                ("open_top", C.c_int)]
 
 
 class StokesStats(C.Structure):
@@ -146,6 +152,10 @@ def load_library():
     L.stokes_attach_learned.restype = C.c_int
     L.stokes_learned_tuple.argtypes = [C.c_void_p, C.c_void_p * 3, dp, C.c_int, C.c_int, dp, dp, dp, dp]
     L.stokes_learned_tuple.restype = C.c_int
+    L.stokes_wave_inflow.argtypes = [C.POINTER(StokesGrid), C.POINTER(StokesWave), C.c_double, dp, dp, dp]
+    L.stokes_wave_inflow.restype = C.c_int
+    L.stokes_inflow_lift.argtypes = [C.c_void_p, dp, dp, C.c_void_p * 3, dp]
+    L.stokes_inflow_lift.restype = C.c_int
     L.stokes_density_workspace_size.argtypes = [C.POINTER(StokesGrid)]
     L.stokes_density_workspace_size.restype = C.c_size_t
     L.stokes_density_rk3.argtypes = [C.POINTER(StokesGrid), C.c_double, C.c_void_p * 3, C.c_void_p * 9,
@@ -258,6 +268,29 @@ def stokes_profile_read(ctx):
     ms, n, b = C.c_double(), C.c_longlong(), C.c_double()
     load_library().stokes_profile_read(ctx, C.byref(ms), C.byref(n), C.byref(b))
     return ms.value, n.value, b.value
+
+
+def make_wave(height, depth, wavelength, omega, gravity=9.81, n_cells=1.5) -> StokesWave:
+    w = StokesWave()
+    w.height, w.depth, w.wavelength, w.omega, w.gravity, w.n_cells = (
+        float(height), float(depth), float(wavelength), float(omega), float(gravity), float(n_cells))
+    return w
+
+
+def stokes_wave_inflow(grid, wave, t, u_n, u_t, stream=None) -> None:
+    """Second-order Stokes wave inflow data on x = 0 into the device tensors u_n, u_t."""
+    st = load_library().stokes_wave_inflow(C.byref(grid), C.byref(wave), float(t), _ptr(u_n), _ptr(u_t),
+                                          _stream(stream))
+    if st != 0:
+        raise StokesError(st, "stokes_wave_inflow failed")
+
+
+def stokes_inflow_lift(ctx, u_n, u_t, rhs_u, rhs_p) -> None:
+    """Subtract the inflow data's contribution from (rhs_u, rhs_p), in place."""
+    L = load_library()
+    st = L.stokes_inflow_lift(ctx, _ptr(u_n), _ptr(u_t), _ptr3(list(rhs_u) + [None] * 3), _ptr(rhs_p))
+    if st != 0:
+        raise StokesError(st, L.stokes_last_error(ctx).decode())
 
 
 def stokes_density_workspace_size(grid: StokesGrid) -> int:

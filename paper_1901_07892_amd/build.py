@@ -7,7 +7,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = [os.path.join(HERE, "csrc", f) for f in ("stokes.hip", "unet.hip", "coef.hip", "rigid.hip", "rhs.hip", "transport.hip")]
+SRC = [os.path.join(HERE, "csrc", f) for f in ("stokes.hip", "unet.hip", "coef.hip", "rigid.hip", "rhs.hip", "transport.hip", "wave.hip")]
 LIB = os.path.join(HERE, "libstokes.so")
 
 HIPCC_FLAGS = [

@@ -25,6 +25,9 @@ struct Box {
     int stride;              // nb + 2*guard: field-to-field distance in a vector
     double hx, hy, hz;
     double ihx, ihy, ihz;    // 1/h
+    int open_top;            // 1: the upper end of the vertical axis (y in 2D, z in 3D) is open
+                             // (zero pressure, zero tangential velocity); the vertical velocity on
+                             // its faces (index ny / nz) is an unknown
 };
 
 inline Box make_box(int dim, int nx, int ny, int nz, double hx, double hy, double hz) {
@@ -39,6 +42,7 @@ inline Box make_box(int dim, int nx, int ny, int nz, double hx, double hy, doubl
     b.stride = ((b.stride + 63) / 64) * 64;
     b.hx = hx; b.hy = hy; b.hz = dim == 3 ? hz : hx;
     b.ihx = 1.0 / b.hx; b.ihy = 1.0 / b.hy; b.ihz = 1.0 / b.hz;
+    b.open_top = 0;
     return b;
 }
 

@@ -95,14 +95,18 @@ __device__ inline void row_v(const Box &b, int idx, int i, int k, const R *u, co
     const int sy = b.px, sz = b.plane;
     const R ihx = (R)b.ihx, ihy = (R)b.ihy, ihz = (R)b.ihz;
     const bool vu = valid & VALID_U, vv = valid & VALID_V, vw = valid & VALID_W;
-    R vN = vv ? v[idx + sy] : R(0), vS = vv ? v[idx - sy] : R(0);
+    // on an open top (2D, j = ny) the cell above is a ghost: its normal stress is
+    // minus the one below (v and mu mirrored) and the tangential u above is minus
+    // the one below
+    const bool tp = b.dim == 2 && b.open_top && (idx / b.px) % b.py == b.ny;
+    R vN = vv ? v[tp ? idx - sy : idx + sy] : R(0), vS = vv ? v[idx - sy] : R(0);
     R vE = (i + 1 < b.nx && vv) ? v[idx + 1] : R(0);
     R vW = (i > 0 && vv) ? v[idx - 1] : R(0);
     R gE = i + 1 < b.nx ? R(1) : R(2), gW = i > 0 ? R(1) : R(2);
-    R m1 = c.mu[idx], m0 = c.mu[idx - sy];
+    R m1 = c.mu[tp ? idx - sy : idx], m0 = c.mu[idx - sy];
     R mE = c.mxy[idx + 1], mW = c.mxy[idx];
-    R duE = vu ? (u[idx + 1] - u[idx + 1 - sy]) : R(0);
-    R duW = vu ? (u[idx] - u[idx - sy]) : R(0);
+    R duE = vu ? (tp ? R(-2) * u[idx + 1 - sy] : u[idx + 1] - u[idx + 1 - sy]) : R(0);
+    R duW = vu ? (tp ? R(-2) * u[idx - sy] : u[idx] - u[idx - sy]) : R(0);
     R lap = R(2) * (m1 * vN + m0 * vS) * ihy * ihy
           + (mE * (vE * ihx + duE * ihy) - mW * (-vW * ihx + duW * ihy)) * ihx;
     R dg = R(2) * (m0 + m1) * ihy * ihy + (mE * gE + mW * gW) * ihx * ihx;
@@ -126,20 +130,24 @@ __device__ inline void row_w(const Box &b, int idx, int i, int j, const R *u, co
     const int sy = b.px, sz = b.plane;
     const R ihx = (R)b.ihx, ihy = (R)b.ihy, ihz = (R)b.ihz;
     const bool vu = valid & VALID_U, vv = valid & VALID_V, vw = valid & VALID_W;
-    R wT = vw ? w[idx + sz] : R(0), wB = vw ? w[idx - sz] : R(0);
+    // on an open top (k = nz) the cell above is a ghost: its normal stress is minus
+    // the one below (w and mu mirrored) and the tangential u, v above are minus the
+    // ones below
+    const bool tp = b.open_top && idx / b.plane == b.nz;
+    R wT = vw ? w[tp ? idx - sz : idx + sz] : R(0), wB = vw ? w[idx - sz] : R(0);
     R wE = (i + 1 < b.nx && vw) ? w[idx + 1] : R(0);
     R wW = (i > 0 && vw) ? w[idx - 1] : R(0);
     R wN = (j + 1 < b.ny && vw) ? w[idx + sy] : R(0);
     R wS = (j > 0 && vw) ? w[idx - sy] : R(0);
     R gE = i + 1 < b.nx ? R(1) : R(2), gW = i > 0 ? R(1) : R(2);
     R gN = j + 1 < b.ny ? R(1) : R(2), gS = j > 0 ? R(1) : R(2);
-    R m1 = c.mu[idx], m0 = c.mu[idx - sz];
+    R m1 = c.mu[tp ? idx - sz : idx], m0 = c.mu[idx - sz];
     R mE = c.mxz[idx + 1], mW = c.mxz[idx];
     R mN = c.myz[idx + sy], mS = c.myz[idx];
-    R duE = vu ? (u[idx + 1] - u[idx + 1 - sz]) : R(0);
-    R duW = vu ? (u[idx] - u[idx - sz]) : R(0);
-    R dvN = vv ? (v[idx + sy] - v[idx + sy - sz]) : R(0);
-    R dvS = vv ? (v[idx] - v[idx - sz]) : R(0);
+    R duE = vu ? (tp ? R(-2) * u[idx + 1 - sz] : u[idx + 1] - u[idx + 1 - sz]) : R(0);
+    R duW = vu ? (tp ? R(-2) * u[idx - sz] : u[idx] - u[idx - sz]) : R(0);
+    R dvN = vv ? (tp ? R(-2) * v[idx + sy - sz] : v[idx + sy] - v[idx + sy - sz]) : R(0);
+    R dvS = vv ? (tp ? R(-2) * v[idx - sz] : v[idx] - v[idx - sz]) : R(0);
     R lap = R(2) * (m1 * wT + m0 * wB) * ihz * ihz
           + (mE * (wE * ihx + duE * ihz) - mW * (-wW * ihx + duW * ihz)) * ihx
           + (mN * (wN * ihy + dvN * ihz) - mS * (-wS * ihy + dvS * ihz)) * ihy;
@@ -148,9 +156,17 @@ __device__ inline void row_w(const Box &b, int idx, int i, int j, const R *u, co
     diag = c.mass[2][idx] + c.theta * dg;
 }
 
+// Unknown faces of each component: interior faces, plus the faces of the open top
+// (y = Ly in 2D, z = Lz in 3D) when the box has one.
+__device__ inline bool top_v(const Box &b, int j) { return b.open_top && b.dim == 2 && j == b.ny; }
+__device__ inline bool top_w(const Box &b, int k) { return b.open_top && b.dim == 3 && k == b.nz; }
 __device__ inline bool is_ux(const Box &b, int i, int j, int k) { return i >= 1 && i < b.nx && j < b.ny && k < b.nz; }
-__device__ inline bool is_vy(const Box &b, int i, int j, int k) { return j >= 1 && j < b.ny && i < b.nx && k < b.nz; }
-__device__ inline bool is_wz(const Box &b, int i, int j, int k) { return k >= 1 && k < b.nz && i < b.nx && j < b.ny; }
+__device__ inline bool is_vy(const Box &b, int i, int j, int k) {
+    return j >= 1 && (j < b.ny || top_v(b, j)) && i < b.nx && k < b.nz;
+}
+__device__ inline bool is_wz(const Box &b, int i, int j, int k) {
+    return k >= 1 && (k < b.nz || top_w(b, k)) && i < b.nx && j < b.ny;
+}
 __device__ inline bool is_cell(const Box &b, int i, int j, int k) { return i < b.nx && j < b.ny && k < b.nz; }
 
 // ---------------------------------------------------------------- fine operator (FP64)
@@ -181,7 +197,9 @@ __global__ void __launch_bounds__(kBlock) k_apply(Box b, VelCoef<double> c,
     r = 0.0;
     if (is_vy(b, i, j, k)) {
         row_v<DIM, double>(b, idx, i, k, xu, xv, xw, all, c, off, dg);
-        r = dg * xv[idx] + off + (xp[idx] - xp[idx - sy]) * b.ihy;
+        // open top: zero pressure on the face, the ghost above is minus the cell below
+        const double pN = top_v(b, j) ? -xp[idx - sy] : xp[idx];
+        r = dg * xv[idx] + off + (pN - xp[idx - sy]) * b.ihy;
         if (fv) r = fv[idx] - r;
     }
     yv[idx] = r;
@@ -189,7 +207,8 @@ __global__ void __launch_bounds__(kBlock) k_apply(Box b, VelCoef<double> c,
         r = 0.0;
         if (is_wz(b, i, j, k)) {
             row_w<double>(b, idx, i, j, xu, xv, xw, all, c, off, dg);
-            r = dg * xw[idx] + off + (xp[idx] - xp[idx - sz]) * b.ihz;
+            const double pT = top_w(b, k) ? -xp[idx - sz] : xp[idx];
+            r = dg * xw[idx] + off + (pT - xp[idx - sz]) * b.ihz;
             if (fw) r = fw[idx] - r;
         }
         yw[idx] = r;
@@ -294,6 +313,21 @@ __global__ void __launch_bounds__(TX *TY) k_apply3_z(Box b, int kc, VelCoef<doub
         U0 = U1; U1 = U2; V0 = V1; V1 = V2; W0 = W1; W1 = W2;
         P0 = P1; M0 = M1; XZ1 = XZ2; YZ1 = YZ2;
     }
+}
+
+// z-momentum rows of the open top's faces (k = nz), which the z-marching matvec
+// does not visit: one thread per (i, j), same row formulas as k_apply.
+__global__ void __launch_bounds__(kBlock) k_apply_top3(Box b, VelCoef<double> c,
+        const double *__restrict__ xu, const double *__restrict__ xv, const double *__restrict__ xw,
+        const double *__restrict__ xp, const double *__restrict__ fw, double *__restrict__ yw) {
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= b.nx * b.ny) return;
+    const int i = t % b.nx, j = t / b.nx;
+    const int idx = box_index(b, i, j, b.nz);
+    double off, dg;
+    row_w<double>(b, idx, i, j, xu, xv, xw, VALID_U | VALID_V | VALID_W, c, off, dg);
+    const double r = dg * xw[idx] + off + (-xp[idx - b.plane] - xp[idx - b.plane]) * b.ihz;
+    yw[idx] = fw ? fw[idx] - r : r;
 }
 
 // ---------------------------------------------------------------- velocity multigrid
@@ -1162,7 +1196,8 @@ __global__ void __launch_bounds__(64 * kPackRows) k_pack(Box b, int comp, int mo
         const int k = r / b.py, j = r - k * b.py;
         const int ex = b.nx + (comp == 0), ey = b.ny + (comp == 1), ez = b.nz + (comp == 2);
         const bool row_in = j < ey && k < ez;
-        const bool row_wall = (comp == 1 && (j == 0 || j == b.ny)) || (comp == 2 && (k == 0 || k == b.nz));
+        const bool row_wall = (comp == 1 && (j == 0 || (j == b.ny && !(b.open_top && b.dim == 2)))) ||
+                              (comp == 2 && (k == 0 || (k == b.nz && !(b.open_top && b.dim == 3))));
         const double *sr = src + (row_in ? ex * (j + ey * k) : 0);
         double *dr = dst + r * b.px;
         for (int i = threadIdx.x; i < b.px; i += 64) {
@@ -1199,8 +1234,8 @@ __global__ void __launch_bounds__(64 * kPackRows) k_unpack(Box b, int comp, cons
 }
 
 // Face densities of one component -> mass = rho/dt and beta = 1/rho in one pass
-// over rho, in the row form of k_pack: interior faces only, everything else in
-// the box written as 0.  flag[0] = 1 if an interior mass value is not > 0 or not
+// over rho, in the row form of k_pack: interior faces (and the open top's, where
+// beta = 2/rho) only, everything else in the box written as 0.  flag[0] = 1 if an interior mass value is not > 0 or not
 // finite (one vector store per block at most, after a block-wide OR).
 __global__ void __launch_bounds__(64 * kPackRows) k_pack_rho(Box b, int comp, double inv_dt,
         const double *__restrict__ src, double *__restrict__ mass, double *__restrict__ beta,
@@ -1211,7 +1246,8 @@ __global__ void __launch_bounds__(64 * kPackRows) k_pack_rho(Box b, int comp, do
         const int k = r / b.py, j = r - k * b.py;
         const int ex = b.nx + (comp == 0), ey = b.ny + (comp == 1), ez = b.nz + (comp == 2);
         const bool row_in = j < ey && k < ez;
-        const bool row_wall = (comp == 1 && (j == 0 || j == b.ny)) || (comp == 2 && (k == 0 || k == b.nz));
+        const bool row_wall = (comp == 1 && (j == 0 || (j == b.ny && !(b.open_top && b.dim == 2)))) ||
+                              (comp == 2 && (k == 0 || (k == b.nz && !(b.open_top && b.dim == 3))));
         const double *sr = src + (row_in ? ex * (j + ey * k) : 0);
         double *mr = mass + r * b.px, *br = beta + r * b.px;
         for (int i = threadIdx.x; i < b.px; i += 64) {
@@ -1219,7 +1255,10 @@ __global__ void __launch_bounds__(64 * kPackRows) k_pack_rho(Box b, int comp, do
             if (row_in && i < ex && !(row_wall || (comp == 0 && (i == 0 || i == b.nx)))) {
                 const double x = sr[i];
                 m = inv_dt * x;
-                be = 1.0 / x;
+                // the open top's faces: zero pressure on the face, half a cell from the
+                // centre below, so the Poisson flux through them carries a factor 2
+                const bool topf = (comp == 2 && b.dim == 3 && k == b.nz) || (comp == 1 && b.dim == 2 && j == b.ny);
+                be = (topf ? 2.0 : 1.0) / x;
                 bad |= !(m > 0.0) || !isfinite(m);
             }
             mr[i] = m;

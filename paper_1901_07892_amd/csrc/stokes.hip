@@ -97,7 +97,9 @@ bool can_coarsen(const Box &b) {
 }
 
 Box coarse_of(const Box &f) {
-    return make_box(f.dim, f.nx / 2, f.ny / 2, f.dim == 3 ? f.nz / 2 : 1, 2 * f.hx, 2 * f.hy, 2 * f.hz);
+    Box c = make_box(f.dim, f.nx / 2, f.ny / 2, f.dim == 3 ? f.nz / 2 : 1, 2 * f.hx, 2 * f.hy, 2 * f.hz);
+    c.open_top = f.open_top;
+    return c;
 }
 
 }  // namespace
@@ -702,6 +704,10 @@ void apply_fine(stokes_ctx &c, double *x, double *f, double *y) {
             b, kc, fine_coef(c), c.fld(x, 0), c.fld(x, 1), c.fld(x, 2), c.fld(x, 3),
             f ? c.fld(f, 0) : nullptr, f ? c.fld(f, 1) : nullptr, f ? c.fld(f, 2) : nullptr,
             f ? c.fld(f, 3) : nullptr, c.fld(y, 0), c.fld(y, 1), c.fld(y, 2), c.fld(y, 3));
+        if (b.open_top)
+            k_apply_top3<<<(unsigned)((b.nx * b.ny + kBlock - 1) / kBlock), kBlock, 0, c.stream>>>(
+                b, fine_coef(c), c.fld(x, 0), c.fld(x, 1), c.fld(x, 2), c.fld(x, 3), f ? c.fld(f, 2) : nullptr,
+                c.fld(y, 2));
         return;
     }
     k_apply<DIM><<<nblocks_box(c.fine), kBlock, 0, c.stream>>>(
@@ -843,8 +849,9 @@ stokes_status fgmres(stokes_ctx &c, MG<R> &mg, double tol, bool zero_guess, stok
         HIPCHK(hipMemcpyAsync(dy, y.data(), sizeof(double) * nj, hipMemcpyHostToDevice, c.stream));
         maxpy(c, 1.0, c.Z, nj, dy, c.xk);
         // zero-mean pressure before the true residual is formed, so that the
-        // residual left in V[0] on return belongs to the returned iterate
-        remove_p_mean(c, c.xk);
+        // residual left in V[0] on return belongs to the returned iterate (with an
+        // open top the pressure is fixed by its zero value there)
+        if (!c.fine.open_top) remove_p_mean(c, c.xk);
         if (breakdown) {
             apply_fine<DIM>(c, c.xk, c.bk, v0);
             multidot(c, v0, 1, v0, w2, dh);
@@ -858,8 +865,8 @@ stokes_status fgmres(stokes_ctx &c, MG<R> &mg, double tol, bool zero_guess, stok
 }
 
 // ---------------------------------------------------------------- setup helpers
-// Dense pseudo-inverse of the coarsest Neumann operator -D beta G: with
-// B = L + (s/n) 1 1^T (s = mean diagonal) nonsingular, L^+ = B^{-1} - 1 1^T/(s n).
+// Dense inverse of the coarsest pressure operator -D beta G: the pseudo-inverse
+// of the singular all-walls (Neumann) operator, or the inverse with the open top.
 template <class R>
 void build_dense(stokes_ctx &c, MG<R> &mg) {
     Level<R> &L = mg.L[mg.nlev - 1];
@@ -885,9 +892,15 @@ void build_dense(stokes_ctx &c, MG<R> &mg) {
                     for (int side = 0; side < 2; ++side) {
                         int nb[3] = {i, j, k};
                         nb[a] += side ? 1 : -1;
-                        if (nb[a] < 0 || nb[a] >= ext[a]) continue;
                         int f[3] = {i, j, k};
                         if (side) f[a] += 1;
+                        if (nb[a] < 0 || nb[a] >= ext[a]) {
+                            // the open top: zero pressure on the face (its beta carries the
+                            // factor 2 of the half-cell distance); walls carry no flux
+                            if (b.open_top && side == 1 && a == d - 1)
+                                A[(size_t)r * n + r] += (double)bt[a][box_index(b, f[0], f[1], f[2])] * ih2[a];
+                            continue;
+                        }
                         double w = (double)bt[a][box_index(b, f[0], f[1], f[2])] * ih2[a];
                         A[(size_t)r * n + r] += w;
                         A[(size_t)r * n + cid(nb[0], nb[1], nb[2])] -= w;
@@ -895,10 +908,15 @@ void build_dense(stokes_ctx &c, MG<R> &mg) {
                 }
                 (void)pos;
             }
+    // walls everywhere: the operator is singular (constants); with
+    // B = L + (s/n) 1 1^T (s the mean diagonal) nonsingular, L^+ = B^{-1} - 1 1^T/(s n).
+    // With the open top it is nonsingular and M is its inverse.
+    const bool neumann = !b.open_top;
     double sdiag = 0.0;
     for (int r = 0; r < n; ++r) sdiag += A[(size_t)r * n + r];
     sdiag /= n;
-    for (auto &x : A) x += sdiag / n;
+    if (neumann)
+        for (auto &x : A) x += sdiag / n;
     // Gauss-Jordan inverse with partial pivoting
     std::vector<double> Inv((size_t)n * n, 0.0);
     for (int r = 0; r < n; ++r) Inv[(size_t)r * n + r] = 1.0;
@@ -928,7 +946,7 @@ void build_dense(stokes_ctx &c, MG<R> &mg) {
         }
     }
     std::vector<R> M((size_t)n * n);
-    const double corr = 1.0 / (sdiag * n);
+    const double corr = neumann ? 1.0 / (sdiag * n) : 0.0;
     for (size_t t = 0; t < M.size(); ++t) M[t] = (R)(Inv[t] - corr);
     HIPCHK(hipMemcpyAsync(mg.dense, M.data(), sizeof(R) * M.size(), hipMemcpyHostToDevice, c.stream));
     HIPCHK(hipMemcpyAsync(mg.dmap, map.data(), sizeof(int) * n, hipMemcpyHostToDevice, c.stream));
@@ -1139,6 +1157,7 @@ stokes_options defaults() {
     o.p_wdepth = 2;
     o.p_cycles_next = 0;
     o.p_nu_second = 0;
+    o.open_top = 0;
     return o;
 }
 
@@ -1169,6 +1188,7 @@ const char *check_grid_opts(const stokes_grid *g, const stokes_options &o) {
     if (o.p_small != 0 && o.p_small != 1) return "p_small must be 0 or 1";
     if (o.p_nu_second < 0) return "p_nu_second must be >= 0";
     if (o.p_wdepth < 0) return "p_wdepth must be >= 0";
+    if (o.open_top != 0 && o.open_top != 1) return "open_top must be 0 or 1";
     return nullptr;
 }
 
@@ -1198,11 +1218,13 @@ void init_ctx_shape(stokes_ctx &c, const stokes_grid *g, const stokes_options &o
     c.nu_mid1 = o.p_nu_second == 0 && sec_auto ? std::min(o.nu1, 1) : o.nu1;
     c.fine = make_box(g->dim, g->n[0], g->n[1], g->dim == 3 ? g->n[2] : 1, g->h[0], g->h[1],
                       g->dim == 3 ? g->h[2] : g->h[0]);
+    c.fine.open_top = o.open_top;
     {
         const Box &b = c.fine;
         double nc = (double)b.nx * b.ny * b.nz;
         c.unknowns = nc + (double)(b.nx - 1) * b.ny * b.nz + (double)b.nx * (b.ny - 1) * b.nz +
-                     (g->dim == 3 ? (double)b.nx * b.ny * (b.nz - 1) : 0.0);
+                     (g->dim == 3 ? (double)b.nx * b.ny * (b.nz - 1) : 0.0) +
+                     (o.open_top ? (double)b.nx * (g->dim == 3 ? b.ny : 1) : 0.0);
     }
 }
 
@@ -1250,6 +1272,11 @@ stokes_status setup_impl(stokes_ctx &c, const double *const rho[3], const double
     {
         int nv = c.opt.precision == 1 ? c.mgf.nvlev : c.mgd.nvlev;
         c.diag_vel = c.opt.vel_smoother == 1 && nv == 1 && c.opt.vel_sweeps == 1 && c.opt.vel_cycles == 1;
+    }
+    if (c.fine.open_top && !c.diag_vel) {
+        c.err = "open_top needs the single-level diagonal velocity step (a mass-dominated operator, "
+                "or vel_levels = 1 with the default vel_smoother, vel_sweeps and vel_cycles)";
+        return STOKES_EINVAL;
     }
     // continuity weight
     if (c.opt.cont_scale > 0.0) {
@@ -1313,8 +1340,10 @@ stokes_status solve_impl(stokes_ctx &c, const double *const rhs_u[3], const doub
         HIPCHK(hipMemcpyAsync(&flag, c.dflag, sizeof(int), hipMemcpyDeviceToHost, c.stream));
         sync_read(c, c.dsc, &s, 1);
         if (flag) { c.err = "non-finite right-hand side"; return STOKES_ENAN; }
-        st.g_mean = s / ((double)c.fine.nx * c.fine.ny * c.fine.nz);
-        k_sub_mean<<<nblocks_box(c.fine), kBlock, 0, c.stream>>>(c.fine, c.dsc, c.fld(c.bk, DIM));
+        if (!c.fine.open_top) {            // walls everywhere: the mean of rhs_p is incompatible
+            st.g_mean = s / ((double)c.fine.nx * c.fine.ny * c.fine.nz);
+            k_sub_mean<<<nblocks_box(c.fine), kBlock, 0, c.stream>>>(c.fine, c.dsc, c.fld(c.bk, DIM));
+        }
     }
     pack_vector<DIM>(c, x_u, x_p, c.xk, c.dflag + 2);
     int xflag[2] = {0, 0};
@@ -1322,7 +1351,7 @@ stokes_status solve_impl(stokes_ctx &c, const double *const rhs_u[3], const doub
     HIPCHK(hipStreamSynchronize(c.stream));
     if (xflag[0]) { c.err = "non-finite initial guess"; return STOKES_ENAN; }
     const bool zero_guess = xflag[1] == 0;
-    if (!zero_guess) remove_p_mean(c, c.xk);     // an all-zero guess has zero mean
+    if (!zero_guess && !c.fine.open_top) remove_p_mean(c, c.xk);   // an all-zero guess has zero mean
     stokes_status s = c.opt.precision == 1 ? fgmres<DIM, float>(c, c.mgf, tol, zero_guess, st)
                                            : fgmres<DIM, double>(c, c.mgd, tol, zero_guess, st);
     if (s < 0) return s;
@@ -1422,6 +1451,56 @@ void learned_tuple(stokes_ctx &c, MG<R> &mg, int lc, int cycles, float *f0, floa
     k_normalise_planar<R><<<1, 1024, 0, c.stream>>>(C.b, ss, 0, s_c, c.lstat);
     k_normalise_planar<R><<<1, 1024, 0, c.stream>>>(C.b, pp, 1, phi_c, c.lstat + 3);
     learned_static<R>(c, mg, lc, f0, f1);
+}
+
+// Right-hand-side lift of Dirichlet inflow data on the x = 0 side: the rows next
+// to that wall move the known boundary values to the right (see
+// stokes_inflow_lift).  One thread per (j, k) of the wall plane; caller layouts
+// for the right-hand side, box layout for the viscosities.
+__global__ void __launch_bounds__(kBlock) k_inflow_lift(Box b, const double *__restrict__ mu,
+        const double *__restrict__ mxy, const double *__restrict__ mxz, double theta,
+        const double *__restrict__ un, const double *__restrict__ ut,
+        double *__restrict__ fu, double *__restrict__ fv, double *__restrict__ fw, double *__restrict__ fp) {
+    const int ny = b.ny, nz = b.nz, nx = b.nx;
+    const int vert = b.dim - 1;                             // 1 in 2D, 2 in 3D
+    const int nvert = vert == 1 ? ny : nz;
+    // thread over (j, k) in [0, ny] x [0, nz] (2D: k = 0 only): cell rows and node rows
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    const int pj = ny + 1, pk = b.dim == 3 ? nz + 1 : 1;
+    if (t >= pj * pk) return;
+    const int j = t % pj, k = t / pj;
+    const double ihx = b.ihx, ihy = b.ihy, ihz = b.ihz;
+    const bool cell = j < ny && k < (b.dim == 3 ? nz : 1);
+    // un is (Nz, Ny) (2D: Ny); ut (Nz+1, Ny) (2D: Ny+1)
+    auto UN = [&](int jj, int kk) { return un[jj + ny * kk]; };
+    if (cell) {
+        const double u0 = UN(j, k);
+        fp[nx * (j + ny * k)] -= u0 * ihx;                                  // continuity of cell (0, j, k)
+        fu[1 + (nx + 1) * (j + ny * k)] += theta * 2.0 * mu[box_index(b, 0, j, k)] * u0 * ihx * ihx;
+    }
+    // vertical component on the faces (0, .) next to the wall: its wall edge's shear
+    // stress has the known parts -2 u_t / h_x and d u_n / d(vertical)
+    const int iv = vert == 1 ? j : k;                        // face index along the vertical
+    const bool vfaces = vert == 1 ? (k == 0 && j >= 1 && (j < ny || (b.open_top && j == ny)))
+                                  : (j < ny && k >= 1 && (k < nz || (b.open_top && k == nz)));
+    if (vfaces) {
+        double dun;
+        if (iv < nvert) {
+            dun = vert == 1 ? (UN(j, 0) - UN(j - 1, 0)) * ihy : (UN(j, k) - UN(j, k - 1)) * ihz;
+        } else {                                            // open top: u above = -u below
+            dun = vert == 1 ? -2.0 * UN(j - 1, 0) * ihy : -2.0 * UN(j, k - 1) * ihz;
+        }
+        const double utv = vert == 1 ? ut[j] : ut[j + ny * k];
+        const double me = vert == 1 ? mxy[box_index(b, 0, j, 0)] : mxz[box_index(b, 0, j, k)];
+        const double tau = me * (-2.0 * utv * ihx + dun);
+        if (vert == 1) fv[nx * (j + (ny + 1) * k)] -= theta * tau * ihx;
+        else fw[nx * (j + ny * k)] -= theta * tau * ihx;
+    }
+    // 3D lateral component v on the faces (0, j, k), 1 <= j < ny: d u_n / d y on the wall edge
+    if (b.dim == 3 && k < nz && j >= 1 && j < ny) {
+        const double tau = mxy[box_index(b, 0, j, k)] * (UN(j, k) - UN(j - 1, k)) * ihy;
+        fv[nx * (j + (ny + 1) * k)] -= theta * tau * ihx;
+    }
 }
 
 // One pressure-multigrid kernel of the finest level on caller data (the test
@@ -1701,6 +1780,26 @@ stokes_status stokes_learned_tuple(stokes_ctx *ctx, const double *const rhs_u[3]
         HIPCHK(hipGetLastError());
     } catch (const HipError &e) {
         ctx->err = std::string("HIP error in ") + e.what + ": " + hipGetErrorString(e.e);
+        return STOKES_EHIP;
+    }
+    return STOKES_OK;
+}
+
+stokes_status stokes_inflow_lift(stokes_ctx *ctx, const double *u_n, const double *u_t, double *const rhs_u[3],
+                                 double *rhs_p) {
+    if (!ctx) return STOKES_EINVAL;
+    ctx->err.clear();
+    const int d = ctx->dim;
+    if (!u_n || !u_t || !rhs_u || !rhs_u[0] || !rhs_u[1] || (d == 3 && !rhs_u[2]) || !rhs_p) {
+        ctx->err = "NULL array pointer";
+        return STOKES_EINVAL;
+    }
+    const Box &b = ctx->fine;
+    const long long pts = (long long)(b.ny + 1) * (d == 3 ? b.nz + 1 : 1);
+    k_inflow_lift<<<(unsigned)((pts + kBlock - 1) / kBlock), kBlock, 0, ctx->stream>>>(
+        b, ctx->mu, ctx->mxy, ctx->mxz, ctx->theta, u_n, u_t, rhs_u[0], rhs_u[1], d == 3 ? rhs_u[2] : nullptr, rhs_p);
+    if (hipGetLastError() != hipSuccess) {
+        ctx->err = "k_inflow_lift launch failed";
         return STOKES_EHIP;
     }
     return STOKES_OK;

@@ -62,9 +62,10 @@ def _as_precision(a, precision):
     return a if precision == 0 else a.astype(np.float32).astype(np.float64)
 
 
-def _run(prob, precision, ops, p_prolong=0):
+def _run(prob, precision, ops, p_prolong=0, open_top=0):
     import torch
-    s = solver_for(prob, precision=precision, p_prolong=p_prolong)
+    extra = {"vel_levels": 1} if open_top else {}          # the open top needs the diagonal velocity step
+    s = solver_for(prob, precision=precision, p_prolong=p_prolong, open_top=open_top, **extra)
     e, r, ec = _inputs(prob, 7)
     out = {}
     try:
@@ -88,20 +89,21 @@ OPS = [("sweep", 0, True, False), ("sweep_flat", 1, True, False),
        ("restrict", 2, True, False), ("restrict_flat", 3, True, False)]
 
 
-def _oracle(prob, precision, e, r, ec, names, lin=False):
+def _oracle(prob, precision, e, r, ec, names, lin=False, open_top=False):
     """The oracle's result of each kernel in ``names`` on the same (rounded) inputs."""
     dim = prob.dim
     rho = [np.asarray(prob.rho_faces[c]) for c in range(dim)]
-    beta = M.betas(dim, rho)
+    beta = M.betas(dim, rho, open_top)
     if precision == 1:
         beta = [_as_precision(b, 1) for b in beta]
     e, r, ec = (_as_precision(a, precision) for a in (e, r, ec))
     h = prob.h
+    ot = open_top
     make = {
-        "sweep": lambda: M.rb_gs_sweep(dim, h, beta, e, r),
-        "sweep_zero": lambda: M.rb_gs_sweep(dim, h, beta, np.zeros_like(e), r),
-        "sweep_ec": lambda: M.rb_gs_sweep(dim, h, beta, e + M.prolong(dim, ec, lin), r),
-        "restrict": lambda: M.residual_restrict(dim, h, beta, e, r),
+        "sweep": lambda: M.rb_gs_sweep(dim, h, beta, e, r, ot),
+        "sweep_zero": lambda: M.rb_gs_sweep(dim, h, beta, np.zeros_like(e), r, ot),
+        "sweep_ec": lambda: M.rb_gs_sweep(dim, h, beta, e + M.prolong(dim, ec, lin), r, ot),
+        "restrict": lambda: M.residual_restrict(dim, h, beta, e, r, ot),
     }
     return {k: make[k]() for k in names}
 
@@ -174,3 +176,17 @@ def test_pressure_op_argument_errors():
             assert ei.value.status == -1
     finally:
         s.close()
+
+
+@pytest.mark.parametrize("name,maker", [
+    ("config4_1024x96x96_open_top", lambda: W.config4()),
+    ("config4_2d_512x48_open_top", lambda: W.config4_2d(512, 48)),
+    ("rand_136x72x112_open_top", lambda: _rand_coeff_problem((136, 72, 112), 13)),
+])
+def test_pressure_kernels_open_top_match_oracle(name, maker):
+    """With the wave tank's open top the pressure is zero on the top faces (a
+    Dirichlet row in every kernel, carried by doubled top-face coefficients)."""
+    prob = maker()
+    print("pressure kernels, open top", name, prob.n, flush=True)
+    e, r, ec, got = _run(prob, 0, OPS, open_top=1)
+    _check(prob, 0, got, _oracle(prob, 0, e, r, ec, [k for k in got if not k.endswith("_flat")], open_top=True))

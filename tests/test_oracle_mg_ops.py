@@ -140,3 +140,20 @@ def test_prolongation():
     # 2D: only the x and y axes are refined
     e2 = rng.standard_normal((1, 3, 4))
     assert M.prolong(2, e2, lin=False).shape == (1, 6, 8)
+
+
+@pytest.mark.parametrize("dim,n", [(2, (7, 6, 1)), (3, (5, 4, 6))])
+def test_open_top_apply_equals_assembled_operator(dim, n):
+    h, rho, e, r = _random_case(dim, n, 7)
+    g = A.OGrid(dim, n, h, open_top=True)
+    Lp = A.pressure_laplacian(g, rho)
+    y_ref = (Lp @ e.ravel()).reshape(e.shape)
+    beta = M.betas(dim, rho, open_top=True)
+    y = M.apply(dim, h, beta, e, open_top=True)
+    assert np.abs(y - y_ref).max() <= 1e-13 * np.abs(y_ref).max()
+    d = M.diagonal(dim, h, beta, e.shape, open_top=True)
+    assert np.allclose(d.ravel(), Lp.diagonal(), rtol=1e-14, atol=0)
+    # the sweep zeroes the residual rows of each colour with the Dirichlet top too
+    e1 = M.gs_colour(dim, h, beta, e, r, 0, open_top=True)
+    res = r - M.apply(dim, h, beta, e1, open_top=True)
+    assert np.abs(res[M.colour_mask(e.shape, 0)]).max() <= 1e-9 * np.abs(r).max()

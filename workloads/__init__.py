@@ -346,6 +346,26 @@ def config4(scale: int = 1, seed: int = 1004) -> Problem:
                         seed, rhs_rng=rng)
 
 
+def config4_2d(nx: int = 512, ny: int = 48, seed: int = 1004) -> Problem:
+    """The wave tank of config 4 in its vertical x-z plane (2D: x along the tank, y up):
+    the same free surface and a floating box 0.3 x 0.2, rho_s = 500, on
+    [0, 32/3] x [0, 1] with isotropic spacing (nx = 32/3 ny)."""
+    n, h = _grid(2, (nx, ny), (32.0 / 3.0, 1.0))
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ph0 = float(rng.uniform(0.0, 2.0 * math.pi))
+    Hw, d, lam = 0.04, 0.5, 1.5
+    k = 2.0 * math.pi / lam
+    a2 = stokes_wave_second_order_coeff(Hw, d, lam)
+
+    def phi_fn(X, Y, Z):
+        eta = 0.5 + 0.5 * Hw * np.cos(k * X + ph0) + a2 * np.cos(2.0 * k * X + 2.0 * ph0)
+        deta = -0.5 * Hw * k * np.sin(k * X + ph0) - 2.0 * k * a2 * np.sin(2.0 * k * X + 2.0 * ph0)
+        return (Y - eta) / np.sqrt(1.0 + deta * deta)
+
+    box = (lambda X, Y, Z: sdf_box(X, Y, Z, (16.0 / 3.0, 0.5), (0.15, 0.1), 2), 500.0)
+    return make_problem("config4_2d_%dx%d" % (nx, ny), 2, n, h, 1e-5, 1e-8, phi_fn, [box], seed, rhs_rng=rng)
+
+
 def config5(scale: int = 1, seed: int = 900000, n_cells: Optional[int] = None,
             dt: Optional[float] = None) -> Problem:
     """256^3 random interface surface with 0-4 seeded spheres/boxes, density ratio exactly 1000.
