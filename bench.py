@@ -44,6 +44,10 @@ def parse():
                          "'bench.py --calibrate-copy' into profiles/traffic.json and print a summary")
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the config 3 (128^3) and config 4 (1024x96x96) legs")
+    ap.add_argument("--learned-study", type=int, default=0, metavar="SEEDS",
+                    help="no bench line: measure what a (perfect or learned) initial guess is worth to the "
+                         "pressure cycles on SEEDS fresh instances of the headline recipe, and the U-Net's "
+                         "forward cost from 32^3 to 256^3; prints one JSON line")
     ap.add_argument("--verbose", action="store_true")
     return ap.parse_args()
 
@@ -56,6 +60,9 @@ def main():
     args = parse()
     if args.traffic_from:
         traffic_from_counters(*args.traffic_from, n=args.n, precision=args.precision)
+        return
+    if args.learned_study and args.gpus == 1:
+        print(json.dumps(learned_study(args.learned_study, args.n)), flush=True)
         return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the solve is a single-GPU kernel path "
@@ -204,6 +211,142 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, int(np.median(iters)))
     print(json.dumps(out), flush=True)
+
+
+def _cycles_to_reach(curve, target):
+    """Fractional number of cycles after which a residual curve (entries k = 0, 1, ...)
+    first reaches `target`, interpolating log-linearly between whole cycles; None
+    if it never does."""
+    for k, v in enumerate(curve):
+        if v <= target:
+            if k == 0:
+                return 0.0
+            a, b = np.log(curve[k - 1]), np.log(v)
+            return k - 1 + (a - np.log(target)) / (a - b) if a > b else float(k)
+    return None
+
+
+def learned_study(nseeds, n=256, ref_cycles=30, max_cycles=8, k_first=4):
+    """What an initial guess of the pressure cycles is worth, on fresh seeds of the
+    headline recipe (seeds 910000 + i: neither the training seeds 0-1999 nor the
+    headline's 900000).  For the first preconditioner application (k_first plain
+    cycles from zero in the solve) it finds how many cycles each start needs to
+    reach the residual of k_first plain cycles: from the trained network's guess
+    (32^3 level) and from the ideal guess a perfect predictor on level l (128^3,
+    64^3, 32^3, 16^3) could give (the converged solution averaged to that level,
+    same fit and prolongation).  Next to it: the measured cost of one pressure
+    cycle at this size and of one U-Net forward pass from 32^3 to 256^3 (BF16 on the
+    matrix cores), so that a predictor on level l pays only if its cycles saved x
+    cycle cost exceed its forward cost."""
+    import torch
+    import workloads as W
+    import paper_1901_07892_amd as S
+    from paper_1901_07892_amd import learned
+    dev = torch.device("cuda:0")
+    params, meta = learned.load_params()
+    td = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    rows = ["zero", "network_32^3"] + ["ideal_level%d_%d^3" % (l, n >> l) for l in range(1, S._binding.STUDY_ROWS - 1)]
+    seeds = []
+    cycle_ms = []
+    for i in range(nseeds):
+        seed = 910000 + i
+        t0 = time.time()
+        prob = W.config5(n_cells=n, seed=seed)
+        log("study seed %d: workload in %.1fs" % (seed, time.time() - t0))
+        rho = [td(r) for r in prob.rho_faces[:3]]
+        mu = td(prob.mu)
+        rhs_u = [td(f) for f in prob.rhs_u[:3]]
+        rhs_p = td(prob.rhs_p)
+        solver = S.StokesSolver(3, prob.n, prob.h, rho, mu, prob.dt)
+        net = None
+        if params is not None:
+            net = S.UNet(meta["grid"])
+            net.set_params(params)
+            S.stokes_attach_learned(solver.ctx, net, 0.9)
+        curves = S.stokes_learned_study(solver.ctx, rhs_u, rhs_p, ref_cycles, max_cycles)
+        # cost of one pressure cycle: the same call with 21 and with 1 reference cycles
+        tt = []
+        for rc in (1, 21):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            S.stokes_learned_study(solver.ctx, rhs_u, rhs_p, rc, 0)
+            torch.cuda.synchronize()
+            tt.append(time.perf_counter() - t)
+        cycle_ms.append((tt[1] - tt[0]) * 1e3 / 20)
+        # plain and learned solves of the same instance
+        xu = [torch.zeros_like(f) for f in rhs_u]
+        xp = torch.zeros_like(rhs_p)
+        solves = {}
+        for name, attach in (("plain", False), ("learned", True)):
+            if attach and net is None:
+                continue
+            S.stokes_attach_learned(solver.ctx, net if attach else None, 0.9)
+            for a in xu:
+                a.zero_()
+            xp.zero_()
+            st, stats = solver.solve(rhs_u, rhs_p, prob.tol, xu, xp)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for a in xu:
+                a.zero_()
+            xp.zero_()
+            st, stats = solver.solve(rhs_u, rhs_p, prob.tol, xu, xp)
+            torch.cuda.synchronize()
+            solves[name] = {"ms": (time.perf_counter() - t) * 1e3, "fgmres_iters": stats.iters, "status": st,
+                            "vcycles": stats.vcycles, "fell_back": stats.fell_back,
+                            "rel_res_true": stats.rel_res_true}
+        target = curves[0][k_first]
+        rec = {"seed": seed, "solids": len(prob.psi or []),
+               "target_residual_after_%d_plain_cycles" % k_first: target, "curves": {}, "cycles_to_target": {},
+               "cycles_saved": {}, "solves": solves}
+        for r, name in enumerate(rows):
+            c = curves[r]
+            if np.all(np.isnan(c)):
+                continue
+            rec["curves"][name] = [float(v) for v in c]
+            k = _cycles_to_reach(list(c), target)
+            rec["cycles_to_target"][name] = k
+            rec["cycles_saved"][name] = (k_first - k) if k is not None else None
+        log("seed %d: cycles to the residual of %d plain cycles: %s" % (
+            seed, k_first, {k: (round(v, 2) if v is not None else None) for k, v in rec["cycles_to_target"].items()}))
+        seeds.append(rec)
+        if net is not None:
+            net.close()
+        solver.close()
+        del solver
+        torch.cuda.empty_cache()
+    # U-Net forward cost by grid size
+    fwd = {}
+    for g in (32, 64, 128, 256):
+        net = S.UNet(g)
+        f = [torch.randn((g, g, g), dtype=torch.float32, device=dev) for _ in range(3)]
+        pred = torch.zeros_like(f[0])
+        net.forward(f[0], f[1], f[2], pred)
+        reps = 20 if g <= 64 else 3
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            net.forward(f[0], f[1], f[2], pred)
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) / reps * 1e3
+        fl = S.stokes_unet_forward_flops(g)
+        fwd["%d^3" % g] = {"us": us, "flops": fl, "TFLOPs": fl / (us * 1e-6) / 1e12,
+                           "frac_of_bf16_peak": fl / (us * 1e-6) / 2.5e15}
+        log("U-Net forward %d^3: %.1f us, %.1f TFLOP/s" % (g, us, fl / (us * 1e-6) / 1e12))
+        net.close()
+        del net, f, pred
+        torch.cuda.empty_cache()
+    saved = {}
+    for name in rows:
+        v = [r["cycles_saved"].get(name) for r in seeds if r["cycles_saved"].get(name) is not None]
+        if v:
+            saved[name] = {"mean": float(np.mean(v)), "min": float(np.min(v)), "max": float(np.max(v))}
+    return {"study": "learned-stage bound", "grid": n, "ref_cycles": ref_cycles, "first_application_cycles": k_first,
+            "pressure_cycle_ms": float(np.mean(cycle_ms)), "cycles_saved": saved, "unet_forward": fwd,
+            "model": {k: meta.get(k) for k in ("instances", "epochs", "fine_grid", "level_grid")} if meta else None,
+            "final_val_loss": meta["history"][-1]["val_loss"] if meta and meta.get("history") else None,
+            "seeds": seeds}
 
 
 def fp32_form(S, prob, rho, mu, rhs_u, rhs_p, xu64, xp64, overrides, ms64, steps):
@@ -592,9 +735,9 @@ def traffic_from_counters(fetch_dir, write_dir, n=256, precision=0, path=None):
                           "(bench.py --calibrate-copy); written by bench.py --traffic-from.")
     rec["commands"] = [
         "rocprofv3 --pmc FETCH_SIZE --output-format csv -d %s -o run -- python3 -u bench.py --steps 1 "
-        "--warmup 0 --no-cpu-baseline --no-forms --calibrate-copy" % fetch_dir,
+        "--warmup 0 --no-cpu-baseline --no-forms --no-configs --calibrate-copy" % fetch_dir,
         "rocprofv3 --pmc WRITE_SIZE --output-format csv -d %s -o run -- python3 -u bench.py --steps 1 "
-        "--warmup 0 --no-cpu-baseline --no-forms --calibrate-copy" % write_dir,
+        "--warmup 0 --no-cpu-baseline --no-forms --no-configs --calibrate-copy" % write_dir,
         "python3 bench.py --traffic-from %s %s" % (fetch_dir, write_dir)]
     rec.setdefault("entries", {})["1/%d/%d" % (n, precision)] = entry
     with open(path, "w") as f:

@@ -522,6 +522,26 @@ stokes_status stokes_attach_learned(stokes_ctx *ctx, stokes_unet *net, double st
 stokes_status stokes_learned_tuple(stokes_ctx *ctx, const double *const rhs_u[3], const double *rhs_p, int n,
                                    int cycles, float *f0, float *f1, float *s_c, float *phi_c);
 
+/* Measurement hook for the learned stage: what an initial guess is worth to
+ * the pressure cycles of the first preconditioner application on the packed
+ * right-hand side (rhs_u, rhs_p as in stokes_solve; 3D only).  The reference
+ * solution phi* of that pressure subsolve is `ref_cycles` (>= 1) cycles from
+ * zero.  res (host, STOKES_STUDY_ROWS x (max_cycles + 1), row-major; 0 <=
+ * max_cycles <= 64) receives the relative residual ||s - (-L_rho) phi_k|| /
+ * ||s|| after k = 0 .. max_cycles cycles started from:
+ *   row 0      zero (the plain solve);
+ *   row 1      the attached network's guess (NaN without a network);
+ *   row 1 + l  (l = 1 .. STOKES_STUDY_ROWS - 2) the ideal guess of a perfect
+ *              predictor on multigrid level l (2^l times coarser): phi*
+ *              averaged to that level, then the amplitude fit and trilinear
+ *              prolongation the network's output takes (NaN if the hierarchy
+ *              has no level l).
+ * The solve is not changed; the Krylov scratch it uses is cleared again by the
+ * next solve.  Blocks until done. */
+#define STOKES_STUDY_ROWS 6
+stokes_status stokes_learned_study(stokes_ctx *ctx, const double *const rhs_u[3], const double *rhs_p, int ref_cycles,
+                                   int max_cycles, double *res);
+
 /* ---------------------------------------------------------------------------
  * Test hook: one kernel of the pressure multigrid on the finest level, run on
  * caller data exactly as the cycle launches it.  The operator is the pressure

@@ -152,6 +152,8 @@ def load_library():
     L.stokes_attach_learned.restype = C.c_int
     L.stokes_learned_tuple.argtypes = [C.c_void_p, C.c_void_p * 3, dp, C.c_int, C.c_int, dp, dp, dp, dp]
     L.stokes_learned_tuple.restype = C.c_int
+    L.stokes_learned_study.argtypes = [C.c_void_p, C.c_void_p * 3, dp, C.c_int, C.c_int, C.POINTER(C.c_double)]
+    L.stokes_learned_study.restype = C.c_int
     L.stokes_wave_inflow.argtypes = [C.POINTER(StokesGrid), C.POINTER(StokesWave), C.c_double, dp, dp, dp]
     L.stokes_wave_inflow.restype = C.c_int
     L.stokes_inflow_lift.argtypes = [C.c_void_p, dp, dp, C.c_void_p * 3, dp]
@@ -574,3 +576,20 @@ def stokes_learned_tuple(ctx, rhs_u, rhs_p, n, cycles, f0, f1, s_c, phi_c) -> No
                                 _fptr(f0), _fptr(f1), _fptr(s_c), _fptr(phi_c))
     if st != 0:
         raise StokesError(st, L.stokes_last_error(ctx).decode())
+
+
+STUDY_ROWS = 6
+
+
+def stokes_learned_study(ctx, rhs_u, rhs_p, ref_cycles: int, max_cycles: int):
+    """Relative pressure residuals after 0..max_cycles cycles of the first
+    preconditioner application from each start (rows: zero, the network's
+    guess, the ideal guess on levels 1..STUDY_ROWS-2); a numpy array."""
+    import numpy as np
+    L = load_library()
+    out = np.full((STUDY_ROWS, int(max_cycles) + 1), np.nan)
+    st = L.stokes_learned_study(ctx, _ptr3(list(rhs_u) + [None] * 3), _ptr(rhs_p), int(ref_cycles), int(max_cycles),
+                                out.ctypes.data_as(C.POINTER(C.c_double)))
+    if st != 0:
+        raise StokesError(st, L.stokes_last_error(ctx).decode())
+    return out

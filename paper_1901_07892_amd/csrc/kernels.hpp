@@ -1708,6 +1708,30 @@ __global__ void __launch_bounds__(kBlock) k_sub_mean(Box b, const double *__rest
     p[idx] -= sum[0] / ((double)b.nx * b.ny * b.nz);
 }
 
+// Partial sums of the squared residual r - (-L_rho) e and of r^2 over the cells of
+// one 3D level (grid-stride; block b writes partial[b] and partial[gridDim.x + b]).
+template <class R>
+__global__ void __launch_bounds__(kBlock) k_p_res_partial(Box b, const R *__restrict__ e, const R *__restrict__ r,
+        const R *__restrict__ bx, const R *__restrict__ by, const R *__restrict__ bz, double *__restrict__ partial) {
+    __shared__ double lds[2 * (kBlock / 64)];
+    double v[2] = {0.0, 0.0};
+    for (int idx = blockIdx.x * kBlock + threadIdx.x; idx < b.nb; idx += gridDim.x * kBlock) {
+        int i, j, k;
+        decompose(b, idx, i, j, k);
+        if (!is_cell(b, i, j, k)) continue;
+        R off, dg;
+        prow<3, R>(b, idx, e, bx, by, bz, off, dg);
+        const double res = (double)r[idx] - ((double)dg * (double)e[idx] - (double)off);
+        v[0] += res * res;
+        v[1] += (double)r[idx] * (double)r[idx];
+    }
+    block_reduce<2>(v, lds);
+    if (threadIdx.x == 0) {
+        partial[blockIdx.x] = v[0];
+        partial[gridDim.x + blockIdx.x] = v[1];
+    }
+}
+
 // partial sums (plain) of a range; used for means and norms of sub-blocks
 __global__ void __launch_bounds__(kBlock) k_partial_sum(long long n, const double *__restrict__ x, int squared,
         double *__restrict__ partial) {

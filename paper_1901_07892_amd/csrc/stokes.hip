@@ -551,19 +551,19 @@ R *p_vcycle(stokes_ctx &c, MG<R> &mg, int l, R *e, R *r, bool zero_guess) {
 // squares against that level's operator, and the result is prolonged
 // (trilinearly, level by level) to the finest level.
 template <class R>
-void learned_guess(stokes_ctx &c, MG<R> &mg, R *phi0) {
-    const int lc = c.lc;
+void restrict_rhs_to(stokes_ctx &c, MG<R> &mg, int lc) {
     const R *src = mg.L[0].rp;
     for (int l = 0; l < lc; ++l) {
         k_restrict_avg3<R><<<nblocks_box(mg.L[l + 1].b), kBlock, 0, c.stream>>>(mg.L[l].b, mg.L[l + 1].b, src, mg.L[l + 1].rp);
         src = mg.L[l + 1].rp;
     }
+}
+
+// A coarse prediction in mg.L[lc].ep2 (with the restricted right-hand side in
+// that level's rp) -> fitted amplitude, prolonged trilinearly to phi0.
+template <class R>
+void guess_from_coarse(stokes_ctx &c, MG<R> &mg, int lc, R *phi0) {
     Level<R> &C = mg.L[lc];
-    const int nc = C.b.nx * C.b.ny * C.b.nz;
-    k_normalise_planar<R><<<1, 1024, 0, c.stream>>>(C.b, C.rp, 0, c.lf[2], c.lstat);
-    stokes_status st = stokes_unet_forward(c.net, c.lf[0], c.lf[1], c.lf[2], c.lf[3]);
-    if (st != STOKES_OK) throw HipError{hipErrorUnknown, "stokes_unet_forward"};
-    k_planar_to_box<R><<<(nc + kBlock - 1) / kBlock, kBlock, 0, c.stream>>>(C.b, c.lf[3], C.ep2);
     k_p_apply3<R><<<nblocks_box(C.b), kBlock, 0, c.stream>>>(C.b, C.ep2, C.beta[0], C.beta[1], C.beta[2], C.ep);
     k_fit_amplitude<R><<<1, 1024, 0, c.stream>>>(C.b, C.ep, C.rp, C.ep2, c.lstat);
     R *cur = C.ep2;
@@ -573,6 +573,19 @@ void learned_guess(stokes_ctx &c, MG<R> &mg, R *phi0) {
         k_p_prolong_add<3, R><<<nblocks_box(mg.L[l].b), kBlock, 0, c.stream>>>(mg.L[l].b, mg.L[l + 1].b, 1, cur, dst);
         cur = dst;
     }
+}
+
+template <class R>
+void learned_guess(stokes_ctx &c, MG<R> &mg, R *phi0) {
+    const int lc = c.lc;
+    restrict_rhs_to<R>(c, mg, lc);
+    Level<R> &C = mg.L[lc];
+    const int nc = C.b.nx * C.b.ny * C.b.nz;
+    k_normalise_planar<R><<<1, 1024, 0, c.stream>>>(C.b, C.rp, 0, c.lf[2], c.lstat);
+    stokes_status st = stokes_unet_forward(c.net, c.lf[0], c.lf[1], c.lf[2], c.lf[3]);
+    if (st != STOKES_OK) throw HipError{hipErrorUnknown, "stokes_unet_forward"};
+    k_planar_to_box<R><<<(nc + kBlock - 1) / kBlock, kBlock, 0, c.stream>>>(C.b, c.lf[3], C.ep2);
+    guess_from_coarse<R>(c, mg, lc, phi0);
 }
 
 // Pressure subsolve of the preconditioner: cyc_now cycles on -L_rho phi = r
@@ -1407,7 +1420,7 @@ void learned_static(stokes_ctx &c, MG<R> &mg, int lc, float *f0, float *f1) {
 // pressure right-hand side of the first preconditioner application (unit RMS)
 // and the restricted converged pressure solution (zero mean, unit RMS).
 template <class R>
-void learned_tuple(stokes_ctx &c, MG<R> &mg, int lc, int cycles, float *f0, float *f1, float *s_c, float *phi_c) {
+void first_p3_rhs(stokes_ctx &c, MG<R> &mg) {
     const Box &fb = c.fine;
     Level<R> &L0 = mg.L[0];
     double *v = c.bk;
@@ -1436,6 +1449,15 @@ void learned_tuple(stokes_ctx &c, MG<R> &mg, int lc, int cycles, float *f0, floa
         for (int cyc = 0; cyc < std::max(1, c.opt.vel_cycles); ++cyc) vel_vcycle<3, R>(c, mg, 0, eu, ru, cyc == 0);
         k_precond_div<3, R><<<nblocks_box(fb), kBlock, 0, c.stream>>>(fb, eu[0], eu[1], eu[2], c.fld(v, 3), c.dt, c.q, L0.rp);
     }
+}
+
+// Training tuple on the level with n^3 cells: static features, the restricted
+// pressure right-hand side of the first preconditioner application (unit RMS)
+// and the restricted converged pressure solution (zero mean, unit RMS).
+template <class R>
+void learned_tuple(stokes_ctx &c, MG<R> &mg, int lc, int cycles, float *f0, float *f1, float *s_c, float *phi_c) {
+    Level<R> &L0 = mg.L[0];
+    first_p3_rhs<R>(c, mg);
     R *phi = L0.ep;
     for (int cyc = 0; cyc < cycles; ++cyc) phi = p_vcycle<3, R>(c, mg, 0, phi, L0.rp, cyc == 0);
     const R *ss = L0.rp;
@@ -1451,6 +1473,72 @@ void learned_tuple(stokes_ctx &c, MG<R> &mg, int lc, int cycles, float *f0, floa
     k_normalise_planar<R><<<1, 1024, 0, c.stream>>>(C.b, ss, 0, s_c, c.lstat);
     k_normalise_planar<R><<<1, 1024, 0, c.stream>>>(C.b, pp, 1, phi_c, c.lstat + 3);
     learned_static<R>(c, mg, lc, f0, f1);
+}
+
+// What an initial guess is worth to the pressure cycles of the first
+// preconditioner application (a measurement; the solve never calls it).  The
+// reference solution phi* of that subsolve is ref_cycles cycles from zero.
+// Row 0 starts from zero, row 1 from the attached network's guess, row 1 + l
+// (l = 1 .. kStudyRows - 2) from the ideal guess a perfect predictor on level l
+// could give: phi* averaged down to level l, then the same amplitude fit and
+// trilinear prolongation the network's output takes.  out[row][k] = relative
+// residual ||s - (-L_rho) phi_k|| / ||s|| after k = 0 .. max_cycles cycles;
+// NaN for a row with no network or no such level.
+constexpr int kStudyRows = STOKES_STUDY_ROWS;
+
+template <class R>
+double p_rel_residual(stokes_ctx &c, MG<R> &mg, const R *e) {
+    Level<R> &L0 = mg.L[0];
+    const int g = kRedBlocks;
+    k_p_res_partial<R><<<g, kBlock, 0, c.stream>>>(L0.b, e, L0.rp, L0.beta[0], L0.beta[1], L0.beta[2], c.partial);
+    k_reduce_partials<<<2, kBlock, 0, c.stream>>>(g, c.partial, c.dsc, 0, nullptr);
+    double h[2];
+    sync_read(c, c.dsc, h, 2);
+    return h[1] > 0.0 ? std::sqrt(h[0] / h[1]) : 0.0;
+}
+
+template <class R>
+void learned_study(stokes_ctx &c, MG<R> &mg, int ref_cycles, int max_cycles, double *out) {
+    Level<R> &L0 = mg.L[0];
+    const int nk = max_cycles + 1;
+    first_p3_rhs<R>(c, mg);
+    // phi* into the first Krylov Z vector (scratch here; re-cleared before the next solve)
+    R *star = reinterpret_cast<R *>(c.vec(c.Z, 0)) + L0.b.guard;
+    R *phi = L0.ep;
+    for (int k = 0; k < ref_cycles; ++k) phi = p_vcycle<3, R>(c, mg, 0, phi, L0.rp, k == 0);
+    k_cast<R, R><<<nblocks_stream(L0.b.stride), kBlock, 0, c.stream>>>(L0.b.stride, phi - L0.b.guard, star - L0.b.guard);
+    for (int row = 0; row < kStudyRows; ++row) {
+        const int l = row - 1;
+        const bool have = row == 0 || (row == 1 && c.net && c.lc >= 0) || (row >= 2 && l < mg.nlev);
+        if (!have) {
+            for (int k = 0; k < nk; ++k) out[row * nk + k] = std::nan("");
+            continue;
+        }
+        bool zero = row == 0;
+        if (zero) {
+            fill<R>(c, L0.ep - L0.b.guard, L0.b.stride, R(0));
+        } else if (row == 1) {
+            learned_guess<R>(c, mg, L0.ep);
+        } else {
+            const R *src = star;
+            for (int m = 0; m < l; ++m) {
+                k_restrict_avg3<R><<<nblocks_box(mg.L[m + 1].b), kBlock, 0, c.stream>>>(mg.L[m].b, mg.L[m + 1].b, src,
+                                                                                       mg.L[m + 1].ep);
+                src = mg.L[m + 1].ep;
+            }
+            Level<R> &C = mg.L[l];
+            k_cast<R, R><<<nblocks_stream(C.b.stride), kBlock, 0, c.stream>>>(C.b.stride, C.ep - C.b.guard, C.ep2 - C.b.guard);
+            restrict_rhs_to<R>(c, mg, l);
+            guess_from_coarse<R>(c, mg, l, L0.ep);
+        }
+        phi = L0.ep;
+        out[row * nk] = p_rel_residual<R>(c, mg, phi);
+        for (int k = 1; k < nk; ++k) {
+            phi = p_vcycle<3, R>(c, mg, 0, phi, L0.rp, zero && k == 1);
+            out[row * nk + k] = p_rel_residual<R>(c, mg, phi);
+        }
+    }
+    c.z_clear = 0;
 }
 
 // Right-hand-side lift of Dirichlet inflow data on the x = 0 side: the rows next
@@ -1776,6 +1864,28 @@ stokes_status stokes_learned_tuple(stokes_ctx *ctx, const double *const rhs_u[3]
         pack_vector<3>(*ctx, rhs_u, rhs_p, ctx->bk);
         if (ctx->opt.precision == 1) learned_tuple<float>(*ctx, ctx->mgf, lc, cycles, f0, f1, s_c, phi_c);
         else learned_tuple<double>(*ctx, ctx->mgd, lc, cycles, f0, f1, s_c, phi_c);
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        HIPCHK(hipGetLastError());
+    } catch (const HipError &e) {
+        ctx->err = std::string("HIP error in ") + e.what + ": " + hipGetErrorString(e.e);
+        return STOKES_EHIP;
+    }
+    return STOKES_OK;
+}
+
+stokes_status stokes_learned_study(stokes_ctx *ctx, const double *const rhs_u[3], const double *rhs_p, int ref_cycles,
+                                   int max_cycles, double *res) {
+    if (!ctx) return STOKES_EINVAL;
+    ctx->err.clear();
+    if (ctx->dim != 3 || !rhs_u || !rhs_u[0] || !rhs_u[1] || !rhs_u[2] || !rhs_p || !res || ref_cycles < 1 ||
+        max_cycles < 0 || max_cycles > 64) {
+        ctx->err = "bad argument";
+        return STOKES_EINVAL;
+    }
+    try {
+        pack_vector<3>(*ctx, rhs_u, rhs_p, ctx->bk);
+        if (ctx->opt.precision == 1) learned_study<float>(*ctx, ctx->mgf, ref_cycles, max_cycles, res);
+        else learned_study<double>(*ctx, ctx->mgd, ref_cycles, max_cycles, res);
         HIPCHK(hipStreamSynchronize(ctx->stream));
         HIPCHK(hipGetLastError());
     } catch (const HipError &e) {
