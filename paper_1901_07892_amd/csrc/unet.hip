@@ -3,10 +3,10 @@
 // backward pass and an Adam optimiser, all hand-written.
 //
 // Activations are channel-last BF16 ([z][y][x][c], c fastest) on cubic grids
-// of n^3 cells (n divisible by 8).  Convolutions are implicit GEMMs on
-// v_mfma_f32_16x16x16_bf16: a wavefront computes 16 output channels x 16
-// voxels, the K dimension running over (tap, input channel); the input tile
-// with its 1-voxel halo is staged in LDS.  Architecture (layer: level, in ->
+// of n^3 cells (n divisible by 8).  Convolutions are implicit GEMMs on the
+// matrix cores (v_mfma_f32_16x16x32_bf16 for grids of at least 16 cells per
+// axis, see k_conv): the K dimension runs over (tap, input channel) and the
+// input tile with its 1-voxel halo is staged in LDS.  Architecture (layer: level, in ->
 // out channels):
 //   encoder  e0a 0 16->16, e0b 0 16->16 (s0), pool
 //            e1a 1 16->32, e1b 1 32->32 (s1), pool
@@ -33,8 +33,10 @@ namespace {
 typedef uint16_t bf16;
 typedef short s4v __attribute__((ext_vector_type(4)));
 typedef float f4v __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 
 constexpr int kLayers = 15;
+constexpr int kBiasBlocks = 1024;      // blocks (partial sums) of the bias-gradient launch
 constexpr int kLevels = 4;
 constexpr int kCh[kLevels] = {16, 32, 48, 64};
 
@@ -64,74 +66,119 @@ __host__ __device__ inline bf16 f2bf(float f) {
 // out[v][co] = act( sum_{tap, ci} W[co][tap][ci] * in[v + off(tap)][ci] + bias[co] + skip[v][co] )
 // in:  n^3 x CIN, W: COUT x 27 x CIN (bf16), out: n^3 x COUT.  Zero padding.
 // mask != nullptr (backward-data use): the result is multiplied by (mask[v][co] > 0).
-// Block: 16 (x) x 4 (y) voxels at one z, 4 wavefronts (one y row each).
+//
+// Implicit GEMM on v_mfma_f32_16x16x32_bf16 with K = (tap, ci) flattened (27 CIN,
+// in chunks of 32; a lane's 8 consecutive k never straddle a tap since CIN is a
+// multiple of 16).  A block owns 16 (x) x 4 (y) voxels and marches over zc
+// z-planes; wavefront w computes y row w, all COUT channels at once (one
+// accumulator per 16 channels, so each B operand read from LDS feeds COUT/16
+// MFMAs).  LDS holds a ring of three input planes with the 1-voxel x-y halo
+// (voxel stride CIN + 8 to spread the banks) and, when they fit in 32 KiB (the
+// 16 -> 16, 16 -> 32 and 32 -> 16 layers, which run on the two finest levels),
+// the layer's weights, staged once per block; larger layers read their weights
+// through the caches (staging 55 KiB and more would leave one block per CU).
+constexpr int kConvWLds = 32 * 1024;
+
 template <int CIN, int COUT>
-__global__ void __launch_bounds__(256) k_conv(int n, const bf16 *__restrict__ in, const bf16 *__restrict__ W,
+__global__ void __launch_bounds__(256) k_conv(int n, int zc, const bf16 *__restrict__ in, const bf16 *__restrict__ W,
         const float *__restrict__ bias, const bf16 *__restrict__ skip, const bf16 *__restrict__ mask, int relu,
         bf16 *__restrict__ out, float *__restrict__ out32) {
-    __shared__ bf16 halo[3 * 6 * 18 * CIN];
-    const int x0 = blockIdx.x * 16, y0 = blockIdx.y * 4, z = blockIdx.z;
-    const int tid = threadIdx.x;
-    // stage the input tile with its halo, 4 channels (8 bytes) per load
-    constexpr int Q = CIN / 4;
-    for (int t = tid; t < 324 * Q; t += 256) {
-        const int vq = t / Q, cq = t % Q;
-        const int hx = vq % 18, hy = (vq / 18) % 6, hz = vq / 108;
-        const int gx = x0 + hx - 1, gy = y0 + hy - 1, gz = z + hz - 1;
-        uint2 val = make_uint2(0u, 0u);
-        if (gx >= 0 && gx < n && gy >= 0 && gy < n && gz >= 0 && gz < n)
-            val = *reinterpret_cast<const uint2 *>(in + ((size_t)((gz * n + gy) * n + gx)) * CIN + cq * 4);
-        *reinterpret_cast<uint2 *>(halo + vq * CIN + cq * 4) = val;
+    constexpr int K = 27 * CIN, NCH = (K + 31) / 32, NCO = COUT / 16;
+    constexpr int VS = CIN + 8, HP = 6 * 18 * VS;          // halo voxel stride, plane size (elements)
+    constexpr int WS = K + 8;                              // LDS weight row stride (elements)
+    constexpr bool WL = COUT * WS * 2 <= kConvWLds;
+    __shared__ __attribute__((aligned(16))) bf16 ring[3 * HP];
+    __shared__ __attribute__((aligned(16))) bf16 wsh[WL ? COUT * WS : 8];
+    const int x0 = blockIdx.x * 16, y0 = blockIdx.y * 4, z0 = blockIdx.z * zc;
+    const int z1 = min(z0 + zc, n);
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const int j = lane & 15, g = lane >> 4;
+    constexpr int Q = CIN / 8;                             // 16-byte quads per voxel
+    auto load_plane = [&](int p) {                         // input plane p -> ring slot p mod 3
+        bf16 *dst = ring + ((p + 3) % 3) * HP;
+        for (int t = tid; t < 108 * Q; t += 256) {
+            const int vq = t / Q, cq = t % Q;
+            const int hx = vq % 18, hy = vq / 18;
+            const int gx = x0 + hx - 1, gy = y0 + hy - 1;
+            uint4 val = make_uint4(0u, 0u, 0u, 0u);
+            if (gx >= 0 && gx < n && gy >= 0 && gy < n && p >= 0 && p < n)
+                val = *reinterpret_cast<const uint4 *>(in + ((size_t)((p * n + gy) * n + gx)) * CIN + cq * 8);
+            *reinterpret_cast<uint4 *>(dst + (hy * 18 + hx) * VS + cq * 8) = val;
+        }
+    };
+    if (WL) {
+        for (int t = tid; t < COUT * (K / 8); t += 256) {
+            const int co = t / (K / 8), q = t % (K / 8);
+            *reinterpret_cast<uint4 *>(wsh + co * WS + q * 8) =
+                *reinterpret_cast<const uint4 *>(W + (size_t)co * K + q * 8);
+        }
     }
-    __syncthreads();
-    const int w = tid >> 6, lane = tid & 63;
-    const int j = lane & 15, kq = lane >> 4;
+    load_plane(z0 - 1);
+    load_plane(z0);
     const int x = x0 + j, y = y0 + w;
-    const size_t v = (size_t)((z * n + y) * n + x);
-#pragma unroll 1
-    for (int co0 = 0; co0 < COUT; co0 += 16) {
-        f4v acc = {0.f, 0.f, 0.f, 0.f};
-        const bf16 *wrow = W + (size_t)(co0 + j) * 27 * CIN + kq * 4;
-#pragma unroll 1
-        for (int tap = 0; tap < 27; ++tap) {
-            const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;
-            const bf16 *hb = halo + ((dz * 6 + (w + dy)) * 18 + (j + dx)) * CIN + kq * 4;
+    for (int z = z0; z < z1; ++z) {
+        load_plane(z + 1);
+        __syncthreads();
+        f4v acc[NCO];
 #pragma unroll
-            for (int ci0 = 0; ci0 < CIN; ci0 += 16) {
-                s4v a = *reinterpret_cast<const s4v *>(wrow + tap * CIN + ci0);
-                s4v bb = *reinterpret_cast<const s4v *>(hb + ci0);
-                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bb, acc, 0, 0, 0);
+        for (int c = 0; c < NCO; ++c) acc[c] = f4v{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+        for (int ch = 0; ch < NCH; ++ch) {
+            const int k0 = ch * 32 + g * 8;
+            uint4 bq = make_uint4(0u, 0u, 0u, 0u);
+            const bool kin = k0 < K;
+            if (kin) {
+                const int tap = k0 / CIN, ci = k0 % CIN;
+                const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;
+                bq = *reinterpret_cast<const uint4 *>(ring + ((z - 1 + dz + 3) % 3) * HP + ((w + dy) * 18 + j + dx) * VS + ci);
+            }
+            const bf8v bv = __builtin_bit_cast(bf8v, bq);
+#pragma unroll
+            for (int c = 0; c < NCO; ++c) {
+                uint4 aq = make_uint4(0u, 0u, 0u, 0u);
+                if (kin) {
+                    if (WL) aq = *reinterpret_cast<const uint4 *>(wsh + (c * 16 + j) * WS + k0);
+                    else aq = *reinterpret_cast<const uint4 *>(W + (size_t)(c * 16 + j) * K + k0);
+                }
+                acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8v, aq), bv, acc[c], 0, 0, 0);
             }
         }
-        // lane holds voxel j and output channels co0 + 4*kq + e
-        float r[4] = {acc[0], acc[1], acc[2], acc[3]};
+        // lane holds voxel x and output channels 16 c + 4 g + e
+        const size_t v = (size_t)((z * n + y) * n + x);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int co = co0 + kq * 4 + e;
-            float val = r[e];
-            if (bias) val += bias[co];
-            if (skip) val += bf2f(skip[v * COUT + co]);
-            if (relu) val = fmaxf(val, 0.f);
-            if (mask && !(bf2f(mask[v * COUT + co]) > 0.f)) val = 0.f;
-            r[e] = val;
+        for (int c = 0; c < NCO; ++c) {
+            const int cb = c * 16 + g * 4;
+            float r[4] = {acc[c][0], acc[c][1], acc[c][2], acc[c][3]};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int co = cb + e;
+                float val = r[e];
+                if (bias) val += bias[co];
+                if (skip) val += bf2f(skip[v * COUT + co]);
+                if (relu) val = fmaxf(val, 0.f);
+                if (mask && !(bf2f(mask[v * COUT + co]) > 0.f)) val = 0.f;
+                r[e] = val;
+            }
+            if (out) {
+                ushort4 o;
+                o.x = f2bf(r[0]); o.y = f2bf(r[1]); o.z = f2bf(r[2]); o.w = f2bf(r[3]);
+                *reinterpret_cast<ushort4 *>(out + v * COUT + cb) = o;
+            }
+            if (out32) *reinterpret_cast<float4 *>(out32 + v * COUT + cb) = make_float4(r[0], r[1], r[2], r[3]);
         }
-        if (out) {
-            ushort4 o;
-            o.x = f2bf(r[0]); o.y = f2bf(r[1]); o.z = f2bf(r[2]); o.w = f2bf(r[3]);
-            *reinterpret_cast<ushort4 *>(out + v * COUT + co0 + kq * 4) = o;
-        }
-        if (out32) {
-            *reinterpret_cast<float4 *>(out32 + v * COUT + co0 + kq * 4) = make_float4(r[0], r[1], r[2], r[3]);
-        }
+        __syncthreads();                                   // ring slot of z - 1 is loaded next
     }
 }
 
-// Weight gradient: dW[co][tap][ci] += sum_v dy[v][co] * in[v + off(tap)][ci].
+// Weight gradient: dW[co][tap][ci] = sum_v dy[v][co] * in[v + off(tap)][ci], as
+// one partial copy of dW per block along x (part[blockIdx.x][co][tap][ci]),
+// summed in block order by k_sum_partials so that training is deterministic.
 // Grid: x = voxel-tile groups (each block walks `tiles` tiles of 16x4x1 voxels),
 // y = (co tile, ci tile) pair.  Wave w accumulates the taps w, w+4, ... .
 template <int CIN, int COUT>
 __global__ void __launch_bounds__(256) k_conv_wgrad(int n, int tiles, const bf16 *__restrict__ in,
-        const bf16 *__restrict__ dy, float *__restrict__ dW) {
+        const bf16 *__restrict__ dy, float *__restrict__ part) {
+    float *dW = part + (size_t)blockIdx.x * COUT * 27 * CIN;
     __shared__ bf16 hx_s[3 * 6 * 18 * 16];   // input halo, 16 channels of this ci tile
     __shared__ bf16 dy_s[64 * 16];           // gradient tile, 16 channels of this co tile
     constexpr int NCI = CIN / 16;
@@ -191,13 +238,12 @@ __global__ void __launch_bounds__(256) k_conv_wgrad(int n, int tiles, const bf16
         const int tap = w + 4 * t;
         if (tap < 27) {
 #pragma unroll
-            for (int e = 0; e < 4; ++e)
-                atomicAdd(dW + ((size_t)(co0 + kq * 4 + e) * 27 + tap) * CIN + ci0 + j, acc[t][e]);
+            for (int e = 0; e < 4; ++e) dW[((size_t)(co0 + kq * 4 + e) * 27 + tap) * CIN + ci0 + j] = acc[t][e];
         }
     }
 }
 
-// Small grids (n < 16): the same convolution without LDS staging.  A wavefront
+// Small grids (n < 16, or not a multiple of 16): the same convolution without LDS staging.  A wavefront
 // takes 16 consecutive voxels of the flattened grid and gathers its operands
 // from global memory (zero outside the grid).
 template <int CIN, int COUT>
@@ -249,10 +295,12 @@ __global__ void __launch_bounds__(256) k_conv_small(int n, const bf16 *__restric
 }
 
 // Small-grid weight gradient: one wavefront per (tap, co tile, ci tile) and
-// voxel chunk; operands gathered from global memory.
+// voxel chunk; operands gathered from global memory; one partial copy of dW
+// per chunk (as k_conv_wgrad).
 template <int CIN, int COUT>
 __global__ void __launch_bounds__(64) k_conv_wgrad_small(int n, int chunk, const bf16 *__restrict__ in,
-        const bf16 *__restrict__ dy, float *__restrict__ dW) {
+        const bf16 *__restrict__ dy, float *__restrict__ part) {
+    float *dW = part + (size_t)blockIdx.x * COUT * 27 * CIN;
     constexpr int NCI = CIN / 16;
     const int tap = blockIdx.y % 27, pair = blockIdx.y / 27;
     const int co0 = (pair / NCI) * 16, ci0 = (pair % NCI) * 16;
@@ -278,7 +326,7 @@ __global__ void __launch_bounds__(64) k_conv_wgrad_small(int n, int chunk, const
         acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bb, acc, 0, 0, 0);
     }
 #pragma unroll
-    for (int e = 0; e < 4; ++e) atomicAdd(dW + ((size_t)(co0 + kq * 4 + e) * 27 + tap) * CIN + ci0 + j, acc[e]);
+    for (int e = 0; e < 4; ++e) dW[((size_t)(co0 + kq * 4 + e) * 27 + tap) * CIN + ci0 + j] = acc[e];
 }
 
 // Backward-data weights: Wt[ci][26 - tap][co] = W[co][tap][ci]
@@ -290,14 +338,33 @@ __global__ void k_flip_weights(int cin, int cout, const bf16 *__restrict__ W, bf
     Wt[((size_t)ci * 27 + (26 - tap)) * cout + co] = W[t];
 }
 
-// bias gradient: db[c] += sum_v dy[v][c]  (block-strided partial sums, then atomics)
-__global__ void k_bias_grad(long long nv, int C, const bf16 *__restrict__ dy, float *__restrict__ db) {
+// out[i] += sum_b part[b][i] over b = 0 .. nb-1 in order (i < m)
+__global__ void k_sum_partials(long long m, int nb, const float *__restrict__ part, float *__restrict__ out) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (long long)gridDim.x * blockDim.x) {
+        float acc = 0.f;
+        for (int b = 0; b < nb; ++b) acc += part[(size_t)b * m + i];
+        out[i] += acc;
+    }
+}
+
+// bias gradient, one partial per block: part[block][c] = sum over the block's
+// voxels of dy[v][c] (block-strided; the block's lane groups summed in order)
+__global__ void __launch_bounds__(256) k_bias_grad(long long nv, int C, const bf16 *__restrict__ dy,
+                                                   float *__restrict__ part) {
+    __shared__ float sh[256];
     const int c = threadIdx.x % C;
     const int lanes = blockDim.x / C;
     float s = 0.f;
-    for (long long v = (long long)blockIdx.x * lanes + threadIdx.x / C; v < nv; v += (long long)gridDim.x * lanes)
-        s += bf2f(dy[v * C + c]);
-    if (threadIdx.x / C < lanes) atomicAdd(db + c, s);
+    if (threadIdx.x / C < lanes)
+        for (long long v = (long long)blockIdx.x * lanes + threadIdx.x / C; v < nv; v += (long long)gridDim.x * lanes)
+            s += bf2f(dy[v * C + c]);
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x < C) {
+        float acc = 0.f;
+        for (int gq = 0; gq < lanes; ++gq) acc += sh[gq * C + threadIdx.x];
+        part[(size_t)blockIdx.x * C + threadIdx.x] = acc;
+    }
 }
 
 // g = (g1 + g2) * (act > 0)   (g2 optional), elementwise over n
@@ -389,8 +456,8 @@ __global__ void k_unpack_output(long long nv, const float *__restrict__ y, float
 }
 
 // mean-square loss on channel 0 and its gradient (BF16, channel-last, 16 channels)
-__global__ void k_mse(long long nv, const float *__restrict__ y, const float *__restrict__ target,
-                      bf16 *__restrict__ dy, float *__restrict__ loss) {
+__global__ void __launch_bounds__(256) k_mse(long long nv, const float *__restrict__ y, const float *__restrict__ target,
+                      bf16 *__restrict__ dy, float *__restrict__ part) {
     long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     float l = 0.f;
     if (v < nv) {
@@ -400,7 +467,10 @@ __global__ void k_mse(long long nv, const float *__restrict__ y, const float *__
         for (int c = 1; c < 16; ++c) dy[v * 16 + c] = 0;
     }
     for (int o = 32; o > 0; o >>= 1) l += __shfl_down(l, o, 64);
-    if ((threadIdx.x & 63) == 0) atomicAdd(loss, l / (float)nv);
+    __shared__ float sh[4];
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = l / (float)nv;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
 }
 
 // Adam on FP32 master parameters; refreshes the BF16 weight copy
@@ -440,29 +510,53 @@ __global__ void k_init_uniform(long long n, unsigned long long seed, float a, fl
 template <int CIN, int COUT>
 void conv_launch(hipStream_t s, int n, const bf16 *in, const bf16 *W, const float *bias, const bf16 *skip,
                  const bf16 *mask, int relu, bf16 *out, float *out32) {
-    if (n < 16) {
+    if (n < 16 || n % 16 != 0) {
         long long nv = (long long)n * n * n;
         k_conv_small<CIN, COUT><<<(unsigned)((nv + 63) / 64), 256, 0, s>>>(n, in, W, bias, skip, mask, relu, out, out32);
         return;
     }
-    dim3 g(n / 16, n / 4, n);
-    k_conv<CIN, COUT><<<g, 256, 0, s>>>(n, in, W, bias, skip, mask, relu, out, out32);
+    // z planes per block: enough blocks to fill the chip, at most 16 planes
+    const long long tiles = (long long)(n / 16) * (n / 4);
+    int zc = 1;
+    while (zc < 16 && tiles * (n / (2 * zc)) >= 2048 && n % (2 * zc) == 0) zc *= 2;
+    dim3 g(n / 16, n / 4, n / zc);
+    k_conv<CIN, COUT><<<g, 256, 0, s>>>(n, zc, in, W, bias, skip, mask, relu, out, out32);
 }
 
-template <int CIN, int COUT>
-void wgrad_launch(hipStream_t s, int n, const bf16 *in, const bf16 *dy, float *dW) {
-    if (n < 16) {
-        long long nv = (long long)n * n * n;
-        const int chunk = 64;
-        dim3 g((unsigned)((nv + chunk - 1) / chunk), 27 * (COUT / 16) * (CIN / 16));
-        k_conv_wgrad_small<CIN, COUT><<<g, 64, 0, s>>>(n, chunk, in, dy, dW);
-        return;
+// Voxels per block of the small-grid weight gradient (a multiple of 16, at most
+// 512 blocks) and the number of partial copies of dW either launch writes.
+inline long long wgrad_chunk(long long nv) {
+    long long c = (nv + 511) / 512;
+    return std::max<long long>(64, ((c + 15) / 16) * 16);
+}
+inline bool wgrad_small(int n) { return n < 16 || n % 16 != 0; }
+inline int wgrad_parts(int n) {
+    if (wgrad_small(n)) {
+        const long long nv = (long long)n * n * n;
+        return (int)((nv + wgrad_chunk(nv) - 1) / wgrad_chunk(nv));
     }
-    long long ntiles = (long long)(n / 16) * (n / 4) * n;
-    int tiles = (int)std::max<long long>(1, (ntiles + 511) / 512);
-    int gx = (int)((ntiles + tiles - 1) / tiles);
-    dim3 g(gx, (COUT / 16) * (CIN / 16));
-    k_conv_wgrad<CIN, COUT><<<g, 256, 0, s>>>(n, tiles, in, dy, dW);
+    const long long ntiles = (long long)(n / 16) * (n / 4) * n;
+    const long long tiles = std::max<long long>(1, (ntiles + 511) / 512);
+    return (int)((ntiles + tiles - 1) / tiles);
+}
+
+// dW += the weight gradient, through `part` (wgrad_parts(n) copies of dW)
+template <int CIN, int COUT>
+void wgrad_launch(hipStream_t s, int n, const bf16 *in, const bf16 *dy, float *part, float *dW) {
+    const long long wn = (long long)COUT * 27 * CIN;
+    const int parts = wgrad_parts(n);
+    if (wgrad_small(n)) {
+        const long long nv = (long long)n * n * n;
+        const int chunk = (int)wgrad_chunk(nv);
+        dim3 g((unsigned)parts, 27 * (COUT / 16) * (CIN / 16));
+        k_conv_wgrad_small<CIN, COUT><<<g, 64, 0, s>>>(n, chunk, in, dy, part);
+    } else {
+        const long long ntiles = (long long)(n / 16) * (n / 4) * n;
+        const int tiles = (int)std::max<long long>(1, (ntiles + 511) / 512);
+        dim3 g(parts, (COUT / 16) * (CIN / 16));
+        k_conv_wgrad<CIN, COUT><<<g, 256, 0, s>>>(n, tiles, in, dy, part);
+    }
+    k_sum_partials<<<(unsigned)std::min<long long>((wn + 255) / 256, 1024), 256, 0, s>>>(wn, parts, part, dW);
 }
 
 #define CONV_CASES(X)                                                                       \
@@ -480,11 +574,11 @@ bool conv_any(hipStream_t s, int cin, int cout, int n, const bf16 *in, const bf1
     return false;
 }
 
-bool wgrad_any(hipStream_t s, int cin, int cout, int n, const bf16 *in, const bf16 *dy, float *dW) {
-#define X(a, b)                                    \
-    if (cin == a && cout == b) {                   \
-        wgrad_launch<a, b>(s, n, in, dy, dW);      \
-        return true;                               \
+bool wgrad_any(hipStream_t s, int cin, int cout, int n, const bf16 *in, const bf16 *dy, float *part, float *dW) {
+#define X(a, b)                                        \
+    if (cin == a && cout == b) {                       \
+        wgrad_launch<a, b>(s, n, in, dy, part, dW);    \
+        return true;                                   \
     }
     CONV_CASES(X)
 #undef X
@@ -510,6 +604,7 @@ struct stokes_unet {
     // activations and their gradients (BF16, channel-last)
     bf16 *act[24] = {}, *grad[24] = {};
     float *y = nullptr, *loss = nullptr;
+    float *part = nullptr;               // per-block partial sums of the gradients and the loss
     bf16 *dy = nullptr;
     std::string err;
 };
@@ -560,6 +655,10 @@ size_t carve(stokes_unet &u, char *base) {
     u.y = (float *)take(sizeof(float) * nv * 16);
     u.dy = (bf16 *)take(sizeof(bf16) * nv * 16);
     u.loss = (float *)take(sizeof(float) * 64);
+    long long parts = std::max<long long>((long long)kBiasBlocks * 64, (nv + 255) / 256);
+    for (int l = 0; l < kLayers; ++l)
+        parts = std::max<long long>(parts, (long long)wgrad_parts(u.n >> kSpec[l].level) * kSpec[l].cout * 27 * kSpec[l].cin);
+    u.part = (float *)take(sizeof(float) * parts);
     return off + 256;
 }
 
@@ -621,9 +720,10 @@ void conv_backward(stokes_unet &u, int l, int in, const bf16 *gpre, bool need_di
     const LayerSpec &L = kSpec[l];
     const int n = u.n >> L.level;
     const long long nv = (long long)n * n * n;
-    wgrad_any(s, L.cin, L.cout, n, u.act[in], gpre, u.g + u.woff[l]);
+    wgrad_any(s, L.cin, L.cout, n, u.act[in], gpre, u.part, u.g + u.woff[l]);
     int tpb = 256 - 256 % L.cout;
-    k_bias_grad<<<1024, tpb, 0, s>>>(nv, L.cout, gpre, u.g + u.boff[l]);
+    k_bias_grad<<<kBiasBlocks, tpb, 0, s>>>(nv, L.cout, gpre, u.part);
+    k_sum_partials<<<1, 256, 0, s>>>(L.cout, kBiasBlocks, u.part, u.g + u.boff[l]);
     if (need_din) {
         long long wn = (long long)L.cout * 27 * L.cin;
         k_flip_weights<<<gridfor(wn), 256, 0, s>>>(L.cin, L.cout, u.wb + u.woff[l], u.wt + u.woff[l]);
@@ -804,7 +904,8 @@ stokes_status stokes_unet_train_step(stokes_unet *u, const float *f0, const floa
         k_pack_input<<<gridfor(nv), 256, 0, s>>>(nv, f0, f1, f2, u->act[X_IN]);
         forward(*u);
         UCHK(hipMemsetAsync(u->loss, 0, sizeof(float), s));
-        k_mse<<<gridfor(nv), 256, 0, s>>>(nv, u->y, target, u->dy, u->loss);
+        k_mse<<<gridfor(nv), 256, 0, s>>>(nv, u->y, target, u->dy, u->part);
+        k_sum_partials<<<1, 256, 0, s>>>(1, (int)gridfor(nv), u->part, u->loss);
         UCHK(hipMemsetAsync(u->g, 0, sizeof(float) * u->np, s));
         backward(*u);
         u->step++;

@@ -39,7 +39,7 @@ def _feats(n, seed):
     return f, dev
 
 
-@pytest.mark.parametrize("n", [8, 16, 32])
+@pytest.mark.parametrize("n", [8, 16, 32, 64])
 def test_unet_forward_matches_oracle(n):
     import torch
     net, p = _net(n)
@@ -102,6 +102,42 @@ def test_unet_training_reduces_loss():
     losses = [net.train_step(dev[0], dev[1], dev[2], target, 2e-3) for _ in range(60)]
     print("loss %.4f -> %.4f" % (losses[0], losses[-1]))
     assert losses[-1] < 0.3 * losses[0]
+    net.close()
+
+
+@pytest.mark.parametrize("n", [16, 24])
+def test_unet_training_is_deterministic(n):
+    """Weight, bias and loss reductions go through per-block partial sums added in
+    a fixed order: the same steps from the same start give bitwise-equal
+    parameters and losses (n = 24 takes the ragged-grid kernels)."""
+    import torch
+    f, dev = _feats(n, 31)
+    target = torch.from_numpy(np.random.default_rng(32).standard_normal((n, n, n)).astype(np.float32)).cuda()
+    runs = []
+    for _ in range(2):
+        net, _p = _net(n, seed=9)
+        losses = [net.train_step(dev[0], dev[1], dev[2], target, 1e-3) for _ in range(3)]
+        runs.append((losses, net.get_params(), net.get_grads()))
+        net.close()
+    assert runs[0][0] == runs[1][0]
+    assert np.array_equal(runs[0][1], runs[1][1])
+    assert np.array_equal(runs[0][2], runs[1][2])
+
+
+def test_unet_forward_ragged_grid_matches_oracle():
+    """n = 24 (a multiple of 8, not of 16) takes the gather kernel on every level."""
+    import torch
+    n = 24
+    net, p = _net(n)
+    f, dev = _feats(n, 17)
+    out = torch.zeros((n, n, n), dtype=torch.float32, device="cuda")
+    net.forward(dev[0], dev[1], dev[2], out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().astype(np.float64)
+    ref = OU.forward(p, f, bf16=True)
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    print("unet forward n=%d rel L2 %.2e" % (n, err))
+    assert err <= 2e-2
     net.close()
 
 
