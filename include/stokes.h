@@ -61,6 +61,15 @@ typedef struct {
     int dim;          /* 2 or 3 */
     int n[3];         /* cells Nx, Ny, Nz (Nz ignored and taken as 1 in 2D) */
     double h[3];      /* spacings hx, hy, hz */
+    int periodic[3];  /* per axis: 0 no-slip walls at both ends, 1 periodic (an even
+                         number of cells; cells and faces 0 .. N-1 wrap).  Arrays keep
+                         the wall layouts below: on a periodic axis the last face
+                         (index N) repeats face 0, is ignored on input and receives
+                         face 0's value on output.  Only the solve (setup, apply,
+                         solve, pressure_op and the learned hooks) takes periodic axes;
+                         the steps around it (coefficients, explicit right-hand side,
+                         rigid projection, density transport, wave inflow and its
+                         lift) need walls and return STOKES_EINVAL. */
 } stokes_grid;
 
 typedef struct {

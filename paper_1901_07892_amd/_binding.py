@@ -25,7 +25,7 @@ class StokesError(RuntimeError):
 
 
 class StokesGrid(C.Structure):
-    _fields_ = [("dim", C.c_int), ("n", C.c_int * 3), ("h", C.c_double * 3)]
+    _fields_ = [("dim", C.c_int), ("n", C.c_int * 3), ("h", C.c_double * 3), ("periodic", C.c_int * 3)]
 
 
 class StokesFluids(C.Structure):
@@ -195,12 +195,13 @@ def _stream(stream) -> Optional[int]:
     return getattr(stream, "cuda_stream", stream)
 
 
-def make_grid(dim: int, n: Sequence[int], h: Sequence[float]) -> StokesGrid:
+def make_grid(dim: int, n: Sequence[int], h: Sequence[float], periodic: Sequence[int] = (0, 0, 0)) -> StokesGrid:
     g = StokesGrid()
     g.dim = dim
     for a in range(3):
         g.n[a] = int(n[a]) if a < len(n) else 1
         g.h[a] = float(h[a]) if a < len(h) else float(h[0])
+        g.periodic[a] = int(bool(periodic[a])) if a < len(periodic) else 0
     return g
 
 
@@ -438,10 +439,10 @@ class StokesSolver:
     """
 
     def __init__(self, dim, n, h, rho_face, mu_cell, dt, opts: Optional[StokesOptions] = None,
-                 stream=None, **overrides):
+                 stream=None, periodic=(0, 0, 0), **overrides):
         import torch
         load_library()
-        self.grid = make_grid(dim, n, h)
+        self.grid = make_grid(dim, n, h, periodic)
         self.opts = opts if opts is not None else stokes_default_options()
         for k, v in overrides.items():
             setattr(self.opts, k, v)

@@ -9,7 +9,8 @@
 // the field.  Slots that are not an unknown (wall-normal faces, padding) hold
 // zero.  Each field is surrounded by a zero guard of at least one plane, so a
 // +-1 neighbour of any box point is a valid address; stencils whose weight
-// vanishes there (beta = 0 on wall faces) need no branch.
+// vanishes there (beta = 0 on wall faces) need no branch.  Along a periodic
+// axis the flat kernels wrap the neighbour offsets instead (see Nbr).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -28,6 +29,8 @@ struct Box {
     int open_top;            // 1: the upper end of the vertical axis (y in 2D, z in 3D) is open
                              // (zero pressure, zero tangential velocity); the vertical velocity on
                              // its faces (index ny / nz) is an unknown
+    int per[3];              // 1: the axis is periodic (cells and faces 0 .. n-1 wrap; face n is
+                             // face 0 and its slot is padding), 0: walls at both ends
 };
 
 inline Box make_box(int dim, int nx, int ny, int nz, double hx, double hy, double hz) {
@@ -43,6 +46,7 @@ inline Box make_box(int dim, int nx, int ny, int nz, double hx, double hy, doubl
     b.hx = hx; b.hy = hy; b.hz = dim == 3 ? hz : hx;
     b.ihx = 1.0 / b.hx; b.ihy = 1.0 / b.hy; b.ihz = 1.0 / b.hz;
     b.open_top = 0;
+    b.per[0] = b.per[1] = b.per[2] = 0;
     return b;
 }
 

@@ -161,6 +161,7 @@ extern "C" stokes_status stokes_coefficients(const stokes_grid *grid, const stok
     const int dim = grid->dim;
     if (dim != 2 && dim != 3) return STOKES_EINVAL;
     for (int a = 0; a < dim; ++a) {
+        if (grid->periodic[a]) return STOKES_EINVAL;     // walls only (mirrored out-of-domain cells)
         if (grid->n[a] < 1) return STOKES_ESHAPE;
         if (!finite_pos(grid->h[a])) return STOKES_EINVAL;
     }

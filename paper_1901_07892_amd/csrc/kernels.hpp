@@ -50,38 +50,59 @@ struct VelCoef {
 // zero fill of the correction.
 enum { VALID_U = 1, VALID_V = 2, VALID_W = 4 };
 
+// Neighbour offsets of box point (i, j, k) along each axis.  A wall axis steps
+// to the next slot (the padding or guard holds zero beyond the last cell); a
+// periodic axis wraps index 0 to n-1 and n-1 to 0, for cells, faces and edges
+// alike (all indexed 0 .. n-1 along that axis).
+struct Nbr {
+    int xm, xp, ym, yp, zm, zp;
+};
+__device__ inline Nbr nbr(const Box &b, int i, int j, int k) {
+    Nbr o;
+    o.xm = (b.per[0] && i == 0) ? b.nx - 1 : -1;
+    o.xp = (b.per[0] && i == b.nx - 1) ? 1 - b.nx : 1;
+    o.ym = ((b.per[1] && j == 0) ? b.ny - 1 : -1) * b.px;
+    o.yp = ((b.per[1] && j == b.ny - 1) ? 1 - b.ny : 1) * b.px;
+    o.zm = ((b.per[2] && k == 0) ? b.nz - 1 : -1) * b.plane;
+    o.zp = ((b.per[2] && k == b.nz - 1) ? 1 - b.nz : 1) * b.plane;
+    return o;
+}
+
 // ---------------------------------------------------------------- momentum rows
 // Each returns the off-diagonal part of one momentum row (the row evaluated with
 // the centre value set to zero, wall ghosts included) and its diagonal, so that
 // (A u)_row = diag * u_c + off.  Formulas: strain-rate divergence on the MAC
 // grid; normal stresses 2 mu du/dx at cells, shear stresses mu_e (du/dy + dv/dx)
-// at edges; tangential ghosts beyond a wall are minus the interior value.
+// at edges; tangential ghosts beyond a wall are minus the interior value; a
+// periodic axis has no wall (its neighbours wrap, see Nbr).
 
 template <int DIM, class R>
-__device__ inline void row_u(const Box &b, int idx, int j, int k, const R *u, const R *v,
+__device__ inline void row_u(const Box &b, int idx, int i, int j, int k, const R *u, const R *v,
                              const R *w, int valid, const VelCoef<R> &c, R &off, R &diag) {
-    const int sy = b.px, sz = b.plane;
+    const Nbr o = nbr(b, i, j, k);
     const R ihx = (R)b.ihx, ihy = (R)b.ihy, ihz = (R)b.ihz;
     const bool vu = valid & VALID_U, vv = valid & VALID_V, vw = valid & VALID_W;
-    R uE = vu ? u[idx + 1] : R(0), uW = vu ? u[idx - 1] : R(0);
-    R uN = (j + 1 < b.ny && vu) ? u[idx + sy] : R(0);
-    R uS = (j > 0 && vu) ? u[idx - sy] : R(0);
-    R gN = j + 1 < b.ny ? R(1) : R(2), gS = j > 0 ? R(1) : R(2);
-    R m1 = c.mu[idx], m0 = c.mu[idx - 1];
-    R mN = c.mxy[idx + sy], mS = c.mxy[idx];
-    R dvN = vv ? (v[idx + sy] - v[idx + sy - 1]) : R(0);
-    R dvS = vv ? (v[idx] - v[idx - 1]) : R(0);
+    const bool hN = b.per[1] || j + 1 < b.ny, hS = b.per[1] || j > 0;
+    R uE = vu ? u[idx + o.xp] : R(0), uW = vu ? u[idx + o.xm] : R(0);
+    R uN = (hN && vu) ? u[idx + o.yp] : R(0);
+    R uS = (hS && vu) ? u[idx + o.ym] : R(0);
+    R gN = hN ? R(1) : R(2), gS = hS ? R(1) : R(2);
+    R m1 = c.mu[idx], m0 = c.mu[idx + o.xm];
+    R mN = c.mxy[idx + o.yp], mS = c.mxy[idx];
+    R dvN = vv ? (v[idx + o.yp] - v[idx + o.yp + o.xm]) : R(0);
+    R dvS = vv ? (v[idx] - v[idx + o.xm]) : R(0);
     // lap with u_c = 0
     R lap = R(2) * (m1 * uE + m0 * uW) * ihx * ihx
           + (mN * (uN * ihy + dvN * ihx) - mS * (-uS * ihy + dvS * ihx)) * ihy;
     R dg = R(2) * (m0 + m1) * ihx * ihx + (mN * gN + mS * gS) * ihy * ihy;
     if (DIM == 3) {
-        R uT = (k + 1 < b.nz && vu) ? u[idx + sz] : R(0);
-        R uB = (k > 0 && vu) ? u[idx - sz] : R(0);
-        R gT = k + 1 < b.nz ? R(1) : R(2), gB = k > 0 ? R(1) : R(2);
-        R mT = c.mxz[idx + sz], mB = c.mxz[idx];
-        R dwT = vw ? (w[idx + sz] - w[idx + sz - 1]) : R(0);
-        R dwB = vw ? (w[idx] - w[idx - 1]) : R(0);
+        const bool hT = b.per[2] || k + 1 < b.nz, hB = b.per[2] || k > 0;
+        R uT = (hT && vu) ? u[idx + o.zp] : R(0);
+        R uB = (hB && vu) ? u[idx + o.zm] : R(0);
+        R gT = hT ? R(1) : R(2), gB = hB ? R(1) : R(2);
+        R mT = c.mxz[idx + o.zp], mB = c.mxz[idx];
+        R dwT = vw ? (w[idx + o.zp] - w[idx + o.zp + o.xm]) : R(0);
+        R dwB = vw ? (w[idx] - w[idx + o.xm]) : R(0);
         lap += (mT * (uT * ihz + dwT * ihx) - mB * (-uB * ihz + dwB * ihx)) * ihz;
         dg += (mT * gT + mB * gB) * ihz * ihz;
     }
@@ -90,33 +111,35 @@ __device__ inline void row_u(const Box &b, int idx, int j, int k, const R *u, co
 }
 
 template <int DIM, class R>
-__device__ inline void row_v(const Box &b, int idx, int i, int k, const R *u, const R *v,
+__device__ inline void row_v(const Box &b, int idx, int i, int j, int k, const R *u, const R *v,
                              const R *w, int valid, const VelCoef<R> &c, R &off, R &diag) {
-    const int sy = b.px, sz = b.plane;
+    const Nbr o = nbr(b, i, j, k);
     const R ihx = (R)b.ihx, ihy = (R)b.ihy, ihz = (R)b.ihz;
     const bool vu = valid & VALID_U, vv = valid & VALID_V, vw = valid & VALID_W;
     // on an open top (2D, j = ny) the cell above is a ghost: its normal stress is
     // minus the one below (v and mu mirrored) and the tangential u above is minus
     // the one below
-    const bool tp = b.dim == 2 && b.open_top && (idx / b.px) % b.py == b.ny;
-    R vN = vv ? v[tp ? idx - sy : idx + sy] : R(0), vS = vv ? v[idx - sy] : R(0);
-    R vE = (i + 1 < b.nx && vv) ? v[idx + 1] : R(0);
-    R vW = (i > 0 && vv) ? v[idx - 1] : R(0);
-    R gE = i + 1 < b.nx ? R(1) : R(2), gW = i > 0 ? R(1) : R(2);
-    R m1 = c.mu[tp ? idx - sy : idx], m0 = c.mu[idx - sy];
-    R mE = c.mxy[idx + 1], mW = c.mxy[idx];
-    R duE = vu ? (tp ? R(-2) * u[idx + 1 - sy] : u[idx + 1] - u[idx + 1 - sy]) : R(0);
-    R duW = vu ? (tp ? R(-2) * u[idx - sy] : u[idx] - u[idx - sy]) : R(0);
+    const bool tp = b.dim == 2 && b.open_top && j == b.ny;
+    const bool hE = b.per[0] || i + 1 < b.nx, hW = b.per[0] || i > 0;
+    R vN = vv ? v[tp ? idx + o.ym : idx + o.yp] : R(0), vS = vv ? v[idx + o.ym] : R(0);
+    R vE = (hE && vv) ? v[idx + o.xp] : R(0);
+    R vW = (hW && vv) ? v[idx + o.xm] : R(0);
+    R gE = hE ? R(1) : R(2), gW = hW ? R(1) : R(2);
+    R m1 = c.mu[tp ? idx + o.ym : idx], m0 = c.mu[idx + o.ym];
+    R mE = c.mxy[idx + o.xp], mW = c.mxy[idx];
+    R duE = vu ? (tp ? R(-2) * u[idx + o.xp + o.ym] : u[idx + o.xp] - u[idx + o.xp + o.ym]) : R(0);
+    R duW = vu ? (tp ? R(-2) * u[idx + o.ym] : u[idx] - u[idx + o.ym]) : R(0);
     R lap = R(2) * (m1 * vN + m0 * vS) * ihy * ihy
           + (mE * (vE * ihx + duE * ihy) - mW * (-vW * ihx + duW * ihy)) * ihx;
     R dg = R(2) * (m0 + m1) * ihy * ihy + (mE * gE + mW * gW) * ihx * ihx;
     if (DIM == 3) {
-        R vT = (k + 1 < b.nz && vv) ? v[idx + sz] : R(0);
-        R vB = (k > 0 && vv) ? v[idx - sz] : R(0);
-        R gT = k + 1 < b.nz ? R(1) : R(2), gB = k > 0 ? R(1) : R(2);
-        R mT = c.myz[idx + sz], mB = c.myz[idx];
-        R dwT = vw ? (w[idx + sz] - w[idx + sz - sy]) : R(0);
-        R dwB = vw ? (w[idx] - w[idx - sy]) : R(0);
+        const bool hT = b.per[2] || k + 1 < b.nz, hB = b.per[2] || k > 0;
+        R vT = (hT && vv) ? v[idx + o.zp] : R(0);
+        R vB = (hB && vv) ? v[idx + o.zm] : R(0);
+        R gT = hT ? R(1) : R(2), gB = hB ? R(1) : R(2);
+        R mT = c.myz[idx + o.zp], mB = c.myz[idx];
+        R dwT = vw ? (w[idx + o.zp] - w[idx + o.zp + o.ym]) : R(0);
+        R dwB = vw ? (w[idx] - w[idx + o.ym]) : R(0);
         lap += (mT * (vT * ihz + dwT * ihy) - mB * (-vB * ihz + dwB * ihy)) * ihz;
         dg += (mT * gT + mB * gB) * ihz * ihz;
     }
@@ -125,29 +148,31 @@ __device__ inline void row_v(const Box &b, int idx, int i, int k, const R *u, co
 }
 
 template <class R>
-__device__ inline void row_w(const Box &b, int idx, int i, int j, const R *u, const R *v,
+__device__ inline void row_w(const Box &b, int idx, int i, int j, int k, const R *u, const R *v,
                              const R *w, int valid, const VelCoef<R> &c, R &off, R &diag) {
-    const int sy = b.px, sz = b.plane;
+    const Nbr o = nbr(b, i, j, k);
     const R ihx = (R)b.ihx, ihy = (R)b.ihy, ihz = (R)b.ihz;
     const bool vu = valid & VALID_U, vv = valid & VALID_V, vw = valid & VALID_W;
     // on an open top (k = nz) the cell above is a ghost: its normal stress is minus
     // the one below (w and mu mirrored) and the tangential u, v above are minus the
     // ones below
-    const bool tp = b.open_top && idx / b.plane == b.nz;
-    R wT = vw ? w[tp ? idx - sz : idx + sz] : R(0), wB = vw ? w[idx - sz] : R(0);
-    R wE = (i + 1 < b.nx && vw) ? w[idx + 1] : R(0);
-    R wW = (i > 0 && vw) ? w[idx - 1] : R(0);
-    R wN = (j + 1 < b.ny && vw) ? w[idx + sy] : R(0);
-    R wS = (j > 0 && vw) ? w[idx - sy] : R(0);
-    R gE = i + 1 < b.nx ? R(1) : R(2), gW = i > 0 ? R(1) : R(2);
-    R gN = j + 1 < b.ny ? R(1) : R(2), gS = j > 0 ? R(1) : R(2);
-    R m1 = c.mu[tp ? idx - sz : idx], m0 = c.mu[idx - sz];
-    R mE = c.mxz[idx + 1], mW = c.mxz[idx];
-    R mN = c.myz[idx + sy], mS = c.myz[idx];
-    R duE = vu ? (tp ? R(-2) * u[idx + 1 - sz] : u[idx + 1] - u[idx + 1 - sz]) : R(0);
-    R duW = vu ? (tp ? R(-2) * u[idx - sz] : u[idx] - u[idx - sz]) : R(0);
-    R dvN = vv ? (tp ? R(-2) * v[idx + sy - sz] : v[idx + sy] - v[idx + sy - sz]) : R(0);
-    R dvS = vv ? (tp ? R(-2) * v[idx - sz] : v[idx] - v[idx - sz]) : R(0);
+    const bool tp = b.open_top && k == b.nz;
+    const bool hE = b.per[0] || i + 1 < b.nx, hW = b.per[0] || i > 0;
+    const bool hN = b.per[1] || j + 1 < b.ny, hS = b.per[1] || j > 0;
+    R wT = vw ? w[tp ? idx + o.zm : idx + o.zp] : R(0), wB = vw ? w[idx + o.zm] : R(0);
+    R wE = (hE && vw) ? w[idx + o.xp] : R(0);
+    R wW = (hW && vw) ? w[idx + o.xm] : R(0);
+    R wN = (hN && vw) ? w[idx + o.yp] : R(0);
+    R wS = (hS && vw) ? w[idx + o.ym] : R(0);
+    R gE = hE ? R(1) : R(2), gW = hW ? R(1) : R(2);
+    R gN = hN ? R(1) : R(2), gS = hS ? R(1) : R(2);
+    R m1 = c.mu[tp ? idx + o.zm : idx], m0 = c.mu[idx + o.zm];
+    R mE = c.mxz[idx + o.xp], mW = c.mxz[idx];
+    R mN = c.myz[idx + o.yp], mS = c.myz[idx];
+    R duE = vu ? (tp ? R(-2) * u[idx + o.xp + o.zm] : u[idx + o.xp] - u[idx + o.xp + o.zm]) : R(0);
+    R duW = vu ? (tp ? R(-2) * u[idx + o.zm] : u[idx] - u[idx + o.zm]) : R(0);
+    R dvN = vv ? (tp ? R(-2) * v[idx + o.yp + o.zm] : v[idx + o.yp] - v[idx + o.yp + o.zm]) : R(0);
+    R dvS = vv ? (tp ? R(-2) * v[idx + o.zm] : v[idx] - v[idx + o.zm]) : R(0);
     R lap = R(2) * (m1 * wT + m0 * wB) * ihz * ihz
           + (mE * (wE * ihx + duE * ihz) - mW * (-wW * ihx + duW * ihz)) * ihx
           + (mN * (wN * ihy + dvN * ihz) - mS * (-wS * ihy + dvS * ihz)) * ihy;
@@ -160,12 +185,14 @@ __device__ inline void row_w(const Box &b, int idx, int i, int j, const R *u, co
 // (y = Ly in 2D, z = Lz in 3D) when the box has one.
 __device__ inline bool top_v(const Box &b, int j) { return b.open_top && b.dim == 2 && j == b.ny; }
 __device__ inline bool top_w(const Box &b, int k) { return b.open_top && b.dim == 3 && k == b.nz; }
-__device__ inline bool is_ux(const Box &b, int i, int j, int k) { return i >= 1 && i < b.nx && j < b.ny && k < b.nz; }
+__device__ inline bool is_ux(const Box &b, int i, int j, int k) {
+    return (i >= 1 || b.per[0]) && i < b.nx && j < b.ny && k < b.nz;
+}
 __device__ inline bool is_vy(const Box &b, int i, int j, int k) {
-    return j >= 1 && (j < b.ny || top_v(b, j)) && i < b.nx && k < b.nz;
+    return (j >= 1 || b.per[1]) && (j < b.ny || top_v(b, j)) && i < b.nx && k < b.nz;
 }
 __device__ inline bool is_wz(const Box &b, int i, int j, int k) {
-    return k >= 1 && (k < b.nz || top_w(b, k)) && i < b.nx && j < b.ny;
+    return (k >= 1 || b.per[2]) && (k < b.nz || top_w(b, k)) && i < b.nx && j < b.ny;
 }
 __device__ inline bool is_cell(const Box &b, int i, int j, int k) { return i < b.nx && j < b.ny && k < b.nz; }
 
@@ -188,35 +215,36 @@ __global__ void __launch_bounds__(kBlock) k_apply(Box b, VelCoef<double> c,
     const int all = VALID_U | VALID_V | VALID_W;
     double off, dg, r;
     r = 0.0;
+    const Nbr o = nbr(b, i, j, k);
     if (is_ux(b, i, j, k)) {
-        row_u<DIM, double>(b, idx, j, k, xu, xv, xw, all, c, off, dg);
-        r = dg * xu[idx] + off + (xp[idx] - xp[idx - 1]) * b.ihx;
+        row_u<DIM, double>(b, idx, i, j, k, xu, xv, xw, all, c, off, dg);
+        r = dg * xu[idx] + off + (xp[idx] - xp[idx + o.xm]) * b.ihx;
         if (fu) r = fu[idx] - r;
     }
     yu[idx] = r;
     r = 0.0;
     if (is_vy(b, i, j, k)) {
-        row_v<DIM, double>(b, idx, i, k, xu, xv, xw, all, c, off, dg);
+        row_v<DIM, double>(b, idx, i, j, k, xu, xv, xw, all, c, off, dg);
         // open top: zero pressure on the face, the ghost above is minus the cell below
-        const double pN = top_v(b, j) ? -xp[idx - sy] : xp[idx];
-        r = dg * xv[idx] + off + (pN - xp[idx - sy]) * b.ihy;
+        const double pN = top_v(b, j) ? -xp[idx + o.ym] : xp[idx];
+        r = dg * xv[idx] + off + (pN - xp[idx + o.ym]) * b.ihy;
         if (fv) r = fv[idx] - r;
     }
     yv[idx] = r;
     if (DIM == 3) {
         r = 0.0;
         if (is_wz(b, i, j, k)) {
-            row_w<double>(b, idx, i, j, xu, xv, xw, all, c, off, dg);
-            const double pT = top_w(b, k) ? -xp[idx - sz] : xp[idx];
-            r = dg * xw[idx] + off + (pT - xp[idx - sz]) * b.ihz;
+            row_w<double>(b, idx, i, j, k, xu, xv, xw, all, c, off, dg);
+            const double pT = top_w(b, k) ? -xp[idx + o.zm] : xp[idx];
+            r = dg * xw[idx] + off + (pT - xp[idx + o.zm]) * b.ihz;
             if (fw) r = fw[idx] - r;
         }
         yw[idx] = r;
     }
     r = 0.0;
     if (is_cell(b, i, j, k)) {
-        double dv = (xu[idx + 1] - xu[idx]) * b.ihx + (xv[idx + sy] - xv[idx]) * b.ihy;
-        if (DIM == 3) dv += (xw[idx + sz] - xw[idx]) * b.ihz;
+        double dv = (xu[idx + o.xp] - xu[idx]) * b.ihx + (xv[idx + o.yp] - xv[idx]) * b.ihy;
+        if (DIM == 3) dv += (xw[idx + o.zp] - xw[idx]) * b.ihz;
         r = -dv;
         if (fp) r = fp[idx] - r;
     }
@@ -325,7 +353,7 @@ __global__ void __launch_bounds__(kBlock) k_apply_top3(Box b, VelCoef<double> c,
     const int i = t % b.nx, j = t / b.nx;
     const int idx = box_index(b, i, j, b.nz);
     double off, dg;
-    row_w<double>(b, idx, i, j, xu, xv, xw, VALID_U | VALID_V | VALID_W, c, off, dg);
+    row_w<double>(b, idx, i, j, b.nz, xu, xv, xw, VALID_U | VALID_V | VALID_W, c, off, dg);
     const double r = dg * xw[idx] + off + (-xp[idx - b.plane] - xp[idx - b.plane]) * b.ihz;
     yw[idx] = fw ? fw[idx] - r : r;
 }
@@ -344,14 +372,14 @@ __global__ void __launch_bounds__(kBlock) k_vel_residual(Box b, VelCoef<R> c,
     const int all = VALID_U | VALID_V | VALID_W;
     R off, dg;
     R t = 0;
-    if (is_ux(b, i, j, k)) { row_u<DIM, R>(b, idx, j, k, eu, ev, ew, all, c, off, dg); t = ru[idx] - (dg * eu[idx] + off); }
+    if (is_ux(b, i, j, k)) { row_u<DIM, R>(b, idx, i, j, k, eu, ev, ew, all, c, off, dg); t = ru[idx] - (dg * eu[idx] + off); }
     tu[idx] = t;
     t = 0;
-    if (is_vy(b, i, j, k)) { row_v<DIM, R>(b, idx, i, k, eu, ev, ew, all, c, off, dg); t = rv[idx] - (dg * ev[idx] + off); }
+    if (is_vy(b, i, j, k)) { row_v<DIM, R>(b, idx, i, j, k, eu, ev, ew, all, c, off, dg); t = rv[idx] - (dg * ev[idx] + off); }
     tv[idx] = t;
     if (DIM == 3) {
         t = 0;
-        if (is_wz(b, i, j, k)) { row_w<R>(b, idx, i, j, eu, ev, ew, all, c, off, dg); t = rw[idx] - (dg * ew[idx] + off); }
+        if (is_wz(b, i, j, k)) { row_w<R>(b, idx, i, j, k, eu, ev, ew, all, c, off, dg); t = rw[idx] - (dg * ew[idx] + off); }
         tw[idx] = t;
     }
 }
@@ -369,15 +397,15 @@ __global__ void __launch_bounds__(kBlock) k_vel_gs(Box b, VelCoef<R> c, int comp
     R off, dg;
     if (comp == 0) {
         if (!is_ux(b, i, j, k)) return;
-        row_u<DIM, R>(b, idx, j, k, eu, ev, ew, valid, c, off, dg);
+        row_u<DIM, R>(b, idx, i, j, k, eu, ev, ew, valid, c, off, dg);
         eu[idx] = (ru[idx] - off) / dg;
     } else if (comp == 1) {
         if (!is_vy(b, i, j, k)) return;
-        row_v<DIM, R>(b, idx, i, k, eu, ev, ew, valid, c, off, dg);
+        row_v<DIM, R>(b, idx, i, j, k, eu, ev, ew, valid, c, off, dg);
         ev[idx] = (rv[idx] - off) / dg;
     } else {
         if (!is_wz(b, i, j, k)) return;
-        row_w<R>(b, idx, i, j, eu, ev, ew, valid, c, off, dg);
+        row_w<R>(b, idx, i, j, k, eu, ev, ew, valid, c, off, dg);
         ew[idx] = (rw[idx] - off) / dg;
     }
 }
@@ -397,6 +425,9 @@ __global__ void __launch_bounds__(kBlock) k_face_restrict(Box fb, Box cb, int co
     const int s[3] = {1, fb.px, fb.plane};
     int base = box_index(fb, 2 * I, 2 * J, DIM == 3 ? 2 * K : 0);
     const int sn = s[comp];
+    const int CI[3] = {I, J, K}, nfine[3] = {fb.nx, fb.ny, fb.nz};
+    // the fine face half a coarse cell below coarse face 0 wraps on a periodic axis
+    const int snm = (fb.per[comp] && CI[comp] == 0) ? (nfine[comp] - 1) * sn : -sn;
     const int t1 = comp == 0 ? s[1] : s[0];
     const int t2 = comp == 2 ? s[1] : s[2];
     R acc = 0;
@@ -404,7 +435,7 @@ __global__ void __launch_bounds__(kBlock) k_face_restrict(Box fb, Box cb, int co
     for (int a2 = 0; a2 < n2; ++a2)
         for (int a1 = 0; a1 < 2; ++a1) {
             int q = base + a1 * t1 + a2 * t2;
-            acc += R(2) * f[q] + f[q - sn] + f[q + sn];
+            acc += R(2) * f[q] + f[q + snm] + f[q + sn];
         }
     c[idx] = acc * (DIM == 3 ? R(1.0 / 16.0) : R(1.0 / 8.0));
 }
@@ -424,30 +455,33 @@ __global__ void __launch_bounds__(kBlock) k_face_prolong_add(Box fb, Box cb, int
     int fi[3] = {i, j, k};
     const int cs[3] = {1, cb.px, cb.plane};
     int q = box_index(cb, ci[0], ci[1], ci[2]);
+    const int ncs[3] = {cb.nx, cb.ny, cb.nz};
+    // the coarse face above the last one is coarse face 0 on a periodic axis
+    const int up = (cb.per[comp] && ci[comp] == ncs[comp] - 1) ? (1 - ncs[comp]) * cs[comp] : cs[comp];
     R val;
     if ((fi[comp] & 1) == 0) {
         val = c[q];
     } else {
-        val = R(0.5) * (c[q] + c[q + cs[comp]]);
+        val = R(0.5) * (c[q] + c[q + up]);
     }
     f[idx] += val;
 }
 
 // ---------------------------------------------------------------- pressure multigrid
-// -L_rho phi = -D beta G phi at a cell; beta is zero on wall faces, so the
-// Neumann walls need no branch.
+// -L_rho phi = -D beta G phi at cell (i, j, k) (box point idx); beta is zero on
+// wall faces, so the Neumann walls need no branch; periodic axes wrap (Nbr).
 template <int DIM, class R>
-__device__ inline void prow(const Box &b, int idx, const R *e, const R *bx, const R *by,
+__device__ inline void prow(const Box &b, int idx, int i, int j, int k, const R *e, const R *bx, const R *by,
                             const R *bz, R &off, R &diag) {
-    const int sy = b.px, sz = b.plane;
+    const Nbr o = nbr(b, i, j, k);
     const R ix2 = R(b.ihx * b.ihx), iy2 = R(b.ihy * b.ihy), iz2 = R(b.ihz * b.ihz);
-    R wW = bx[idx] * ix2, wE = bx[idx + 1] * ix2;
-    R wS = by[idx] * iy2, wN = by[idx + sy] * iy2;
-    off = wW * e[idx - 1] + wE * e[idx + 1] + wS * e[idx - sy] + wN * e[idx + sy];
+    R wW = bx[idx] * ix2, wE = bx[idx + o.xp] * ix2;
+    R wS = by[idx] * iy2, wN = by[idx + o.yp] * iy2;
+    off = wW * e[idx + o.xm] + wE * e[idx + o.xp] + wS * e[idx + o.ym] + wN * e[idx + o.yp];
     diag = wW + wE + wS + wN;
     if (DIM == 3) {
-        R wB = bz[idx] * iz2, wT = bz[idx + sz] * iz2;
-        off += wB * e[idx - sz] + wT * e[idx + sz];
+        R wB = bz[idx] * iz2, wT = bz[idx + o.zp] * iz2;
+        off += wB * e[idx + o.zm] + wT * e[idx + o.zp];
         diag += wB + wT;
     }
 }
@@ -462,7 +496,7 @@ __global__ void __launch_bounds__(kBlock) k_p_gs(Box b, int colour, int zero_gue
     decompose(b, idx, i, j, k);
     if (!is_cell(b, i, j, k) || ((i + j + k) & 1) != colour) return;
     R off, dg;
-    prow<DIM, R>(b, idx, e, bx, by, bz, off, dg);
+    prow<DIM, R>(b, idx, i, j, k, e, bx, by, bz, off, dg);
     if (zero_guess) off = R(0);
     e[idx] = dg > R(0) ? (r[idx] + off) / dg : R(0);
 }
@@ -483,9 +517,10 @@ __global__ void __launch_bounds__(kBlock) k_p_residual_restrict(Box fb, Box cb, 
     for (int dk = 0; dk < n2; ++dk)
         for (int dj = 0; dj < 2; ++dj)
             for (int di = 0; di < 2; ++di) {
-                int q = box_index(fb, 2 * I + di, 2 * J + dj, DIM == 3 ? 2 * K + dk : 0);
+                const int fi = 2 * I + di, fj = 2 * J + dj, fk = DIM == 3 ? 2 * K + dk : 0;
+                int q = box_index(fb, fi, fj, fk);
                 R off, dg;
-                prow<DIM, R>(fb, q, e, bx, by, bz, off, dg);
+                prow<DIM, R>(fb, q, fi, fj, fk, e, bx, by, bz, off, dg);
                 acc += r[q] - (dg * e[q] - off);
             }
     rc[idx] = acc * (DIM == 3 ? R(0.125) : R(0.25));
@@ -569,22 +604,23 @@ __global__ void __launch_bounds__(TX *TY) k_p_residual_restrict3_z(Box fb, Box c
 // Prolonged coarse correction at fine cell (i,j,k).  lin == 0: the parent's
 // value (piecewise constant).  lin == 1: bi/trilinear interpolation between the
 // cell centres, weights 3/4 (parent) and 1/4 (the coarse neighbour on the
-// child's side) per axis; beyond a wall the parent is mirrored.
+// child's side) per axis; beyond a wall the parent is mirrored, along a
+// periodic axis the neighbour wraps.
 template <int DIM, class R>
 __device__ inline R prolong_value(const Box &cb, const R *ec, int i, int j, int k, int lin) {
     const int I = i >> 1, J = j >> 1, K = DIM == 3 ? (k >> 1) : 0;
     if (!lin) return ec[box_index(cb, I, J, K)];
     int I2 = (i & 1) ? I + 1 : I - 1;
     int J2 = (j & 1) ? J + 1 : J - 1;
-    I2 = I2 < 0 ? 0 : (I2 >= cb.nx ? cb.nx - 1 : I2);
-    J2 = J2 < 0 ? 0 : (J2 >= cb.ny ? cb.ny - 1 : J2);
+    I2 = cb.per[0] ? (I2 + cb.nx) % cb.nx : (I2 < 0 ? 0 : (I2 >= cb.nx ? cb.nx - 1 : I2));
+    J2 = cb.per[1] ? (J2 + cb.ny) % cb.ny : (J2 < 0 ? 0 : (J2 >= cb.ny ? cb.ny - 1 : J2));
     const R a = R(0.75), b = R(0.25);
     if (DIM == 2) {
         return a * (a * ec[box_index(cb, I, J, 0)] + b * ec[box_index(cb, I2, J, 0)])
              + b * (a * ec[box_index(cb, I, J2, 0)] + b * ec[box_index(cb, I2, J2, 0)]);
     }
     int K2 = (k & 1) ? K + 1 : K - 1;
-    K2 = K2 < 0 ? 0 : (K2 >= cb.nz ? cb.nz - 1 : K2);
+    K2 = cb.per[2] ? (K2 + cb.nz) % cb.nz : (K2 < 0 ? 0 : (K2 >= cb.nz ? cb.nz - 1 : K2));
     R p0 = a * (a * ec[box_index(cb, I, J, K)] + b * ec[box_index(cb, I2, J, K)])
          + b * (a * ec[box_index(cb, I, J2, K)] + b * ec[box_index(cb, I2, J2, K)]);
     R p1 = a * (a * ec[box_index(cb, I, J, K2)] + b * ec[box_index(cb, I2, J, K2)])
@@ -669,7 +705,7 @@ __device__ inline void small_gs(const Box &b, R *e, const R *r, BP bx, BP by, BP
         if (i >= b.nx) continue;
         const int idx = box_index(b, i, j, k);
         R off, dg;
-        prow<3, R>(b, idx, e, bx, by, bz, off, dg);
+        prow<3, R>(b, idx, i, j, k, e, bx, by, bz, off, dg);
         if (zg) off = R(0);
         e[idx] = dg > R(0) ? (r[idx] + off) / dg : R(0);
     }
@@ -688,7 +724,7 @@ __device__ inline void small_restrict(const Box &fb, const Box &cb, const R *e, 
                 for (int di = 0; di < 2; ++di) {
                     const int q = box_index(fb, 2 * I + di, 2 * J + dj, 2 * K + dk);
                     R off, dg;
-                    prow<3, R>(fb, q, e, bx, by, bz, off, dg);
+                    prow<3, R>(fb, q, 2 * I + di, 2 * J + dj, 2 * K + dk, e, bx, by, bz, off, dg);
                     acc += r[q] - (dg * e[q] - off);
                 }
         rc[box_index(cb, I, J, K)] = acc * R(0.125);
@@ -1136,7 +1172,7 @@ __global__ void __launch_bounds__(kBlock) k_coarsen_beta(Box fb, Box cb, int com
 }
 
 // Edge viscosities of a level: harmonic mean of the 4 cells around each edge,
-// out-of-domain cells mirrored.  mxy at (x-face i, y-face j, cell k), mxz at
+// out-of-domain cells mirrored (wrapped along a periodic axis).  mxy at (x-face i, y-face j, cell k), mxz at
 // (x-face i, cell j, z-face k), myz at (cell i, y-face j, z-face k).
 template <int DIM, class R>
 __global__ void __launch_bounds__(kBlock) k_edge_mu(Box b, const R *__restrict__ mu, R *__restrict__ mxy,
@@ -1145,8 +1181,10 @@ __global__ void __launch_bounds__(kBlock) k_edge_mu(Box b, const R *__restrict__
     if (idx >= b.nb) return;
     int i, j, k;
     decompose(b, idx, i, j, k);
-    auto cl = [](int a, int n) { return a < 0 ? 0 : (a > n - 1 ? n - 1 : a); };
-    int i0 = cl(i - 1, b.nx), i1 = cl(i, b.nx), j0 = cl(j - 1, b.ny), j1 = cl(j, b.ny);
+    // out-of-domain cells: mirrored at a wall, wrapped on a periodic axis
+    auto cl = [](int a, int n, int per) { return per ? (a + n) % n : (a < 0 ? 0 : (a > n - 1 ? n - 1 : a)); };
+    int i0 = cl(i - 1, b.nx, b.per[0]), i1 = cl(i, b.nx, b.per[0]);
+    int j0 = cl(j - 1, b.ny, b.per[1]), j1 = cl(j, b.ny, b.per[1]);
     if (k < b.nz) {
         double s = 1.0 / (double)mu[box_index(b, i0, j0, k)] + 1.0 / (double)mu[box_index(b, i1, j0, k)]
                  + 1.0 / (double)mu[box_index(b, i0, j1, k)] + 1.0 / (double)mu[box_index(b, i1, j1, k)];
@@ -1155,7 +1193,7 @@ __global__ void __launch_bounds__(kBlock) k_edge_mu(Box b, const R *__restrict__
         mxy[idx] = R(0);
     }
     if (DIM == 3) {
-        int k0 = cl(k - 1, b.nz), k1 = cl(k, b.nz);
+        int k0 = cl(k - 1, b.nz, b.per[2]), k1 = cl(k, b.nz, b.per[2]);
         if (j < b.ny) {
             double s = 1.0 / (double)mu[box_index(b, i0, j, k0)] + 1.0 / (double)mu[box_index(b, i1, j, k0)]
                      + 1.0 / (double)mu[box_index(b, i0, j, k1)] + 1.0 / (double)mu[box_index(b, i1, j, k1)];
@@ -1188,6 +1226,16 @@ __global__ void __launch_bounds__(kBlock) k_edge_mu(Box b, const R *__restrict__
 // thread divides a flat point index.
 constexpr int kPackRows = 4;
 
+// Face rows (j, k) of component comp (1: y-faces, 2: z-faces) that are not
+// unknowns: the walls (and, on a periodic axis, face n, the slot that repeats
+// face 0).  x-faces: the same along x.
+__device__ inline bool face_row_wall(const Box &b, int comp, int j, int k) {
+    if (comp == 1) return (j == 0 && !b.per[1]) || (j == b.ny && !(b.open_top && b.dim == 2));
+    if (comp == 2) return (k == 0 && !b.per[2]) || (k == b.nz && !(b.open_top && b.dim == 3));
+    return false;
+}
+__device__ inline bool x_wall_face(const Box &b, int i) { return (i == 0 && !b.per[0]) || i == b.nx; }
+
 __global__ void __launch_bounds__(64 * kPackRows) k_pack(Box b, int comp, int mode, int keep_walls, double s,
         const double *__restrict__ src, double *__restrict__ dst, int *__restrict__ flag, int check) {
     const int r = blockIdx.x * kPackRows + threadIdx.y;     // row j + py k
@@ -1196,13 +1244,12 @@ __global__ void __launch_bounds__(64 * kPackRows) k_pack(Box b, int comp, int mo
         const int k = r / b.py, j = r - k * b.py;
         const int ex = b.nx + (comp == 0), ey = b.ny + (comp == 1), ez = b.nz + (comp == 2);
         const bool row_in = j < ey && k < ez;
-        const bool row_wall = (comp == 1 && (j == 0 || (j == b.ny && !(b.open_top && b.dim == 2)))) ||
-                              (comp == 2 && (k == 0 || (k == b.nz && !(b.open_top && b.dim == 3))));
+        const bool row_wall = face_row_wall(b, comp, j, k);
         const double *sr = src + (row_in ? ex * (j + ey * k) : 0);
         double *dr = dst + r * b.px;
         for (int i = threadIdx.x; i < b.px; i += 64) {
             double val = 0.0;
-            if (row_in && i < ex && (keep_walls || !(row_wall || (comp == 0 && (i == 0 || i == b.nx))))) {
+            if (row_in && i < ex && (keep_walls || !(row_wall || (comp == 0 && x_wall_face(b, i))))) {
                 const double x = sr[i];
                 bad |= check ? !(x >= 0.0) || !isfinite(x) : !isfinite(x);
                 nz |= x != 0.0;
@@ -1220,7 +1267,8 @@ __global__ void __launch_bounds__(64 * kPackRows) k_pack(Box b, int comp, int mo
     }
 }
 
-// Box -> caller layout for every point of the caller's array (wall faces included).
+// Box -> caller layout for every point of the caller's array (wall faces included;
+// along a periodic axis the caller's last face, which repeats face 0, gets face 0).
 __global__ void __launch_bounds__(64 * kPackRows) k_unpack(Box b, int comp, const double *__restrict__ src,
         double *__restrict__ dst) {
     const int r = blockIdx.x * kPackRows + threadIdx.y;
@@ -1229,8 +1277,11 @@ __global__ void __launch_bounds__(64 * kPackRows) k_unpack(Box b, int comp, cons
     const int ex = b.nx + (comp == 0), ey = b.ny + (comp == 1), ez = b.nz + (comp == 2);
     if (j >= ey || k >= ez) return;
     double *dr = dst + ex * (j + ey * k);
-    const double *sr = src + r * b.px;
-    for (int i = threadIdx.x; i < ex; i += 64) dr[i] = sr[i];
+    // on a periodic axis the caller's face n repeats face 0
+    const int js = (comp == 1 && b.per[1] && j == b.ny) ? 0 : j;
+    const int ks = (comp == 2 && b.per[2] && k == b.nz) ? 0 : k;
+    const double *sr = src + (js + b.py * ks) * b.px;
+    for (int i = threadIdx.x; i < ex; i += 64) dr[i] = sr[(comp == 0 && b.per[0] && i == b.nx) ? 0 : i];
 }
 
 // Face densities of one component -> mass = rho/dt and beta = 1/rho in one pass
@@ -1246,13 +1297,12 @@ __global__ void __launch_bounds__(64 * kPackRows) k_pack_rho(Box b, int comp, do
         const int k = r / b.py, j = r - k * b.py;
         const int ex = b.nx + (comp == 0), ey = b.ny + (comp == 1), ez = b.nz + (comp == 2);
         const bool row_in = j < ey && k < ez;
-        const bool row_wall = (comp == 1 && (j == 0 || (j == b.ny && !(b.open_top && b.dim == 2)))) ||
-                              (comp == 2 && (k == 0 || (k == b.nz && !(b.open_top && b.dim == 3))));
+        const bool row_wall = face_row_wall(b, comp, j, k);
         const double *sr = src + (row_in ? ex * (j + ey * k) : 0);
         double *mr = mass + r * b.px, *br = beta + r * b.px;
         for (int i = threadIdx.x; i < b.px; i += 64) {
             double m = 0.0, be = 0.0;
-            if (row_in && i < ex && !(row_wall || (comp == 0 && (i == 0 || i == b.nx)))) {
+            if (row_in && i < ex && !(row_wall || (comp == 0 && x_wall_face(b, i)))) {
                 const double x = sr[i];
                 m = inv_dt * x;
                 // the open top's faces: zero pressure on the face, half a cell from the
@@ -1281,8 +1331,9 @@ __global__ void __launch_bounds__(kBlock) k_precond_div(Box b, const R *__restri
     decompose(b, idx, i, j, k);
     double qq = 0.0;
     if (is_cell(b, i, j, k)) {
-        double dv = ((double)eu[idx + 1] - (double)eu[idx]) * b.ihx + ((double)ev[idx + b.px] - (double)ev[idx]) * b.ihy;
-        if (DIM == 3) dv += ((double)ew[idx + b.plane] - (double)ew[idx]) * b.ihz;
+        const Nbr o = nbr(b, i, j, k);
+        double dv = ((double)eu[idx + o.xp] - (double)eu[idx]) * b.ihx + ((double)ev[idx + o.yp] - (double)ev[idx]) * b.ihy;
+        if (DIM == 3) dv += ((double)ew[idx + o.zp] - (double)ew[idx]) * b.ihz;
         qq = rp[idx] + dv;
     }
     q[idx] = qq;
@@ -1302,15 +1353,16 @@ __global__ void __launch_bounds__(kBlock) k_precond_update(Box b, const R *eu, c
     int i, j, k;
     decompose(b, idx, i, j, k);
     const double ph = (double)phi[idx];
+    const Nbr o = nbr(b, i, j, k);
     double z = 0.0;
-    if (is_ux(b, i, j, k)) z = (double)eu[idx] - dt * bx[idx] * (ph - (double)phi[idx - 1]) * b.ihx;
+    if (is_ux(b, i, j, k)) z = (double)eu[idx] - dt * bx[idx] * (ph - (double)phi[idx + o.xm]) * b.ihx;
     zu[idx] = z;
     z = 0.0;
-    if (is_vy(b, i, j, k)) z = (double)ev[idx] - dt * by[idx] * (ph - (double)phi[idx - b.px]) * b.ihy;
+    if (is_vy(b, i, j, k)) z = (double)ev[idx] - dt * by[idx] * (ph - (double)phi[idx + o.ym]) * b.ihy;
     zv[idx] = z;
     if (DIM == 3) {
         z = 0.0;
-        if (is_wz(b, i, j, k)) z = (double)ew[idx] - dt * bz[idx] * (ph - (double)phi[idx - b.plane]) * b.ihz;
+        if (is_wz(b, i, j, k)) z = (double)ew[idx] - dt * bz[idx] * (ph - (double)phi[idx + o.zm]) * b.ihz;
         zw[idx] = z;
     }
     z = 0.0;
@@ -1334,9 +1386,10 @@ __global__ void __launch_bounds__(kBlock) k_precond_div_jac(Box b, const double 
     decompose(b, idx, i, j, k);
     double qq = 0.0;
     if (is_cell(b, i, j, k)) {
-        double d = (vu[idx + 1] * du[idx + 1] - vu[idx] * du[idx]) * b.ihx
-                 + (vv[idx + b.px] * dv[idx + b.px] - vv[idx] * dv[idx]) * b.ihy;
-        if (DIM == 3) d += (vw[idx + b.plane] * dw[idx + b.plane] - vw[idx] * dw[idx]) * b.ihz;
+        const Nbr o = nbr(b, i, j, k);
+        double d = (vu[idx + o.xp] * du[idx + o.xp] - vu[idx] * du[idx]) * b.ihx
+                 + (vv[idx + o.yp] * dv[idx + o.yp] - vv[idx] * dv[idx]) * b.ihy;
+        if (DIM == 3) d += (vw[idx + o.zp] * dw[idx + o.zp] - vw[idx] * dw[idx]) * b.ihz;
         qq = vs * (rp[idx] + d);
     }
     q[idx] = qq;
@@ -1355,15 +1408,16 @@ __global__ void __launch_bounds__(kBlock) k_precond_update_jac(Box b, const doub
     int i, j, k;
     decompose(b, idx, i, j, k);
     const double ph = (double)phi[idx];
+    const Nbr o = nbr(b, i, j, k);
     double z = 0.0;
-    if (is_ux(b, i, j, k)) z = vs * vu[idx] * du[idx] - dt * bx[idx] * (ph - (double)phi[idx - 1]) * b.ihx;
+    if (is_ux(b, i, j, k)) z = vs * vu[idx] * du[idx] - dt * bx[idx] * (ph - (double)phi[idx + o.xm]) * b.ihx;
     zu[idx] = z;
     z = 0.0;
-    if (is_vy(b, i, j, k)) z = vs * vv[idx] * dv[idx] - dt * by[idx] * (ph - (double)phi[idx - b.px]) * b.ihy;
+    if (is_vy(b, i, j, k)) z = vs * vv[idx] * dv[idx] - dt * by[idx] * (ph - (double)phi[idx + o.ym]) * b.ihy;
     zv[idx] = z;
     if (DIM == 3) {
         z = 0.0;
-        if (is_wz(b, i, j, k)) z = vs * vw[idx] * dw[idx] - dt * bz[idx] * (ph - (double)phi[idx - b.plane]) * b.ihz;
+        if (is_wz(b, i, j, k)) z = vs * vw[idx] * dw[idx] - dt * bz[idx] * (ph - (double)phi[idx + o.zm]) * b.ihz;
         zw[idx] = z;
     }
     z = 0.0;
@@ -1380,14 +1434,14 @@ __global__ void __launch_bounds__(kBlock) k_vel_inv_diag(Box b, VelCoef<double> 
     int i, j, k;
     decompose(b, idx, i, j, k);
     double off, dg, v = 0.0;
-    if (is_ux(b, i, j, k)) { row_u<DIM, double>(b, idx, j, k, nullptr, nullptr, nullptr, 0, c, off, dg); v = 1.0 / dg; }
+    if (is_ux(b, i, j, k)) { row_u<DIM, double>(b, idx, i, j, k, nullptr, nullptr, nullptr, 0, c, off, dg); v = 1.0 / dg; }
     du[idx] = v;
     v = 0.0;
-    if (is_vy(b, i, j, k)) { row_v<DIM, double>(b, idx, i, k, nullptr, nullptr, nullptr, 0, c, off, dg); v = 1.0 / dg; }
+    if (is_vy(b, i, j, k)) { row_v<DIM, double>(b, idx, i, j, k, nullptr, nullptr, nullptr, 0, c, off, dg); v = 1.0 / dg; }
     dv[idx] = v;
     if (DIM == 3) {
         v = 0.0;
-        if (is_wz(b, i, j, k)) { row_w<double>(b, idx, i, j, nullptr, nullptr, nullptr, 0, c, off, dg); v = 1.0 / dg; }
+        if (is_wz(b, i, j, k)) { row_w<double>(b, idx, i, j, k, nullptr, nullptr, nullptr, 0, c, off, dg); v = 1.0 / dg; }
         dw[idx] = v;
     }
 }
@@ -1418,7 +1472,7 @@ __global__ void __launch_bounds__(kBlock) k_p_apply3(Box b, const R *__restrict_
     R v = 0;
     if (is_cell(b, i, j, k)) {
         R off, dg;
-        prow<3, R>(b, idx, e, bx, by, bz, off, dg);
+        prow<3, R>(b, idx, i, j, k, e, bx, by, bz, off, dg);
         v = dg * e[idx] - off;
     }
     y[idx] = v;
@@ -1720,7 +1774,7 @@ __global__ void __launch_bounds__(kBlock) k_p_res_partial(Box b, const R *__rest
         decompose(b, idx, i, j, k);
         if (!is_cell(b, i, j, k)) continue;
         R off, dg;
-        prow<3, R>(b, idx, e, bx, by, bz, off, dg);
+        prow<3, R>(b, idx, i, j, k, e, bx, by, bz, off, dg);
         const double res = (double)r[idx] - ((double)dg * (double)e[idx] - (double)off);
         v[0] += res * res;
         v[1] += (double)r[idx] * (double)r[idx];

@@ -250,6 +250,7 @@ extern "C" stokes_status stokes_explicit_rhs(const stokes_grid *grid, const doub
     const int dim = grid->dim;
     if (dim != 2 && dim != 3) return STOKES_EINVAL;
     for (int d = 0; d < dim; ++d) {
+        if (grid->periodic[d]) return STOKES_EINVAL;     // walls only
         if (grid->n[d] < 2) return STOKES_ESHAPE;
         if (!finite_pos(grid->h[d])) return STOKES_EINVAL;
         if (!rho_face[d] || !u_n[d] || !f[d] || (rho_force && !rho_force[d])) return STOKES_EINVAL;

@@ -238,6 +238,8 @@ stokes_status rigid_check(const stokes_grid *grid, double *const u[3], long long
     if (!grid || !u || !body || n_markers < 0) return STOKES_EINVAL;
     const int dim = grid->dim;
     if (dim != 2 && dim != 3) return STOKES_EINVAL;
+    for (int d = 0; d < dim; ++d)
+        if (grid->periodic[d]) return STOKES_EINVAL;     // walls only (mirrored stencils)
     g = RigidGrid{};
     g.dim = dim;
     for (int d = 0; d < 3; ++d) {

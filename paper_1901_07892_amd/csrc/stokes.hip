@@ -99,6 +99,7 @@ bool can_coarsen(const Box &b) {
 Box coarse_of(const Box &f) {
     Box c = make_box(f.dim, f.nx / 2, f.ny / 2, f.dim == 3 ? f.nz / 2 : 1, 2 * f.hx, 2 * f.hy, 2 * f.hz);
     c.open_top = f.open_top;
+    for (int a = 0; a < 3; ++a) c.per[a] = f.per[a];
     return c;
 }
 
@@ -243,6 +244,10 @@ void carve_all(Carver &cv, stokes_ctx &c) {
     c.dflag = cv.take<int>(64);
     c.ws_need = cv.off + 256;
 }
+
+// The z-marching kernels assume walls on every side; a level with a periodic
+// axis takes the flat kernels, which wrap.
+inline bool any_periodic(const Box &b) { return b.per[0] || b.per[1] || b.per[2]; }
 
 // ---------------------------------------------------------------- launch helpers
 inline unsigned nblocks_box(const Box &b) { return (unsigned)((b.nb + kBlock - 1) / kBlock); }
@@ -456,7 +461,7 @@ template <int DIM, class R>
 void p_residual_restrict(stokes_ctx &c, const Level<R> &L, const Level<R> &C, const R *e, const R *r, R *rc,
                          bool flat_only) {
     const R *bz = DIM == 3 ? L.beta[2] : L.beta[1];
-    if (DIM == 3 && !flat_only && (long long)L.b.nx * L.b.ny * L.b.nz >= (1LL << 21)) {
+    if (DIM == 3 && !flat_only && !any_periodic(L.b) && (long long)L.b.nx * L.b.ny * L.b.nz >= (1LL << 21)) {
         constexpr int TX = 64, TY = 4;
         const int gx = (C.b.nx + TX - 1) / TX, gy = (C.b.ny + TY - 1) / TY;
         int kc = C.b.nz;
@@ -480,7 +485,7 @@ void p_level_sweep(stokes_ctx &c, Level<R> &L, R *&cur, R *&spare, const R *r, b
                    bool flat_only) {
     // levels of at most 64^3 cells are latency-bound: two flat colour passes beat
     // a z-marching launch there
-    const bool flat = DIM == 2 || flat_only || (long long)L.b.nx * L.b.ny * L.b.nz <= (1LL << 18);
+    const bool flat = DIM == 2 || flat_only || any_periodic(L.b) || (long long)L.b.nx * L.b.ny * L.b.nz <= (1LL << 18);
     if (flat) {
         if (ec) k_p_prolong_add<DIM, R><<<nblocks_box(L.b), kBlock, 0, c.stream>>>(L.b, *cb, c.opt.p_prolong, ec, cur);
         p_smooth<DIM, R>(c, L, cur, r, 1, zg);
@@ -706,7 +711,7 @@ void apply_fine(stokes_ctx &c, double *x, double *f, double *y) {
     // x: 4 unknown fields, coefficients: DIM mass + mu + edges; y: 4 fields; f: 4 more
     const int nedge = DIM == 3 ? 3 : 1;
     ProfScope ps(c, STOKES_PROF_MATVEC, cells * 8.0 * ((DIM + 1) * (f ? 3 : 2) + DIM + 1 + nedge));
-    if (DIM == 3 && c.opt.matvec_z) {
+    if (DIM == 3 && c.opt.matvec_z && !any_periodic(c.fine)) {
         constexpr int TX = 64, TY = 4;
         const Box &b = c.fine;
         int gx = (b.nx + TX - 1) / TX, gy = (b.ny + TY - 1) / TY;
@@ -908,11 +913,17 @@ void build_dense(stokes_ctx &c, MG<R> &mg) {
                         int f[3] = {i, j, k};
                         if (side) f[a] += 1;
                         if (nb[a] < 0 || nb[a] >= ext[a]) {
-                            // the open top: zero pressure on the face (its beta carries the
-                            // factor 2 of the half-cell distance); walls carry no flux
-                            if (b.open_top && side == 1 && a == d - 1)
-                                A[(size_t)r * n + r] += (double)bt[a][box_index(b, f[0], f[1], f[2])] * ih2[a];
-                            continue;
+                            if (b.per[a]) {
+                                // periodic: the neighbour and the face wrap
+                                nb[a] = (nb[a] + ext[a]) % ext[a];
+                                f[a] %= ext[a];
+                            } else {
+                                // the open top: zero pressure on the face (its beta carries the
+                                // factor 2 of the half-cell distance); walls carry no flux
+                                if (b.open_top && side == 1 && a == d - 1)
+                                    A[(size_t)r * n + r] += (double)bt[a][box_index(b, f[0], f[1], f[2])] * ih2[a];
+                                continue;
+                            }
                         }
                         double w = (double)bt[a][box_index(b, f[0], f[1], f[2])] * ih2[a];
                         A[(size_t)r * n + r] += w;
@@ -1134,9 +1145,9 @@ __global__ void k_visc_ratio(Box b, VelCoef<double> c, double *__restrict__ out)
         int i, j, k;
         decompose(b, idx, i, j, k);
         double off, dg;
-        if (is_ux(b, i, j, k)) { row_u<DIM, double>(b, idx, j, k, nullptr, nullptr, nullptr, 0, c, off, dg); mx = fmax(mx, dg / c.mass[0][idx] - 1.0); }
-        if (is_vy(b, i, j, k)) { row_v<DIM, double>(b, idx, i, k, nullptr, nullptr, nullptr, 0, c, off, dg); mx = fmax(mx, dg / c.mass[1][idx] - 1.0); }
-        if (DIM == 3 && is_wz(b, i, j, k)) { row_w<double>(b, idx, i, j, nullptr, nullptr, nullptr, 0, c, off, dg); mx = fmax(mx, dg / c.mass[2][idx] - 1.0); }
+        if (is_ux(b, i, j, k)) { row_u<DIM, double>(b, idx, i, j, k, nullptr, nullptr, nullptr, 0, c, off, dg); mx = fmax(mx, dg / c.mass[0][idx] - 1.0); }
+        if (is_vy(b, i, j, k)) { row_v<DIM, double>(b, idx, i, j, k, nullptr, nullptr, nullptr, 0, c, off, dg); mx = fmax(mx, dg / c.mass[1][idx] - 1.0); }
+        if (DIM == 3 && is_wz(b, i, j, k)) { row_w<double>(b, idx, i, j, k, nullptr, nullptr, nullptr, 0, c, off, dg); mx = fmax(mx, dg / c.mass[2][idx] - 1.0); }
     }
     sm[threadIdx.x] = mx;
     __syncthreads();
@@ -1202,6 +1213,12 @@ const char *check_grid_opts(const stokes_grid *g, const stokes_options &o) {
     if (o.p_nu_second < 0) return "p_nu_second must be >= 0";
     if (o.p_wdepth < 0) return "p_wdepth must be >= 0";
     if (o.open_top != 0 && o.open_top != 1) return "open_top must be 0 or 1";
+    for (int a = 0; a < g->dim; ++a) {
+        if (g->periodic[a] != 0 && g->periodic[a] != 1) return "periodic[a] must be 0 or 1";
+        // red-black colouring stays a colouring across the wrap only for even counts
+        if (g->periodic[a] && g->n[a] % 2 != 0) return "a periodic axis needs an even number of cells";
+    }
+    if (o.open_top && g->periodic[g->dim - 1]) return "open_top needs walls, not a periodic vertical axis";
     return nullptr;
 }
 
@@ -1232,11 +1249,12 @@ void init_ctx_shape(stokes_ctx &c, const stokes_grid *g, const stokes_options &o
     c.fine = make_box(g->dim, g->n[0], g->n[1], g->dim == 3 ? g->n[2] : 1, g->h[0], g->h[1],
                       g->dim == 3 ? g->h[2] : g->h[0]);
     c.fine.open_top = o.open_top;
+    for (int a = 0; a < g->dim; ++a) c.fine.per[a] = g->periodic[a];
     {
         const Box &b = c.fine;
         double nc = (double)b.nx * b.ny * b.nz;
-        c.unknowns = nc + (double)(b.nx - 1) * b.ny * b.nz + (double)b.nx * (b.ny - 1) * b.nz +
-                     (g->dim == 3 ? (double)b.nx * b.ny * (b.nz - 1) : 0.0) +
+        c.unknowns = nc + (double)(b.nx - 1 + b.per[0]) * b.ny * b.nz + (double)b.nx * (b.ny - 1 + b.per[1]) * b.nz +
+                     (g->dim == 3 ? (double)b.nx * b.ny * (b.nz - 1 + b.per[2]) : 0.0) +
                      (o.open_top ? (double)b.nx * (g->dim == 3 ? b.ny : 1) : 0.0);
     }
 }
@@ -1905,6 +1923,10 @@ stokes_status stokes_inflow_lift(stokes_ctx *ctx, const double *u_n, const doubl
         return STOKES_EINVAL;
     }
     const Box &b = ctx->fine;
+    if (b.per[0]) {
+        ctx->err = "inflow data needs a wall at x = 0, not a periodic x axis";
+        return STOKES_EINVAL;
+    }
     const long long pts = (long long)(b.ny + 1) * (d == 3 ? b.nz + 1 : 1);
     k_inflow_lift<<<(unsigned)((pts + kBlock - 1) / kBlock), kBlock, 0, ctx->stream>>>(
         b, ctx->mu, ctx->mxy, ctx->mxz, ctx->theta, u_n, u_t, rhs_u[0], rhs_u[1], d == 3 ? rhs_u[2] : nullptr, rhs_p);

@@ -146,6 +146,8 @@ extern "C" stokes_status stokes_density_rk3(const stokes_grid *grid, double dt, 
     if (!grid || !rho_n || !u_stage || !rho_out) return STOKES_EINVAL;
     const int dim = grid->dim;
     if (dim != 2 && dim != 3) return STOKES_EINVAL;
+    for (int d = 0; d < dim; ++d)
+        if (grid->periodic[d]) return STOKES_EINVAL;     // walls only
     if (!(dt > 0.0) || !std::isfinite(dt)) return STOKES_EINVAL;
     TrGrid g{};
     g.dim = dim;

@@ -56,6 +56,7 @@ extern "C" stokes_status stokes_wave_inflow(const stokes_grid *grid, const stoke
     const int dim = grid->dim;
     if (dim != 2 && dim != 3) return STOKES_EINVAL;
     for (int a = 0; a < dim; ++a) {
+        if (grid->periodic[a]) return STOKES_EINVAL;     // the wave tank has walls
         if (grid->n[a] < 2) return STOKES_ESHAPE;
         if (!(grid->h[a] > 0.0) || !std::isfinite(grid->h[a])) return STOKES_EINVAL;
     }
