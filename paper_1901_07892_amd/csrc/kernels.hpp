@@ -252,12 +252,17 @@ __global__ void __launch_bounds__(kBlock) k_apply(Box b, VelCoef<double> c,
 }
 
 // 3D y = K x (or f - K x) marching in z: a block owns a TX x TY tile of cells
-// and a chunk of kc planes; each thread walks its column and keeps the centre
-// values that the next planes need (u, v, w, p, mu and the xz/yz edge viscosity
-// at k-1, k, k+1) in registers, so every value is fetched from HBM about once;
-// in-plane neighbours are read back from cache.  Only unknown positions
-// (i < nx, j < ny, k < nz) are visited: the padding and wall-normal slots of y
-// hold zero already and are not written.  Same row formulas as k_apply.
+// and a chunk of kc planes.  u, v and w sit in three-plane LDS rings (planes
+// k-1, k, k+1) and the cell and xy-edge viscosity of plane k in LDS, each on the
+// tile plus a one-point halo, so every plane of those five fields is read from
+// memory once per block (the stencil's in-plane neighbours come from LDS, not
+// from caches that the other blocks' streams evict); the centre-only fields
+// (mass, f), the pressure and the xz / yz edge viscosity (one-sided
+// neighbours) are read from memory directly, with their values at k-1 / k+1
+// carried in registers.  Only unknown positions (i < nx, j < ny, k < nz) are
+// visited: the padding and wall-normal slots of y hold zero already and are not
+// written.  Halo points outside the box (index -1) are never used by a row and
+// are not loaded.  Same row formulas as k_apply.
 template <int TX, int TY>
 __global__ void __launch_bounds__(TX *TY) k_apply3_z(Box b, int kc, VelCoef<double> c,
         const double *__restrict__ xu, const double *__restrict__ xv,
@@ -266,80 +271,123 @@ __global__ void __launch_bounds__(TX *TY) k_apply3_z(Box b, int kc, VelCoef<doub
         const double *__restrict__ fw, const double *__restrict__ fp,
         double *__restrict__ yu, double *__restrict__ yv,
         double *__restrict__ yw, double *__restrict__ yp) {
+    constexpr int HX = TX + 2, HY = TY + 2, HP = HX * HY, NT = TX * TY;
+    __shared__ double sU[3][HP], sV[3][HP], sW[3][HP], sM[HP], sXY[HP];
     const int G = gridDim.x * gridDim.y * gridDim.z;
     int t = xcd_swizzle(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z), G);
     const int bx_ = t % gridDim.x;
     t /= gridDim.x;
     const int by_ = t % gridDim.y, bz_ = t / gridDim.y;
-    const int i = bx_ * TX + (int)(threadIdx.x % TX), j = by_ * TY + (int)(threadIdx.x / TX);
-    if (i >= b.nx || j >= b.ny) return;
+    const int tid = threadIdx.x, tx = tid % TX, ty = tid / TX;
+    const int i0 = bx_ * TX, j0 = by_ * TY;
+    const int i = i0 + tx, j = j0 + ty;
+    const bool own = i < b.nx && j < b.ny;
     const int k0 = bz_ * kc, k1 = min(k0 + kc, b.nz);
     const int sy = b.px, sz = b.plane;
     const double ihx = b.ihx, ihy = b.ihy, ihz = b.ihz, th = c.theta;
-    const bool ux = i >= 1, vy = j >= 1;
+    auto slot = [](int k) { return (k + 3) % 3; };          // k >= -1
+    // halo point t of plane k: box point (i0 - 1 + t % HX, j0 - 1 + t / HX, k) if it
+    // lies in the box (0 <= i <= nx, 0 <= j <= ny, 0 <= k <= nz), else none
+    auto hq = [&](int tt, int k) {
+        const int gi = i0 - 1 + tt % HX, gj = j0 - 1 + tt / HX;
+        return (gi >= 0 && gi <= b.nx && gj >= 0 && gj <= b.ny && k >= 0 && k <= b.nz) ? gi + sy * (gj + b.py * k) : -1;
+    };
+    auto load_vel = [&](int k) {
+        const int sl = slot(k);
+        for (int tt = tid; tt < HP; tt += NT) {
+            const int q = hq(tt, k);
+            sU[sl][tt] = q >= 0 ? xu[q] : 0.0;
+            sV[sl][tt] = q >= 0 ? xv[q] : 0.0;
+            sW[sl][tt] = q >= 0 ? xw[q] : 0.0;
+        }
+    };
+    auto load_mu = [&](int k) {
+        for (int tt = tid; tt < HP; tt += NT) {
+            const int q = hq(tt, k);
+            sM[tt] = q >= 0 ? c.mu[q] : 0.0;
+            sXY[tt] = q >= 0 ? c.mxy[q] : 0.0;
+        }
+    };
     const double gE = i + 1 < b.nx ? 1.0 : 2.0, gW = i > 0 ? 1.0 : 2.0;
     const double gN = j + 1 < b.ny ? 1.0 : 2.0, gS = j > 0 ? 1.0 : 2.0;
-    int idx = box_index(b, i, j, k0);
-    // centre values at k-1 and k (the guard plane below k = 0 holds zeros)
-    double U0 = xu[idx - sz], U1 = xu[idx], V0 = xv[idx - sz], V1 = xv[idx], W0 = xw[idx - sz], W1 = xw[idx];
-    double P0 = xp[idx - sz], M0 = c.mu[idx - sz], XZ1 = c.mxz[idx], YZ1 = c.myz[idx];
+    const bool ux = i >= 1, vy = j >= 1;
+    const int c0 = (ty + 1) * HX + (tx + 1);
+    int idx = own ? box_index(b, i, j, k0) : 0;
+    // values at k-1 carried in registers (the guard plane below k = 0 holds zeros)
+    double P0 = own ? xp[idx - sz] : 0.0, M0 = own ? c.mu[idx - sz] : 0.0;
+    double XZ1 = own ? c.mxz[idx] : 0.0, YZ1 = own ? c.myz[idx] : 0.0;
+    load_vel(k0 - 1);
+    load_vel(k0);
     for (int k = k0; k < k1; ++k, idx += sz) {
-        const double U2 = xu[idx + sz], V2 = xv[idx + sz], W2 = xw[idx + sz];
-        const double XZ2 = c.mxz[idx + sz], YZ2 = c.myz[idx + sz];
-        const double P1 = xp[idx], M1 = c.mu[idx];
-        const bool top = k + 1 < b.nz, bot = k > 0;
-        const double gT = top ? 1.0 : 2.0, gB = bot ? 1.0 : 2.0;
-        // x-momentum
-        if (ux) {
-            const double uE = xu[idx + 1], uW = xu[idx - 1];
-            const double uN = j + 1 < b.ny ? xu[idx + sy] : 0.0, uS = j > 0 ? xu[idx - sy] : 0.0;
-            const double uT = top ? U2 : 0.0, uB = bot ? U0 : 0.0;
-            const double m0 = c.mu[idx - 1], mN = c.mxy[idx + sy], mS = c.mxy[idx];
-            const double dvN = xv[idx + sy] - xv[idx + sy - 1], dvS = V1 - xv[idx - 1];
-            const double dwT = W2 - xw[idx + sz - 1], dwB = W1 - xw[idx - 1];
-            double lap = 2.0 * (M1 * uE + m0 * uW) * ihx * ihx
-                       + (mN * (uN * ihy + dvN * ihx) - mS * (-uS * ihy + dvS * ihx)) * ihy
-                       + (XZ2 * (uT * ihz + dwT * ihx) - XZ1 * (-uB * ihz + dwB * ihx)) * ihz;
-            double dg = 2.0 * (m0 + M1) * ihx * ihx + (mN * gN + mS * gS) * ihy * ihy + (XZ2 * gT + XZ1 * gB) * ihz * ihz;
-            double r = (c.mass[0][idx] + th * dg) * U1 - th * lap + (P1 - xp[idx - 1]) * ihx;
-            yu[idx] = fu ? fu[idx] - r : r;
+        load_vel(k + 1);
+        load_mu(k);
+        __syncthreads();
+        if (own) {
+            const double *Um = sU[slot(k - 1)], *U0 = sU[slot(k)], *Up = sU[slot(k + 1)];
+            const double *Vm = sV[slot(k - 1)], *V0 = sV[slot(k)], *Vp = sV[slot(k + 1)];
+            const double *Wm = sW[slot(k - 1)], *W0 = sW[slot(k)], *Wp = sW[slot(k + 1)];
+            const double U1 = U0[c0], V1 = V0[c0], W1 = W0[c0];
+            const double W2 = Wp[c0];
+            const double XZ2 = c.mxz[idx + sz], YZ2 = c.myz[idx + sz];
+            const double P1 = xp[idx], M1 = sM[c0];
+            const bool top = k + 1 < b.nz, bot = k > 0;
+            const double gT = top ? 1.0 : 2.0, gB = bot ? 1.0 : 2.0;
+            // x-momentum
+            if (ux) {
+                const double uE = U0[c0 + 1], uW = U0[c0 - 1];
+                const double uN = j + 1 < b.ny ? U0[c0 + HX] : 0.0, uS = j > 0 ? U0[c0 - HX] : 0.0;
+                const double uT = top ? Up[c0] : 0.0, uB = bot ? Um[c0] : 0.0;
+                const double m0 = sM[c0 - 1], mN = sXY[c0 + HX], mS = sXY[c0];
+                const double dvN = V0[c0 + HX] - V0[c0 + HX - 1], dvS = V1 - V0[c0 - 1];
+                const double dwT = W2 - Wp[c0 - 1], dwB = W1 - W0[c0 - 1];
+                double lap = 2.0 * (M1 * uE + m0 * uW) * ihx * ihx
+                           + (mN * (uN * ihy + dvN * ihx) - mS * (-uS * ihy + dvS * ihx)) * ihy
+                           + (XZ2 * (uT * ihz + dwT * ihx) - XZ1 * (-uB * ihz + dwB * ihx)) * ihz;
+                double dg = 2.0 * (m0 + M1) * ihx * ihx + (mN * gN + mS * gS) * ihy * ihy + (XZ2 * gT + XZ1 * gB) * ihz * ihz;
+                double r = (c.mass[0][idx] + th * dg) * U1 - th * lap + (P1 - xp[idx - 1]) * ihx;
+                yu[idx] = fu ? fu[idx] - r : r;
+            }
+            // y-momentum
+            if (vy) {
+                const double vN = V0[c0 + HX], vS = V0[c0 - HX];
+                const double vE = i + 1 < b.nx ? V0[c0 + 1] : 0.0, vW = i > 0 ? V0[c0 - 1] : 0.0;
+                const double vT = top ? Vp[c0] : 0.0, vB = bot ? Vm[c0] : 0.0;
+                const double m0 = sM[c0 - HX], mE = sXY[c0 + 1], mW = sXY[c0];
+                const double duE = U0[c0 + 1] - U0[c0 + 1 - HX], duW = U1 - U0[c0 - HX];
+                const double dwT = W2 - Wp[c0 - HX], dwB = W1 - W0[c0 - HX];
+                double lap = 2.0 * (M1 * vN + m0 * vS) * ihy * ihy
+                           + (mE * (vE * ihx + duE * ihy) - mW * (-vW * ihx + duW * ihy)) * ihx
+                           + (YZ2 * (vT * ihz + dwT * ihy) - YZ1 * (-vB * ihz + dwB * ihy)) * ihz;
+                double dg = 2.0 * (m0 + M1) * ihy * ihy + (mE * gE + mW * gW) * ihx * ihx + (YZ2 * gT + YZ1 * gB) * ihz * ihz;
+                double r = (c.mass[1][idx] + th * dg) * V1 - th * lap + (P1 - xp[idx - sy]) * ihy;
+                yv[idx] = fv ? fv[idx] - r : r;
+            }
+            // z-momentum
+            if (bot) {
+                const double W0c = Wm[c0];
+                const double wE = i + 1 < b.nx ? W0[c0 + 1] : 0.0, wW = i > 0 ? W0[c0 - 1] : 0.0;
+                const double wN = j + 1 < b.ny ? W0[c0 + HX] : 0.0, wS = j > 0 ? W0[c0 - HX] : 0.0;
+                const double mE = c.mxz[idx + 1], mN = c.myz[idx + sy];
+                const double duE = U0[c0 + 1] - Um[c0 + 1], duW = U1 - Um[c0];
+                const double dvN = V0[c0 + HX] - Vm[c0 + HX], dvS = V1 - Vm[c0];
+                double lap = 2.0 * (M1 * W2 + M0 * W0c) * ihz * ihz
+                           + (mE * (wE * ihx + duE * ihz) - XZ1 * (-wW * ihx + duW * ihz)) * ihx
+                           + (mN * (wN * ihy + dvN * ihz) - YZ1 * (-wS * ihy + dvS * ihz)) * ihy;
+                double dg = 2.0 * (M0 + M1) * ihz * ihz + (mE * gE + XZ1 * gW) * ihx * ihx + (mN * gN + YZ1 * gS) * ihy * ihy;
+                double r = (c.mass[2][idx] + th * dg) * W1 - th * lap + (P1 - P0) * ihz;
+                yw[idx] = fw ? fw[idx] - r : r;
+            }
+            // continuity
+            {
+                double d = (U0[c0 + 1] - U1) * ihx + (V0[c0 + HX] - V1) * ihy + (W2 - W1) * ihz;
+                yp[idx] = fp ? fp[idx] + d : -d;
+            }
+            P0 = P1;
+            M0 = M1;
+            XZ1 = XZ2;
+            YZ1 = YZ2;
         }
-        // y-momentum
-        if (vy) {
-            const double vN = xv[idx + sy], vS = xv[idx - sy];
-            const double vE = i + 1 < b.nx ? xv[idx + 1] : 0.0, vW = i > 0 ? xv[idx - 1] : 0.0;
-            const double vT = top ? V2 : 0.0, vB = bot ? V0 : 0.0;
-            const double m0 = c.mu[idx - sy], mE = c.mxy[idx + 1], mW = c.mxy[idx];
-            const double duE = xu[idx + 1] - xu[idx + 1 - sy], duW = U1 - xu[idx - sy];
-            const double dwT = W2 - xw[idx + sz - sy], dwB = W1 - xw[idx - sy];
-            double lap = 2.0 * (M1 * vN + m0 * vS) * ihy * ihy
-                       + (mE * (vE * ihx + duE * ihy) - mW * (-vW * ihx + duW * ihy)) * ihx
-                       + (YZ2 * (vT * ihz + dwT * ihy) - YZ1 * (-vB * ihz + dwB * ihy)) * ihz;
-            double dg = 2.0 * (m0 + M1) * ihy * ihy + (mE * gE + mW * gW) * ihx * ihx + (YZ2 * gT + YZ1 * gB) * ihz * ihz;
-            double r = (c.mass[1][idx] + th * dg) * V1 - th * lap + (P1 - xp[idx - sy]) * ihy;
-            yv[idx] = fv ? fv[idx] - r : r;
-        }
-        // z-momentum
-        if (bot) {
-            const double wE = i + 1 < b.nx ? xw[idx + 1] : 0.0, wW = i > 0 ? xw[idx - 1] : 0.0;
-            const double wN = j + 1 < b.ny ? xw[idx + sy] : 0.0, wS = j > 0 ? xw[idx - sy] : 0.0;
-            const double mE = c.mxz[idx + 1], mN = c.myz[idx + sy];
-            const double duE = xu[idx + 1] - xu[idx + 1 - sz], duW = U1 - U0;
-            const double dvN = xv[idx + sy] - xv[idx + sy - sz], dvS = V1 - V0;
-            double lap = 2.0 * (M1 * W2 + M0 * W0) * ihz * ihz
-                       + (mE * (wE * ihx + duE * ihz) - XZ1 * (-wW * ihx + duW * ihz)) * ihx
-                       + (mN * (wN * ihy + dvN * ihz) - YZ1 * (-wS * ihy + dvS * ihz)) * ihy;
-            double dg = 2.0 * (M0 + M1) * ihz * ihz + (mE * gE + XZ1 * gW) * ihx * ihx + (mN * gN + YZ1 * gS) * ihy * ihy;
-            double r = (c.mass[2][idx] + th * dg) * W1 - th * lap + (P1 - P0) * ihz;
-            yw[idx] = fw ? fw[idx] - r : r;
-        }
-        // continuity
-        {
-            double d = (xu[idx + 1] - U1) * ihx + (xv[idx + sy] - V1) * ihy + (W2 - W1) * ihz;
-            yp[idx] = fp ? fp[idx] + d : -d;
-        }
-        U0 = U1; U1 = U2; V0 = V1; V1 = V2; W0 = W1; W1 = W2;
-        P0 = P1; M0 = M1; XZ1 = XZ2; YZ1 = YZ2;
+        __syncthreads();                        // the next step overwrites plane k-1's slot and sM, sXY
     }
 }
 

@@ -712,7 +712,7 @@ void apply_fine(stokes_ctx &c, double *x, double *f, double *y) {
     const int nedge = DIM == 3 ? 3 : 1;
     ProfScope ps(c, STOKES_PROF_MATVEC, cells * 8.0 * ((DIM + 1) * (f ? 3 : 2) + DIM + 1 + nedge));
     if (DIM == 3 && c.opt.matvec_z && !any_periodic(c.fine)) {
-        constexpr int TX = 64, TY = 4;
+        constexpr int TX = 64, TY = 8;
         const Box &b = c.fine;
         int gx = (b.nx + TX - 1) / TX, gy = (b.ny + TY - 1) / TY;
         int kc = b.nz;
