@@ -653,22 +653,23 @@ __global__ void __launch_bounds__(TX *TY) k_p_residual_restrict3_z(Box fb, Box c
 // value (piecewise constant).  lin == 1: bi/trilinear interpolation between the
 // cell centres, weights 3/4 (parent) and 1/4 (the coarse neighbour on the
 // child's side) per axis; beyond a wall the parent is mirrored, along a
-// periodic axis the neighbour wraps.
-template <int DIM, class R>
+// periodic axis the neighbour wraps (PER = false: walls only, for the
+// z-marching kernels, which periodic levels never reach).
+template <int DIM, class R, bool PER = true>
 __device__ inline R prolong_value(const Box &cb, const R *ec, int i, int j, int k, int lin) {
     const int I = i >> 1, J = j >> 1, K = DIM == 3 ? (k >> 1) : 0;
     if (!lin) return ec[box_index(cb, I, J, K)];
     int I2 = (i & 1) ? I + 1 : I - 1;
     int J2 = (j & 1) ? J + 1 : J - 1;
-    I2 = cb.per[0] ? (I2 + cb.nx) % cb.nx : (I2 < 0 ? 0 : (I2 >= cb.nx ? cb.nx - 1 : I2));
-    J2 = cb.per[1] ? (J2 + cb.ny) % cb.ny : (J2 < 0 ? 0 : (J2 >= cb.ny ? cb.ny - 1 : J2));
+    I2 = (PER && cb.per[0]) ? (I2 + cb.nx) % cb.nx : (I2 < 0 ? 0 : (I2 >= cb.nx ? cb.nx - 1 : I2));
+    J2 = (PER && cb.per[1]) ? (J2 + cb.ny) % cb.ny : (J2 < 0 ? 0 : (J2 >= cb.ny ? cb.ny - 1 : J2));
     const R a = R(0.75), b = R(0.25);
     if (DIM == 2) {
         return a * (a * ec[box_index(cb, I, J, 0)] + b * ec[box_index(cb, I2, J, 0)])
              + b * (a * ec[box_index(cb, I, J2, 0)] + b * ec[box_index(cb, I2, J2, 0)]);
     }
     int K2 = (k & 1) ? K + 1 : K - 1;
-    K2 = cb.per[2] ? (K2 + cb.nz) % cb.nz : (K2 < 0 ? 0 : (K2 >= cb.nz ? cb.nz - 1 : K2));
+    K2 = (PER && cb.per[2]) ? (K2 + cb.nz) % cb.nz : (K2 < 0 ? 0 : (K2 >= cb.nz ? cb.nz - 1 : K2));
     R p0 = a * (a * ec[box_index(cb, I, J, K)] + b * ec[box_index(cb, I2, J, K)])
          + b * (a * ec[box_index(cb, I, J2, K)] + b * ec[box_index(cb, I2, J2, K)]);
     R p1 = a * (a * ec[box_index(cb, I, J, K2)] + b * ec[box_index(cb, I2, J, K2)])
@@ -689,7 +690,26 @@ __global__ void __launch_bounds__(kBlock) k_p_prolong_add(Box fb, Box cb, int li
 }
 
 // Coarsest pressure level: e = M r with M the dense pseudo-inverse of the
-// level's Neumann operator (it also projects out the constant).  One block.
+// level's Neumann operator (it also projects out the constant).  One block of
+// 1024 threads, 16 per row (dense_row).
+// Row t of M rs, computed by 16 lanes: lane g of the group sums the contiguous
+// segment q = g*L .. g*L + L - 1 (L = ceil(n/16)) in order, then the 16 partial
+// sums are added pairwise (lanes g and g^8, then ^4, ^2, ^1).  Every lane of the
+// group returns the row's value.  blockDim.x is a multiple of 64, so a group
+// never straddles wavefronts and all of its lanes take part.
+template <class R, class MP>
+__device__ inline R dense_row(MP M, const R *rs, int n, int t, int g) {
+    const int L = (n + 15) >> 4;
+    R acc = 0;
+    if (t < n) {
+        const int q0 = g * L, q1 = min(q0 + L, n);
+        for (int q = q0; q < q1; ++q) acc += M[(size_t)t * n + q] * rs[q];
+    }
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 16);
+    return acc;
+}
+
 template <class R>
 __global__ void __launch_bounds__(1024) k_dense_solve(int n, const R *__restrict__ M, const int *__restrict__ map,
         const R *__restrict__ r, R *__restrict__ e) {
@@ -697,11 +717,11 @@ __global__ void __launch_bounds__(1024) k_dense_solve(int n, const R *__restrict
     R *rs = reinterpret_cast<R *>(smem_raw);
     for (int t = threadIdx.x; t < n; t += blockDim.x) rs[t] = r[map[t]];
     __syncthreads();
-    for (int t = threadIdx.x; t < n; t += blockDim.x) {
-        R acc = 0;
-        const R *row = M + (size_t)t * n;
-        for (int q = 0; q < n; ++q) acc += row[q] * rs[q];
-        e[map[t]] = acc;
+    const int g = threadIdx.x & 15, rows = blockDim.x >> 4;
+    for (int t0 = 0; t0 < n; t0 += rows) {
+        const int t = t0 + (threadIdx.x >> 4);
+        const R v = dense_row<R, const R *__restrict__>(M, rs, n, t, g);
+        if (t < n && g == 0) e[map[t]] = v;
     }
 }
 
@@ -718,6 +738,7 @@ __global__ void __launch_bounds__(1024) k_dense_solve(int n, const R *__restrict
 enum { SOP_GS = 0, SOP_RESTRICT = 1, SOP_PROLONG = 2, SOP_DENSE = 3, SOP_ZERO = 4 };
 constexpr int kSmallMaxLev = 8;
 constexpr int kSmallThreads = 1024;
+constexpr int kSmallCached = 2;     // first-level cells per thread and colour set up once per launch
 
 // One pass: x = kind, y = level (0 = the first small level), z = colour of a
 // smoothing pass, w = its zero-guess flag (0 no, 1 yes, 2 the launch's).
@@ -767,8 +788,11 @@ __device__ inline void small_restrict(const Box &fb, const Box &cb, const R *e, 
         const int I = t % cb.nx, JK = t / cb.nx;
         const int J = JK % cb.ny, K = JK / cb.ny;
         R acc = 0;
+#pragma unroll 1
         for (int dk = 0; dk < 2; ++dk)
+#pragma unroll 1
             for (int dj = 0; dj < 2; ++dj)
+#pragma unroll 1
                 for (int di = 0; di < 2; ++di) {
                     const int q = box_index(fb, 2 * I + di, 2 * J + dj, 2 * K + dk);
                     R off, dg;
@@ -786,11 +810,14 @@ __device__ inline void small_dense(const Box &b, int n, MP M, R *rs, const R *r,
         rs[t] = r[box_index(b, i, jk % b.ny, jk / b.ny)];
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < n; t += kSmallThreads) {
-        R acc = 0;
-        for (int q = 0; q < n; ++q) acc += M[(size_t)t * n + q] * rs[q];
-        const int i = t % b.nx, jk = t / b.nx;
-        e[box_index(b, i, jk % b.ny, jk / b.ny)] = acc;
+    const int g = threadIdx.x & 15;
+    for (int t0 = 0; t0 < n; t0 += kSmallThreads / 16) {
+        const int t = t0 + (threadIdx.x >> 4);
+        const R v = dense_row<R, MP>(M, rs, n, t, g);
+        if (t < n && g == 0) {
+            const int i = t % b.nx, jk = t / b.nx;
+            e[box_index(b, i, jk % b.ny, jk / b.ny)] = v;
+        }
     }
 }
 
@@ -799,9 +826,45 @@ __global__ void __launch_bounds__(kSmallThreads) k_p_small_cycle(SmallMG<R> m, c
         int nops, int zero_guess, R *__restrict__ e, const R *__restrict__ r) {
     extern __shared__ unsigned char smem_raw[];
     R *S = reinterpret_cast<R *>(smem_raw);
+    // The first level's smoothing passes dominate the cycle and are bound by the
+    // instructions of one CU.  When that level has walls on every side and each
+    // thread has at most kSmallCached of its cells per colour, the thread's cells
+    // (box index, or -1) and their weights beta/h^2 are set up once, before the
+    // LDS fills so that their loads overlap them; the passes then only load the
+    // iterate from LDS (the same products and sums as prow, so the results do
+    // not change).
+    const Box &b0 = m.b[0];
+    const int hx0 = (b0.nx + 1) >> 1, half0 = hx0 * b0.ny * b0.nz;
+    const bool fast0 = b0.dim == 3 && !(b0.per[0] || b0.per[1] || b0.per[2]) && half0 <= kSmallThreads * kSmallCached;
+    int q0[2][kSmallCached];
+    R w0[2][kSmallCached][6];
+    if (fast0) {
+        const R ix2 = R(b0.ihx * b0.ihx), iy2 = R(b0.ihy * b0.ihy), iz2 = R(b0.ihz * b0.ihz);
+#pragma unroll
+        for (int col = 0; col < 2; ++col)
+#pragma unroll
+            for (int q = 0; q < kSmallCached; ++q) {
+                const int t = threadIdx.x + q * kSmallThreads;
+                q0[col][q] = -1;
+#pragma unroll
+                for (int a = 0; a < 6; ++a) w0[col][q][a] = R(0);
+                if (t >= half0) continue;
+                const int ii = t % hx0, jk = t / hx0;
+                const int j = jk % b0.ny, k = jk / b0.ny;
+                const int i = 2 * ii + ((j + k + col) & 1);
+                if (i >= b0.nx) continue;
+                const int idx = box_index(b0, i, j, k);
+                q0[col][q] = idx;
+                w0[col][q][0] = m.gbeta[0][0][idx] * ix2;
+                w0[col][q][1] = m.gbeta[0][0][idx + 1] * ix2;
+                w0[col][q][2] = m.gbeta[0][1][idx] * iy2;
+                w0[col][q][3] = m.gbeta[0][1][idx + b0.px] * iy2;
+                w0[col][q][4] = m.gbeta[0][2][idx] * iz2;
+                w0[col][q][5] = m.gbeta[0][2][idx + b0.plane] * iz2;
+            }
+    }
     for (int t = threadIdx.x; t < m.lds_elems; t += kSmallThreads) S[t] = R(0);
     __syncthreads();
-    const Box &b0 = m.b[0];
     for (int t = threadIdx.x; t < b0.nb; t += kSmallThreads) {
         S[m.off_r[0] + t] = r[t];
         if (!zero_guess) S[m.off_e[0] + t] = e[t];
@@ -823,7 +886,23 @@ __global__ void __launch_bounds__(kSmallThreads) k_p_small_cycle(SmallMG<R> m, c
         R *Rr = S + m.off_r[l];
         if (op.kind == SOP_GS) {
             const bool zg = op.zero_guess == 2 ? zero_guess != 0 : op.zero_guess != 0;
-            if (l == 0) {
+            if (l == 0 && fast0) {
+                const int col = op.colour, sy = b.px, sz = b.plane;
+#pragma unroll
+                for (int q = 0; q < kSmallCached; ++q) {
+                    const int idx = col ? q0[1][q] : q0[0][q];
+                    if (idx < 0) continue;
+                    const R wW = col ? w0[1][q][0] : w0[0][q][0], wE = col ? w0[1][q][1] : w0[0][q][1];
+                    const R wS = col ? w0[1][q][2] : w0[0][q][2], wN = col ? w0[1][q][3] : w0[0][q][3];
+                    const R wB = col ? w0[1][q][4] : w0[0][q][4], wT = col ? w0[1][q][5] : w0[0][q][5];
+                    R off = wW * E[idx - 1] + wE * E[idx + 1] + wS * E[idx - sy] + wN * E[idx + sy];
+                    R dg = wW + wE + wS + wN;
+                    off += wB * E[idx - sz] + wT * E[idx + sz];
+                    dg += wB + wT;
+                    if (zg) off = R(0);
+                    E[idx] = dg > R(0) ? (Rr[idx] + off) / dg : R(0);
+                }
+            } else if (l == 0) {
                 small_gs<R, const R *__restrict__>(b, E, Rr, m.gbeta[0][0], m.gbeta[0][1], m.gbeta[0][2], op.colour, zg);
             } else {
                 const R *B = S + m.off_b[l];
@@ -904,7 +983,7 @@ __global__ void __launch_bounds__(TX *TY) k_p_sweep3(Box b, int kc, int zero_gue
             if (e < N2 && !zero_guess && k >= 0 && k < b.nz && i >= 0 && i < b.nx && j >= 0 && j < b.ny) {
                 const int q = box_index(b, i, j, k);
                 v[p] = ein[q];
-                if (ec) v[p] += prolong_value<3, R>(cb, ec, i, j, k, lin);
+                if (ec) v[p] += prolong_value<3, R, false>(cb, ec, i, j, k, lin);
             }
         }
         R *dst = oldp[slot(k)];
@@ -1047,7 +1126,7 @@ __global__ void __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(8))
             if (!zero_guess && k >= 0 && k < b.nz && i >= 0 && i < b.nx && j >= 0 && j < b.ny) {
                 int q = box_index(b, i, j, k);
                 v = ein[q];
-                if (ec) v += prolong_value<3, R>(cb, ec, i, j, k, lin);
+                if (ec) v += prolong_value<3, R, false>(cb, ec, i, j, k, lin);
             }
             dst[t] = v;
         }
@@ -1105,7 +1184,7 @@ __global__ void __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(8))
                 if (!zero_guess && kn >= 0 && kn < b.nz && ii >= 0 && ii < b.nx && jj >= 0 && jj < b.ny) {
                     int q = box_index(b, ii, jj, kn);
                     v = ein[q];
-                    if (ec) v += prolong_value<3, R>(cb, ec, ii, jj, kn, lin);
+                    if (ec) v += prolong_value<3, R, false>(cb, ec, ii, jj, kn, lin);
                 }
                 return v;
             };

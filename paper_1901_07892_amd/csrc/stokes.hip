@@ -513,8 +513,7 @@ R *p_vcycle(stokes_ctx &c, MG<R> &mg, int l, R *e, R *r, bool zero_guess) {
     };
     if (l == mg.nlev - 1) {
         if (mg.use_dense) {
-            int nt = std::min(1024, ((mg.ndense + 63) / 64) * 64);
-            k_dense_solve<R><<<1, nt, mg.ndense * sizeof(R), c.stream>>>(mg.ndense, mg.dense, mg.dmap, r, e);
+            k_dense_solve<R><<<1, 1024, mg.ndense * sizeof(R), c.stream>>>(mg.ndense, mg.dense, mg.dmap, r, e);
         } else if (DIM == 3) {
             for (int s = 0; s < std::max(1, c.opt.coarse_sweeps); ++s) sweep(zero_guess && s == 0, nullptr, nullptr);
         } else {
