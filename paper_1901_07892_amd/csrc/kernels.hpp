@@ -57,8 +57,15 @@ enum { VALID_U = 1, VALID_V = 2, VALID_W = 4 };
 struct Nbr {
     int xm, xp, ym, yp, zm, zp;
 };
+// PER = false: the caller knows that the level has walls on every side (the
+// offsets are then the plain +-1, +-px, +-plane).
+template <bool PER = true>
 __device__ inline Nbr nbr(const Box &b, int i, int j, int k) {
     Nbr o;
+    if (!PER) {
+        o.xm = -1; o.xp = 1; o.ym = -b.px; o.yp = b.px; o.zm = -b.plane; o.zp = b.plane;
+        return o;
+    }
     o.xm = (b.per[0] && i == 0) ? b.nx - 1 : -1;
     o.xp = (b.per[0] && i == b.nx - 1) ? 1 - b.nx : 1;
     o.ym = ((b.per[1] && j == 0) ? b.ny - 1 : -1) * b.px;
@@ -518,10 +525,10 @@ __global__ void __launch_bounds__(kBlock) k_face_prolong_add(Box fb, Box cb, int
 // ---------------------------------------------------------------- pressure multigrid
 // -L_rho phi = -D beta G phi at cell (i, j, k) (box point idx); beta is zero on
 // wall faces, so the Neumann walls need no branch; periodic axes wrap (Nbr).
-template <int DIM, class R>
+template <int DIM, class R, bool PER = true>
 __device__ inline void prow(const Box &b, int idx, int i, int j, int k, const R *e, const R *bx, const R *by,
                             const R *bz, R &off, R &diag) {
-    const Nbr o = nbr(b, i, j, k);
+    const Nbr o = nbr<PER>(b, i, j, k);
     const R ix2 = R(b.ihx * b.ihx), iy2 = R(b.ihy * b.ihy), iz2 = R(b.ihz * b.ihz);
     R wW = bx[idx] * ix2, wE = bx[idx + o.xp] * ix2;
     R wS = by[idx] * iy2, wN = by[idx + o.yp] * iy2;
@@ -534,7 +541,7 @@ __device__ inline void prow(const Box &b, int idx, int i, int j, int k, const R 
     }
 }
 
-template <int DIM, class R>
+template <int DIM, class R, bool PER>
 __global__ void __launch_bounds__(kBlock) k_p_gs(Box b, int colour, int zero_guess, R *e,
         const R *__restrict__ r, const R *__restrict__ bx, const R *__restrict__ by,
         const R *__restrict__ bz) {
@@ -544,14 +551,14 @@ __global__ void __launch_bounds__(kBlock) k_p_gs(Box b, int colour, int zero_gue
     decompose(b, idx, i, j, k);
     if (!is_cell(b, i, j, k) || ((i + j + k) & 1) != colour) return;
     R off, dg;
-    prow<DIM, R>(b, idx, i, j, k, e, bx, by, bz, off, dg);
+    prow<DIM, R, PER>(b, idx, i, j, k, e, bx, by, bz, off, dg);
     if (zero_guess) off = R(0);
     e[idx] = dg > R(0) ? (r[idx] + off) / dg : R(0);
 }
 
 // Coarse right-hand side: average over the 2^d children of the fine residual
 // r - (-L_rho) e.
-template <int DIM, class R>
+template <int DIM, class R, bool PER>
 __global__ void __launch_bounds__(kBlock) k_p_residual_restrict(Box fb, Box cb, const R *__restrict__ e,
         const R *__restrict__ r, const R *__restrict__ bx, const R *__restrict__ by,
         const R *__restrict__ bz, R *__restrict__ rc) {
@@ -568,7 +575,7 @@ __global__ void __launch_bounds__(kBlock) k_p_residual_restrict(Box fb, Box cb, 
                 const int fi = 2 * I + di, fj = 2 * J + dj, fk = DIM == 3 ? 2 * K + dk : 0;
                 int q = box_index(fb, fi, fj, fk);
                 R off, dg;
-                prow<DIM, R>(fb, q, fi, fj, fk, e, bx, by, bz, off, dg);
+                prow<DIM, R, PER>(fb, q, fi, fj, fk, e, bx, by, bz, off, dg);
                 acc += r[q] - (dg * e[q] - off);
             }
     rc[idx] = acc * (DIM == 3 ? R(0.125) : R(0.25));
@@ -678,7 +685,7 @@ __device__ inline R prolong_value(const Box &cb, const R *ec, int i, int j, int 
 }
 
 // Fine correction += prolonged coarse correction (see prolong_value).
-template <int DIM, class R>
+template <int DIM, class R, bool PER>
 __global__ void __launch_bounds__(kBlock) k_p_prolong_add(Box fb, Box cb, int lin, const R *__restrict__ c,
         R *__restrict__ f) {
     int idx = box_thread_index();
@@ -686,7 +693,7 @@ __global__ void __launch_bounds__(kBlock) k_p_prolong_add(Box fb, Box cb, int li
     int i, j, k;
     decompose(fb, idx, i, j, k);
     if (!is_cell(fb, i, j, k)) return;
-    f[idx] += prolong_value<DIM, R>(cb, c, i, j, k, lin);
+    f[idx] += prolong_value<DIM, R, PER>(cb, c, i, j, k, lin);
 }
 
 // Coarsest pressure level: e = M r with M the dense pseudo-inverse of the
@@ -763,7 +770,7 @@ struct SmallMG {
     int lds_elems;                   // LDS size in elements of R
 };
 
-template <class R, class BP>
+template <class R, class BP, bool PER>
 __device__ inline void small_gs(const Box &b, R *e, const R *r, BP bx, BP by, BP bz, int colour, bool zg) {
     const int hx = (b.nx + 1) >> 1;
     const int total = hx * b.ny * b.nz;
@@ -774,13 +781,13 @@ __device__ inline void small_gs(const Box &b, R *e, const R *r, BP bx, BP by, BP
         if (i >= b.nx) continue;
         const int idx = box_index(b, i, j, k);
         R off, dg;
-        prow<3, R>(b, idx, i, j, k, e, bx, by, bz, off, dg);
+        prow<3, R, PER>(b, idx, i, j, k, e, bx, by, bz, off, dg);
         if (zg) off = R(0);
         e[idx] = dg > R(0) ? (r[idx] + off) / dg : R(0);
     }
 }
 
-template <class R, class BP>
+template <class R, class BP, bool PER>
 __device__ inline void small_restrict(const Box &fb, const Box &cb, const R *e, const R *r, BP bx, BP by, BP bz,
                                       R *rc) {
     const int total = cb.nx * cb.ny * cb.nz;
@@ -796,7 +803,7 @@ __device__ inline void small_restrict(const Box &fb, const Box &cb, const R *e, 
                 for (int di = 0; di < 2; ++di) {
                     const int q = box_index(fb, 2 * I + di, 2 * J + dj, 2 * K + dk);
                     R off, dg;
-                    prow<3, R>(fb, q, 2 * I + di, 2 * J + dj, 2 * K + dk, e, bx, by, bz, off, dg);
+                    prow<3, R, PER>(fb, q, 2 * I + di, 2 * J + dj, 2 * K + dk, e, bx, by, bz, off, dg);
                     acc += r[q] - (dg * e[q] - off);
                 }
         rc[box_index(cb, I, J, K)] = acc * R(0.125);
@@ -821,7 +828,7 @@ __device__ inline void small_dense(const Box &b, int n, MP M, R *rs, const R *r,
     }
 }
 
-template <class R>
+template <class R, bool PER>
 __global__ void __launch_bounds__(kSmallThreads) k_p_small_cycle(SmallMG<R> m, const SmallOp *__restrict__ ops,
         int nops, int zero_guess, R *__restrict__ e, const R *__restrict__ r) {
     extern __shared__ unsigned char smem_raw[];
@@ -835,7 +842,7 @@ __global__ void __launch_bounds__(kSmallThreads) k_p_small_cycle(SmallMG<R> m, c
     // not change).
     const Box &b0 = m.b[0];
     const int hx0 = (b0.nx + 1) >> 1, half0 = hx0 * b0.ny * b0.nz;
-    const bool fast0 = b0.dim == 3 && !(b0.per[0] || b0.per[1] || b0.per[2]) && half0 <= kSmallThreads * kSmallCached;
+    const bool fast0 = !PER && b0.dim == 3 && half0 <= kSmallThreads * kSmallCached;
     int q0[2][kSmallCached];
     R w0[2][kSmallCached][6];
     if (fast0) {
@@ -903,18 +910,18 @@ __global__ void __launch_bounds__(kSmallThreads) k_p_small_cycle(SmallMG<R> m, c
                     E[idx] = dg > R(0) ? (Rr[idx] + off) / dg : R(0);
                 }
             } else if (l == 0) {
-                small_gs<R, const R *__restrict__>(b, E, Rr, m.gbeta[0][0], m.gbeta[0][1], m.gbeta[0][2], op.colour, zg);
+                small_gs<R, const R *__restrict__, PER>(b, E, Rr, m.gbeta[0][0], m.gbeta[0][1], m.gbeta[0][2], op.colour, zg);
             } else {
                 const R *B = S + m.off_b[l];
-                small_gs<R, const R *>(b, E, Rr, B, B + m.stride_b[l], B + 2 * m.stride_b[l], op.colour, zg);
+                small_gs<R, const R *, PER>(b, E, Rr, B, B + m.stride_b[l], B + 2 * m.stride_b[l], op.colour, zg);
             }
         } else if (op.kind == SOP_RESTRICT) {
             R *rc = S + m.off_r[l + 1];
             if (l == 0) {
-                small_restrict<R, const R *__restrict__>(b, m.b[1], E, Rr, m.gbeta[0][0], m.gbeta[0][1], m.gbeta[0][2], rc);
+                small_restrict<R, const R *__restrict__, PER>(b, m.b[1], E, Rr, m.gbeta[0][0], m.gbeta[0][1], m.gbeta[0][2], rc);
             } else {
                 const R *B = S + m.off_b[l];
-                small_restrict<R, const R *>(b, m.b[l + 1], E, Rr, B, B + m.stride_b[l], B + 2 * m.stride_b[l], rc);
+                small_restrict<R, const R *, PER>(b, m.b[l + 1], E, Rr, B, B + m.stride_b[l], B + 2 * m.stride_b[l], rc);
             }
         } else if (op.kind == SOP_PROLONG) {
             const Box &cb = m.b[l + 1];
@@ -923,7 +930,7 @@ __global__ void __launch_bounds__(kSmallThreads) k_p_small_cycle(SmallMG<R> m, c
             for (int t = threadIdx.x; t < total; t += kSmallThreads) {
                 const int i = t % b.nx, jk = t / b.nx;
                 const int j = jk % b.ny, k = jk / b.ny;
-                E[box_index(b, i, j, k)] += prolong_value<3, R>(cb, ec, i, j, k, m.lin);
+                E[box_index(b, i, j, k)] += prolong_value<3, R, PER>(cb, ec, i, j, k, m.lin);
             }
         } else if (op.kind == SOP_DENSE) {
             if (m.off_dense >= 0) small_dense<R, const R *>(b, m.ndense, S + m.off_dense, S + m.off_rs, Rr, E);

@@ -250,6 +250,8 @@ void carve_all(Carver &cv, stokes_ctx &c) {
 inline bool any_periodic(const Box &b) { return b.per[0] || b.per[1] || b.per[2]; }
 
 // ---------------------------------------------------------------- launch helpers
+template <int DIM, class R>
+void prolong_add(stokes_ctx &c, const Box &fb, const Box &cb, int lin, const R *ec, R *f);
 inline unsigned nblocks_box(const Box &b) { return (unsigned)((b.nb + kBlock - 1) / kBlock); }
 inline unsigned nblocks_stream(long long n) {
     long long g = (n + kBlock - 1) / kBlock;
@@ -402,17 +404,31 @@ int gamma_at(const stokes_ctx &c, const MG<R> &mg, int l) {
     return (c.opt.p_wdepth == 0 || l < c.opt.p_wdepth) ? c.opt.p_gamma : 1;
 }
 
+// f += the prolonged coarse correction on the cells of level fb
+template <int DIM, class R>
+void prolong_add(stokes_ctx &c, const Box &fb, const Box &cb, int lin, const R *ec, R *f) {
+    if (any_periodic(fb))
+        k_p_prolong_add<DIM, R, true><<<nblocks_box(fb), kBlock, 0, c.stream>>>(fb, cb, lin, ec, f);
+    else
+        k_p_prolong_add<DIM, R, false><<<nblocks_box(fb), kBlock, 0, c.stream>>>(fb, cb, lin, ec, f);
+}
+
 // Pre- and post-smoothing sweeps of pressure level l.
 inline int p_nu_pre(const stokes_ctx &c, int l) { return l == 1 ? c.nu_sec1 : (l == 2 || l == 3) ? c.nu_mid1 : c.opt.nu1; }
 inline int p_nu_post(const stokes_ctx &c, int l) { return l == 1 ? c.nu_sec2 : c.opt.nu2; }
 
 template <int DIM, class R>
 void p_smooth(stokes_ctx &c, Level<R> &L, R *e, const R *r, int sweeps, bool zero_guess) {
+    const bool per = any_periodic(L.b);
     for (int s = 0; s < sweeps; ++s)
-        for (int colour = 0; colour < 2; ++colour)
-            k_p_gs<DIM, R><<<nblocks_box(L.b), kBlock, 0, c.stream>>>(
-                L.b, colour, (zero_guess && s == 0 && colour == 0) ? 1 : 0, e, r, L.beta[0], L.beta[1],
-                DIM == 3 ? L.beta[2] : L.beta[1]);
+        for (int colour = 0; colour < 2; ++colour) {
+            const int zg = (zero_guess && s == 0 && colour == 0) ? 1 : 0;
+            const R *bz = DIM == 3 ? L.beta[2] : L.beta[1];
+            if (per)
+                k_p_gs<DIM, R, true><<<nblocks_box(L.b), kBlock, 0, c.stream>>>(L.b, colour, zg, e, r, L.beta[0], L.beta[1], bz);
+            else
+                k_p_gs<DIM, R, false><<<nblocks_box(L.b), kBlock, 0, c.stream>>>(L.b, colour, zg, e, r, L.beta[0], L.beta[1], bz);
+        }
 }
 
 // One fused 3D sweep from `in` into `out` (optionally adding the prolonged coarse
@@ -470,7 +486,10 @@ void p_residual_restrict(stokes_ctx &c, const Level<R> &L, const Level<R> &C, co
         k_p_residual_restrict3_z<R, TX, TY><<<dim3(gx, gy, gz), TX * TY, 0, c.stream>>>(
             L.b, C.b, kc, e, r, L.beta[0], L.beta[1], bz, rc);
     } else {
-        k_p_residual_restrict<DIM, R><<<nblocks_box(C.b), kBlock, 0, c.stream>>>(L.b, C.b, e, r, L.beta[0], L.beta[1], bz, rc);
+        if (any_periodic(L.b))
+            k_p_residual_restrict<DIM, R, true><<<nblocks_box(C.b), kBlock, 0, c.stream>>>(L.b, C.b, e, r, L.beta[0], L.beta[1], bz, rc);
+        else
+            k_p_residual_restrict<DIM, R, false><<<nblocks_box(C.b), kBlock, 0, c.stream>>>(L.b, C.b, e, r, L.beta[0], L.beta[1], bz, rc);
     }
 }
 
@@ -487,7 +506,7 @@ void p_level_sweep(stokes_ctx &c, Level<R> &L, R *&cur, R *&spare, const R *r, b
     // a z-marching launch there
     const bool flat = DIM == 2 || flat_only || any_periodic(L.b) || (long long)L.b.nx * L.b.ny * L.b.nz <= (1LL << 18);
     if (flat) {
-        if (ec) k_p_prolong_add<DIM, R><<<nblocks_box(L.b), kBlock, 0, c.stream>>>(L.b, *cb, c.opt.p_prolong, ec, cur);
+        if (ec) prolong_add<DIM, R>(c, L.b, *cb, c.opt.p_prolong, ec, cur);
         p_smooth<DIM, R>(c, L, cur, r, 1, zg);
         return;
     }
@@ -501,7 +520,8 @@ void p_level_sweep(stokes_ctx &c, Level<R> &L, R *&cur, R *&spare, const R *r, b
 template <int DIM, class R>
 R *p_vcycle(stokes_ctx &c, MG<R> &mg, int l, R *e, R *r, bool zero_guess) {
     if (DIM == 3 && l == mg.small_l0) {
-        k_p_small_cycle<R><<<1, kSmallThreads, mg.small_lds, c.stream>>>(mg.small, mg.ops, mg.nops,
+        auto kern = any_periodic(mg.small.b[0]) ? k_p_small_cycle<R, true> : k_p_small_cycle<R, false>;
+        kern<<<1, kSmallThreads, mg.small_lds, c.stream>>>(mg.small, mg.ops, mg.nops,
                                                                        zero_guess ? 1 : 0, e, r);
         return e;
     }
@@ -538,7 +558,7 @@ R *p_vcycle(stokes_ctx &c, MG<R> &mg, int l, R *e, R *r, bool zero_guess) {
         sweep(false, ce, &C.b);                    // prolongation folded into the first post-sweep
         for (int s = 1; s < nu2; ++s) sweep(false, nullptr, nullptr);
     } else {
-        k_p_prolong_add<DIM, R><<<nblocks_box(L.b), kBlock, 0, c.stream>>>(L.b, C.b, c.opt.p_prolong, ce, cur);
+        prolong_add<DIM, R>(c, L.b, C.b, c.opt.p_prolong, ce, cur);
         if (DIM == 3) {
             for (int s = 0; s < nu2; ++s) sweep(false, nullptr, nullptr);
         } else {
@@ -574,7 +594,7 @@ void guess_from_coarse(stokes_ctx &c, MG<R> &mg, int lc, R *phi0) {
     for (int l = lc - 1; l >= 0; --l) {
         R *dst = l == 0 ? phi0 : mg.L[l].ep2;
         fill<R>(c, dst - mg.L[l].b.guard, mg.L[l].b.stride, R(0));
-        k_p_prolong_add<3, R><<<nblocks_box(mg.L[l].b), kBlock, 0, c.stream>>>(mg.L[l].b, mg.L[l + 1].b, 1, cur, dst);
+        prolong_add<3, R>(c, mg.L[l].b, mg.L[l + 1].b, 1, cur, dst);
         cur = dst;
     }
 }
@@ -1053,8 +1073,10 @@ void plan_small(stokes_ctx &c, MG<R> &mg) {
         gen_small_ops<R>(c, mg, l0, l0, 2, ops);
         if (ops.size() > (size_t)kSmallMaxOps) continue;
         if (off * sizeof(R) > 64 * 1024 &&
-            hipFuncSetAttribute(reinterpret_cast<const void *>(&k_p_small_cycle<R>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)(off * sizeof(R))) != hipSuccess) {
+            (hipFuncSetAttribute(reinterpret_cast<const void *>(&k_p_small_cycle<R, false>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)(off * sizeof(R))) != hipSuccess ||
+             hipFuncSetAttribute(reinterpret_cast<const void *>(&k_p_small_cycle<R, true>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)(off * sizeof(R))) != hipSuccess)) {
             // the runtime refuses more than 64 KiB: plan again within that
             (void)hipGetLastError();
             budget = 64 * 1024;
