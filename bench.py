@@ -48,6 +48,8 @@ def parse():
                     help="no bench line: measure what a (perfect or learned) initial guess is worth to the "
                          "pressure cycles on SEEDS fresh instances of the headline recipe, and the U-Net's "
                          "forward cost from 32^3 to 256^3; prints one JSON line")
+    ap.add_argument("--velocity-mg-only", action="store_true",
+                    help="no bench line: run only the viscous-dominated velocity-multigrid leg and print it")
     ap.add_argument("--verbose", action="store_true")
     return ap.parse_args()
 
@@ -60,6 +62,10 @@ def main():
     args = parse()
     if args.traffic_from:
         traffic_from_counters(*args.traffic_from, n=args.n, precision=args.precision)
+        return
+    if args.velocity_mg_only and args.gpus == 1:
+        import paper_1901_07892_amd as S
+        print(json.dumps(velocity_mg_leg(S)), flush=True)
         return
     if args.learned_study and args.gpus == 1:
         print(json.dumps(learned_study(args.learned_study, args.n)), flush=True)
@@ -208,6 +214,7 @@ def main():
     if not args.no_configs:
         out["configs"] = {"config3_128^3 dam break": config_leg(S, 3),
                           "config4_1024x96x96 wave tank": config_leg(S, 4)}
+        out["velocity_multigrid"] = velocity_mg_leg(S)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, int(np.median(iters)))
     print(json.dumps(out), flush=True)
@@ -786,6 +793,48 @@ def cpu_baseline(prob, gpu_iters):
                                   "sample": "estimate, not timed: the value above times the one-thread / "
                                             "%d-thread time ratio of a full 64^3 oracle solve of the same recipe "
                                             "(%.2f s / %.2f s)" % (nth, t_one, t_all)}}
+
+
+def velocity_mg_leg(S, n=128, dt=1.0, steps=5):
+    """A viscous-dominated solve, where the automatic rule runs the velocity
+    multigrid (at the workload configs the velocity operator is mass-dominated and
+    one diagonal step replaces it): the headline recipe at n^3 with dt = 1 (viscous
+    / mass diagonal ratio above 1e-2 in the air), tol 1e-8, FP64 and FP32
+    multigrid; ms per solve, iterations and cycles, against the same solve with
+    the diagonal velocity step forced (vel_levels = 1)."""
+    import torch
+    import workloads as W
+    prob = W.config5(n_cells=n, dt=dt)
+    dev = torch.device("cuda:0")
+    td = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    rho = [td(r) for r in prob.rho_faces[:3]]
+    mu = td(prob.mu)
+    rhs_u = [td(f) for f in prob.rhs_u[:3]]
+    rhs_p = td(prob.rhs_p)
+    leg = {"grid": list(prob.n), "dt": dt, "tol": prob.tol}
+    for name, over in (("fp64", {}), ("fp32_multigrid", {"precision": 1}),
+                       ("fp64_diagonal_velocity_step", {"vel_levels": 1, "max_iters": 60})):
+        solver = S.StokesSolver(3, prob.n, prob.h, rho, mu, dt, **over)
+        xu = [torch.zeros_like(f) for f in rhs_u]
+        xp = torch.zeros_like(rhs_p)
+        times = []
+        for it in range(steps + 1):
+            for a in xu:
+                a.zero_()
+            xp.zero_()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            st, stats = solver.solve(rhs_u, rhs_p, prob.tol, xu, xp)
+            torch.cuda.synchronize()
+            if it > 0:
+                times.append((time.perf_counter() - t) * 1e3)
+        leg[name] = {"ms_per_solve": float(np.median(times)), "status": st, "fgmres_iters": stats.iters,
+                     "cycles": stats.vcycles, "rel_res_true": stats.rel_res_true}
+        log("velocity multigrid leg %s: %.2f ms, status %d, %d iterations, %d cycles, res %.2e"
+            % (name, leg[name]["ms_per_solve"], st, stats.iters, stats.vcycles, stats.rel_res_true))
+        solver.close()
+        del solver
+    return leg
 
 
 def config_leg(S, num, steps=5, warmup=2):
