@@ -586,8 +586,10 @@ __global__ void __launch_bounds__(kBlock) k_p_residual_restrict(Box fb, Box cb, 
 // columns at the four planes a coarse plane needs (2K-1 .. 2K+2) stay in
 // registers, so each fine plane is read once instead of twice (the per-cell
 // kernel above re-reads the planes shared with the coarse cells below and
-// above) and the upper z coefficient of plane 2K+1 is reused.  Same formulas
-// and summation order as k_p_residual_restrict.
+// above) and the upper z coefficient of plane 2K+1 is reused; the fine columns
+// just west and east of a thread's pair come from the neighbouring lanes
+// (shuffles), not from memory.  Same formulas and summation order as
+// k_p_residual_restrict.
 template <class R, int TX, int TY>
 __global__ void __launch_bounds__(TX *TY) k_p_residual_restrict3_z(Box fb, Box cb, int kc,
         const R *__restrict__ e, const R *__restrict__ r, const R *__restrict__ bx,
@@ -597,10 +599,16 @@ __global__ void __launch_bounds__(TX *TY) k_p_residual_restrict3_z(Box fb, Box c
     const int bx_ = t % gridDim.x;
     t /= gridDim.x;
     const int by_ = t % gridDim.y, bz_ = t / gridDim.y;
-    const int I = bx_ * TX + (int)(threadIdx.x % TX), J = by_ * TY + (int)(threadIdx.x / TX);
-    if (I >= cb.nx || J >= cb.ny) return;
+    static_assert(TX == 64, "one wavefront per row of the tile: x-neighbours by lane shuffles");
+    const int lane = (int)(threadIdx.x % TX);
+    const int I0 = bx_ * TX + lane, J0 = by_ * TY + (int)(threadIdx.x / TX);
+    // lanes past the last coarse column or row take part in the shuffles with the
+    // values of a valid column and store nothing
+    const bool active = I0 < cb.nx && J0 < cb.ny;
+    const int I = min(I0, cb.nx - 1), J = min(J0, cb.ny - 1);
+    const bool east_in = I0 + 1 < cb.nx;                 // lane + 1 holds the column to the east
     const int K0 = bz_ * kc, K1 = min(K0 + kc, cb.nz);
-    if (K0 >= K1) return;
+    if (K0 >= K1) return;                                // uniform over the block
     const int sy = fb.px, sz = fb.plane;
     const R ix2 = R(fb.ihx * fb.ihx), iy2 = R(fb.ihy * fb.ihy), iz2 = R(fb.ihz * fb.ihz);
     // fine columns c = di + 2 dj at offsets co[c] from the (2I, 2J) column
@@ -624,13 +632,23 @@ __global__ void __launch_bounds__(TX *TY) k_p_residual_restrict3_z(Box fb, Box c
             const R *ce = dk == 0 ? ea : eb;
             const R *hi = dk == 0 ? eb : ep;
 #pragma unroll
-            for (int dj = 0; dj < 2; ++dj)
+            for (int dj = 0; dj < 2; ++dj) {
+                // the fine columns west and east of this thread's pair are the
+                // neighbouring lanes' east and west columns
+                const R from_w = __shfl_up(ce[1 + 2 * dj], 1, 64);
+                const R from_e = __shfl_down(ce[2 * dj], 1, 64);
 #pragma unroll
                 for (int di = 0; di < 2; ++di) {
                     const int c = di + 2 * dj;
                     const int p = q + co[c] + dk * sz;
-                    const R eW = di == 1 ? ce[c - 1] : e[p - 1];
-                    const R eE = di == 0 ? ce[c + 1] : e[p + 1];
+                    R eW, eE;
+                    if (di == 1) {
+                        eW = ce[c - 1];
+                        eE = east_in && lane < 63 ? from_e : e[p + 1];
+                    } else {
+                        eW = lane > 0 ? from_w : e[p - 1];
+                        eE = ce[c + 1];
+                    }
                     const R eS = dj == 1 ? ce[c - 2] : e[p - sy];
                     const R eN = dj == 0 ? ce[c + 2] : e[p + sy];
                     const R wW = bx[p] * ix2, wE = bx[p + 1] * ix2;
@@ -642,8 +660,9 @@ __global__ void __launch_bounds__(TX *TY) k_p_residual_restrict3_z(Box fb, Box c
                     dg += wB + wT;
                     acc += r[p] - (dg * ce[c] - off);
                 }
+            }
         }
-        rc[box_index(cb, I, J, K)] = acc * R(0.125);
+        if (active) rc[box_index(cb, I, J, K)] = acc * R(0.125);
         if (K + 1 < K1) {
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
