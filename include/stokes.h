@@ -111,8 +111,9 @@ typedef struct {
     int p_wdepth;        /* levels that use p_gamma coarse cycles: the p_wdepth finest (0 =
                             all); coarser levels take one (a V-cycle below them) */
     int p_cycles_next;   /* pressure cycles in the later applications (>= 1), 0 = automatic:
-                            6 for 3D FP64 when p_cycles is automatic, else p_cycles (FGMRES is
-                            flexible, so the preconditioner may change between iterations) */
+                            for 3D FP64 when p_cycles is automatic 5 with the automatic p_omega
+                            and 6 with any other, else p_cycles (FGMRES is flexible, so the
+                            preconditioner may change between iterations) */
     int p_nu_second;     /* pre- and post-smoothing sweeps on the second-finest pressure level
                             (>= 0; the coarser levels keep nu1 / nu2).  0 = automatic: with FP64
                             multigrid and W-cycles (the second level is cycled twice per visit of
@@ -131,6 +132,10 @@ typedef struct {
                             rhs_p nor p is made mean-free.  Needs the single-level diagonal
                             velocity step (a mass-dominated operator, as at every workload here;
                             EINVAL otherwise).  0 (default): walls everywhere. */
+    double p_omega;      /* over-relaxation factor of the red-black pressure smoother on every
+                            level (red-black SOR): each point's Gauss-Seidel value g replaces its
+                            old value e by e + p_omega (g - e); 1 is plain Gauss-Seidel.  0 =
+                            automatic: 1.1 on 3D grids, 1 in 2D; otherwise in (0, 2) */
 } stokes_options;
 
 typedef struct {
@@ -154,8 +159,9 @@ typedef struct stokes_ctx stokes_ctx;
 
 /* Fill *opts with the defaults (FP64, theta 1, automatic sigma, restart 30,
  * max_iters 200, (2,2) smoothing, one velocity cycle and an automatic number of
- * pressure cycles (4 then 6 for 3D FP64, otherwise 3) that are W-cycles on
- * the two finest levels and V-cycles below, 40 coarse sweeps,
+ * pressure cycles (4 then 5 for 3D FP64, otherwise 3) that are W-cycles on
+ * the two finest levels and V-cycles below, red-black SOR smoothing with an
+ * automatic relaxation factor (1.1 in 3D, 1 in 2D), 40 coarse sweeps,
  * automatic velocity levels, 1 single-level velocity sweep, piecewise-constant
  * pressure prolongation, diagonal velocity step, one-pass Gram-Schmidt, z-marching
  * matvec, small levels cycled in one workgroup, in FP64 one sweep on each side on

@@ -16,9 +16,11 @@ arrays (C order (Nz, Ny, Nx), x fastest):
 * ``gs_colour`` / ``rb_gs_sweep``: red-black Gauss-Seidel.  The cells of one
   colour ((i+j+k) even = 0, odd = 1) are replaced by the value that zeroes
   their own residual row with every other value held fixed,
-  e_c <- (r_c + sum_nb w_nb e_nb) / sum_nb w_nb; cells of one colour never
+  g_c = (r_c + sum_nb w_nb e_nb) / sum_nb w_nb; cells of one colour never
   neighbour each other, so this is Gauss-Seidel in any order within the
-  colour.  A sweep is colour 0 then colour 1.
+  colour.  A sweep is colour 0 then colour 1.  With a relaxation factor
+  omega != 1 (red-black SOR, the smoother's reading: the paper fixes no
+  smoother) the cell takes e_c + omega (g_c - e_c) instead of g_c.
 * ``residual_restrict``: the coarse right-hand side, the mean over the 2^d
   children of the fine residual r - (-L_rho) e.
 * ``prolong``: the coarse correction on the fine cells, piecewise constant, or
@@ -119,20 +121,22 @@ def colour_mask(shape, colour: int) -> np.ndarray:
     return ((i + j + k) % 2) == colour
 
 
-def gs_colour(dim, h, beta, e, r, colour, open_top=False):
-    """One colour of red-black Gauss-Seidel for -L_rho e = r (returns a new array)."""
+def gs_colour(dim, h, beta, e, r, colour, open_top=False, omega=1.0):
+    """One colour of red-black Gauss-Seidel (SOR with factor omega) for
+    -L_rho e = r (returns a new array)."""
     e = np.array(e, dtype=np.float64, copy=True)
     d = diagonal(dim, h, beta, e.shape, open_top)
     off = d * e - apply(dim, h, beta, e, open_top)          # sum_nb w_nb e_nb
     m = colour_mask(e.shape, colour)
-    e[m] = (r[m] + off[m]) / d[m]
+    g = (r[m] + off[m]) / d[m]
+    e[m] = g if omega == 1.0 else e[m] + omega * (g - e[m])
     return e
 
 
-def rb_gs_sweep(dim, h, beta, e, r, open_top=False):
-    """One red-black Gauss-Seidel sweep, colour 0 ((i+j+k) even) first."""
-    e = gs_colour(dim, h, beta, e, r, 0, open_top)
-    return gs_colour(dim, h, beta, e, r, 1, open_top)
+def rb_gs_sweep(dim, h, beta, e, r, open_top=False, omega=1.0):
+    """One red-black Gauss-Seidel (SOR) sweep, colour 0 ((i+j+k) even) first."""
+    e = gs_colour(dim, h, beta, e, r, 0, open_top, omega)
+    return gs_colour(dim, h, beta, e, r, 1, open_top, omega)
 
 
 def residual_restrict(dim, h, beta, e, r, open_top=False) -> np.ndarray:

@@ -56,7 +56,7 @@ class StokesOptions(C.Structure):
                 ("vel_smoother", C.c_int), ("orth", C.c_int), ("matvec_z", C.c_int),
                 ("p_gamma", C.c_int), ("p_small", C.c_int),
                 ("p_wdepth", C.c_int), ("p_cycles_next", C.c_int), ("p_nu_second", C.c_int),
-                ("open_top", C.c_int)]
+                ("open_top", C.c_int), ("p_omega", C.c_double)]
 
 
 class StokesStats(C.Structure):

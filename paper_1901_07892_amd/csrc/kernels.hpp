@@ -541,19 +541,34 @@ __device__ inline void prow(const Box &b, int idx, int i, int j, int k, const R 
     }
 }
 
+// Red-black SOR update of one point: the Gauss-Seidel value gs (its equation
+// solved with the neighbours held) relaxed by omega from the old value.
+// omega = 1 is plain Gauss-Seidel and returns gs itself (no blend), so that its
+// results stay those of the unrelaxed sweep.
+template <class R>
+__device__ inline R sor(R old, R gs, R omega) {
+    return omega == R(1) ? gs : old + omega * (gs - old);
+}
+
 template <int DIM, class R, bool PER>
-__global__ void __launch_bounds__(kBlock) k_p_gs(Box b, int colour, int zero_guess, R *e,
+__global__ void __launch_bounds__(kBlock) k_p_gs(Box b, int colour, int zero_guess, R omega, R *e,
         const R *__restrict__ r, const R *__restrict__ bx, const R *__restrict__ by,
         const R *__restrict__ bz) {
     int idx = box_thread_index();
     if (idx >= b.nb) return;
     int i, j, k;
     decompose(b, idx, i, j, k);
-    if (!is_cell(b, i, j, k) || ((i + j + k) & 1) != colour) return;
+    if (!is_cell(b, i, j, k)) return;
+    if (((i + j + k) & 1) != colour) {
+        // a relaxed update reads the point's own old value: after a zero guess
+        // the points of the other colour must read as zero too
+        if (zero_guess && omega != R(1)) e[idx] = R(0);
+        return;
+    }
     R off, dg;
     prow<DIM, R, PER>(b, idx, i, j, k, e, bx, by, bz, off, dg);
     if (zero_guess) off = R(0);
-    e[idx] = dg > R(0) ? (r[idx] + off) / dg : R(0);
+    e[idx] = dg > R(0) ? sor(zero_guess ? R(0) : e[idx], (r[idx] + off) / dg, omega) : R(0);
 }
 
 // Coarse right-hand side: average over the 2^d children of the fine residual
@@ -787,22 +802,28 @@ struct SmallMG {
     int off_rs;                      // LDS staging of the coarsest right-hand side (ndense)
     int lin;                         // prolongation (see prolong_value)
     int lds_elems;                   // LDS size in elements of R
+    R omega;                         // smoother over-relaxation (1: Gauss-Seidel)
 };
 
 template <class R, class BP, bool PER>
-__device__ inline void small_gs(const Box &b, R *e, const R *r, BP bx, BP by, BP bz, int colour, bool zg) {
+__device__ inline void small_gs(const Box &b, R *e, const R *r, BP bx, BP by, BP bz, int colour, bool zg,
+                                R omega) {
     const int hx = (b.nx + 1) >> 1;
     const int total = hx * b.ny * b.nz;
     for (int t = threadIdx.x; t < total; t += kSmallThreads) {
         const int ii = t % hx, jk = t / hx;
         const int j = jk % b.ny, k = jk / b.ny;
         const int i = 2 * ii + ((j + k + colour) & 1);
+        if (zg && omega != R(1)) {
+            const int i2 = 2 * ii + ((j + k + colour + 1) & 1);     // the other colour (see k_p_gs)
+            if (i2 < b.nx) e[box_index(b, i2, j, k)] = R(0);
+        }
         if (i >= b.nx) continue;
         const int idx = box_index(b, i, j, k);
         R off, dg;
         prow<3, R, PER>(b, idx, i, j, k, e, bx, by, bz, off, dg);
         if (zg) off = R(0);
-        e[idx] = dg > R(0) ? (r[idx] + off) / dg : R(0);
+        e[idx] = dg > R(0) ? sor(zg ? R(0) : e[idx], (r[idx] + off) / dg, omega) : R(0);
     }
 }
 
@@ -917,6 +938,10 @@ __global__ void __launch_bounds__(kSmallThreads) k_p_small_cycle(SmallMG<R> m, c
 #pragma unroll
                 for (int q = 0; q < kSmallCached; ++q) {
                     const int idx = col ? q0[1][q] : q0[0][q];
+                    if (zg && m.omega != R(1)) {                  // the other colour reads as zero (see k_p_gs)
+                        const int i2 = col ? q0[0][q] : q0[1][q];
+                        if (i2 >= 0) E[i2] = R(0);
+                    }
                     if (idx < 0) continue;
                     const R wW = col ? w0[1][q][0] : w0[0][q][0], wE = col ? w0[1][q][1] : w0[0][q][1];
                     const R wS = col ? w0[1][q][2] : w0[0][q][2], wN = col ? w0[1][q][3] : w0[0][q][3];
@@ -926,13 +951,13 @@ __global__ void __launch_bounds__(kSmallThreads) k_p_small_cycle(SmallMG<R> m, c
                     off += wB * E[idx - sz] + wT * E[idx + sz];
                     dg += wB + wT;
                     if (zg) off = R(0);
-                    E[idx] = dg > R(0) ? (Rr[idx] + off) / dg : R(0);
+                    E[idx] = dg > R(0) ? sor(zg ? R(0) : E[idx], (Rr[idx] + off) / dg, m.omega) : R(0);
                 }
             } else if (l == 0) {
-                small_gs<R, const R *__restrict__, PER>(b, E, Rr, m.gbeta[0][0], m.gbeta[0][1], m.gbeta[0][2], op.colour, zg);
+                small_gs<R, const R *__restrict__, PER>(b, E, Rr, m.gbeta[0][0], m.gbeta[0][1], m.gbeta[0][2], op.colour, zg, m.omega);
             } else {
                 const R *B = S + m.off_b[l];
-                small_gs<R, const R *, PER>(b, E, Rr, B, B + m.stride_b[l], B + 2 * m.stride_b[l], op.colour, zg);
+                small_gs<R, const R *, PER>(b, E, Rr, B, B + m.stride_b[l], B + 2 * m.stride_b[l], op.colour, zg, m.omega);
             }
         } else if (op.kind == SOP_RESTRICT) {
             R *rc = S + m.off_r[l + 1];
@@ -978,7 +1003,7 @@ __global__ void __launch_bounds__(kSmallThreads) k_p_small_cycle(SmallMG<R> m, c
 // prolonged coarse correction (see prolong_value): the prolongation is folded
 // into the sweep that follows it.
 template <class R, int TX, int TY>
-__global__ void __launch_bounds__(TX *TY) k_p_sweep3(Box b, int kc, int zero_guess, const R *__restrict__ ein,
+__global__ void __launch_bounds__(TX *TY) k_p_sweep3(Box b, int kc, int zero_guess, R omega, const R *__restrict__ ein,
         const R *__restrict__ ec, Box cb, int lin, R *__restrict__ eout, const R *__restrict__ r,
         const R *__restrict__ bx, const R *__restrict__ by, const R *__restrict__ bz) {
     constexpr int NT = TX * TY;
@@ -1049,7 +1074,7 @@ __global__ void __launch_bounds__(TX *TY) k_p_sweep3(Box b, int kc, int zero_gue
                 R dg = wv[p][0] + wv[p][1] + wv[p][2] + wv[p][3] + wv[p][4] + wv[p][5];
                 R off = wv[p][0] * oc[o2 - 1] + wv[p][1] * oc[o2 + 1] + wv[p][2] * oc[o2 - EX2] +
                         wv[p][3] * oc[o2 + EX2] + wv[p][4] * om[o2] + wv[p][5] * op[o2];
-                v = dg > R(0) ? (rv[p] + off) / dg : R(0);
+                v = dg > R(0) ? sor(oc[o2], (rv[p] + off) / dg, omega) : R(0);
             } else if (k >= 0 && k < b.nz && i >= 0 && i < b.nx && j >= 0 && j < b.ny) {
                 v = oc[o2];
             }
@@ -1074,7 +1099,7 @@ __global__ void __launch_bounds__(TX *TY) k_p_sweep3(Box b, int kc, int zero_gue
         if (blk) {
             R dg = w0 + w1 + w2 + w3 + w4 + w5;
             R off = w0 * nc[o1 - 1] + w1 * nc[o1 + 1] + w2 * nc[o1 - EX1] + w3 * nc[o1 + EX1] + w4 * nm[o1] + w5 * np[o1];
-            v = dg > R(0) ? (rr + off) / dg : R(0);
+            v = dg > R(0) ? sor(nc[o1], (rr + off) / dg, omega) : R(0);
         }
         eout[q] = v;
     };
@@ -1123,7 +1148,7 @@ __global__ void __launch_bounds__(TX *TY) k_p_sweep3(Box b, int kc, int zero_gue
 // (one HBM round trip per plane instead of two); that keeps the coefficients
 // live across the barrier and fits the 64 registers only in float.
 template <class R, int TX, int TY, bool EARLY>
-__global__ void __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(8))) k_p_sweep3c(Box b, int kc, int zero_guess, const R *__restrict__ ein,
+__global__ void __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(8))) k_p_sweep3c(Box b, int kc, int zero_guess, R omega, const R *__restrict__ ein,
         const R *__restrict__ ec, Box cb, int lin, R *__restrict__ eout, const R *__restrict__ r,
         const R *__restrict__ bx, const R *__restrict__ by, const R *__restrict__ bz) {
     constexpr int NT = TX * TY;
@@ -1241,7 +1266,7 @@ __global__ void __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(8))
                     const R dg = wW + wE + wS + wN + wB + wT;
                     const R off = wW * oc[o2 - 1] + wE * oc[o2 + 1] + wS * oc[o2 - EX2] + wN * oc[o2 + EX2]
                                 + wB * om[o2] + wT * op[o2];
-                    v = dg > R(0) ? (cr + off) / dg : R(0);
+                    v = dg > R(0) ? sor(oc[o2], (cr + off) / dg, omega) : R(0);
                 } else {
                     kW = wW; kE = wE; kS = wS; kN = wN; kB = wB; kT = wT; kr = cr;
                     v = oc[o2];
@@ -1260,7 +1285,7 @@ __global__ void __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(8))
                     const R dg = wW + wE + wS + wN + wB + wT;
                     const R off = wW * oc[ro2 - 1] + wE * oc[ro2 + 1] + wS * oc[ro2 - EX2] + wN * oc[ro2 + EX2]
                                 + wB * om[ro2] + wT * op[ro2];
-                    v = dg > R(0) ? (ar + off) / dg : R(0);
+                    v = dg > R(0) ? sor(oc[ro2], (ar + off) / dg, omega) : R(0);
                 } else {
                     v = oc[ro2];
                 }
@@ -1278,7 +1303,7 @@ __global__ void __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(8))
                 const R dg = kW + kE + kS + kN + kB + kT;
                 const R off = kW * nc[o1 - 1] + kE * nc[o1 + 1] + kS * nc[o1 - EX1] + kN * nc[o1 + EX1]
                             + kB * nm[o1] + kT * np[o1];
-                v = dg > R(0) ? (kr + off) / dg : R(0);
+                v = dg > R(0) ? sor(nc[o1], (kr + off) / dg, omega) : R(0);
             } else {
                 v = nc[o1];
             }

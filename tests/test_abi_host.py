@@ -92,6 +92,13 @@ def test_options_struct_layout_matches_library(S):
     assert S.stokes_workspace_size(g, o) == 0
     o.p_nu_second = 3
     assert S.stokes_workspace_size(g, o) > 0
+    # the last field: the smoother's relaxation (0 = automatic, else in (0, 2))
+    assert o.p_omega == 0.0
+    for bad in (-0.5, 2.0, 2.5, float("nan")):
+        o.p_omega = bad
+        assert S.stokes_workspace_size(g, o) == 0, bad
+    o.p_omega = 1.1
+    assert S.stokes_workspace_size(g, o) > 0
 
 
 def test_stream_copy_rejects_bad_arguments_on_host(S):

@@ -8,7 +8,9 @@ forms, on the workloads' own coefficients at their stated sizes (config 3's
 128^3, config 4's 1024x96x96, the 256^3 headline) and on ragged grids that
 leave partial tiles.  Each result is compared element by element with the
 oracle's definition of the kernel (oracle/mg_ops.py); fused and flat forms
-are compared with each other as well.
+are compared with each other as well.  The sweeps run with the relaxation
+factor of the 3D default (red-black SOR, omega = 1.1) and, on config 3, as
+plain Gauss-Seidel (omega = 1).
 """
 import numpy as np
 import pytest
@@ -18,6 +20,8 @@ from oracle import mg_ops as M
 from tests.gpu_util import solver_for, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
+
+OMEGA = 1.1          # the automatic relaxation of 3D grids
 
 
 def _rand_coeff_problem(n, seed, h=None):
@@ -62,10 +66,10 @@ def _as_precision(a, precision):
     return a if precision == 0 else a.astype(np.float32).astype(np.float64)
 
 
-def _run(prob, precision, ops, p_prolong=0, open_top=0):
+def _run(prob, precision, ops, p_prolong=0, open_top=0, omega=OMEGA):
     import torch
     extra = {"vel_levels": 1} if open_top else {}          # the open top needs the diagonal velocity step
-    s = solver_for(prob, precision=precision, p_prolong=p_prolong, open_top=open_top, **extra)
+    s = solver_for(prob, precision=precision, p_prolong=p_prolong, open_top=open_top, p_omega=omega, **extra)
     e, r, ec = _inputs(prob, 7)
     out = {}
     try:
@@ -89,7 +93,7 @@ OPS = [("sweep", 0, True, False), ("sweep_flat", 1, True, False),
        ("restrict", 2, True, False), ("restrict_flat", 3, True, False)]
 
 
-def _oracle(prob, precision, e, r, ec, names, lin=False, open_top=False):
+def _oracle(prob, precision, e, r, ec, names, lin=False, open_top=False, omega=OMEGA):
     """The oracle's result of each kernel in ``names`` on the same (rounded) inputs."""
     dim = prob.dim
     rho = [np.asarray(prob.rho_faces[c]) for c in range(dim)]
@@ -100,9 +104,9 @@ def _oracle(prob, precision, e, r, ec, names, lin=False, open_top=False):
     h = prob.h
     ot = open_top
     make = {
-        "sweep": lambda: M.rb_gs_sweep(dim, h, beta, e, r, ot),
-        "sweep_zero": lambda: M.rb_gs_sweep(dim, h, beta, np.zeros_like(e), r, ot),
-        "sweep_ec": lambda: M.rb_gs_sweep(dim, h, beta, e + M.prolong(dim, ec, lin), r, ot),
+        "sweep": lambda: M.rb_gs_sweep(dim, h, beta, e, r, ot, omega),
+        "sweep_zero": lambda: M.rb_gs_sweep(dim, h, beta, np.zeros_like(e), r, ot, omega),
+        "sweep_ec": lambda: M.rb_gs_sweep(dim, h, beta, e + M.prolong(dim, ec, lin), r, ot, omega),
         "restrict": lambda: M.residual_restrict(dim, h, beta, e, r, ot),
     }
     return {k: make[k]() for k in names}
@@ -132,6 +136,14 @@ def test_pressure_kernels_match_oracle(name, maker):
     _check(prob, 0, got, _oracle(prob, 0, e, r, ec, [k for k in got if not k.endswith("_flat")]))
 
 
+def test_pressure_kernels_gauss_seidel_match_oracle():
+    """omega = 1: the unrelaxed update (the Gauss-Seidel value itself, no blend)."""
+    prob = W.config3()
+    print("pressure kernels, Gauss-Seidel", prob.n, flush=True)
+    e, r, ec, got = _run(prob, 0, OPS, omega=1.0)
+    _check(prob, 0, got, _oracle(prob, 0, e, r, ec, [k for k in got if not k.endswith("_flat")], omega=1.0))
+
+
 @pytest.mark.parametrize("name,maker", [CASES[0], CASES[2]])
 def test_pressure_kernels_fp32_match_oracle(name, maker):
     prob = maker()
@@ -147,7 +159,7 @@ def test_pressure_kernels_trilinear_prolongation():
     e, r, ec, got = _run(prob, 0, ops, p_prolong=1)
     dim = prob.dim
     beta = M.betas(dim, prob.rho_faces[:dim])
-    want = M.rb_gs_sweep(dim, prob.h, beta, e + M.prolong(dim, ec, lin=True), r)
+    want = M.rb_gs_sweep(dim, prob.h, beta, e + M.prolong(dim, ec, lin=True), r, omega=OMEGA)
     _check(prob, 0, got, {"sweep_ec": want})
 
 

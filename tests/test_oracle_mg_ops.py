@@ -36,8 +36,9 @@ def test_apply_equals_assembled_operator(dim, n):
     assert np.allclose(d.ravel(), Lp.diagonal(), rtol=1e-14, atol=0)
 
 
-def _brute_rb_sweep(dim, n, h, rho, e, r):
-    """Point-by-point red-black Gauss-Seidel from the face densities, cell by cell."""
+def _brute_rb_sweep(dim, n, h, rho, e, r, omega=1.0):
+    """Point-by-point red-black Gauss-Seidel (relaxed by omega) from the face
+    densities, cell by cell."""
     nx, ny, nz = n
     e = e.copy()
     ext = (nx, ny, nz)
@@ -58,16 +59,34 @@ def _brute_rb_sweep(dim, n, h, rho, e, r):
                     w = 1.0 / rho[a][f[2], f[1], f[0]] / h[a] ** 2
                     num += w * e[p[2], p[1], p[0]]
                     den += w
-            e[k, j, i] = num / den
+            e[k, j, i] = (1.0 - omega) * e[k, j, i] + omega * (num / den)
     return e
 
 
+@pytest.mark.parametrize("omega", [1.0, 1.1, 0.7])
 @pytest.mark.parametrize("dim,n", CASES)
-def test_rb_sweep_equals_brute_force(dim, n):
+def test_rb_sweep_equals_brute_force(dim, n, omega):
     h, rho, e, r = _random_case(dim, n, 2)
-    ref = _brute_rb_sweep(dim, n, h, rho, e, r)
-    got = M.rb_gs_sweep(dim, h, M.betas(dim, rho), e, r)
+    ref = _brute_rb_sweep(dim, n, h, rho, e, r, omega)
+    got = M.rb_gs_sweep(dim, h, M.betas(dim, rho), e, r, omega=omega)
     assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("dim,n", CASES)
+def test_relaxed_colour_scales_its_residual_rows(dim, n):
+    """Red-black SOR: a cell's own row has the residual d_c (g_c - e_c), and the
+    relaxed update leaves the fraction 1 - omega of it (same-colour cells do not
+    neighbour, so the other rows of the colour keep their neighbour sums)."""
+    h, rho, e, r = _random_case(dim, n, 6)
+    beta = M.betas(dim, rho)
+    omega = 1.1
+    res0 = r - M.apply(dim, h, beta, e)
+    for colour in (0, 1):
+        e1 = M.gs_colour(dim, h, beta, e, r, colour, omega=omega)
+        res1 = r - M.apply(dim, h, beta, e1)
+        m = M.colour_mask(e.shape, colour)
+        assert np.abs(res1[m] - (1.0 - omega) * res0[m]).max() <= 1e-12 * np.abs(res0).max() * 1e3
+        assert np.array_equal(e1[~m], e[~m])
 
 
 @pytest.mark.parametrize("dim,n", CASES)
@@ -97,8 +116,9 @@ def test_sweep_leaves_the_exact_solution_fixed():
     x[keep] = spla.spsolve(Lp[keep][:, keep], r.ravel()[keep])
     assert np.abs(Lp @ x - r.ravel()).max() <= 1e-9 * np.abs(r).max()
     e = x.reshape(r.shape)
-    out = M.rb_gs_sweep(dim, h, M.betas(dim, rho), e, r)
-    assert np.abs(out - e).max() <= 1e-8 * np.abs(e).max()
+    for omega in (1.0, 1.1):
+        out = M.rb_gs_sweep(dim, h, M.betas(dim, rho), e, r, omega=omega)
+        assert np.abs(out - e).max() <= 1e-8 * np.abs(e).max()
 
 
 @pytest.mark.parametrize("dim,n", [(2, (8, 6, 1)), (3, (6, 4, 8))])
