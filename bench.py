@@ -140,7 +140,7 @@ def main():
     n_cells = prob.n_cells
     kms, klaunch, kbytes = S.stokes_profile_read(solver.ctx)
     S.stokes_profile_kernel(solver.ctx, -1)
-    names = {0: "k_apply3_z (Stokes matvec)", 1: "k_p_sweep3c (fused pressure RB-GS sweep, finest level)",
+    names = {0: "k_apply3_z (Stokes matvec)", 1: "k_p_sweep3c (fused pressure red-black sweep, finest level)",
              2: "k_multidot", 3: "k_maxpy"}
     achieved = kbytes / (kms * 1e-3) / 1e9 if kms > 0 else None
     roofline = {"bound": "hbm", "kernel": names.get(args.prof_kernel),
@@ -387,7 +387,7 @@ def fp32_form(S, prob, rho, mu, rhs_u, rhs_p, xu64, xp64, overrides, ms64, steps
     S.stokes_profile_kernel(solver.ctx, -1)
     solver.close()
     achieved = kb / (kms * 1e-3) / 1e9 if kms > 0 else None
-    roofline = {"bound": "hbm", "kernel": "k_p_sweep3c<float> (fused pressure RB-GS sweep, finest level)",
+    roofline = {"bound": "hbm", "kernel": "k_p_sweep3c<float> (fused pressure red-black sweep, finest level)",
                 "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
                 "frac": achieved / 8000.0 if achieved else None, "launches": kn,
                 "avg_launch_us": kms * 1e3 / max(kn, 1), "algorithmic_bytes_per_launch": kb / max(kn, 1)}

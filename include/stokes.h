@@ -21,7 +21,8 @@
  * The solver is restarted flexible GMRES on the coupled (u, p) system
  * (Sec. 4.2.4), right-preconditioned by a projection step with a
  * local-viscosity pressure update whose velocity and pressure subsolves are
- * geometric-multigrid V-cycles with red-black Gauss-Seidel smoothing.
+ * geometric-multigrid cycles with red-black Gauss-Seidel smoothing (the
+ * pressure smoother over-relaxed, red-black SOR, see p_omega).
  *
  * Conventions for every entry point
  *   - Arrays are C order with x fastest.  u is (Nz, Ny, Nx+1), v is
@@ -564,7 +565,8 @@ stokes_status stokes_learned_study(stokes_ctx *ctx, const double *const rhs_u[3]
  * 1/rho on interior faces and Neumann walls (Sec. 4.2.4 names the projection
  * preconditioner; the multigrid is this library's subsolve for it).
  *   STOKES_POP_SWEEP          one red-black Gauss-Seidel sweep of -L_rho e = r
- *                             (cells with i+j+k even first, then odd), in the
+ *                             (cells with i+j+k even first, then odd; relaxed
+ *                             by the context's p_omega as in the cycle), in the
  *                             form the cycle uses on this level: the fused
  *                             z-marching kernel on 3D levels of more than 2^18
  *                             cells, two colour passes otherwise;
