@@ -730,6 +730,46 @@ __global__ void __launch_bounds__(kBlock) k_p_prolong_add(Box fb, Box cb, int li
     f[idx] += prolong_value<DIM, R, PER>(cb, c, i, j, k, lin);
 }
 
+// One colour pass of the first red-black sweep after a coarse correction on a
+// flat level (walls only), with the prolongation folded in: every cell reads as
+// e + P(ec) (prolong_value) until its colour is updated, points outside the
+// domain as the zero they hold.  Colour 0 reads its neighbours and, relaxed, its
+// own old value that way; colour 1 only its own old value (its neighbours are
+// colour 0 and already updated).  Same values, summed in the same order, as
+// k_p_prolong_add followed by the two k_p_gs passes, with one launch less.
+template <int DIM, class R>
+__global__ void __launch_bounds__(kBlock) k_p_gs_ec(Box b, int colour, R omega, R *e,
+        const R *__restrict__ r, const R *__restrict__ bx, const R *__restrict__ by,
+        const R *__restrict__ bz, Box cb, int lin, const R *__restrict__ ec) {
+    int idx = box_thread_index();
+    if (idx >= b.nb) return;
+    int i, j, k;
+    decompose(b, idx, i, j, k);
+    if (!is_cell(b, i, j, k) || ((i + j + k) & 1) != colour) return;
+    auto val = [&](int q, int ii, int jj, int kk) -> R {
+        if (ii < 0 || ii >= b.nx || jj < 0 || jj >= b.ny || kk < 0 || kk >= b.nz) return e[q];
+        return e[q] + prolong_value<DIM, R, false>(cb, ec, ii, jj, kk, lin);
+    };
+    R off, dg;
+    if (colour == 0) {
+        const int sy = b.px, sz = b.plane;
+        const R ix2 = R(b.ihx * b.ihx), iy2 = R(b.ihy * b.ihy), iz2 = R(b.ihz * b.ihz);
+        R wW = bx[idx] * ix2, wE = bx[idx + 1] * ix2;
+        R wS = by[idx] * iy2, wN = by[idx + sy] * iy2;
+        off = wW * val(idx - 1, i - 1, j, k) + wE * val(idx + 1, i + 1, j, k) + wS * val(idx - sy, i, j - 1, k)
+            + wN * val(idx + sy, i, j + 1, k);
+        dg = wW + wE + wS + wN;
+        if (DIM == 3) {
+            R wB = bz[idx] * iz2, wT = bz[idx + sz] * iz2;
+            off += wB * val(idx - sz, i, j, k - 1) + wT * val(idx + sz, i, j, k + 1);
+            dg += wB + wT;
+        }
+    } else {
+        prow<DIM, R, false>(b, idx, i, j, k, e, bx, by, bz, off, dg);
+    }
+    e[idx] = dg > R(0) ? sor(omega == R(1) ? R(0) : val(idx, i, j, k), (r[idx] + off) / dg, omega) : R(0);
+}
+
 // Coarsest pressure level: e = M r with M the dense pseudo-inverse of the
 // level's Neumann operator (it also projects out the constant).  One block of
 // 1024 threads, 16 per row (dense_row).

@@ -418,6 +418,17 @@ void prolong_add(stokes_ctx &c, const Box &fb, const Box &cb, int lin, const R *
 inline int p_nu_pre(const stokes_ctx &c, int l) { return l == 1 ? c.nu_sec1 : (l == 2 || l == 3) ? c.nu_mid1 : c.opt.nu1; }
 inline int p_nu_post(const stokes_ctx &c, int l) { return l == 1 ? c.nu_sec2 : c.opt.nu2; }
 
+// The first sweep after a coarse correction on a flat level with walls: the
+// prolongation folded into its two colour passes (k_p_gs_ec), the values of
+// prolong_add + p_smooth with one launch less.
+template <int DIM, class R>
+void p_sweep_flat_ec(stokes_ctx &c, Level<R> &L, R *e, const R *r, const R *ec, const Box &cb) {
+    const R *bz = DIM == 3 ? L.beta[2] : L.beta[1];
+    for (int colour = 0; colour < 2; ++colour)
+        k_p_gs_ec<DIM, R><<<nblocks_box(L.b), kBlock, 0, c.stream>>>(L.b, colour, R(c.p_omega), e, r, L.beta[0],
+                                                                      L.beta[1], bz, cb, c.opt.p_prolong, ec);
+}
+
 template <int DIM, class R>
 void p_smooth(stokes_ctx &c, Level<R> &L, R *e, const R *r, int sweeps, bool zero_guess) {
     const bool per = any_periodic(L.b);
@@ -507,6 +518,10 @@ void p_level_sweep(stokes_ctx &c, Level<R> &L, R *&cur, R *&spare, const R *r, b
     // a z-marching launch there
     const bool flat = DIM == 2 || flat_only || any_periodic(L.b) || (long long)L.b.nx * L.b.ny * L.b.nz <= (1LL << 18);
     if (flat) {
+        if (ec && !flat_only && !any_periodic(L.b)) {
+            p_sweep_flat_ec<DIM, R>(c, L, cur, r, ec, *cb);
+            return;
+        }
         if (ec) prolong_add<DIM, R>(c, L.b, *cb, c.opt.p_prolong, ec, cur);
         p_smooth<DIM, R>(c, L, cur, r, 1, zg);
         return;
@@ -558,6 +573,9 @@ R *p_vcycle(stokes_ctx &c, MG<R> &mg, int l, R *e, R *r, bool zero_guess) {
     if (DIM == 3 && nu2 > 0) {
         sweep(false, ce, &C.b);                    // prolongation folded into the first post-sweep
         for (int s = 1; s < nu2; ++s) sweep(false, nullptr, nullptr);
+    } else if (DIM == 2 && nu2 > 0 && !any_periodic(L.b)) {
+        p_sweep_flat_ec<DIM, R>(c, L, cur, r, ce, C.b);   // prolongation folded into the first post-sweep
+        p_smooth<DIM, R>(c, L, cur, r, nu2 - 1, false);
     } else {
         prolong_add<DIM, R>(c, L.b, C.b, c.opt.p_prolong, ce, cur);
         if (DIM == 3) {

@@ -44,6 +44,9 @@ CASES = [
     ("rand_136x136x120", lambda: _rand_coeff_problem((136, 136, 120), 12)),
     # between 2^18 and 2^20 cells: the pipelined 32x16 fused sweep
     ("config5_96", lambda: W.config5(n_cells=96)),
+    # at most 2^18 cells: two flat colour passes, the prolongation folded into them
+    ("config5_64", lambda: W.config5(n_cells=64)),
+    ("rand_64x48x40", lambda: _rand_coeff_problem((64, 48, 40), 14)),
     ("config2_512", lambda: W.config2()),
 ]
 
