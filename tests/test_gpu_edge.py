@@ -357,6 +357,36 @@ def test_stream_copy_copies_exactly(n, offset):
         assert torch.all(dst_full[:offset] == -1.0)
 
 
+@pytest.mark.parametrize("case", ["3d_auto", "3d_gauss_seidel", "3d_fp32", "2d_auto"])
+def test_automatic_relaxation_sets_the_cycle_schedule(case):
+    """The automatic rule: 3D FP64 with the automatic relaxation (red-black SOR,
+    omega 1.1) runs 4 pressure cycles in the first preconditioner application and 5
+    in each later one; an explicit p_omega (here 1, plain Gauss-Seidel) keeps 4 + 6;
+    FP32 multigrid and 2D grids run 3 per application.  Every variant solves to tol
+    and agrees with the default's solution.  (The velocity subsolve is held at its
+    single diagonal step, so that vcycles counts pressure cycles only.)"""
+    base = {"vel_levels": 1}
+    if case.startswith("3d"):
+        prob, opts = W.config5(n_cells=64), {}
+        if case == "3d_gauss_seidel":
+            opts = {"p_omega": 1.0}
+        elif case == "3d_fp32":
+            opts = {"precision": 1}
+        first, later = {"3d_auto": (4, 5), "3d_gauss_seidel": (4, 6), "3d_fp32": (3, 3)}[case]
+    else:
+        prob, opts, (first, later) = W.config2(scale=4), {}, (3, 3)
+    print("cycle schedule", case, prob.n, opts, flush=True)
+    tol = 1e-11                            # tight, so that the variants' solutions agree closely
+    xu, xp, st, stats = gpu_solve(prob, tol=tol, **base, **opts)
+    assert st == 0 and stats.rel_res_true <= tol, stats.as_dict()
+    assert stats.vcycles == first + later * (stats.iters - 1), stats.as_dict()
+    if opts:
+        ru, rp, _, _ = gpu_solve(prob, tol=tol, **base)
+        errs = [rel(xu[c], ru[c]) for c in range(prob.dim)] + [rel(xp - xp.mean(), rp - rp.mean())]
+        print("  iters %d, rel diff to the default's solution %s" % (stats.iters, ["%.1e" % e for e in errs]))
+        assert max(errs) <= 1e-7, errs
+
+
 def test_profile_hook_counts_launches_and_bytes():
     """The measurement hook behind the bench's roofline: the finest fused sweep
     runs (nu1 + nu2) times per pressure cycle, p_cycles cycles in the first
