@@ -2,7 +2,8 @@
 //
 // A level with Nx x Ny x Nz cells stores every field -- cell (p, mu), face
 // (u, v, w, rho, beta) and edge (mu_xy, mu_xz, mu_yz) -- in one index space of
-// (Nx+1) x (Ny+1) x (Nz+1) points (Nz+1 -> 1 in 2D), x fastest.  Point (i,j,k)
+// (Nx+1) x (Ny+1) x (Nz+1) points (Nz+1 -> 1 in 2D; rows may be widened to Px >
+// Nx+1 points, see pad_rows), x fastest.  Point (i,j,k)
 // holds cell (i,j,k), the x-face at x = i*hx, the y-face at y = j*hy, the
 // z-face at z = k*hz and the edges through the lower corner of that cell, so
 // that every stencil uses the same neighbour offsets (1, px, px*py) whatever
@@ -48,6 +49,19 @@ inline Box make_box(int dim, int nx, int ny, int nz, double hx, double hy, doubl
     b.open_top = 0;
     b.per[0] = b.per[1] = b.per[2] = 0;
     return b;
+}
+
+// Widens the rows of a box to a multiple of `mult` points (the slots past x = nx
+// are padding, holding zero like slot nx).  With mult = 16 an FP64 row starts on a
+// 128-byte boundary, so the row segments the z-marching kernels read per tile are
+// whole cache lines; the guard and the field stride follow the wider plane.
+inline void pad_rows(Box &b, int mult) {
+    b.px = ((b.nx + 1 + mult - 1) / mult) * mult;
+    b.plane = b.px * b.py;
+    b.nb = b.plane * b.pz;
+    b.guard = ((b.plane + 1 + 63) / 64) * 64;
+    b.stride = b.nb + 2 * b.guard;
+    b.stride = ((b.stride + 63) / 64) * 64;
 }
 
 __host__ __device__ inline int box_index(const Box &b, int i, int j, int k) {
