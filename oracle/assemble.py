@@ -190,8 +190,10 @@ class Assembler:
         return [(a, b) for a in range(d) for b in range(a + 1, d)]
 
     def edge_mu(self, mu_cell: np.ndarray, a: int, b: int) -> np.ndarray:
-        """Harmonic mean of mu over the cells around each (a, b) edge, mirrored at walls."""
-        inv = 1.0 / mu_cell.ravel()
+        """Harmonic mean of mu over the cells around each (a, b) edge, mirrored at walls
+        (a zero-viscosity cell makes its edges' mean zero: 1/0 = inf, 1/inf = 0)."""
+        with np.errstate(divide="ignore"):
+            inv = 1.0 / mu_cell.ravel()
         pos = self._pos(None)
         m1 = self._op_along(a, "avg", pos)
         pos_a = list(pos)
