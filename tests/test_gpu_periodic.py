@@ -67,6 +67,8 @@ APPLY = [
     (3, (6, 8, 4), (0, 1, 1)),
     (3, (4, 6, 8), (1, 1, 1)),
     (3, (2, 2, 2), (1, 1, 1)),
+    # at least 256 cells along x: the finest box's rows are padded (periodic x wraps at nx)
+    (3, (256, 4, 4), (1, 0, 0)),
 ]
 
 
@@ -222,6 +224,7 @@ SOLVE = [
     (3, (16, 8, 8), (1, 1, 0), 1e-3),
     (3, (8, 8, 8), (1, 1, 1), 1e-3),
     (2, (16, 16, 1), (1, 0, 0), 100.0),                   # viscous-dominated: velocity multigrid
+    (3, (256, 8, 8), (1, 0, 0), 1e-3),                    # padded finest rows
 ]
 
 
