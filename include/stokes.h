@@ -120,7 +120,9 @@ typedef struct {
                             multigrid and W-cycles (the second level is cycled twice per visit of
                             the finest, the third and fourth four times) at most one sweep on
                             each side of the second (min(nu1, 1), min(nu2, 1)) and one
-                            pre-smoothing sweep on the third and fourth (min(nu1, 1)); otherwise
+                            pre-smoothing sweep on the third and fourth (min(nu1, 1)), and, with
+                            the automatic p_omega on a 3D grid, one post-smoothing sweep
+                            (min(nu2, 1)) on the levels of at most 16^3 cells; otherwise
                             nu1 / nu2 */
     int open_top;        /* 1: the upper end of the vertical axis (y = Ly in 2D, z = Lz in 3D) is
                             the wave tank's open top (Sec. 7.1): zero pressure and zero tangential

@@ -24,6 +24,7 @@ namespace {
 
 constexpr int kMaxLev = 24;
 constexpr int kDenseMax = 2048;     // largest coarsest pressure level solved densely
+constexpr long long kSmallPostCells = 16 * 16 * 16;   // "small" pressure levels (lighter post-smoothing)
 constexpr int kRedBlocks = 2048;    // blocks of the streaming reduction kernels
 constexpr int kGroup = 8;           // vectors per multidot / maxpy launch
 static_assert(kGroup >= 3, "c.partial holds the 3 partials per block of the setup min/max");
@@ -135,6 +136,7 @@ struct stokes_ctx {
     double p_omega = 1.0;               // pressure smoother over-relaxation (resolved p_omega)
     int nu_sec1 = 2, nu_sec2 = 2;       // pre-/post-smoothing sweeps on the second pressure level
     int nu_mid1 = 2;                    // pre-smoothing sweeps on the third and fourth pressure levels
+    int nu_small2 = 2;                  // post-smoothing sweeps on the 3D levels of at most 16^3 cells
     double visc_ratio = -1.0;   // max viscous/mass diagonal ratio (automatic velocity levels)
     bool diag_vel = false;      // velocity subsolve is one diagonal step (see stokes_options.vel_smoother)
     // learned stage: network, the level it runs on, feature/prediction buffers
@@ -416,7 +418,14 @@ void prolong_add(stokes_ctx &c, const Box &fb, const Box &cb, int lin, const R *
 
 // Pre- and post-smoothing sweeps of pressure level l.
 inline int p_nu_pre(const stokes_ctx &c, int l) { return l == 1 ? c.nu_sec1 : (l == 2 || l == 3) ? c.nu_mid1 : c.opt.nu1; }
-inline int p_nu_post(const stokes_ctx &c, int l) { return l == 1 ? c.nu_sec2 : c.opt.nu2; }
+inline int p_nu_post(const stokes_ctx &c, int l) {
+    if (l == 1) return c.nu_sec2;
+    // the small levels (at most 16^3 cells, coarsened from the fine box by 2 per axis)
+    if (c.dim == 3 && l >= 2 &&
+        (long long)(c.fine.nx >> l) * (c.fine.ny >> l) * (c.fine.nz >> l) <= kSmallPostCells)
+        return c.nu_small2;
+    return c.opt.nu2;
+}
 
 // The first sweep after a coarse correction on a flat level with walls: the
 // prolongation folded into its two colour passes (k_p_gs_ec), the values of
@@ -1309,6 +1318,9 @@ void init_ctx_shape(stokes_ctx &c, const stokes_grid *g, const stokes_options &o
     c.nu_sec1 = o.p_nu_second > 0 ? o.p_nu_second : (sec_auto ? std::min(o.nu1, 1) : o.nu1);
     c.nu_sec2 = o.p_nu_second > 0 ? o.p_nu_second : (sec_auto ? std::min(o.nu2, 1) : o.nu2);
     c.nu_mid1 = o.p_nu_second == 0 && sec_auto ? std::min(o.nu1, 1) : o.nu1;
+    // and with the automatic relaxation one post-smoothing sweep on the small levels
+    // (at most 16^3 cells, the single-workgroup cycle's) keeps every iteration count
+    c.nu_small2 = o.p_nu_second == 0 && sec_auto && omega_auto ? std::min(o.nu2, 1) : o.nu2;
     c.fine = fine_box(g);
     c.fine.open_top = o.open_top;
     for (int a = 0; a < g->dim; ++a) c.fine.per[a] = g->periodic[a];
