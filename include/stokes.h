@@ -182,7 +182,8 @@ size_t stokes_workspace_size(const stokes_grid *grid, const stokes_options *opts
  *   mu_cell      cell viscosities, >= 0
  *   dt           time step (> 0); the mass term is rho_face/dt
  *   workspace    device buffer of ws_bytes >= stokes_workspace_size(grid, opts),
- *                owned by the caller and kept alive until stokes_destroy
+ *                owned by the caller and kept alive until stokes_destroy; any
+ *                alignment (the library starts at its first 256-byte boundary)
  *   stream       hipStream_t (as void*)
  * Validates shapes and options on the host, copies the coefficients into the
  * workspace (the caller may free its arrays afterwards), builds the multigrid

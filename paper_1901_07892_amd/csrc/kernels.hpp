@@ -1844,30 +1844,48 @@ __device__ inline void block_reduce(double (&v)[NV], double *lds /* [NV][kBlock/
     }
 }
 
-// partial[m * gridDim.x + block] = sum over this block's elements of
-// wgt * V_m[t] * w[t], for m < nv (nv <= NV); wgt = w2 for t >= pstart.
-template <int NV>
-__global__ void __launch_bounds__(kBlock) k_multidot(long long n, long long pstart, double w2,
-        const double *__restrict__ V, long long ldv, int nv, const double *__restrict__ w,
-        double *__restrict__ partial) {
+// The Krylov BLAS kernels stream whole vectors (n even, every vector 16-byte
+// aligned) as element pairs with 16-byte non-temporal accesses.  Each block owns
+// a contiguous chunk of kBlock * P pairs, thread t the pairs t, t + kBlock, ...
+// of it (coalesced), and issues all of its loads before the arithmetic: with P
+// chosen so that about two dozen pairs (multidot) or 8-12 (maxpy, which also
+// stores) are in flight per thread this reaches 6.0-6.4 and 5.7 TB/s at the
+// 256^3 vector length, where grid-stride loops over 2048-16384 blocks reach
+// 5.1-5.4 and 4.5 TB/s.
+typedef double dpair __attribute__((ext_vector_type(2)));
+
+// partial[m * gridDim.x + block] = sum over this block's pairs of
+// wgt * V_m[t] * w[t], m < NV; wgt = w2 for pair index >= pstart2 (pstart even).
+// SELF (NV = 1, V = w): the weighted squared norm, each pair loaded once.
+template <int NV, int P, bool SELF = false>
+__global__ void __launch_bounds__(kBlock) k_multidot(long long n2, long long pstart2, double w2,
+        const dpair *__restrict__ V, long long ldv2, const dpair *__restrict__ w, double *__restrict__ partial) {
+    static_assert(!SELF || NV == 1, "a self product has one vector");
     __shared__ double lds[NV * (kBlock / 64)];
+    const long long base = (long long)blockIdx.x * (kBlock * P) + threadIdx.x;
+    dpair x[P], v[NV][P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const long long u = base + (long long)p * kBlock;
+        const dpair z = {0.0, 0.0};
+        x[p] = u < n2 ? __builtin_nontemporal_load(w + u) : z;
+#pragma unroll
+        for (int m = 0; m < NV; ++m) v[m][p] = SELF ? x[p] : u < n2 ? __builtin_nontemporal_load(V + m * ldv2 + u) : z;
+    }
     double acc[NV];
 #pragma unroll
     for (int m = 0; m < NV; ++m) acc[m] = 0.0;
-    long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
-    long long st = (long long)gridDim.x * kBlock;
-    for (; t < n; t += st) {
-        double x = w[t];
-        if (t >= pstart) x *= w2;
 #pragma unroll
-        for (int m = 0; m < NV; ++m)
-            if (m < nv) acc[m] += V[m * ldv + t] * x;
+    for (int p = 0; p < P; ++p) {
+        dpair xp = x[p];
+        if (base + (long long)p * kBlock >= pstart2) xp *= w2;
+#pragma unroll
+        for (int m = 0; m < NV; ++m) acc[m] += v[m][p].x * xp.x + v[m][p].y * xp.y;
     }
     block_reduce<NV>(acc, lds);
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int m = 0; m < NV; ++m)
-            if (m < nv) partial[m * gridDim.x + blockIdx.x] = acc[m];
+        for (int m = 0; m < NV; ++m) partial[m * gridDim.x + blockIdx.x] = acc[m];
     }
 }
 
@@ -1879,6 +1897,7 @@ __global__ void __launch_bounds__(kBlock) k_reduce_partials(int nblk, const doub
     __shared__ double lds[kBlock / 64];
     const int m = blockIdx.x;
     double v[1] = {0.0};
+#pragma unroll 8
     for (int t = threadIdx.x; t < nblk; t += kBlock) v[0] += partial[(size_t)m * nblk + t];
     block_reduce<1>(v, lds);
     if (threadIdx.x == 0) {
@@ -1892,28 +1911,40 @@ __global__ void k_set_scalar(double *__restrict__ p, double v) {
     if (threadIdx.x == 0) p[0] = v;
 }
 
-// w[t] += sign * sum_m c[m] * s[m] * V_m[t]   (c and the optional per-vector
-// scales s on the device; s = 1 when vscale is nullptr).  With partial !=
-// nullptr also the weighted squared norm of the updated w (weight w2 from
-// pstart on), one partial sum per block.
-template <int NV>
-__global__ void __launch_bounds__(kBlock) k_maxpy(long long n, double sign, const double *__restrict__ V,
-        long long ldv, int nv, const double *__restrict__ c, const double *__restrict__ vscale,
-        double *__restrict__ w, long long pstart, double w2, double *__restrict__ partial) {
+// w[t] += sign * sum_m c[m] * s[m] * V_m[t], m < NV (c and the optional per-vector
+// scales s on the device; s = 1 when vscale is nullptr), over element pairs as
+// k_multidot.  With partial != nullptr also the weighted squared norm of the
+// updated w (weight w2 from pair index pstart2 on), one partial sum per block.
+template <int NV, int P>
+__global__ void __launch_bounds__(kBlock) k_maxpy(long long n2, double sign, const dpair *__restrict__ V,
+        long long ldv2, const double *__restrict__ c, const double *__restrict__ vscale, dpair *__restrict__ w,
+        long long pstart2, double w2, double *__restrict__ partial) {
     __shared__ double lds[kBlock / 64];
     double cc[NV];
 #pragma unroll
-    for (int m = 0; m < NV; ++m) cc[m] = m < nv ? sign * c[m] * (vscale ? vscale[m] : 1.0) : 0.0;
-    double nrm[1] = {0.0};
-    long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
-    long long st = (long long)gridDim.x * kBlock;
-    for (; t < n; t += st) {
-        double x = w[t];
+    for (int m = 0; m < NV; ++m) cc[m] = sign * c[m] * (vscale ? vscale[m] : 1.0);
+    const long long base = (long long)blockIdx.x * (kBlock * P) + threadIdx.x;
+    dpair x[P], v[NV][P];
 #pragma unroll
-        for (int m = 0; m < NV; ++m)
-            if (m < nv) x += cc[m] * V[m * ldv + t];
-        w[t] = x;
-        nrm[0] += (t >= pstart ? w2 : 1.0) * x * x;
+    for (int p = 0; p < P; ++p) {
+        const long long u = base + (long long)p * kBlock;
+        if (u < n2) {
+            x[p] = __builtin_nontemporal_load(w + u);
+#pragma unroll
+            for (int m = 0; m < NV; ++m) v[m][p] = __builtin_nontemporal_load(V + m * ldv2 + u);
+        }
+    }
+    double nrm[1] = {0.0};
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const long long u = base + (long long)p * kBlock;
+        if (u < n2) {
+            dpair y = x[p];
+#pragma unroll
+            for (int m = 0; m < NV; ++m) y += cc[m] * v[m][p];
+            __builtin_nontemporal_store(y, w + u);
+            nrm[0] += (u >= pstart2 ? w2 : 1.0) * (y.x * y.x + y.y * y.y);
+        }
     }
     if (partial) {
         block_reduce<1>(nrm, lds);

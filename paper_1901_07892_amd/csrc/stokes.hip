@@ -112,7 +112,7 @@ struct stokes_ctx {
     double dt = 0, theta = 1, sigma = 1;
     hipStream_t stream = nullptr;
     char *ws = nullptr;
-    size_t ws_bytes = 0, ws_need = 0;
+    size_t ws_bytes = 0, ws_need = 0, ws_used = 0;
     int v_clear = 0, z_clear = 0;       // leading Krylov vectors V, Z zero-filled since setup
     int dim = 3, nf = 4;
     Box fine;
@@ -218,6 +218,27 @@ void carve_mg(Carver &cv, stokes_ctx &c, MG<R> &mg, bool alias_level0) {
     if (b.dim == 3 && c.opt.p_small) mg.ops = cv.take<SmallOp>(kSmallMaxOps);
 }
 
+// Pairs per thread of the Krylov BLAS kernels for NV vectors: about two dozen
+// pairs in flight per thread for multidot, 8-12 for maxpy (larger maxpy chunks
+// take all 256 registers of a lane and leave one wave per SIMD).
+constexpr int dot_pairs(int nv) { return nv == 1 ? 12 : nv == 2 ? 8 : nv == 3 ? 6 : nv <= 5 ? 4 : nv <= 7 ? 3 : 2; }
+constexpr int kSelfPairs = 16;   // a squared norm: one load per pair
+constexpr int axpy_pairs(int nv) { return nv == 1 ? 4 : nv == 2 ? 4 : nv == 3 ? 3 : nv <= 5 ? 2 : 1; }
+inline unsigned chunk_blocks(long long n2, int pairs) {
+    return (unsigned)((n2 + (long long)kBlock * pairs - 1) / ((long long)kBlock * pairs));
+}
+// doubles of c.partial: the per-block partials of the largest BLAS launch
+// (kGroup vectors) and of the streaming reductions
+inline size_t partial_doubles(long long vlen) {
+    size_t need = (size_t)kRedBlocks * kGroup;
+    for (int nv = 1; nv <= kGroup; ++nv) {
+        need = std::max(need, (size_t)nv * chunk_blocks(vlen / 2, dot_pairs(nv)));
+        need = std::max(need, (size_t)chunk_blocks(vlen / 2, axpy_pairs(nv)));
+    }
+    need = std::max(need, (size_t)chunk_blocks(vlen / 2, kSelfPairs));
+    return need;
+}
+
 void carve_all(Carver &cv, stokes_ctx &c) {
     const Box &b = c.fine;
     const int d = c.dim;
@@ -238,14 +259,15 @@ void carve_all(Carver &cv, stokes_ctx &c) {
     c.xk = cv.take<double>((size_t)c.vlen);
     c.bk = cv.take<double>((size_t)c.vlen);
     c.q = cv.fields<double>(b, 1);
-    c.partial = cv.take<double>((size_t)kRedBlocks * kGroup);
+    c.partial = cv.take<double>(partial_doubles(c.vlen));
     c.dsc = cv.take<double>(4 * (size_t)(c.m + 8));
     c.vs = cv.take<double>((size_t)c.m + 2);
     if (d == 3)
         for (int a = 0; a < 4; ++a) c.lf[a] = cv.take<float>((size_t)kLearnedMaxCells);
     c.lstat = cv.take<double>(8);
     c.dflag = cv.take<int>(64);
-    c.ws_need = cv.off + 256;
+    c.ws_used = cv.off;
+    c.ws_need = cv.off + 256;   // room to start the carving at a 256-byte boundary
 }
 
 // The z-marching kernels assume walls on every side; a level with a periodic
@@ -715,16 +737,57 @@ void precond(stokes_ctx &c, MG<R> &mg, double *v, double vs, double *z) {
 }
 
 // ---------------------------------------------------------------- BLAS helpers
+template <int NV, bool SELF = false>
+unsigned launch_multidot(stokes_ctx &c, const double *V, const double *w, double w2) {
+    constexpr int P = SELF ? kSelfPairs : dot_pairs(NV);
+    const long long n2 = c.vlen / 2;
+    const unsigned g = chunk_blocks(n2, P);
+    k_multidot<NV, P, SELF><<<g, kBlock, 0, c.stream>>>(n2, (long long)c.dim * c.fine.stride / 2, w2,
+                                                   reinterpret_cast<const dpair *>(V), n2,
+                                                   reinterpret_cast<const dpair *>(w), c.partial);
+    return g;
+}
+
+template <int NV>
+unsigned launch_maxpy(stokes_ctx &c, double sign, const double *V, const double *coef, const double *vscale,
+                      double *w, double w2, double *partial) {
+    constexpr int P = axpy_pairs(NV);
+    const long long n2 = c.vlen / 2;
+    const unsigned g = chunk_blocks(n2, P);
+    k_maxpy<NV, P><<<g, kBlock, 0, c.stream>>>(n2, sign, reinterpret_cast<const dpair *>(V), n2, coef, vscale,
+                                                reinterpret_cast<dpair *>(w), (long long)c.dim * c.fine.stride / 2,
+                                                w2, partial);
+    return g;
+}
+
+// The vectors of the Krylov BLAS: vlen even (a multiple of 64) and every
+// vector 16-byte aligned (carved at 256-byte boundaries, vlen * 8 bytes apart).
+inline void check_pairs(const stokes_ctx &c, const double *p) {
+    if ((c.vlen & 1) || (reinterpret_cast<uintptr_t>(p) & 15)) throw HipError{hipErrorInvalidValue, "Krylov vector alignment"};
+}
+
 // out[0..nv) = scale[m] * <V_m, w>_W for m < nv (W: pressure block weighted by w2;
 // scale = 1 when nullptr)
 void multidot(stokes_ctx &c, const double *V, int nv, const double *w, double w2, double *out,
               const double *scale = nullptr) {
-    const long long n = c.vlen, pstart = (long long)c.dim * c.fine.stride;
-    const unsigned g = nblocks_stream(n);
+    check_pairs(c, V);
+    check_pairs(c, w);
     for (int m0 = 0; m0 < nv; m0 += kGroup) {
         int cnt = std::min(kGroup, nv - m0);
-        ProfScope ps(c, STOKES_PROF_MULTIDOT, (double)(cnt + 1) * c.unknowns * 8.0);
-        k_multidot<kGroup><<<g, kBlock, 0, c.stream>>>(n, pstart, w2, V + (size_t)m0 * c.vlen, c.vlen, cnt, w, c.partial);
+        const double *Vm = V + (size_t)m0 * c.vlen;
+        // a squared norm (V_0 = w) reads one vector
+        ProfScope ps(c, STOKES_PROF_MULTIDOT, (double)(cnt == 1 && Vm == w ? 1 : cnt + 1) * c.unknowns * 8.0);
+        unsigned g = 0;
+        switch (cnt) {
+        case 1: g = Vm == w ? launch_multidot<1, true>(c, Vm, w, w2) : launch_multidot<1>(c, Vm, w, w2); break;
+        case 2: g = launch_multidot<2>(c, Vm, w, w2); break;
+        case 3: g = launch_multidot<3>(c, Vm, w, w2); break;
+        case 4: g = launch_multidot<4>(c, Vm, w, w2); break;
+        case 5: g = launch_multidot<5>(c, Vm, w, w2); break;
+        case 6: g = launch_multidot<6>(c, Vm, w, w2); break;
+        case 7: g = launch_multidot<7>(c, Vm, w, w2); break;
+        default: g = launch_multidot<8>(c, Vm, w, w2); break;
+        }
         k_reduce_partials<<<cnt, kBlock, 0, c.stream>>>((int)g, c.partial, out + m0, 0, scale ? scale + m0 : nullptr);
     }
 }
@@ -734,15 +797,26 @@ void multidot(stokes_ctx &c, const double *V, int nv, const double *w, double w2
 // the result is reduced into nrm2[0].
 void maxpy(stokes_ctx &c, double sign, const double *V, int nv, const double *coef, double *w,
            double w2 = 1.0, double *nrm2 = nullptr, const double *vscale = nullptr) {
-    const long long n = c.vlen, pstart = (long long)c.dim * c.fine.stride;
-    const unsigned g = nblocks_stream(n);
+    check_pairs(c, V);
+    check_pairs(c, w);
+    unsigned g = 0;
     for (int m0 = 0; m0 < nv; m0 += kGroup) {
         int cnt = std::min(kGroup, nv - m0);
         bool last = m0 + kGroup >= nv;
         ProfScope ps(c, STOKES_PROF_MAXPY, (double)(cnt + 2) * c.unknowns * 8.0);
-        k_maxpy<kGroup><<<g, kBlock, 0, c.stream>>>(n, sign, V + (size_t)m0 * c.vlen, c.vlen, cnt, coef + m0,
-                                                    vscale ? vscale + m0 : nullptr, w, pstart, w2,
-                                                    (last && nrm2) ? c.partial : nullptr);
+        const double *Vm = V + (size_t)m0 * c.vlen;
+        const double *cm = coef + m0, *sm = vscale ? vscale + m0 : nullptr;
+        double *part = (last && nrm2) ? c.partial : nullptr;
+        switch (cnt) {
+        case 1: g = launch_maxpy<1>(c, sign, Vm, cm, sm, w, w2, part); break;
+        case 2: g = launch_maxpy<2>(c, sign, Vm, cm, sm, w, w2, part); break;
+        case 3: g = launch_maxpy<3>(c, sign, Vm, cm, sm, w, w2, part); break;
+        case 4: g = launch_maxpy<4>(c, sign, Vm, cm, sm, w, w2, part); break;
+        case 5: g = launch_maxpy<5>(c, sign, Vm, cm, sm, w, w2, part); break;
+        case 6: g = launch_maxpy<6>(c, sign, Vm, cm, sm, w, w2, part); break;
+        case 7: g = launch_maxpy<7>(c, sign, Vm, cm, sm, w, w2, part); break;
+        default: g = launch_maxpy<8>(c, sign, Vm, cm, sm, w, w2, part); break;
+        }
     }
     if (nrm2) k_reduce_partials<<<1, kBlock, 0, c.stream>>>((int)g, c.partial, nrm2, 0, nullptr);
 }
@@ -1342,7 +1416,7 @@ stokes_status setup_impl(stokes_ctx &c, const double *const rho[3], const double
         const size_t vb = (size_t)(reinterpret_cast<char *>(c.V) - c.ws);
         const size_t ze = (size_t)(reinterpret_cast<char *>(c.Z + (size_t)c.vlen * c.m) - c.ws);
         HIPCHK(hipMemsetAsync(c.ws, 0, vb, c.stream));
-        HIPCHK(hipMemsetAsync(c.ws + ze, 0, c.ws_need - ze, c.stream));
+        HIPCHK(hipMemsetAsync(c.ws + ze, 0, c.ws_used - ze, c.stream));
         c.v_clear = c.z_clear = 0;
     }
     for (int a = 0; a < DIM; ++a) {
@@ -1785,8 +1859,11 @@ stokes_status stokes_setup(const double *const rho_face[3], const double *mu_cel
         delete c;
         return STOKES_ENOMEM;
     }
-    c->ws = reinterpret_cast<char *>(workspace);
-    c->ws_bytes = ws_bytes;
+    // carve from the first 256-byte boundary (the 16-byte vector accesses of the
+    // BLAS kernels need aligned vectors; ws_need holds the slack)
+    const size_t shift = (size_t)(-reinterpret_cast<uintptr_t>(workspace) & 255);
+    c->ws = reinterpret_cast<char *>(workspace) + shift;
+    c->ws_bytes = ws_bytes - shift;
     Carver cv{c->ws};
     carve_all(cv, *c);
     stokes_status s;
