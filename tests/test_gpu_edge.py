@@ -168,6 +168,59 @@ def test_workspace_contents_do_not_matter(precision):
         np.testing.assert_array_equal(a, b)
 
 
+def test_workspace_alignment_does_not_matter():
+    """The library carves its workspace from the first 256-byte boundary: a workspace
+    that starts 8 bytes past an allocation gives bitwise the same matvec and solve."""
+    import torch
+    import paper_1901_07892_amd as S
+    B = S._binding
+    prob = W.config3(scale=4)
+    rho = [to_dev(r) for r in prob.rho_faces[:3]]
+    mu = to_dev(prob.mu)
+    grid = B.make_grid(3, prob.n, prob.h)
+    opts = B.stokes_default_options()
+    nbytes = B.stokes_workspace_size(grid, opts)
+    rng = np.random.default_rng(6)
+    xin = [to_dev(rng.standard_normal(W.face_shape(prob.n, c))) for c in range(3)]
+    pin = to_dev(rng.standard_normal(W.cell_shape(prob.n)))
+    runs = []
+    for offset in (0, 8):
+        ws = torch.zeros((nbytes + offset) // 8 + 1, dtype=torch.float64, device="cuda")
+        ctx = B.stokes_setup(rho, mu, prob.dt, grid, opts, ws.data_ptr() + offset, nbytes)
+        yu = [torch.empty_like(a) for a in xin]
+        yp = torch.empty_like(pin)
+        B.stokes_apply(ctx, xin, pin, yu, yp)
+        xu = [torch.zeros_like(to_dev(f)) for f in prob.rhs_u[:3]]
+        xp = torch.zeros_like(to_dev(prob.rhs_p))
+        st, stats = B.stokes_solve(ctx, [to_dev(f) for f in prob.rhs_u[:3]], to_dev(prob.rhs_p), 1e-10, xu, xp)
+        torch.cuda.synchronize()
+        assert st == 0, stats.as_dict()
+        runs.append([to_host(a) for a in yu] + [to_host(yp)] + [to_host(a) for a in xu] + [to_host(xp)])
+        B.stokes_destroy(ctx)
+    for a, b in zip(*runs):
+        np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("orth", [1, 2])
+def test_long_krylov_runs_match_oracle(oracle_lib, orth):
+    """A deliberately weak preconditioner (one pressure cycle per application,
+    constant prolongation, one sweep each side) needs more than eight FGMRES
+    iterations per restart cycle of twelve, so the Gram-Schmidt products and
+    updates run with every vector count of one launch (1-8) and split into two
+    launches beyond eight, with one- and two-pass Gram-Schmidt; the solution still
+    matches the oracle's."""
+    prob = W.config3(scale=4)
+    ru, rp, info = oracle_lib.solve_problem(prob, tol=1e-13, max_iters=300)
+    xu, xp, st, stats = gpu_solve(prob, tol=1e-12, max_iters=400, restart=12, orth=orth, p_cycles=1,
+                                  p_cycles_next=1, p_prolong=0, nu1=1, nu2=1)
+    print("orth", orth, "iters", stats.iters, "restarts", stats.restarts, "res", stats.rel_res_true, flush=True)
+    assert st == 0 or (st == 1 and stats.rel_res_true <= 1e-11), stats.as_dict()
+    assert stats.iters > 12, stats.as_dict()
+    for c in range(prob.dim):
+        assert rel(xu[c], ru[c]) <= 1e-8
+    assert rel(xp - xp.mean(), rp - rp.mean()) <= 1e-8
+
+
 def test_max_iters_not_converged_returns_best_iterate():
     prob = W.config1(scale=2)
     xu, xp, st, stats = gpu_solve(prob, tol=1e-14, max_iters=1)
