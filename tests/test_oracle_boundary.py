@@ -3,8 +3,11 @@ open top of oracle/assemble.py): the Dirichlet-top Poisson spectrum in closed
 form, second-order convergence of a manufactured solution with inflow on
 x = 0 and the open top, the global mass balance, and the Stokes wave formulas
 (divergence-free, no flow through the bottom, the linear kinematic condition,
-the textbook second-order amplitude).  CPU only."""
+the textbook second-order amplitude, and the paper's printed wave cases, whose
+periods and wavelengths the dispersion relation must reproduce to the printed
+digits: tests/golden/stokes_wave_cases.txt).  CPU only."""
 import math
+import os
 
 import numpy as np
 import pytest
@@ -185,3 +188,68 @@ def test_stokes_inflow_drives_the_liquid_only():
     uc, _ = B.stokes_velocity(H_, D_, LAM_, om, G_, 0.0, zc, 0.3)
     assert np.allclose(un[deep, 0], uc[deep], rtol=1e-15)
     assert np.all(un[:, 0:1] == un)                         # uniform across y
+
+
+def _paper_wave_cases():
+    """The wave cases the paper prints (tests/golden/stokes_wave_cases.txt, Sec. 7.1,
+    Table tab_wave_cases)."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "stokes_wave_cases.txt")
+    g, cases = None, []
+    with open(path) as f:
+        for line in f:
+            line = line.split("#", 1)[0].split()
+            if not line:
+                continue
+            if line[0] == "g":
+                g = float(line[1])
+            else:
+                name, d, h_d, t_c, lam_d, _, _ = line
+                cases.append((name, float(d), float(h_d), float(t_c), lam_d))
+    return g, cases
+
+
+def test_paper_wave_cases_satisfy_the_dispersion_relation():
+    """Each printed (period, wavelength, depth) triple of the paper's wave cases
+    satisfies the oracle's dispersion relation (eq. eq_disp) to the printed digits:
+    the period the oracle gives for the wavelength rounded down by half a unit of
+    its last printed digit, and for it rounded up, brackets the printed period
+    widened by half a unit of its own last digit (the period grows with the
+    wavelength).  A wrong depth inside tanh, a missing square root or k = 1 / lambda
+    moves the period far outside that bracket."""
+    g, cases = _paper_wave_cases()
+    assert g == 9.81 and [c[0] for c in cases] == ["A", "B", "C"]
+    for name, d, _, t_c, lam_d in cases:
+        half = 0.5 * 10.0 ** -len(lam_d.split(".")[1])
+        scale = math.sqrt(d / g)
+
+        def period(lam_over_d):
+            return 2.0 * math.pi / B.dispersion_omega(B.wave_number(lam_over_d * d), d, g) / scale
+
+        lo, hi = period(float(lam_d) - half), period(float(lam_d) + half)
+        assert lo < hi, name
+        assert lo <= t_c + 0.5e-4 and hi >= t_c - 0.5e-4, (name, lo, t_c, hi)
+        # the bracket is tight: half a unit of the wavelength's last digit moves the
+        # period by less than 1e-3 of sqrt(d / g)
+        assert hi - lo < 1e-3, name
+
+
+def test_paper_wave_case_a_velocity_scale():
+    """Case A of the paper (Sec. 7.1) in the oracle's wave formulas: the crest
+    elevation exceeds half the height by the second-order term, which is positive
+    and below a tenth of the first-order amplitude (the case sits in the second-order
+    Stokes regime), and the horizontal velocity under the crest at the still level
+    is H g k / (2 omega) plus the second-order part."""
+    g, cases = _paper_wave_cases()
+    _, d, h_d, _, lam_d = cases[0]
+    H, lam = h_d * d, float(lam_d) * d
+    k = B.wave_number(lam)
+    om = B.dispersion_omega(k, d, g)
+    crest = B.stokes_eta(H, d, lam, om, 0.0, 0.0)
+    second = crest - 0.5 * H
+    assert 0.0 < second < 0.1 * 0.5 * H
+    trough = B.stokes_eta(H, d, lam, om, 0.5 * lam, 0.0)
+    assert crest - trough == pytest.approx(H, rel=1e-12)   # the second harmonic cancels
+    u_crest, v_crest = B.stokes_velocity(H, d, lam, om, g, 0.0, 0.0, 0.0)
+    first = H * g * k / (2.0 * om)
+    assert first < u_crest < 1.1 * first
+    assert v_crest == pytest.approx(0.0, abs=1e-15)
