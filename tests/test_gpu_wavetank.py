@@ -16,6 +16,7 @@ import workloads as W
 from oracle import assemble as A
 from oracle import boundary as B
 from oracle import direct as D
+from tests.golden_data import paper_wave_cases
 from tests.gpu_util import gpu_apply, rel, solver_for, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
@@ -95,6 +96,34 @@ def test_wave_inflow_data_matches_oracle(dim, n, h):
               np.abs(to_host(un) - oun).max(), np.abs(to_host(ut) - out).max()), flush=True)
         assert np.abs(to_host(un) - oun).max() <= 1e-13 * scale
         assert np.abs(to_host(ut) - out).max() <= 1e-13 * scale
+
+
+@pytest.mark.parametrize("case", ["A", "B", "C"])
+def test_wave_inflow_paper_cases_match_oracle(case):
+    """The paper's printed wave cases (Sec. 7.1, Table tab_wave_cases, read from
+    tests/golden/stokes_wave_cases.txt) on its coarsest wave-tank grid: 442 x 66
+    cells over 68 d x 1.3 d with the still level 0.3 d below the top, one cell of
+    smearing; the inflow data on x = 0 equal the oracle's within 1e-13."""
+    import torch
+    import paper_1901_07892_amd as S
+    g, cases = paper_wave_cases()
+    _, d, h_d, _, lam_d = [c for c in cases if c[0] == case][0]
+    H, lam = h_d * d, float(lam_d) * d
+    om = B.dispersion_omega(B.wave_number(lam), d, g)
+    n, h = (442, 66, 1), (68.0 * d / 442, 1.3 * d / 66, 68.0 * d / 442)
+    grid = S._binding.make_grid(2, n, h)
+    un = torch.full((66, 1), np.nan, dtype=torch.float64, device="cuda")
+    ut = torch.full((67, 1), np.nan, dtype=torch.float64, device="cuda")
+    period = 2.0 * np.pi / om
+    for t in (0.0, 0.37 * period, 2.9 * period):
+        print("paper wave case", case, "t %.3f" % t, flush=True)
+        S.stokes_wave_inflow(grid, S.make_wave(H, d, lam, om, g, 1.0), t, un, ut)
+        torch.cuda.synchronize()
+        oun, out = B.stokes_inflow(2, n, h, H, d, lam, om, g, t, d, 1.0)
+        scale = max(np.abs(oun).max(), np.abs(out).max())
+        assert scale > 0.0
+        assert np.abs(to_host(un) - oun.T).max() <= 1e-13 * scale
+        assert np.abs(to_host(ut) - out.T).max() <= 1e-13 * scale
 
 
 @pytest.mark.parametrize("dim,n,h", [(2, (24, 16, 1), (0.05, 0.06, 0.05)), (3, (12, 10, 14), (0.05, 0.06, 0.04))])

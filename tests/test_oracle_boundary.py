@@ -7,7 +7,6 @@ the textbook second-order amplitude, and the paper's printed wave cases, whose
 periods and wavelengths the dispersion relation must reproduce to the printed
 digits: tests/golden/stokes_wave_cases.txt).  CPU only."""
 import math
-import os
 
 import numpy as np
 import pytest
@@ -17,6 +16,7 @@ import workloads as W
 from oracle import assemble as A
 from oracle import boundary as B
 from oracle import direct as D
+from tests.golden_data import paper_wave_cases
 
 
 def test_dirichlet_top_poisson_spectrum():
@@ -190,24 +190,6 @@ def test_stokes_inflow_drives_the_liquid_only():
     assert np.all(un[:, 0:1] == un)                         # uniform across y
 
 
-def _paper_wave_cases():
-    """The wave cases the paper prints (tests/golden/stokes_wave_cases.txt, Sec. 7.1,
-    Table tab_wave_cases)."""
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "stokes_wave_cases.txt")
-    g, cases = None, []
-    with open(path) as f:
-        for line in f:
-            line = line.split("#", 1)[0].split()
-            if not line:
-                continue
-            if line[0] == "g":
-                g = float(line[1])
-            else:
-                name, d, h_d, t_c, lam_d, _, _ = line
-                cases.append((name, float(d), float(h_d), float(t_c), lam_d))
-    return g, cases
-
-
 def test_paper_wave_cases_satisfy_the_dispersion_relation():
     """Each printed (period, wavelength, depth) triple of the paper's wave cases
     satisfies the oracle's dispersion relation (eq. eq_disp) to the printed digits:
@@ -216,7 +198,7 @@ def test_paper_wave_cases_satisfy_the_dispersion_relation():
     widened by half a unit of its own last digit (the period grows with the
     wavelength).  A wrong depth inside tanh, a missing square root or k = 1 / lambda
     moves the period far outside that bracket."""
-    g, cases = _paper_wave_cases()
+    g, cases = paper_wave_cases()
     assert g == 9.81 and [c[0] for c in cases] == ["A", "B", "C"]
     for name, d, _, t_c, lam_d in cases:
         half = 0.5 * 10.0 ** -len(lam_d.split(".")[1])
@@ -239,7 +221,7 @@ def test_paper_wave_case_a_velocity_scale():
     and below a tenth of the first-order amplitude (the case sits in the second-order
     Stokes regime), and the horizontal velocity under the crest at the still level
     is H g k / (2 omega) plus the second-order part."""
-    g, cases = _paper_wave_cases()
+    g, cases = paper_wave_cases()
     _, d, h_d, _, lam_d = cases[0]
     H, lam = h_d * d, float(lam_d) * d
     k = B.wave_number(lam)
