@@ -7,7 +7,7 @@ GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 def paper_wave_cases():
     """(g, [(case, d, H / d, T / sqrt(d / g), lambda / d as printed), ...]) from
-    stokes_wave_cases.txt (Sec. 7.1, Table tab_wave_cases).  The wavelength stays
+    stokes_wave_cases.txt (Sec. 7.2, Table tab_wave_cases).  The wavelength stays
     a string so that callers can see how many digits were printed."""
     g, cases = None, []
     with open(os.path.join(GOLDEN, "stokes_wave_cases.txt")) as f:

@@ -100,7 +100,7 @@ def test_wave_inflow_data_matches_oracle(dim, n, h):
 
 @pytest.mark.parametrize("case", ["A", "B", "C"])
 def test_wave_inflow_paper_cases_match_oracle(case):
-    """The paper's printed wave cases (Sec. 7.1, Table tab_wave_cases, read from
+    """The paper's printed wave cases (Sec. 7.2, Table tab_wave_cases, read from
     tests/golden/stokes_wave_cases.txt) on its coarsest wave-tank grid: 442 x 66
     cells over 68 d x 1.3 d with the still level 0.3 d below the top, one cell of
     smearing; the inflow data on x = 0 equal the oracle's within 1e-13."""

@@ -216,7 +216,7 @@ def test_paper_wave_cases_satisfy_the_dispersion_relation():
 
 
 def test_paper_wave_case_a_velocity_scale():
-    """Case A of the paper (Sec. 7.1) in the oracle's wave formulas: the crest
+    """Case A of the paper (Sec. 7.2) in the oracle's wave formulas: the crest
     elevation exceeds half the height by the second-order term, which is positive
     and below a tenth of the first-order amplitude (the case sits in the second-order
     Stokes regime), and the horizontal velocity under the crest at the still level
