@@ -185,8 +185,9 @@ size_t stokes_workspace_size(const stokes_grid *grid, const stokes_options *opts
  *                owned by the caller and kept alive until stokes_destroy; any
  *                alignment (the library starts at its first 256-byte boundary)
  *   stream       hipStream_t (as void*)
- * Validates shapes and options on the host, copies the coefficients into the
- * workspace (the caller may free its arrays afterwards), builds the multigrid
+ * Validates shapes and options on the host (ESHAPE for fewer than 2 cells along
+ * an axis or a grid whose solution vector would exceed 2^30 entries; EINVAL
+ * for any other bad argument), copies the coefficients into the workspace (the caller may free its arrays afterwards), builds the multigrid
  * hierarchy and factors the coarsest pressure problem.  Checks rho > 0 and
  * mu >= 0 on the device (EINVAL).  Blocks until setup has finished.  On success
  * *out owns a host-side context to release with stokes_destroy. */
@@ -320,7 +321,7 @@ stokes_status stokes_coefficients(const stokes_grid *grid, const stokes_fluids *
  * a bad spacing; ESHAPE for fewer than 2 cells along an axis or a face array of
  * 2^31 entries or more; ENOMEM for a small workspace; EHIP if a launch fails.
  * --------------------------------------------------------------------------- */
-size_t stokes_density_workspace_size(const stokes_grid *grid);
+size_t stokes_density_workspace_size(const stokes_grid *grid);   /* 0 for a grid the update rejects */
 
 stokes_status stokes_density_rk3(const stokes_grid *grid, double dt, const double *const rho_n[3],
                                  const double *const u_stage[9], double *const rho_out[3],

@@ -166,7 +166,8 @@ extern "C" stokes_status stokes_coefficients(const stokes_grid *grid, const stok
         if (!finite_pos(grid->h[a])) return STOKES_EINVAL;
     }
     const long long nz = dim == 3 ? grid->n[2] : 1;
-    if ((long long)(grid->n[0] + 1) * (grid->n[1] + 1) * (nz + 1) >= (1LL << 31)) return STOKES_ESHAPE;
+    // point count in double: a product of three 32-bit extents can exceed 64 bits
+    if (((double)grid->n[0] + 1) * ((double)grid->n[1] + 1) * ((double)nz + 1) >= 2147483648.0) return STOKES_ESHAPE;
     if (!finite_pos(fluids->rho_liquid) || !finite_pos(fluids->rho_gas) || !finite_nonneg(fluids->mu_liquid) ||
         !finite_nonneg(fluids->mu_gas) || !finite_pos(fluids->n_cells))
         return STOKES_EINVAL;

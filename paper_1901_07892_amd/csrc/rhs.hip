@@ -260,8 +260,9 @@ extern "C" stokes_status stokes_explicit_rhs(const stokes_grid *grid, const doub
                       (dim == 3 && !std::isfinite(gravity[2]))))
         return STOKES_EINVAL;
     const long long nz = dim == 3 ? grid->n[2] : 1;
-    const long long pts = (long long)(grid->n[0] + 1) * (grid->n[1] + 1) * (dim == 3 ? nz + 1 : 1);
-    if (pts >= (1LL << 31) - kRhsBlock) return STOKES_ESHAPE;   // 32-bit point and array indices
+    // point count in double: a product of three 32-bit extents can exceed 64 bits
+    const double pts = ((double)grid->n[0] + 1) * ((double)grid->n[1] + 1) * (dim == 3 ? (double)nz + 1 : 1.0);
+    if (pts >= (double)((1LL << 31) - kRhsBlock)) return STOKES_ESHAPE;   // 32-bit point and array indices
     RhsArgs a{};
     a.dim = dim;
     a.nx = grid->n[0];

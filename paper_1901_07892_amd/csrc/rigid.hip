@@ -252,7 +252,9 @@ stokes_status rigid_check(const stokes_grid *grid, double *const u[3], long long
         g.L[d] = g.n[d] * g.h[d];
         if (!u[d]) return STOKES_EINVAL;
     }
-    if ((long long)(g.n[0] + 1) * (g.n[1] + 1) * (dim == 3 ? g.n[2] + 1 : 1) >= (1LL << 40)) return STOKES_ESHAPE;
+    // point count in double: a product of three 32-bit extents can exceed 64 bits
+    if (((double)g.n[0] + 1) * ((double)g.n[1] + 1) * (dim == 3 ? (double)g.n[2] + 1 : 1.0) >= 1099511627776.0)
+        return STOKES_ESHAPE;
     if (!finite_pos(dV) || (free_body != 0 && free_body != 1)) return STOKES_EINVAL;
     for (int d = 0; d < 3; ++d)
         if (!std::isfinite(body->x_com[d]) || !std::isfinite(body->u_r[d]) || !std::isfinite(body->w_r[d]))

@@ -1318,9 +1318,11 @@ const char *check_grid_opts(const stokes_grid *g, const stokes_options &o) {
         if (!(g->h[a] > 0.0) || !std::isfinite(g->h[a])) return "grid spacings must be positive";
     }
     // box points with the rows as fine_box pads them
-    const long long px = (g->dim == 3 && g->n[0] >= 256) ? ((g->n[0] + 1 + 15) / 16) * 16 : g->n[0] + 1;
-    long long pts = px * (g->n[1] + 1) * (g->dim == 3 ? g->n[2] + 1 : 1);
-    if (pts * (g->dim + 1) > (1LL << 30)) return "grid too large for 32-bit vector indexing";
+    // (in double: a product of three 32-bit extents can exceed 64 bits)
+    const long long nx1 = (long long)g->n[0] + 1;
+    const long long px = (g->dim == 3 && g->n[0] >= 256) ? ((nx1 + 15) / 16) * 16 : nx1;
+    const double pts = (double)px * ((double)g->n[1] + 1) * (g->dim == 3 ? (double)g->n[2] + 1 : 1.0);
+    if (pts * (g->dim + 1) > 1073741824.0) return "grid too large for 32-bit vector indexing";
     if (o.precision != 0 && o.precision != 1) return "precision must be 0 (FP64) or 1 (FP32 multigrid)";
     if (!(o.visc_scale >= 0.0) || !std::isfinite(o.visc_scale)) return "visc_scale must be >= 0";
     if (!(o.cont_scale >= 0.0) || !std::isfinite(o.cont_scale)) return "cont_scale must be >= 0";
@@ -1836,7 +1838,8 @@ stokes_status stokes_setup(const double *const rho_face[3], const double *mu_cel
     stokes_options o = opts ? *opts : defaults();
     if (const char *msg = check_grid_opts(grid, o)) {
         g_setup_error = msg;
-        return (grid && (grid->dim == 2 || grid->dim == 3)) && std::strstr(msg, "cells") ? STOKES_ESHAPE : STOKES_EINVAL;
+        return (grid && (grid->dim == 2 || grid->dim == 3)) && (std::strstr(msg, "cells") || std::strstr(msg, "too large"))
+                   ? STOKES_ESHAPE : STOKES_EINVAL;
     }
     if (!(dt > 0.0) || !std::isfinite(dt)) { g_setup_error = "dt must be > 0"; return STOKES_EINVAL; }
     if (!rho_face || !rho_face[0] || !rho_face[1] || (grid->dim == 3 && !rho_face[2]) || !mu_cell) {

@@ -129,12 +129,24 @@ size_t face_count(const stokes_grid *g, int c) {
     return n;
 }
 
+// True when a face array would hold 2^31 faces or more (32-bit thread and face
+// indices); counted in double, since a product of 32-bit extents can exceed 64 bits.
+bool too_many_faces(const stokes_grid *g) {
+    for (int c = 0; c < g->dim; ++c) {
+        double n = 1.0;
+        for (int a = 0; a < g->dim; ++a) n *= (double)g->n[a] + (a == c ? 1.0 : 0.0);
+        if (n >= 2147483648.0) return true;
+    }
+    return false;
+}
+
 }  // namespace
 
 extern "C" size_t stokes_density_workspace_size(const stokes_grid *grid) {
     if (!grid || (grid->dim != 2 && grid->dim != 3)) return 0;
     for (int a = 0; a < grid->dim; ++a)
         if (grid->n[a] < 2) return 0;
+    if (too_many_faces(grid)) return 0;
     size_t tot = 0;
     for (int c = 0; c < grid->dim; ++c) tot += face_count(grid, c);
     return tot * sizeof(double);
@@ -160,6 +172,7 @@ extern "C" stokes_status stokes_density_rk3(const stokes_grid *grid, double dt, 
         if (!(grid->h[a] > 0.0) || !std::isfinite(grid->h[a])) return STOKES_EINVAL;
         g.ih[a] = 1.0 / grid->h[a];
     }
+    if (too_many_faces(grid)) return STOKES_ESHAPE;
     for (int c = 0; c < dim; ++c) {
         if (!rho_n[c] || !rho_out[c]) return STOKES_EINVAL;
         for (int st = 0; st < 3; ++st)
@@ -181,7 +194,6 @@ extern "C" stokes_status stokes_density_rk3(const stokes_grid *grid, double dt, 
     // one thread per face of the largest component array
     long long most = 0;
     for (int c = 0; c < dim; ++c) most = std::max<long long>(most, (long long)face_count(grid, c));
-    if (most >= (1LL << 31)) return STOKES_ESHAPE;
     const unsigned blocks = (unsigned)((most + kTrBlock - 1) / kTrBlock);
     auto stage = [&](double a_n, double a_s, double c_dt, const double *const rs[3], int st, double *const out[3]) {
         StageArgs a{};

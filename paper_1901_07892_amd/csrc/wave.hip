@@ -66,7 +66,7 @@ extern "C" stokes_status stokes_wave_inflow(const stokes_grid *grid, const stoke
         return STOKES_EINVAL;
     const int v = dim - 1;
     const int nvert = grid->n[v], nlat = dim == 3 ? grid->n[1] : 1;
-    if ((long long)(nvert + 1) * nlat >= (1LL << 31)) return STOKES_ESHAPE;
+    if (((long long)nvert + 1) * nlat >= (1LL << 31)) return STOKES_ESHAPE;
     WaveArgs w{};
     w.H = H;
     w.d = d;

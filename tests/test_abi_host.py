@@ -191,3 +191,40 @@ def test_explicit_rhs_rejects_bad_arguments_on_host(S):
     assert call(theta=-0.1) == -1 and call(theta=1.5) == -1
     assert call(rf=p3, gv=(0.0, float("inf"), 0.0)) == -1
     assert call(rf=[0x1000, None, 0x3000], gv=(0, 0, -9.81)) == -1
+
+
+def test_extreme_extents_rejected_on_host(S):
+    """Grids whose point counts overflow 32-bit indices -- up to extents near
+    INT_MAX, where the counts overflow 64-bit products as well -- are rejected by
+    every entry point's host checks before any device work (the pointers below
+    are never dereferenced)."""
+    B = S._binding
+    L = S.load_library()
+    imax = 2 ** 31 - 1
+    grids = [B.make_grid(3, (imax, imax, imax), (1.0, 1.0, 1.0)), B.make_grid(3, (imax, 8, 8), (1.0, 1.0, 1.0)),
+             B.make_grid(2, (imax, imax, 1), (1.0, 1.0, 1.0)), B.make_grid(3, (2000, 2000, 2000), (1.0, 1.0, 1.0))]
+    p3 = [0x1000, 0x2000, 0x3000]
+    for g in grids:
+        assert S.stokes_workspace_size(g, None) == 0
+        with pytest.raises(S.StokesError) as e:
+            S.stokes_setup(p3, 0x4000, 1e-3, g, None, 8, 16, stream=0)
+        assert e.value.status == -2
+        assert S.stokes_density_workspace_size(g) == 0
+        with pytest.raises(S.StokesError) as e:
+            S.stokes_coefficients(g, B.make_fluids(1e3, 1.0, 1e-3, 1e-5, 1.5), 0x4000, [], [], [], p3, 0x5000,
+                                  None, stream=0)
+        assert e.value.status == -2
+        with pytest.raises(S.StokesError) as e:
+            S.stokes_explicit_rhs(g, p3, 0x4000, 1e-3, 0.5, p3, p3, None, None, stream=0)
+        assert e.value.status == -2
+        us = (ctypes.c_void_p * 9)(*([0x1000] * 9))
+        assert L.stokes_density_rk3(ctypes.byref(g), ctypes.c_double(1e-3), B._ptr3(p3), us, B._ptr3(p3),
+                                    ctypes.c_void_p(0x6000), ctypes.c_size_t(1 << 62), None) == -2
+    # the rigid projection indexes with 64-bit offsets: only beyond 2^40 points
+    b = B.make_body((0.5, 0.5, 0.5))
+    assert L.stokes_rigid_projection(ctypes.byref(grids[0]), B._ptr3(p3), 10, 0x4000, ctypes.c_double(1e-3), 1,
+                                     ctypes.byref(b), 0x5000, 1 << 20, None) == -2
+    # the wave inflow's arrays are (Nv + 1) x N_lateral
+    w = B.make_wave(0.04, 0.5, 1.5, 2.0)
+    assert L.stokes_wave_inflow(ctypes.byref(B.make_grid(2, (8, imax, 1), (1.0, 1.0, 1.0))), ctypes.byref(w),
+                                ctypes.c_double(0.0), 0x1000, 0x2000, None) == -2
