@@ -13,10 +13,13 @@
  * cell centres; shear viscosities on cell edges (2D: nodes) are the harmonic
  * mean of the surrounding cells (Sec. 4.2, footnote on harmonic averaging).
  * theta scales the implicit viscous operator: 1 gives the full operator, 1/2
- * the Crank-Nicolson half of Sec. 4.2.2.  Every boundary is a no-slip wall:
- * wall-normal velocity is zero and is not an unknown, tangential ghosts are
- * minus the interior value, and the pressure is defined up to a constant
- * (returned with zero mean).
+ * the Crank-Nicolson half of Sec. 4.2.2.  By default every boundary is a
+ * no-slip wall: wall-normal velocity is zero and is not an unknown, tangential
+ * ghosts are minus the interior value, and the pressure is defined up to a
+ * constant (returned with zero mean).  An axis may be periodic instead
+ * (stokes_grid.periodic), and the top of the vertical axis may be the wave
+ * tank's open boundary of Sec. 7.1 (stokes_options.open_top: zero pressure
+ * there, so the pressure has no free constant).
  *
  * The solver is restarted flexible GMRES on the coupled (u, p) system
  * (Sec. 4.2.4), right-preconditioned by a projection step with a
@@ -187,8 +190,9 @@ size_t stokes_workspace_size(const stokes_grid *grid, const stokes_options *opts
  *   stream       hipStream_t (as void*)
  * Validates shapes and options on the host (ESHAPE for fewer than 2 cells along
  * an axis or a grid whose solution vector would exceed 2^30 entries; EINVAL
- * for any other bad argument), copies the coefficients into the workspace (the caller may free its arrays afterwards), builds the multigrid
- * hierarchy and factors the coarsest pressure problem.  Checks rho > 0 and
+ * for any other bad argument), copies the coefficients into the workspace (the
+ * caller may free its arrays afterwards), builds the multigrid hierarchy and
+ * factors the coarsest pressure problem.  Checks rho > 0 and
  * mu >= 0 on the device (EINVAL).  Blocks until setup has finished.  On success
  * *out owns a host-side context to release with stokes_destroy. */
 stokes_status stokes_setup(const double *const rho_face[3], const double *mu_cell, double dt,
