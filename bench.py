@@ -58,6 +58,29 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+class Legs:
+    """Runs the measurements beside the headline one at a time, so that a failing
+    leg (a solve that does not converge, missing weights, a host-side error) is
+    reported in its own field and the headline line is still printed.  After a
+    HIP error nothing more is launched on the GPU: the later GPU legs are
+    recorded as skipped; host-only legs still run."""
+
+    def __init__(self):
+        self.gpu_ok = True
+
+    def run(self, name, fn, *args, gpu=True):
+        if gpu and not self.gpu_ok:
+            return {"skipped": "an earlier leg hit a HIP error"}
+        try:
+            return fn(*args)
+        except Exception as e:          # noqa: BLE001 -- reported, not swallowed
+            msg = "%s: %s" % (type(e).__name__, e)
+            log("leg %s failed: %s" % (name, msg))
+            if gpu and ("HIP" in msg or getattr(e, "status", None) == -4):
+                self.gpu_ok = False
+            return {"error": msg}
+
+
 def main():
     args = parse()
     if args.traffic_from:
@@ -200,23 +223,25 @@ def main():
     S._binding.stokes_destroy(ctx2)
     log("setup into the same workspace: %.1f ms" % out["setup_ms_reused_workspace"])
     del solver
-    out["hbm_stream_copy"] = stream_copy(S)
-    out["coefficient_step"] = coefficient_step(S, prob)
-    out["rigid_projection"] = rigid_step(S, prob, xu)
-    out["explicit_rhs"] = explicit_rhs_step(S, prob, rho, mu, xu)
-    out["density_transport"] = density_transport_step(S, prob, xu)
+    legs = Legs()
+    out["hbm_stream_copy"] = legs.run("hbm_stream_copy", stream_copy, S)
+    out["coefficient_step"] = legs.run("coefficient_step", coefficient_step, S, prob)
+    out["rigid_projection"] = legs.run("rigid_projection", rigid_step, S, prob, xu)
+    out["explicit_rhs"] = legs.run("explicit_rhs", explicit_rhs_step, S, prob, rho, mu, xu)
+    out["density_transport"] = legs.run("density_transport", density_transport_step, S, prob, xu)
     if not args.no_forms and args.precision == 0:
-        out["forms"] = {"fp32_multigrid": fp32_form(S, prob, rho, mu, rhs_u, rhs_p, xu, xp, overrides,
-                                                    ms, args.steps)}
-        lf = learned_form(S, prob, rho, mu, rhs_u, rhs_p, xu, xp, overrides, ms, args.steps)
+        out["forms"] = {"fp32_multigrid": legs.run("fp32_multigrid", fp32_form, S, prob, rho, mu, rhs_u, rhs_p,
+                                                   xu, xp, overrides, ms, args.steps)}
+        lf = legs.run("learned", learned_form, S, prob, rho, mu, rhs_u, rhs_p, xu, xp, overrides, ms,
+                      args.steps)
         if lf is not None:
             out["forms"]["learned"] = lf
     if not args.no_configs:
-        out["configs"] = {"config3_128^3 dam break": config_leg(S, 3),
-                          "config4_1024x96x96 wave tank": config_leg(S, 4)}
-        out["velocity_multigrid"] = velocity_mg_leg(S)
+        out["configs"] = {"config3_128^3 dam break": legs.run("config3", config_leg, S, 3),
+                          "config4_1024x96x96 wave tank": legs.run("config4", config_leg, S, 4)}
+        out["velocity_multigrid"] = legs.run("velocity_multigrid", velocity_mg_leg, S)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(prob, int(np.median(iters)))
+        out["cpu_baseline"] = legs.run("cpu_baseline", cpu_baseline, prob, int(np.median(iters)), gpu=False)
     print(json.dumps(out), flush=True)
 
 

@@ -55,3 +55,21 @@ def test_traffic_conversion_uses_the_calibration_copies_and_finest_sweep(tmp_pat
     assert e["bytes_per_launch"] == pytest.approx(305000.0 * 1024 * 2.0 + 130000.0 * 1024)
     assert e["kernel_source_hash"] == bench.kernel_source_hash()
     assert json.load(open(out))["entries"]["1/256/0"]["bytes_per_launch"] == pytest.approx(e["bytes_per_launch"])
+
+
+def test_side_legs_report_failures_without_losing_the_line():
+    """A failing measurement leg becomes an error field; after a HIP error the
+    later GPU legs are skipped and host-only legs still run."""
+    import bench
+
+    class HipFailure(Exception):
+        status = -4
+
+    legs = bench.Legs()
+    assert legs.run("ok", lambda a, b: a + b, 2, 3) == 5
+    r = legs.run("no convergence", lambda: (_ for _ in ()).throw(RuntimeError("solve did not converge")))
+    assert r == {"error": "RuntimeError: solve did not converge"} and legs.gpu_ok
+    r = legs.run("device", lambda: (_ for _ in ()).throw(HipFailure("launch failed")))
+    assert r["error"].startswith("HipFailure") and not legs.gpu_ok
+    assert "skipped" in legs.run("later gpu leg", lambda: 1)
+    assert legs.run("host leg", lambda: 7, gpu=False) == 7
