@@ -8,7 +8,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
-from typing import Optional, Sequence
+from typing import Dict, List, Optional, Sequence, Tuple
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(HERE, "libstokes.so")
@@ -170,22 +170,45 @@ def load_library():
 
 
 # ---------------------------------------------------------------- marshalling helpers
-def _ptr(t) -> Optional[int]:
+def _ptr(t, need: Optional[int] = None) -> Optional[int]:
+    """Device address of a tensor (or an int address as it is).  With ``need``, a
+    tensor must hold at least that many values: the kernels index the caller's
+    arrays from the grid alone, so a shorter one would be read or written past
+    its end."""
     if t is None:
         return None
     if hasattr(t, "data_ptr"):
         import torch
         if t.dtype != torch.float64 or not t.is_contiguous() or not t.is_cuda:
             raise ValueError("arrays must be contiguous float64 CUDA/HIP tensors")
+        if need is not None and t.numel() < need:
+            raise ValueError("array of %d values where the grid needs %d" % (t.numel(), need))
         return t.data_ptr()
     return int(t)
 
 
-def _ptr3(ts: Sequence) -> "C.Array":
+def _ptr3(ts: Sequence, needs: Optional[Sequence[int]] = None) -> "C.Array":
     arr = (C.c_void_p * 3)()
     for a, t in enumerate(list(ts)[:3]):
-        arr[a] = _ptr(t)
+        arr[a] = _ptr(t, needs[a] if needs is not None and a < len(needs) else None)
     return arr
+
+
+def _counts(grid) -> Tuple[List[int], int]:
+    """Values in the caller's arrays for a grid (layouts of include/stokes.h):
+    the face array of each velocity component and the cell array."""
+    d = grid.dim
+    n = [int(grid.n[a]) if a < d else 1 for a in range(3)]
+    faces = [(n[0] + (c == 0)) * (n[1] + (c == 1)) * (n[2] + (c == 2)) for c in range(d)]
+    return faces, n[0] * n[1] * n[2]
+
+
+# array sizes of each live context's grid, for the checks of the calls that take a context
+_CTX_COUNTS: Dict[int, Tuple[List[int], int]] = {}
+
+
+def _ctx_counts(ctx) -> Tuple[Optional[List[int]], Optional[int]]:
+    return _CTX_COUNTS.get(ctx, (None, None))
 
 
 def _stream(stream) -> Optional[int]:
@@ -220,17 +243,21 @@ def stokes_setup(rho_face, mu_cell, dt, grid, opts, workspace, ws_bytes, stream=
     """Returns an opaque context handle (int); raises StokesError on failure."""
     L = load_library()
     ctx = C.c_void_p()
-    st = L.stokes_setup(_ptr3(list(rho_face) + [None] * 3), _ptr(mu_cell), float(dt), C.byref(grid),
+    faces, cells = _counts(grid) if grid is not None and grid.dim in (2, 3) else (None, None)
+    st = L.stokes_setup(_ptr3(list(rho_face) + [None] * 3, faces), _ptr(mu_cell, cells), float(dt), C.byref(grid),
                         C.byref(opts) if opts is not None else None, _ptr(workspace), int(ws_bytes),
                         _stream(stream), C.byref(ctx))
     if st != 0:
         raise StokesError(st, L.stokes_last_error(None).decode())
+    _CTX_COUNTS[ctx.value] = (faces, cells)
     return ctx.value
 
 
 def stokes_apply(ctx, x_u, x_p, y_u, y_p) -> int:
     L = load_library()
-    st = L.stokes_apply(ctx, _ptr3(list(x_u) + [None] * 3), _ptr(x_p), _ptr3(list(y_u) + [None] * 3), _ptr(y_p))
+    faces, cells = _ctx_counts(ctx)
+    st = L.stokes_apply(ctx, _ptr3(list(x_u) + [None] * 3, faces), _ptr(x_p, cells),
+                        _ptr3(list(y_u) + [None] * 3, faces), _ptr(y_p, cells))
     if st < 0:
         raise StokesError(st, L.stokes_last_error(ctx).decode())
     return st
@@ -240,8 +267,9 @@ def stokes_solve(ctx, rhs_u, rhs_p, tol, x_u, x_p):
     """Returns (status, StokesStats); raises StokesError on negative status."""
     L = load_library()
     stats = StokesStats()
-    st = L.stokes_solve(ctx, _ptr3(list(rhs_u) + [None] * 3), _ptr(rhs_p), float(tol),
-                        _ptr3(list(x_u) + [None] * 3), _ptr(x_p), C.byref(stats))
+    faces, cells = _ctx_counts(ctx)
+    st = L.stokes_solve(ctx, _ptr3(list(rhs_u) + [None] * 3, faces), _ptr(rhs_p, cells), float(tol),
+                        _ptr3(list(x_u) + [None] * 3, faces), _ptr(x_p, cells), C.byref(stats))
     if st < 0:
         raise StokesError(st, L.stokes_last_error(ctx).decode())
     return st, stats
@@ -249,6 +277,7 @@ def stokes_solve(ctx, rhs_u, rhs_p, tol, x_u, x_p):
 
 def stokes_destroy(ctx) -> None:
     if ctx:
+        _CTX_COUNTS.pop(ctx, None)
         load_library().stokes_destroy(ctx)
 
 
@@ -282,8 +311,10 @@ def make_wave(height, depth, wavelength, omega, gravity=9.81, n_cells=1.5) -> St
 
 def stokes_wave_inflow(grid, wave, t, u_n, u_t, stream=None) -> None:
     """Second-order Stokes wave inflow data on x = 0 into the device tensors u_n, u_t."""
-    st = load_library().stokes_wave_inflow(C.byref(grid), C.byref(wave), float(t), _ptr(u_n), _ptr(u_t),
-                                          _stream(stream))
+    nv = int(grid.n[grid.dim - 1]) if grid.dim in (2, 3) else 0
+    nl = int(grid.n[1]) if grid.dim == 3 else 1
+    st = load_library().stokes_wave_inflow(C.byref(grid), C.byref(wave), float(t), _ptr(u_n, nv * nl),
+                                          _ptr(u_t, (nv + 1) * nl), _stream(stream))
     if st != 0:
         raise StokesError(st, "stokes_wave_inflow failed")
 
@@ -291,7 +322,8 @@ def stokes_wave_inflow(grid, wave, t, u_n, u_t, stream=None) -> None:
 def stokes_inflow_lift(ctx, u_n, u_t, rhs_u, rhs_p) -> None:
     """Subtract the inflow data's contribution from (rhs_u, rhs_p), in place."""
     L = load_library()
-    st = L.stokes_inflow_lift(ctx, _ptr(u_n), _ptr(u_t), _ptr3(list(rhs_u) + [None] * 3), _ptr(rhs_p))
+    faces, cells = _ctx_counts(ctx)
+    st = L.stokes_inflow_lift(ctx, _ptr(u_n), _ptr(u_t), _ptr3(list(rhs_u) + [None] * 3, faces), _ptr(rhs_p, cells))
     if st != 0:
         raise StokesError(st, L.stokes_last_error(ctx).decode())
 
@@ -304,12 +336,13 @@ def stokes_density_rk3(grid, dt, rho_n, u_stages, rho_out, workspace, stream=Non
     """SSP-RK3 face-density transport: ``u_stages`` is a list of three velocity
     lists (one per stage); all arrays are device float64 tensors."""
     L = load_library()
+    faces = _counts(grid)[0] if grid.dim in (2, 3) else None
     us = (C.c_void_p * 9)()
     for st in range(3):
         for c, t in enumerate(list(u_stages[st])[:3]):
-            us[3 * st + c] = _ptr(t)
-    st = L.stokes_density_rk3(C.byref(grid), float(dt), _ptr3(list(rho_n) + [None] * 3), us,
-                              _ptr3(list(rho_out) + [None] * 3),
+            us[3 * st + c] = _ptr(t, faces[c] if faces is not None and c < len(faces) else None)
+    st = L.stokes_density_rk3(C.byref(grid), float(dt), _ptr3(list(rho_n) + [None] * 3, faces), us,
+                              _ptr3(list(rho_out) + [None] * 3, faces),
                               workspace.data_ptr() if workspace is not None else None,
                               workspace.numel() * workspace.element_size() if workspace is not None else 0,
                               _stream(stream))
@@ -359,16 +392,18 @@ def stokes_coefficients(grid, fluids, phi, psi, rho_solid, mu_solid, rho_face, m
     ns = len(psi)
     if len(rho_solid) != ns or len(mu_solid) != ns:
         raise ValueError("psi, rho_solid and mu_solid must have one entry per solid")
+    faces, cells = _counts(grid) if grid.dim in (2, 3) else (None, None)
     cap = max(ns, 1)
-    ps = (C.c_void_p * cap)(*[_ptr(t) for t in psi])
+    ps = (C.c_void_p * cap)(*[_ptr(t, cells) for t in psi])
     rs = (C.c_double * cap)(*[float(v) for v in rho_solid])
     ms = (C.c_double * cap)(*[float(v) for v in mu_solid])
-    flow = C.byref(_ptr3(list(rho_flow_face) + [None] * 3)) if rho_flow_face is not None else None
-    st = L.stokes_coefficients(C.byref(grid), C.byref(fluids), _ptr(phi), ns,
+    flow = C.byref(_ptr3(list(rho_flow_face) + [None] * 3, faces)) if rho_flow_face is not None else None
+    st = L.stokes_coefficients(C.byref(grid), C.byref(fluids), _ptr(phi, cells), ns,
                                C.cast(ps, C.POINTER(C.c_void_p)) if ns else None,
                                C.cast(rs, C.POINTER(C.c_double)) if ns else None,
                                C.cast(ms, C.POINTER(C.c_double)) if ns else None,
-                               _ptr3(list(rho_face) + [None] * 3), _ptr(mu_cell), flow, _stream(stream))
+                               _ptr3(list(rho_face) + [None] * 3, faces), _ptr(mu_cell, cells), flow,
+                               _stream(stream))
     if st < 0:
         raise StokesError(st, "stokes_coefficients failed")
 
@@ -377,11 +412,12 @@ def stokes_explicit_rhs(grid, rho_face, mu_cell, dt, theta, u_n, f, rho_force=No
                         stream=None) -> None:
     """f = (rho/dt) u^n + (1 - theta) L_mu u^n (+ rho_force g) on the device."""
     L = load_library()
+    faces, cells = _counts(grid) if grid.dim in (2, 3) else (None, None)
     pad = lambda ts: list(ts) + [None] * 3
-    rf = C.byref(_ptr3(pad(rho_force))) if rho_force is not None else None
+    rf = C.byref(_ptr3(pad(rho_force), faces)) if rho_force is not None else None
     gv = C.byref((C.c_double * 3)(*[float(x) for x in (list(gravity) + [0.0] * 3)[:3]])) if gravity is not None else None
-    st = L.stokes_explicit_rhs(C.byref(grid), _ptr3(pad(rho_face)), _ptr(mu_cell), float(dt), float(theta),
-                               _ptr3(pad(u_n)), rf, gv, _ptr3(pad(f)), _stream(stream))
+    st = L.stokes_explicit_rhs(C.byref(grid), _ptr3(pad(rho_face), faces), _ptr(mu_cell, cells), float(dt),
+                               float(theta), _ptr3(pad(u_n), faces), rf, gv, _ptr3(pad(f), faces), _stream(stream))
     if st < 0:
         raise StokesError(st, "stokes_explicit_rhs failed")
 
@@ -405,8 +441,10 @@ def stokes_rigid_projection(grid, u, X, dV, free_body, body, workspace, stream=N
     returns ``body`` with the free-body velocities filled in."""
     L = load_library()
     n = int(X.shape[0]) if X is not None else 0
-    st = L.stokes_rigid_projection(C.byref(grid), _ptr3(list(u) + [None] * 3), n,
-                                   _ptr(X) if n else None, float(dV), int(bool(free_body)), C.byref(body),
+    faces = _counts(grid)[0] if grid.dim in (2, 3) else None
+    st = L.stokes_rigid_projection(C.byref(grid), _ptr3(list(u) + [None] * 3, faces), n,
+                                   _ptr(X, n * grid.dim) if n else None, float(dV), int(bool(free_body)),
+                                   C.byref(body),
                                    workspace.data_ptr() if workspace is not None else None,
                                    workspace.numel() * workspace.element_size() if workspace is not None else 0,
                                    _stream(stream))
@@ -422,9 +460,10 @@ def stokes_rigid_projection_noalloc(grid, u, X, dV, free_body, body, stream=None
     """stokes_rigid_projection without a workspace (the library's fixed scratch)."""
     L = load_library()
     n = int(X.shape[0]) if X is not None else 0
-    st = L.stokes_rigid_projection_noalloc(C.byref(grid), _ptr3(list(u) + [None] * 3), n,
-                                           _ptr(X) if n else None, float(dV), int(bool(free_body)), C.byref(body),
-                                           _stream(stream))
+    faces = _counts(grid)[0] if grid.dim in (2, 3) else None
+    st = L.stokes_rigid_projection_noalloc(C.byref(grid), _ptr3(list(u) + [None] * 3, faces), n,
+                                           _ptr(X, n * grid.dim) if n else None, float(dV), int(bool(free_body)),
+                                           C.byref(body), _stream(stream))
     if st < 0:
         raise StokesError(st, "stokes_rigid_projection_noalloc failed: " + L.stokes_last_error(None).decode())
     return body

@@ -228,3 +228,77 @@ def test_extreme_extents_rejected_on_host(S):
     w = B.make_wave(0.04, 0.5, 1.5, 2.0)
     assert L.stokes_wave_inflow(ctypes.byref(B.make_grid(2, (8, imax, 1), (1.0, 1.0, 1.0))), ctypes.byref(w),
                                 ctypes.c_double(0.0), 0x1000, 0x2000, None) == -2
+
+
+class _FakeTensor:
+    """Stands in for a device tensor in the binding's argument checks (never
+    dereferenced: every call below fails in the binding before the library)."""
+
+    def __init__(self, numel):
+        import torch
+        self.dtype = torch.float64
+        self.is_cuda = True
+        self._n = numel
+        self.shape = (numel,)
+
+    def is_contiguous(self):
+        return True
+
+    def numel(self):
+        return self._n
+
+    def data_ptr(self):
+        return 0x100000
+
+
+def test_binding_refuses_arrays_shorter_than_the_grid(S):
+    """The kernels index the caller's arrays from the grid alone, so the binding
+    refuses a tensor with fewer values than its layout needs (u: (Nz, Ny, Nx+1),
+    p and mu: (Nz, Ny, Nx), ...) instead of letting a kernel run past its end."""
+    B = S._binding
+    n = (6, 5, 4)
+    g = B.make_grid(3, n, (0.1,) * 3)
+    faces, cells = B._counts(g)
+    assert faces == [7 * 5 * 4, 6 * 6 * 4, 6 * 5 * 5] and cells == 120
+    g2 = B.make_grid(2, (6, 5, 1), (0.1,) * 3)
+    assert B._counts(g2) == ([7 * 5, 6 * 6], 30)
+    F = _FakeTensor
+    good = [F(c) for c in faces]
+    short_u = [F(faces[0]), F(faces[1] - 1), F(faces[2])]
+    fl = B.make_fluids(1e3, 1.0, 1e-3, 1e-5, 1.5)
+    with pytest.raises(ValueError, match="grid needs"):
+        S.stokes_coefficients(g, fl, F(cells - 1), [], [], [], good, F(cells))
+    with pytest.raises(ValueError, match="grid needs"):
+        S.stokes_coefficients(g, fl, F(cells), [F(cells - 2)], [500.0], [1e-3], good, F(cells))
+    with pytest.raises(ValueError, match="grid needs"):
+        S.stokes_coefficients(g, fl, F(cells), [], [], [], short_u, F(cells))
+    with pytest.raises(ValueError, match="grid needs"):
+        S.stokes_explicit_rhs(g, good, F(cells), 1e-3, 0.5, short_u, good)
+    with pytest.raises(ValueError, match="grid needs"):
+        S.stokes_rigid_projection(g, good, _FakeMarkers(10, 2), 1e-3, 1,
+                                  B.make_body((0.3, 0.25, 0.2)), None)
+    with pytest.raises(ValueError, match="grid needs"):
+        S.stokes_rigid_projection_noalloc(g, short_u, _FakeMarkers(10, 3), 1e-3, 1, B.make_body((0.3, 0.25, 0.2)))
+    with pytest.raises(ValueError, match="grid needs"):
+        S.stokes_wave_inflow(g, B.make_wave(0.04, 0.5, 1.5, 2.0), 0.0, F(4 * 5 - 1), F(5 * 5))
+    with pytest.raises(ValueError, match="grid needs"):
+        S.stokes_density_rk3(g, 1e-3, good, [good, short_u, good], good, None)
+    with pytest.raises(ValueError, match="grid needs"):
+        S.stokes_setup(short_u, F(cells), 1e-3, g, None, 0x200000, 1 << 20, stream=0)
+    # a context's grid is kept for the calls that take the context
+    B._CTX_COUNTS[0xdead0] = (faces, cells)
+    try:
+        with pytest.raises(ValueError, match="grid needs"):
+            S.stokes_solve(0xdead0, good, F(cells), 1e-8, short_u, F(cells))
+        with pytest.raises(ValueError, match="grid needs"):
+            S.stokes_apply(0xdead0, good, F(cells - 1), good, F(cells))
+    finally:
+        B._CTX_COUNTS.pop(0xdead0)
+
+
+class _FakeMarkers(_FakeTensor):
+    """n markers with c coordinates each (c < dim is too few for the grid)."""
+
+    def __init__(self, n, c):
+        super().__init__(n * c)
+        self.shape = (n, c)
