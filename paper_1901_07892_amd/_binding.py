@@ -203,8 +203,17 @@ def _counts(grid) -> Tuple[List[int], int]:
     return faces, n[0] * n[1] * n[2]
 
 
+def _inflow_counts(grid) -> Tuple[int, int]:
+    """Values in the inflow arrays on x = 0: u_n (Nv x N_lateral) and u_t
+    ((Nv + 1) x N_lateral), Nv the cells along the vertical axis."""
+    nv = int(grid.n[grid.dim - 1])
+    nl = int(grid.n[1]) if grid.dim == 3 else 1
+    return nv * nl, (nv + 1) * nl
+
+
 # array sizes of each live context's grid, for the checks of the calls that take a context
 _CTX_COUNTS: Dict[int, Tuple[List[int], int]] = {}
+_CTX_INFLOW: Dict[int, Tuple[int, int]] = {}
 
 
 def _ctx_counts(ctx) -> Tuple[Optional[List[int]], Optional[int]]:
@@ -250,6 +259,7 @@ def stokes_setup(rho_face, mu_cell, dt, grid, opts, workspace, ws_bytes, stream=
     if st != 0:
         raise StokesError(st, L.stokes_last_error(None).decode())
     _CTX_COUNTS[ctx.value] = (faces, cells)
+    _CTX_INFLOW[ctx.value] = _inflow_counts(grid)
     return ctx.value
 
 
@@ -278,6 +288,7 @@ def stokes_solve(ctx, rhs_u, rhs_p, tol, x_u, x_p):
 def stokes_destroy(ctx) -> None:
     if ctx:
         _CTX_COUNTS.pop(ctx, None)
+        _CTX_INFLOW.pop(ctx, None)
         load_library().stokes_destroy(ctx)
 
 
@@ -311,10 +322,9 @@ def make_wave(height, depth, wavelength, omega, gravity=9.81, n_cells=1.5) -> St
 
 def stokes_wave_inflow(grid, wave, t, u_n, u_t, stream=None) -> None:
     """Second-order Stokes wave inflow data on x = 0 into the device tensors u_n, u_t."""
-    nv = int(grid.n[grid.dim - 1]) if grid.dim in (2, 3) else 0
-    nl = int(grid.n[1]) if grid.dim == 3 else 1
-    st = load_library().stokes_wave_inflow(C.byref(grid), C.byref(wave), float(t), _ptr(u_n, nv * nl),
-                                          _ptr(u_t, (nv + 1) * nl), _stream(stream))
+    n_n, n_t = _inflow_counts(grid) if grid.dim in (2, 3) else (None, None)
+    st = load_library().stokes_wave_inflow(C.byref(grid), C.byref(wave), float(t), _ptr(u_n, n_n),
+                                          _ptr(u_t, n_t), _stream(stream))
     if st != 0:
         raise StokesError(st, "stokes_wave_inflow failed")
 
@@ -323,7 +333,9 @@ def stokes_inflow_lift(ctx, u_n, u_t, rhs_u, rhs_p) -> None:
     """Subtract the inflow data's contribution from (rhs_u, rhs_p), in place."""
     L = load_library()
     faces, cells = _ctx_counts(ctx)
-    st = L.stokes_inflow_lift(ctx, _ptr(u_n), _ptr(u_t), _ptr3(list(rhs_u) + [None] * 3, faces), _ptr(rhs_p, cells))
+    n_n, n_t = _CTX_INFLOW.get(ctx, (None, None))
+    st = L.stokes_inflow_lift(ctx, _ptr(u_n, n_n), _ptr(u_t, n_t), _ptr3(list(rhs_u) + [None] * 3, faces),
+                              _ptr(rhs_p, cells))
     if st != 0:
         raise StokesError(st, L.stokes_last_error(ctx).decode())
 

@@ -287,13 +287,17 @@ def test_binding_refuses_arrays_shorter_than_the_grid(S):
         S.stokes_setup(short_u, F(cells), 1e-3, g, None, 0x200000, 1 << 20, stream=0)
     # a context's grid is kept for the calls that take the context
     B._CTX_COUNTS[0xdead0] = (faces, cells)
+    B._CTX_INFLOW[0xdead0] = B._inflow_counts(g)
     try:
         with pytest.raises(ValueError, match="grid needs"):
             S.stokes_solve(0xdead0, good, F(cells), 1e-8, short_u, F(cells))
         with pytest.raises(ValueError, match="grid needs"):
             S.stokes_apply(0xdead0, good, F(cells - 1), good, F(cells))
+        with pytest.raises(ValueError, match="grid needs"):
+            S.stokes_inflow_lift(0xdead0, F(20), F(24), good, F(cells))
     finally:
         B._CTX_COUNTS.pop(0xdead0)
+        B._CTX_INFLOW.pop(0xdead0)
 
 
 class _FakeMarkers(_FakeTensor):
