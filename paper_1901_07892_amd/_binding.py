@@ -529,11 +529,13 @@ class StokesSolver:
 
 
 # ---------------------------------------------------------------- learned form (U-Net)
-def _fptr(t):
+def _fptr(t, need: Optional[int] = None):
     if hasattr(t, "data_ptr"):
         import torch
         if t.dtype != torch.float32 or not t.is_contiguous() or not t.is_cuda:
             raise ValueError("U-Net arrays must be contiguous float32 device tensors")
+        if need is not None and t.numel() < need:
+            raise ValueError("U-Net array of %d values where the grid needs %d" % (t.numel(), need))
         return t.data_ptr()
     return int(t)
 
@@ -583,6 +585,8 @@ class UNet:
     def set_params(self, a):
         import numpy as np
         a = np.ascontiguousarray(a, dtype=np.float32)
+        if a.size != self.count:
+            raise ValueError("%d parameters given, the network has %d" % (a.size, self.count))
         _chk(load_library().stokes_unet_set_params(self.handle, a.ctypes.data_as(C.POINTER(C.c_float)), self.count),
              "set_params")
 
@@ -594,13 +598,16 @@ class UNet:
         return a
 
     def forward(self, f0, f1, f2, out):
-        _chk(load_library().stokes_unet_forward(self.handle, _fptr(f0), _fptr(f1), _fptr(f2), _fptr(out)),
-             "stokes_unet_forward")
+        v = self.n ** 3
+        _chk(load_library().stokes_unet_forward(self.handle, _fptr(f0, v), _fptr(f1, v), _fptr(f2, v),
+                                                _fptr(out, v)), "stokes_unet_forward")
 
     def train_step(self, f0, f1, f2, target, lr):
         loss = C.c_float()
-        _chk(load_library().stokes_unet_train_step(self.handle, _fptr(f0), _fptr(f1), _fptr(f2), _fptr(target),
-                                                   float(lr), C.byref(loss)), "stokes_unet_train_step")
+        v = self.n ** 3
+        _chk(load_library().stokes_unet_train_step(self.handle, _fptr(f0, v), _fptr(f1, v), _fptr(f2, v),
+                                                   _fptr(target, v), float(lr), C.byref(loss)),
+             "stokes_unet_train_step")
         return loss.value
 
     def close(self):
