@@ -306,3 +306,51 @@ class _FakeMarkers(_FakeTensor):
     def __init__(self, n, c):
         super().__init__(n * c)
         self.shape = (n, c)
+
+
+def test_binding_passes_arrays_of_the_right_size(S, monkeypatch):
+    """Every checked call marshals arrays of exactly the layout sizes (and larger
+    ones) without complaint: run against a stand-in library that records the call
+    and returns OK, so that no device is touched."""
+    B = S._binding
+    calls = []
+
+    class _Lib:
+        def __getattr__(self, name):
+            def f(*a):
+                calls.append(name)
+                return 0
+            return f
+
+    monkeypatch.setattr(B, "_lib", _Lib())
+    F = _FakeTensor
+    for dim, n in ((3, (6, 5, 4)), (2, (6, 5, 1))):
+        g = B.make_grid(dim, n, (0.1,) * 3)
+        faces, cells = B._counts(g)
+        u = [F(c) for c in faces]
+        big = [F(c + 7) for c in faces]
+        fl = B.make_fluids(1e3, 1.0, 1e-3, 1e-5, 1.5)
+        S.stokes_coefficients(g, fl, F(cells), [F(cells)], [500.0], [1e-3], u, F(cells), big, stream=0)
+        S.stokes_explicit_rhs(g, u, F(cells), 1e-3, 0.5, big, u, u, (0.0, -9.81, 0.0), stream=0)
+        S.stokes_rigid_projection(g, u, _FakeMarkers(10, dim), 1e-3, 1, B.make_body((0.3, 0.25, 0.2)), None,
+                                  stream=0)
+        S.stokes_rigid_projection_noalloc(g, u, _FakeMarkers(10, dim), 1e-3, 1, B.make_body((0.3, 0.25, 0.2)),
+                                          stream=0)
+        n_n, n_t = B._inflow_counts(g)
+        S.stokes_wave_inflow(g, B.make_wave(0.04, 0.5, 1.5, 2.0), 0.0, F(n_n), F(n_t), stream=0)
+        S.stokes_density_rk3(g, 1e-3, u, [u, big, u], u, None, stream=0)
+        ctx = S.stokes_setup(u, F(cells), 1e-3, g, None, 0x200000, 1 << 20, stream=0)
+        assert ctx is None                       # the stand-in library writes no context
+        B._CTX_COUNTS[0xbeef0] = (faces, cells)
+        B._CTX_INFLOW[0xbeef0] = (n_n, n_t)
+        try:
+            S.stokes_apply(0xbeef0, u, F(cells), big, F(cells + 1))
+            S.stokes_solve(0xbeef0, u, F(cells), 1e-8, u, F(cells))
+            S.stokes_inflow_lift(0xbeef0, F(n_n), F(n_t), u, F(cells))
+        finally:
+            B._CTX_COUNTS.pop(0xbeef0)
+            B._CTX_INFLOW.pop(0xbeef0)
+    for name in ("stokes_coefficients", "stokes_explicit_rhs", "stokes_rigid_projection",
+                 "stokes_rigid_projection_noalloc", "stokes_wave_inflow", "stokes_density_rk3", "stokes_setup",
+                 "stokes_apply", "stokes_solve", "stokes_inflow_lift"):
+        assert calls.count(name) == 2, name
